@@ -1,0 +1,258 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics
+(no GPU).  Each test names what it pins; none re-types the oracle's formula.
+
+Pins used (the paper prints no worked example and no distances):
+  - hand-derived values (tests/golden/hand_examples.json) of eq. (dtw), the band,
+    eq. (Normalization1), eq. (envelope), the bounds and eq. (OverlapPartitioning);
+  - r = 0 reduces DTW to the squared Euclidean distance (eq. (Euclidean) squared);
+  - DTW(x,x)=0, DTW >= 0, symmetry, monotonicity in r, r >= m-1 = unconstrained;
+  - exhaustive minimum over every warping path equals the recurrence (tiny m);
+  - every lower bound is <= DTW, and at r = 0 both LB_Keogh bounds equal DTW;
+  - z-normalised windows have mean 0 / std 1 and distances are affine-invariant;
+  - a planted exact copy is found at distance 0 with the lowest index;
+  - fragment-wise search reduced by (distance, index) equals the global search;
+  - the C cascade oracle equals NumPy brute force.
+A mutation check at the end plants typical mistakes into copies of the
+recurrence and shows that these pins catch each one.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import reference as R
+from oracle import Cascade
+from paper_1812_10302_amd import workloads as W
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")))
+
+
+@pytest.fixture(scope="module")
+def casc():
+    return Cascade()
+
+
+# ------------------------------------------------------------------ golden
+def test_hand_dtw_values():
+    for ex in GOLD["dtw"]:
+        for r, v in ex["by_r"].items():
+            assert R.dtw(ex["x"], ex["y"], int(r)) == pytest.approx(v, abs=1e-12)
+            assert R.dtw_many(ex["x"], np.array(ex["y"], float)[:, None], int(r))[0] == pytest.approx(v, abs=1e-12)
+
+
+def test_hand_znorm():
+    z = GOLD["znorm"]
+    np.testing.assert_allclose(R.znorm(z["x"]), z["xhat"], rtol=1e-14)
+    mu, sg = R.window_stats(np.array(z["x"], np.float32), 4)
+    assert mu[0] == pytest.approx(z["mu"]) and sg[0] ** 2 == pytest.approx(z["sigma2"])
+
+
+def test_hand_envelope_and_bounds():
+    e = GOLD["envelope_lb"]
+    U, L = R.envelope(e["q"], e["r"])
+    np.testing.assert_array_equal(U, e["U"])
+    np.testing.assert_array_equal(L, e["L"])
+    assert R.lb_keogh(e["c"], U, L) == e["lb_keogh_c_vs_envq"]
+    assert R.lb_kim_fl(e["q"], e["c"]) == e["lb_kim_fl"]
+
+
+def test_hand_fragments():
+    f = GOLD["fragments"]
+    assert [list(x) for x in R.fragments(f["N"], f["F"], f["m"])] == f["start_len"]
+
+
+# ------------------------------------------------------------- closed forms
+def test_r0_is_squared_euclidean():
+    rng = np.random.default_rng(11)
+    for m in (1, 2, 7, 33, 128):
+        x, y = rng.standard_normal(m), rng.standard_normal(m)
+        ed2 = float(np.sum((x - y) ** 2))
+        assert R.dtw(x, y, 0) == pytest.approx(ed2, rel=1e-13)
+
+
+def test_identity_nonnegativity_symmetry():
+    rng = np.random.default_rng(12)
+    for m, r in ((5, 1), (16, 3), (40, 40), (64, 6)):
+        x, y = rng.standard_normal(m), rng.standard_normal(m)
+        assert R.dtw(x, x, r) == 0.0
+        d = R.dtw(x, y, r)
+        assert d >= 0.0
+        assert d == pytest.approx(R.dtw(y, x, r), rel=1e-13)
+
+
+def test_monotone_in_band_and_unconstrained_limit():
+    rng = np.random.default_rng(13)
+    for m in (6, 20, 50):
+        x, y = rng.standard_normal(m), rng.standard_normal(m)
+        vals = [R.dtw(x, y, r) for r in range(0, m + 3)]
+        assert all(vals[k + 1] <= vals[k] + 1e-12 for k in range(len(vals) - 1))
+        assert vals[0] == pytest.approx(float(np.sum((x - y) ** 2)))
+        assert vals[m - 1] == vals[m] == vals[m + 2]
+
+
+def test_exhaustive_paths_equal_recurrence():
+    rng = np.random.default_rng(14)
+    assert R.warping_path_count(8, 7) == 48639      # central Delannoy number D(7,7)
+    for m in range(1, 8):
+        for r in range(0, m):
+            for _ in range(3):
+                x, y = rng.standard_normal(m), rng.standard_normal(m)
+                assert R.dtw(x, y, r) == pytest.approx(R.dtw_allpaths(x, y, r), rel=1e-12, abs=1e-12)
+
+
+# -------------------------------------------------------------- lower bounds
+def test_bounds_below_dtw_and_tight_at_r0():
+    rng = np.random.default_rng(15)
+    T, _ = W.tiny_random(2000, 8, 15)
+    viol = 0
+    for trial in range(300):
+        m = int(rng.integers(2, 40))
+        r = int(rng.integers(0, m))
+        qh = R.znorm(np.cumsum(rng.standard_normal(m)))
+        i = int(rng.integers(0, T.size - m))
+        ch = R.znorm(T[i:i + m])
+        d = R.dtw(qh, ch, r)
+        lbs = [R.lb_kim_fl(qh, ch), R.lb_keogh_q(qh, ch, r), R.lb_keogh_d(qh, ch, r),
+               R.lb_keogh_d_series(T, i, m, r, qh)]
+        viol += sum(lb > d * (1 + 1e-12) + 1e-12 for lb in lbs)
+        # the series-level candidate envelope contains the candidate's own one
+        assert lbs[3] <= lbs[2] + 1e-9
+        if r == 0:
+            assert lbs[1] == pytest.approx(d, rel=1e-12, abs=1e-12)
+            assert lbs[2] == pytest.approx(d, rel=1e-12, abs=1e-12)
+            assert lbs[0] <= lbs[1] + 1e-12
+    assert viol == 0
+
+
+# ------------------------------------------------------------ normalisation
+def test_znorm_moments_and_flat_window():
+    rng = np.random.default_rng(16)
+    x = rng.standard_normal(500) * 37.0 + 1e3
+    z = R.znorm(x)
+    assert abs(z.mean()) < 1e-12 and abs(z.std() - 1.0) < 1e-12
+    assert np.all(R.znorm(np.full(17, 3.25)) == 0.0)
+
+
+def test_distances_affine_invariant():
+    T, Q = W.tiny_random(400, 24, 17)
+    D0 = R.all_distances(T, Q, 3)
+    D1 = R.all_distances(T.astype(np.float64) * 3.0 - 250.0, Q.astype(np.float64) * 0.5 + 9.0, 3)
+    np.testing.assert_allclose(D0, D1, rtol=1e-9, atol=1e-9)
+
+
+def test_planted_copy_found_with_lowest_index():
+    T, _ = W.tiny_random(600, 8, 18)
+    T = T.astype(np.float64)
+    m = 20
+    shape = T[100:100 + m].copy()
+    T[400:400 + m] = shape * 2.0 + 5.0            # second exact (affine) copy, higher index
+    Q = shape * 0.25 - 1.0
+    i, d = R.best_match(T, Q, 2)
+    assert d < 1e-18 and i == 100
+
+
+# ----------------------------------------------------------- brute force
+def test_bruteforce_matches_exhaustive_tiny():
+    for seed in range(4):
+        T, Q = W.tiny_random(30, 5, 100 + seed)
+        for r in range(0, 5):
+            D = R.all_distances(T, Q, r)
+            qh = R.znorm(Q)
+            E = [R.dtw_allpaths(qh, R.znorm(T[i:i + 5]), r) for i in range(T.size - 4)]
+            np.testing.assert_allclose(D, E, rtol=1e-12, atol=1e-12)
+
+
+def test_fragment_decomposition():
+    T, Q = W.tiny_random(500, 16, 19)
+    g = R.best_match(T, Q, 3)
+    for F in range(1, 8):
+        i, d = R.best_match_fragmented(T, Q, 3, F)
+        assert i == g[0] and d == pytest.approx(g[1], rel=1e-12)
+        # every start lies in exactly one fragment
+        N = T.size - 16 + 1
+        cover = np.zeros(N, int)
+        for s, L in R.fragments(N, F, 16):
+            cover[s:s + L - 16 + 1] += 1
+        assert np.all(cover == 1)
+
+
+# --------------------------------------------------------------- C cascade
+@pytest.mark.parametrize("seed,n,m,r", [(1, 300, 16, 0), (2, 500, 16, 3), (3, 700, 32, 6),
+                                        (4, 400, 9, 8), (5, 900, 64, 12), (6, 64, 64, 5)])
+def test_cascade_equals_bruteforce_small(casc, seed, n, m, r):
+    T, Q = W.tiny_random(n, m, seed)
+    i, d = R.best_match(T, Q, r)
+    for threads in (1, 3):
+        j, e, cnt = casc.search(T, Q, r, threads)
+        assert j == i and e == pytest.approx(d, rel=1e-12)
+        assert cnt[0] == n - m + 1
+
+
+def test_cascade_dtw_starts_equals_numpy(casc):
+    T, Q = W.tiny_random(800, 40, 21)
+    starts = np.array([0, 5, 123, 760], np.int64)
+    for r in (0, 4, 39):
+        np.testing.assert_allclose(casc.dtw_starts(T, Q, r, starts), R.distances_at(T, Q, r, starts),
+                                   rtol=1e-12)
+
+
+def test_cascade_equals_bruteforce_on_single_query_workload(casc):
+    """The small random-walk workload (n=262,144, m=128, r=6): full brute force vs cascade."""
+    wl = W.single_query_small()
+    i, d = R.best_match(wl.T, wl.queries[0], wl.bands[0], chunk=16384)
+    j, e, _ = casc.search(wl.T, wl.queries[0], wl.bands[0])
+    assert j == i and e == pytest.approx(d, rel=1e-12)
+    assert abs(i - wl.sources[0]) <= wl.bands[0]   # the noisy cut is found near its source
+
+
+# ------------------------------------------------------- mutation check
+def _mut_dtw(x, y, r, mode):
+    x = np.asarray(x, float)
+    y = np.asarray(y, float)
+    m = x.size
+    r = min(r, m - 1)
+    d = np.full((m + 1, m + 1), np.inf)
+    d[0, 0] = 0.0
+    for i in range(1, m + 1):
+        lo, hi = max(1, i - r), min(m, i + r)
+        if mode == "band_off_by_one":
+            lo, hi = max(1, i - r + 1), min(m, i + r - 1) if r > 0 else i
+            lo = min(lo, i)
+            hi = max(hi, i)
+        for j in range(lo, hi + 1):
+            c = (x[i - 1] - y[j - 1]) ** 2 if mode != "unsquared" else abs(x[i - 1] - y[j - 1])
+            if mode == "no_diagonal":
+                mn = min(d[i - 1, j], d[i, j - 1]) if (i, j) != (1, 1) else 0.0
+            elif mode == "wrong_index":
+                c = (x[i - 1] - y[min(m, j) - 1 if j == i else j - 2 if j > 1 else 0]) ** 2
+                mn = min(d[i - 1, j], d[i, j - 1], d[i - 1, j - 1])
+            else:
+                mn = min(d[i - 1, j], d[i, j - 1], d[i - 1, j - 1])
+            d[i, j] = c + mn
+    return float(d[m, m])
+
+
+def _pins_pass(fn) -> bool:
+    try:
+        for ex in GOLD["dtw"]:
+            for r, v in ex["by_r"].items():
+                if abs(fn(ex["x"], ex["y"], int(r)) - v) > 1e-9:
+                    return False
+        rng = np.random.default_rng(5)
+        for m in (3, 5, 6):
+            for r in range(m):
+                x, y = rng.standard_normal(m), rng.standard_normal(m)
+                if abs(fn(x, y, r) - R.dtw_allpaths(x, y, r)) > 1e-9:
+                    return False
+                if r == 0 and abs(fn(x, y, 0) - float(np.sum((x - y) ** 2))) > 1e-9:
+                    return False
+        return True
+    except Exception:
+        return False
+
+
+@pytest.mark.parametrize("mode", ["no_diagonal", "unsquared", "band_off_by_one", "wrong_index"])
+def test_pins_catch_planted_mistakes(mode):
+    assert _pins_pass(R.dtw)
+    assert not _pins_pass(lambda x, y, r: _mut_dtw(x, y, r, mode))
