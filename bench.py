@@ -1,0 +1,181 @@
+"""Benchmark: exact best-match DTW search on one MI355X.
+
+One step = the whole search path (window statistics, data envelope, bound cascade, banded DTW
+with the device best-so-far, FP64 certification) for every query of the workload, with the
+series already resident in HBM.  Default workload: float32 random walk of n = 1e8 points and
+three queries (m = 128, 512, 1024, cut from the series plus N(0, 0.1) noise, band 5%).
+
+Prints one JSON line.  value = seconds per query (lower is better).  The roofline object is
+for the kernel class with the largest total time, timed with HIP events recorded on the
+launch stream inside the library (DTWS_PROFILE) over a separate profiled pass.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "search s/query and DTW GCUPS (frac. VALU peak), batched+learned vs plain, 1 GPU"
+# MI355X peaks (public figures): HBM3E 8 TB/s; FP32 VALU lane-ops: 256 CU x 4 SIMD x 16 lanes x
+# 2.4 GHz = 39.3e12 /s (no packed math); DTW needs 3 lane-ops per cell -> 13,107 GCUPS.
+HBM_PEAK_GBS = 8000.0
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+DTW_PEAK_GCUPS = VALU_LANE_OPS / 3 / 1e9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cells(m: int, r: int) -> int:
+    r = min(r, m - 1)
+    return m * (2 * r + 1) - r * (r + 1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=100_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="series points for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search shards by "
+              "series fragment across GPUs but this build runs and times a single GPU.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1812_10302_amd as dtws
+    from paper_1812_10302_amd import workloads as W
+
+    t0 = time.time()
+    wl = W.three_queries_large(args.n)
+    log(f"workload {wl.name}: generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    T = torch.from_numpy(wl.T).to(dev)
+    Qs = [torch.from_numpy(q).to(dev) for q in wl.queries]
+    ms = [q.size for q in wl.queries]
+    rs = list(wl.bands)
+    nq = len(Qs)
+    ctx = dtws.Context(0, max_n=wl.T.size, max_m=max(ms), max_queries=nq)
+    torch.cuda.synchronize()
+
+    def step(flags=0):
+        res = []
+        for q, r in zip(Qs, rs):
+            res.append(ctx.search(T, q, r, flags=flags, seed=7))
+        return res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per_query = []
+    for _ in range(args.steps):
+        for q, r in zip(Qs, rs):
+            a = time.perf_counter()
+            out = ctx.search(T, q, r, seed=7)
+            per_query.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    ms_per_step = elapsed / args.steps * 1e3
+    s_per_query = elapsed / args.steps / nq
+    results = step()
+    log("results:", results)
+
+    # ---------------------------------------------------------------- profiled pass
+    prof_total = {k: [0.0, 0] for k in dtws.KERNEL_CLASSES}
+    cnt_total = {}
+    dtw_cells = 0
+    dtw_lane_cells = 0
+    lb_candidates = 0
+    per_query_prof = []
+    if not args.no_profile:
+        for q, r in zip(Qs, rs):
+            ctx.search(T, q, r, flags=dtws.PROFILE, seed=7)
+            p = ctx.profile()
+            c = ctx.counters()
+            per_query_prof.append({"m": int(q.numel()), "r": int(r), "kernel_ms": {k: round(v[0], 4) for k, v in p.items()},
+                                   "counters": c})
+            for k, (t, nl) in p.items():
+                prof_total[k][0] += t
+                prof_total[k][1] += nl
+            for k, v in c.items():
+                cnt_total[k] = cnt_total.get(k, 0) + v
+            dtw_cells += c["dtw_cells"]
+            dtw_lane_cells += c["dtw_lane_cells"]
+            lb_candidates += c["candidates"]
+    dominant = max(prof_total, key=lambda k: prof_total[k][0])
+    roofline = None
+    if not args.no_profile:
+        t_ms, nl = prof_total[dominant]
+        if dominant == "dtw":
+            ach = dtw_cells / (t_ms * 1e-3) / 1e9
+            roofline = {"bound": "alu", "kernel": "k_dtw", "achieved": round(ach, 2), "peak": round(DTW_PEAK_GCUPS, 1),
+                        "unit": "GCUPS", "frac": round(ach / DTW_PEAK_GCUPS, 4), "traffic": None,
+                        "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl,
+                        "issued_frac": round(dtw_lane_cells / (t_ms * 1e-3) / 1e9 / DTW_PEAK_GCUPS, 4)}
+        else:
+            # streaming kernels: algorithmic bytes = 4 B of series + 12 B of window statistics per
+            # candidate (lb), 4 B read + 12 B written (stats), 4 B read + 8 B written (env)
+            per_cand = {"lb": 16, "stats": 16, "env": 12}.get(dominant, 16)
+            ach = lb_candidates * per_cand / (t_ms * 1e-3) / 1e9
+            roofline = {"bound": "hbm", "kernel": f"k_{dominant}", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                        "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
+
+    # ---------------------------------------------------------------- CPU baseline (oracle)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import Cascade
+        casc = Cascade()
+        ns = min(args.cpu_sample, wl.T.size)
+        Ts = wl.T[:ns]
+        t = time.perf_counter()
+        for q, r in zip(wl.queries, rs):
+            casc.search(Ts, q, r)
+        dt = time.perf_counter() - t
+        scale = (wl.T.size - np.mean(ms) + 1) / (ns - np.mean(ms) + 1)
+        cpu = {"value": round(dt / nq * scale, 4), "unit": "s/query", "cores": casc.num_threads(), "kind": "oracle",
+               "sample": f"C FP64 cascade oracle on the first {ns} points for each of the {nq} queries "
+                         f"({dt:.2f}s), scaled linearly to n={wl.T.size}"}
+
+    out = {
+        "metric": METRIC,
+        "value": round(s_per_query, 6),
+        "unit": "s/query",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": int(wl.T.size), "m": ms, "r": rs, "mode": "plain",
+                   "note": wl.note},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_query_s": [round(float(np.median(per_query[i::nq])), 6) for i in range(nq)],
+        "kernel_ms": {k: [round(v[0], 4), v[1]] for k, v in prof_total.items()},
+        "dtw_gcups": round(dtw_cells / (prof_total["dtw"][0] * 1e-3) / 1e9, 2) if prof_total["dtw"][0] > 0 else None,
+        "counters": cnt_total,
+        "per_query_profile": per_query_prof,
+        "results": [[int(i), float(d)] for i, d in results],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * dtws.h -- exact best-match subsequence search under banded, z-normalised,
+ * squared Dynamic Time Warping on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Kraeva & Zymbler, arXiv:1812.10302, Section 2.1, best-match
+ * definition, and Algorithm 1 "PhiBestMatch(in T, Q, r; out bsf, bestmatch)"):
+ * given a series T of n points, a query Q of m points and a Sakoe-Chiba band
+ * of r points, find the start i in [0, n-m] that minimises
+ *     DTW_r( znorm(Q), znorm(T[i .. i+m-1]) )
+ * where DTW is the recurrence of eq. (dtw) with cells |a-b| > r excluded, the
+ * distance is squared (the square root is dropped, Section 2.2, eq. (Euclidean)
+ * and the remark after it) and znorm is eq. (Normalization1) with the
+ * population sigma.  Ties resolve to the lowest start index.  A window whose
+ * sigma is <= 1e-8 normalises to all zeros.  r >= m-1 means unconstrained DTW.
+ *
+ * Conventions for every call below:
+ *  - Pointers named *_dev are DEVICE pointers on the context's device (for
+ *    example torch.Tensor.data_ptr() of a CUDA/HIP tensor), contiguous, owned
+ *    by the caller, never retained after the call returns.  Pointers named
+ *    *_host are host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Kernels are enqueued on it; calls documented as "blocking" synchronise
+ *    it before returning, the others return as soon as the work is enqueued.
+ *  - The context owns every scratch buffer; they are allocated by
+ *    dtws_create and sized by its limits.  Nothing is allocated per call
+ *    except where a call's comment says so.
+ *  - Return value: DTWS_OK or a negative error code.  Argument errors are
+ *    detected before any device work is enqueued.  After DTWS_EHIP,
+ *    dtws_last_error() returns the HIP error text.  No C++ exception ever
+ *    crosses this interface.
+ *  - A context may be used by one host thread at a time; calls that share a
+ *    context must not overlap.
+ */
+#ifndef DTWS_H
+#define DTWS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DTWS_API __attribute__((visibility("default")))
+
+typedef struct dtws_ctx dtws_ctx;
+
+enum dtws_status {
+    DTWS_OK = 0,
+    DTWS_EINVAL = -1,    /* bad argument (null pointer, m < 2, m > n, r < 0, over a limit) */
+    DTWS_ENOMEM = -2,    /* device allocation failed in dtws_create                       */
+    DTWS_ENODEV = -3,    /* no HIP device, or the device ordinal does not exist           */
+    DTWS_EHIP = -4,      /* a HIP runtime call failed; see dtws_last_error                */
+    DTWS_EOVERFLOW = -5, /* an internal list overflowed; the result would not be certain  */
+    DTWS_ENOMODEL = -6   /* learned ordering asked for but no model is loaded/trained     */
+};
+
+/* Search flags (bit set). */
+#define DTWS_ORDER_NATURAL 0u        /* blocks in series order (plain search)                     */
+#define DTWS_ORDER_RANDOM 1u         /* blocks in a seeded random permutation                     */
+#define DTWS_ORDER_LEARNED 2u        /* blocks by ascending score of the learned model            */
+#define DTWS_ORDER_MASK 3u
+#define DTWS_NO_LOWER_BOUNDS 4u      /* skip the bound cascade: DTW (with abandoning) on all      */
+#define DTWS_PROFILE 8u              /* time every kernel with HIP events on the call's stream
+                                        (adds an event pair per launch); see dtws_get_profile     */
+
+/* Kernel classes reported by dtws_get_profile. */
+enum dtws_kernel_class {
+    DTWS_K_PREP = 0,    /* query normalisation, envelope, visiting order        */
+    DTWS_K_STATS = 1,   /* per-window mean / sigma                               */
+    DTWS_K_ENV = 2,     /* raw-series envelope                                   */
+    DTWS_K_LB = 3,      /* lower-bound cascade                                   */
+    DTWS_K_DTW = 4,     /* banded DTW (including the best-so-far update)         */
+    DTWS_K_CERT = 5,    /* FP64 certification                                    */
+    DTWS_K_OTHER = 6,   /* fills and bookkeeping                                 */
+    DTWS_K_COUNT = 7
+};
+
+/* Result of one search: 0-based start and its squared z-normalised DTW
+ * distance, certified in FP64.  status is DTWS_OK or an error code. */
+typedef struct {
+    int64_t index;
+    double distance;
+    int32_t status;
+    int32_t reserved;
+} dtws_match;
+
+/* Counters of the last search call on a context (summed over its queries). */
+typedef struct {
+    int64_t candidates;        /* starts considered                                     */
+    int64_t pruned_kim;        /* discarded by LB_KimFL                                 */
+    int64_t pruned_keogh_q;    /* discarded by LB_Keogh against the query envelope      */
+    int64_t pruned_keogh_d;    /* discarded by LB_Keogh against the data envelope       */
+    int64_t dtw_started;       /* candidates whose DTW was started                      */
+    int64_t dtw_abandoned;     /* ... and abandoned early                               */
+    int64_t dtw_cells;         /* band cells evaluated by DTW (including abandoned)     */
+    int64_t certified;         /* near-best candidates re-evaluated in FP64             */
+    int64_t dtw_lane_cells;    /* lane-cells issued by the DTW kernels: band bucket x
+                                  columns x 64 lanes per wave step, idle lanes included */
+} dtws_counters;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` able to search series of up to
+ * max_n points (max_n < 2^31) with queries of up to max_m points (2 <= max_m
+ * <= 4096) and batches of up to max_queries queries.  Allocates all device
+ * scratch (roughly 24 bytes per series point plus small per-query buffers).
+ * Returns DTWS_ENODEV when no HIP device is present. */
+DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_queries, dtws_ctx **out);
+
+/* Release the context and all its device memory.  NULL is accepted. */
+DTWS_API void dtws_destroy(dtws_ctx *ctx);
+
+/* Static text for an error code. */
+DTWS_API const char *dtws_strerror(int code);
+
+/* Text of the last HIP error seen on this context ("" if none). */
+DTWS_API const char *dtws_last_error(dtws_ctx *ctx);
+
+/* Number of HIP devices visible (0 when there is none). */
+DTWS_API int dtws_device_count(void);
+
+/* Counters of the last dtws_search / dtws_search_batch call. */
+DTWS_API int dtws_get_counters(dtws_ctx *ctx, dtws_counters *out_host);
+
+/* Per-kernel-class time of the last search call made with DTWS_PROFILE:
+ * ms_host[k] = summed HIP-event time of class k's launches, launches_host[k] =
+ * their number (arrays of DTWS_K_COUNT entries).  Zero when the last call
+ * was not profiled. */
+DTWS_API int dtws_get_profile(dtws_ctx *ctx, double *ms_host, int64_t *launches_host);
+
+/* ------------------------------------------------------------------ search */
+
+/* Best match of one query (Section 2.1 best-match definition; Algorithm 1
+ * in its single-fragment form, Section 4.2's single-node variant).
+ *   T_dev[n] float32 series, Q_dev[m] float32 query, band r (clamped to m-1),
+ *   flags: DTWS_ORDER_* and DTWS_NO_LOWER_BOUNDS, seed: picks the random
+ *   candidate whose DTW initialises the best-so-far (Algorithm 1, the random
+ *   subsequence) and the random order.  The result never depends on it.
+ * Blocking: the result is written to *out_host when the call returns. */
+DTWS_API int dtws_search(dtws_ctx *ctx, const float *T_dev, int64_t n, const float *Q_dev, int32_t m,
+                         int32_t r, uint32_t flags, uint64_t seed, void *stream, dtws_match *out_host);
+
+/* Best matches of nq queries of possibly different lengths and bands against
+ * one series, all queries in one persistent launch with a device work queue.
+ *   Q_packed_dev: the queries back to back; q_offsets_host[k] is query k's
+ *   first element in it; m_host[k], r_host[k] its length and band.
+ *   out_host[nq] receives one result per query.
+ * Blocking.  Results are identical to nq calls of dtws_search. */
+DTWS_API int dtws_search_batch(dtws_ctx *ctx, const float *T_dev, int64_t n, const float *Q_packed_dev,
+                               const int64_t *q_offsets_host, const int32_t *m_host, const int32_t *r_host,
+                               int32_t nq, uint32_t flags, uint64_t seed, void *stream, dtws_match *out_host);
+
+/* ------------------------------------------------ stage-level entry points */
+
+/* Per-window mean and population standard deviation of every length-m window
+ * of T (eq. (Normalization1)); mu_dev[i], sigma_dev[i] for i in [0, n-m],
+ * FP64.  Computed from FP64 sums anchored within tiles of the series. */
+DTWS_API int dtws_znorm_stats(dtws_ctx *ctx, const float *T_dev, int64_t n, int32_t m, double *mu_dev,
+                              double *sigma_dev, void *stream);
+
+/* Lower bounds of every candidate i in [0, n-m] against query Q (Section 2.2):
+ *   lb_kim_dev[i]     LB_KimFL, squared first-pair plus last-pair difference;
+ *   lb_keogh_q_dev[i] sum of squared excursions of the normalised candidate
+ *                     outside the query envelope (eq. (envelope), clipped);
+ *   lb_keogh_d_dev[i] sum of squared excursions of the normalised query
+ *                     outside the data envelope: max/min of the raw series
+ *                     over [k-r, k+r] clipped to [0, n), mapped through the
+ *                     candidate's normalisation (contains the candidate's own
+ *                     envelope, hence a valid, looser bound).
+ * Any of the three outputs may be NULL.  FP32.  When survivors_dev is not
+ * NULL, also writes the starts with all three bounds <= threshold (in no
+ * particular order) and their number to *n_survivors_host (blocking then). */
+DTWS_API int dtws_lb_cascade(dtws_ctx *ctx, const float *T_dev, int64_t n, const float *Q_dev, int32_t m,
+                             int32_t r, float threshold, float *lb_kim_dev, float *lb_keogh_q_dev,
+                             float *lb_keogh_d_dev, int32_t *survivors_dev, int64_t *n_survivors_host,
+                             void *stream);
+
+/* Banded DTW (eq. (dtw) with the band) of the normalised query against the
+ * normalised candidates at starts_dev[count] (each in [0, n-m]), FP32
+ * arithmetic: dist_dev[k] receives the distance, or +inf if the evaluation
+ * proved it exceeds abandon_at (pass +inf for exact values, no abandoning). */
+DTWS_API int dtws_dtw_band(dtws_ctx *ctx, const float *T_dev, int64_t n, const float *Q_dev, int32_t m,
+                           int32_t r, const int64_t *starts_dev, int64_t count, float abandon_at,
+                           float *dist_dev, void *stream);
+
+/* Best-so-far update (eq. (bsf)): for each k, atomically lowers keys_dev[0]
+ * to min(keys_dev[0], (bits(d_dev[k]) << 32) | idx_dev[k]).  Keys order by
+ * distance, then by index, so the minimum is the lowest-index best.
+ * d_dev must be non-negative (or +inf), idx_dev in [0, 2^32). */
+DTWS_API int dtws_bsf_update(dtws_ctx *ctx, uint64_t *keys_dev, const float *d_dev, const int64_t *idx_dev,
+                             int64_t count, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DTWS_H */

@@ -1,0 +1,270 @@
+"""Exact best-match subsequence search under banded, z-normalised, squared DTW on AMD MI355X.
+
+Thin ctypes binding over the C ABI of libdtws.so (include/dtws.h).  Every step of the search
+runs in the library's HIP kernels; this module only marshals arguments.  PyTorch supplies
+device memory (tensors) and the current HIP stream.  There is no CPU fallback: if the library
+is missing the calls raise.
+
+    import torch, paper_1812_10302_amd as dtws
+    ctx = dtws.Context(max_n=T.numel(), max_m=1024)
+    index, distance = ctx.search(T_gpu, Q_gpu, r)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdtws.so")
+
+OK, EINVAL, ENOMEM, ENODEV, EHIP, EOVERFLOW, ENOMODEL = 0, -1, -2, -3, -4, -5, -6
+ORDER_NATURAL, ORDER_RANDOM, ORDER_LEARNED = 0, 1, 2
+NO_LOWER_BOUNDS = 4
+PROFILE = 8
+KERNEL_CLASSES = ("prep", "stats", "env", "lb", "dtw", "cert", "other")
+MAX_M = 2048
+
+COUNTER_FIELDS = ("candidates", "pruned_kim", "pruned_keogh_q", "pruned_keogh_d", "dtw_started",
+                  "dtw_abandoned", "dtw_cells", "certified", "dtw_lane_cells")
+
+
+class Match(ctypes.Structure):
+    _fields_ = [("index", ctypes.c_int64), ("distance", ctypes.c_double), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in COUNTER_FIELDS]
+
+
+class DtwsError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        self.code = code
+        msg = f"{what}: {_strerror(code)} ({code})"
+        if detail:
+            msg += f" -- {detail}"
+        super().__init__(msg)
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1812_10302_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7).  Loading torch
+    # first makes libdtws.so bind to that runtime, so the process holds a single HIP runtime and
+    # torch's streams and allocations are valid in the library's calls.  Loading the library
+    # first would bring in a second runtime that then hides the GPU from torch.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32, U64, F32 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                  ctypes.c_uint64, ctypes.c_float)
+    sig = {
+        "dtws_create": ([ctypes.c_int, I64, I32, I32, ctypes.POINTER(P)], ctypes.c_int),
+        "dtws_destroy": ([P], None),
+        "dtws_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "dtws_last_error": ([P], ctypes.c_char_p),
+        "dtws_device_count": ([], ctypes.c_int),
+        "dtws_get_counters": ([P, ctypes.POINTER(Counters)], ctypes.c_int),
+        "dtws_get_profile": ([P, P, P], ctypes.c_int),
+        "dtws_search": ([P, P, I64, P, I32, I32, U32, U64, P, ctypes.POINTER(Match)], ctypes.c_int),
+        "dtws_search_batch": ([P, P, I64, P, P, P, P, I32, U32, U64, P, P], ctypes.c_int),
+        "dtws_znorm_stats": ([P, P, I64, I32, P, P, P], ctypes.c_int),
+        "dtws_lb_cascade": ([P, P, I64, P, I32, I32, F32, P, P, P, P, ctypes.POINTER(I64), P], ctypes.c_int),
+        "dtws_dtw_band": ([P, P, I64, P, I32, I32, P, I64, F32, P, P], ctypes.c_int),
+        "dtws_bsf_update": ([P, P, P, P, I64, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def library():
+    """The loaded ctypes library (raises ImportError when it has not been built)."""
+    return _load()
+
+
+def _strerror(code: int) -> str:
+    try:
+        return _load().dtws_strerror(code).decode()
+    except ImportError:
+        return "error"
+
+
+def device_count() -> int:
+    return int(_load().dtws_device_count())
+
+
+def band(m: int, frac: float) -> int:
+    """Band in points for a band given as a fraction of the query length (floor)."""
+    return int(math.floor(frac * m))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_f32(x, name):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 1:
+        raise TypeError(f"{name} must be a contiguous 1-D float32 tensor")
+    return x
+
+
+def _stream(t):
+    return ctypes.c_void_p(_torch().cuda.current_stream(t.device).cuda_stream)
+
+
+class Context:
+    """A search context on one GPU; owns all device scratch (sized by max_n, max_m, max_queries)."""
+
+    def __init__(self, device: int = 0, max_n: int = 1 << 20, max_m: int = MAX_M, max_queries: int = 1):
+        L = _load()
+        h = ctypes.c_void_p()
+        rc = L.dtws_create(int(device), int(max_n), int(max_m), int(max_queries), ctypes.byref(h))
+        if rc != OK:
+            raise DtwsError(rc, "dtws_create")
+        self._h = h
+        self.device, self.max_n, self.max_m, self.max_queries = device, max_n, max_m, max_queries
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().dtws_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc: int, what: str):
+        if rc != OK:
+            raise DtwsError(rc, what, _load().dtws_last_error(self._h).decode())
+
+    # ------------------------------------------------------------------ search
+    def search(self, T, Q, r: int, flags: int = ORDER_NATURAL, seed: int = 0):
+        """Best match of Q in T with band r: (0-based start, squared z-normalised DTW distance)."""
+        _dev_f32(T, "T")
+        _dev_f32(Q, "Q")
+        out = Match()
+        rc = _load().dtws_search(self._h, T.data_ptr(), T.numel(), Q.data_ptr(), Q.numel(), int(r), int(flags),
+                                 int(seed), _stream(T), ctypes.byref(out))
+        self._check(rc, "dtws_search")
+        return int(out.index), float(out.distance)
+
+    def search_batch(self, T, queries, rs, flags: int = ORDER_NATURAL, seed: int = 0):
+        """Best matches of several queries (list of 1-D float32 tensors); returns a list of pairs."""
+        torch = _torch()
+        _dev_f32(T, "T")
+        qs = [q.reshape(-1) for q in queries]
+        packed = torch.cat(qs).contiguous()
+        _dev_f32(packed, "queries")
+        nq = len(qs)
+        offs = np.zeros(nq, np.int64)
+        offs[1:] = np.cumsum([q.numel() for q in qs])[:-1]
+        ms = np.array([q.numel() for q in qs], np.int32)
+        rr = np.array([int(x) for x in rs], np.int32)
+        out = (Match * nq)()
+        rc = _load().dtws_search_batch(self._h, T.data_ptr(), T.numel(), packed.data_ptr(), offs.ctypes.data,
+                                       ms.ctypes.data, rr.ctypes.data, nq, int(flags), int(seed), _stream(T),
+                                       ctypes.cast(out, ctypes.c_void_p))
+        self._check(rc, "dtws_search_batch")
+        return [(int(o.index), float(o.distance)) for o in out]
+
+    def counters(self) -> dict:
+        c = Counters()
+        self._check(_load().dtws_get_counters(self._h, ctypes.byref(c)), "dtws_get_counters")
+        return {f: int(getattr(c, f)) for f in COUNTER_FIELDS}
+
+    def profile(self) -> dict:
+        """{class: (milliseconds, launches)} of the last search run with the PROFILE flag."""
+        ms = np.zeros(len(KERNEL_CLASSES), np.float64)
+        nl = np.zeros(len(KERNEL_CLASSES), np.int64)
+        self._check(_load().dtws_get_profile(self._h, ms.ctypes.data, nl.ctypes.data), "dtws_get_profile")
+        return {k: (float(ms[i]), int(nl[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    # ------------------------------------------------------------------ stages
+    def znorm_stats(self, T, m: int):
+        """(mu, sigma) of every length-m window, FP64 tensors of n-m+1 elements."""
+        torch = _torch()
+        _dev_f32(T, "T")
+        N = T.numel() - m + 1
+        mu = torch.empty(max(N, 1), dtype=torch.float64, device=T.device)
+        sg = torch.empty_like(mu)
+        rc = _load().dtws_znorm_stats(self._h, T.data_ptr(), T.numel(), int(m), mu.data_ptr(), sg.data_ptr(),
+                                      _stream(T))
+        self._check(rc, "dtws_znorm_stats")
+        return mu[:N], sg[:N]
+
+    def lb_cascade(self, T, Q, r: int, values: bool = True, threshold: float = math.inf, survivors: bool = False):
+        """Bound values (kim, keogh_q, keogh_d) of every candidate and/or the survivors' starts."""
+        torch = _torch()
+        _dev_f32(T, "T")
+        _dev_f32(Q, "Q")
+        N = T.numel() - Q.numel() + 1
+        kim = kq = kd = None
+        ptrs = [None, None, None]
+        if values:
+            kim, kq, kd = (torch.empty(max(N, 1), dtype=torch.float32, device=T.device) for _ in range(3))
+            ptrs = [kim.data_ptr(), kq.data_ptr(), kd.data_ptr()]
+        surv = None
+        nsurv = ctypes.c_int64(0)
+        if survivors:
+            surv = torch.empty(max(N, 1), dtype=torch.int32, device=T.device)
+        rc = _load().dtws_lb_cascade(self._h, T.data_ptr(), T.numel(), Q.data_ptr(), Q.numel(), int(r),
+                                     float(threshold), *ptrs, surv.data_ptr() if survivors else None,
+                                     ctypes.byref(nsurv) if survivors else None, _stream(T))
+        self._check(rc, "dtws_lb_cascade")
+        res = {}
+        if values:
+            res.update(kim=kim[:N], keogh_q=kq[:N], keogh_d=kd[:N])
+        if survivors:
+            res["survivors"] = surv[:nsurv.value]
+        return res
+
+    def dtw_band(self, T, Q, r: int, starts, abandon_at: float = math.inf):
+        """FP32 banded DTW of the normalised query against the candidates at `starts` (int64 tensor)."""
+        torch = _torch()
+        _dev_f32(T, "T")
+        _dev_f32(Q, "Q")
+        if starts.dtype != torch.int64 or not starts.is_cuda or not starts.is_contiguous():
+            raise TypeError("starts must be a contiguous int64 CUDA tensor")
+        out = torch.empty(max(starts.numel(), 1), dtype=torch.float32, device=T.device)
+        rc = _load().dtws_dtw_band(self._h, T.data_ptr(), T.numel(), Q.data_ptr(), Q.numel(), int(r),
+                                   starts.data_ptr(), starts.numel(), float(abandon_at), out.data_ptr(),
+                                   _stream(T))
+        self._check(rc, "dtws_dtw_band")
+        return out[:starts.numel()]
+
+    def bsf_update(self, keys, d, idx):
+        """Atomically lower keys[0] to the minimum packed (distance, index) key."""
+        rc = _load().dtws_bsf_update(self._h, keys.data_ptr(), d.data_ptr(), idx.data_ptr(), d.numel(),
+                                     _stream(d))
+        self._check(rc, "dtws_bsf_update")
+        return keys
+
+
+def unpack_key(key: int):
+    """(distance, index) of a packed best-so-far key."""
+    d = np.array([key >> 32], dtype=np.uint32).view(np.float32)[0]
+    return float(d), int(key & 0xFFFFFFFF)

@@ -1,0 +1,497 @@
+// C ABI of the dtws library: context management, argument checking and the stream-ordered
+// search pipeline (query preparation -> window statistics -> data envelope -> best-so-far
+// initialisation from one seeded random candidate -> chunks of {bound cascade, DTW of the
+// survivors} with the best-so-far kept on the device -> FP64 certification).
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "dtws_internal.h"
+
+using namespace dtws;
+
+namespace {
+
+constexpr int kNumCounters = 16;
+
+void set_err(dtws_ctx *c, hipError_t e, const char *what) {
+    if (!c) return;
+    snprintf(c->lasterr, sizeof(c->lasterr), "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr)                         \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) {                   \
+            set_err((ctx), e_, #expr);            \
+            return DTWS_EHIP;                     \
+        }                                         \
+    } while (0)
+
+// Launch wrapper: in profiling mode, brackets the launch with an event pair of class `cls`.
+struct Prof {
+    dtws_ctx *c;
+    hipStream_t s;
+    int slot = -1;
+    Prof(dtws_ctx *c_, hipStream_t s_, int cls) : c(c_), s(s_) {
+        if (c->profiling && c->ev_used < dtws_ctx::kMaxEvents) {
+            slot = c->ev_used++;
+            c->ev_class[slot] = cls;
+            (void)hipEventRecord(c->ev[2 * slot], s);
+        }
+    }
+    ~Prof() {
+        if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], s);
+    }
+};
+#define PROF(cls) Prof prof_guard_##__LINE__(c, s, (cls))
+
+void prof_begin(dtws_ctx *c, uint32_t flags) {
+    c->profiling = (flags & DTWS_PROFILE) != 0;
+    c->ev_used = 0;
+    for (int k = 0; k < DTWS_K_COUNT; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+}
+
+// After the stream has been synchronised: sum the event pairs per class.
+void prof_end(dtws_ctx *c) {
+    if (!c->profiling) return;
+    for (int e = 0; e < c->ev_used; ++e) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev[2 * e], c->ev[2 * e + 1]) == hipSuccess) {
+            c->prof_ms[c->ev_class[e]] += ms;
+            c->prof_n[c->ev_class[e]] += 1;
+        }
+    }
+    c->profiling = false;
+}
+
+template <class T>
+hipError_t dalloc(T **p, size_t count) {
+    return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
+}
+
+uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+QueryBufs query_bufs(dtws_ctx *c, int slot) {
+    QueryBufs b;
+    b.qpad = c->qpad + (int64_t)slot * c->qstride;
+    b.qhat64 = c->qhat64 + (int64_t)slot * c->max_m;
+    b.qsorted = c->qsorted + (int64_t)slot * c->max_m;
+    b.Usorted = c->Usorted + (int64_t)slot * c->max_m;
+    b.Lsorted = c->Lsorted + (int64_t)slot * c->max_m;
+    b.order = c->order + (int64_t)slot * c->max_m;
+    return b;
+}
+
+int check_series(dtws_ctx *c, const float *T, int64_t n, int32_t m) {
+    if (!c || !T) return DTWS_EINVAL;
+    if (m < 2 || m > c->max_m || n < m || n > c->max_n) return DTWS_EINVAL;
+    return DTWS_OK;
+}
+
+// One query through the plain pipeline, results into the device result slot `slot`.
+// Window statistics for m and the data envelope for r must already be in the context.
+int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int r, uint32_t flags, uint64_t seed,
+              int slot, hipStream_t s) {
+    const int64_t N = n - m + 1;
+    const QueryBufs b = query_bufs(c, slot);
+    uint64_t *key = c->keys + slot;
+    { PROF(DTWS_K_PREP); HIPCHK(c, launch_query_prep(Q, m, r, b, s)); }
+    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u64(key, kEmptyKey, 1, s)); }
+    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u32(c->nb_count, 0, 1, s)); }
+
+    DtwArgs d{};
+    d.T = T;
+    d.m = m;
+    d.r = r;
+    d.w = 2 * r + 1;
+    d.qpad = b.qpad;
+    d.n = n;
+    d.single = -1;
+    d.mu = c->st_mu;
+    d.s = c->st_s;
+    d.o = c->st_o;
+    d.key = key;
+    d.nb_d = c->nb_d;
+    d.nb_idx = c->nb_idx;
+    d.nb_count = c->nb_count;
+    d.counters = c->counters;
+    d.abandon_at = INFINITY;
+
+    // best-so-far from one seeded random candidate (Algorithm 1, before the main loop)
+    {
+        DtwArgs d0 = d;
+        d0.single = (int64_t)(splitmix64(seed) % (uint64_t)N);
+        PROF(DTWS_K_DTW);
+        HIPCHK(c, launch_dtw(d0, true, 1, c->num_cu, c->gen_rows, c->gen_lanes, s));
+    }
+
+    LbArgs l{};
+    l.T = T;
+    l.m = m;
+    l.qh = b.qpad + kQPad;
+    l.qs = b.qsorted;
+    l.Us = b.Usorted;
+    l.Ls = b.Lsorted;
+    l.order = b.order;
+    l.mu = c->st_mu;
+    l.s = c->st_s;
+    l.o = c->st_o;
+    l.envU = c->envU;
+    l.envL = c->envL;
+    l.key = key;
+    l.surv = c->surv;
+    l.surv_count = c->surv_count;
+    l.counters = c->counters;
+
+    // chunks grow geometrically so that the best-so-far tightens before the bulk of the series
+    int64_t size = 1 << 16;
+    for (int64_t a0 = 0; a0 < N;) {
+        const int64_t a1 = (N - a0 < size) ? N : a0 + size;
+        if (flags & DTWS_NO_LOWER_BOUNDS) {
+            DtwArgs dr = d;
+            dr.range_first = a0;
+            dr.count = a1 - a0;
+            PROF(DTWS_K_DTW);
+            HIPCHK(c, launch_dtw(dr, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
+        } else {
+            { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u32(c->surv_count, 0, 1, s)); }
+            l.first = a0;
+            l.last = a1;
+            { PROF(DTWS_K_LB); HIPCHK(c, launch_lb(l, 1, c->num_cu, s)); }
+            DtwArgs ds = d;
+            ds.starts32 = c->surv;
+            ds.count_dev = c->surv_count;
+            ds.count = a1 - a0;
+            PROF(DTWS_K_DTW);
+            HIPCHK(c, launch_dtw(ds, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
+        }
+        a0 = a1;
+        size = size * 4 < c->surv_cap ? size * 4 : c->surv_cap;
+    }
+
+    CertArgs ce{};
+    ce.T = T;
+    ce.m = m;
+    ce.r = r;
+    ce.qhat64 = b.qhat64;
+    ce.key = key;
+    ce.nb_d = c->nb_d;
+    ce.nb_idx = c->nb_idx;
+    ce.nb_count = c->nb_count;
+    ce.scratch = c->cert_rows;
+    ce.res_idx = c->res_idx + slot;
+    ce.res_dist = c->res_dist + slot;
+    ce.res_status = c->res_status + slot;
+    ce.counters = c->counters;
+    { PROF(DTWS_K_CERT); HIPCHK(c, launch_certify(ce, s)); }
+    return DTWS_OK;
+}
+
+int fetch_counters(dtws_ctx *c, int64_t candidates, hipStream_t s) {
+    HIPCHK(c, hipMemcpyAsync(c->h_counters, c->counters, sizeof(unsigned long long) * kNumCounters,
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const unsigned long long *h = c->h_counters;
+    c->last.candidates = candidates;
+    c->last.pruned_kim = (int64_t)h[1];
+    c->last.pruned_keogh_q = (int64_t)h[2];
+    c->last.pruned_keogh_d = (int64_t)h[3];
+    c->last.dtw_started = (int64_t)h[4];
+    c->last.dtw_abandoned = (int64_t)h[5];
+    c->last.dtw_cells = (int64_t)h[6];
+    c->last.certified = (int64_t)h[7];
+    c->last.dtw_lane_cells = (int64_t)h[8];
+    return DTWS_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+DTWS_API const char *dtws_strerror(int code) {
+    switch (code) {
+        case DTWS_OK: return "ok";
+        case DTWS_EINVAL: return "invalid argument";
+        case DTWS_ENOMEM: return "out of device memory";
+        case DTWS_ENODEV: return "no HIP device";
+        case DTWS_EHIP: return "HIP runtime error";
+        case DTWS_EOVERFLOW: return "internal list overflow";
+        case DTWS_ENOMODEL: return "no learned model loaded";
+        default: return "unknown error";
+    }
+}
+
+DTWS_API const char *dtws_last_error(dtws_ctx *ctx) { return ctx ? ctx->lasterr : ""; }
+
+DTWS_API int dtws_device_count(void) {
+    int cnt = 0;
+    if (hipGetDeviceCount(&cnt) != hipSuccess) return 0;
+    return cnt < 0 ? 0 : cnt;
+}
+
+DTWS_API void dtws_destroy(dtws_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    void *dev[] = {c->qpad, c->qhat64, c->qsorted, c->Usorted, c->Lsorted, c->order, c->keys, c->st_mu,
+                   c->st_s, c->st_o, c->envU, c->envL, c->surv, c->surv_count, c->nb_d, c->nb_idx,
+                   c->nb_count, c->cert_rows, c->res_idx, c->res_dist, c->res_status, c->counters, c->gen_rows};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    if (c->ev) {
+        for (int e = 0; e < 2 * dtws_ctx::kMaxEvents; ++e)
+            if (c->ev[e]) (void)hipEventDestroy(c->ev[e]);
+        delete[] c->ev;
+    }
+    delete[] c->ev_class;
+    void *host[] = {c->h_idx, c->h_dist, c->h_status, c->h_counters};
+    for (void *p : host)
+        if (p) (void)hipHostFree(p);
+    delete c;
+}
+
+DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_queries, dtws_ctx **out) {
+    if (!out) return DTWS_EINVAL;
+    *out = nullptr;
+    if (max_n < 2 || max_n >= (int64_t(1) << 31) || max_m < 2 || max_m > kMaxM || max_queries < 1 ||
+        max_queries > 65536)
+        return DTWS_EINVAL;
+    int cnt = 0;
+    if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0 || device < 0 || device >= cnt) return DTWS_ENODEV;
+    if (hipSetDevice(device) != hipSuccess) return DTWS_ENODEV;
+    dtws_ctx *c = new (std::nothrow) dtws_ctx;
+    if (!c) return DTWS_ENOMEM;
+    c->device = device;
+    c->max_n = max_n;
+    c->max_m = max_m;
+    c->max_q = max_queries;
+    if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        c->num_cu <= 0)
+        c->num_cu = 256;
+    c->qstride = 2 * kQPad + max_m;
+    c->surv_cap = max_n < (int64_t(1) << 24) ? max_n : (int64_t(1) << 24);
+    c->gen_lanes = 8192;
+    const int64_t Q = max_queries;
+    bool ok = dalloc(&c->qpad, Q * c->qstride) == hipSuccess && dalloc(&c->qhat64, Q * max_m) == hipSuccess &&
+              dalloc(&c->qsorted, Q * max_m) == hipSuccess && dalloc(&c->Usorted, Q * max_m) == hipSuccess &&
+              dalloc(&c->Lsorted, Q * max_m) == hipSuccess && dalloc(&c->order, Q * max_m) == hipSuccess &&
+              dalloc(&c->keys, Q) == hipSuccess && dalloc(&c->st_mu, max_n) == hipSuccess &&
+              dalloc(&c->st_s, max_n) == hipSuccess && dalloc(&c->st_o, max_n) == hipSuccess &&
+              dalloc(&c->envU, max_n) == hipSuccess && dalloc(&c->envL, max_n) == hipSuccess &&
+              dalloc(&c->surv, c->surv_cap) == hipSuccess && dalloc(&c->surv_count, 1) == hipSuccess &&
+              dalloc(&c->nb_d, kNearBestCap) == hipSuccess && dalloc(&c->nb_idx, kNearBestCap) == hipSuccess &&
+              dalloc(&c->nb_count, 1) == hipSuccess &&
+              dalloc(&c->cert_rows, (size_t)256 * 3 * (max_m + 1)) == hipSuccess &&
+              dalloc(&c->res_idx, Q) == hipSuccess && dalloc(&c->res_dist, Q) == hipSuccess &&
+              dalloc(&c->res_status, Q) == hipSuccess && dalloc(&c->counters, kNumCounters) == hipSuccess &&
+              dalloc(&c->gen_rows, (size_t)c->gen_lanes * 2 * (max_m + 1)) == hipSuccess &&
+              hipHostMalloc((void **)&c->h_idx, sizeof(int64_t) * Q, 0) == hipSuccess &&
+              hipHostMalloc((void **)&c->h_dist, sizeof(double) * Q, 0) == hipSuccess &&
+              hipHostMalloc((void **)&c->h_status, sizeof(int32_t) * Q, 0) == hipSuccess &&
+              hipHostMalloc((void **)&c->h_counters, sizeof(unsigned long long) * kNumCounters, 0) == hipSuccess;
+    if (ok) {
+        c->ev = new (std::nothrow) hipEvent_t[2 * dtws_ctx::kMaxEvents]();
+        c->ev_class = new (std::nothrow) int[dtws_ctx::kMaxEvents]();
+        ok = c->ev && c->ev_class;
+        for (int e = 0; ok && e < 2 * dtws_ctx::kMaxEvents; ++e) ok = hipEventCreate(&c->ev[e]) == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        dtws_destroy(c);
+        return DTWS_ENOMEM;
+    }
+    *out = c;
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_get_profile(dtws_ctx *c, double *ms, int64_t *launches) {
+    if (!c || !ms || !launches) return DTWS_EINVAL;
+    for (int k = 0; k < DTWS_K_COUNT; ++k) {
+        ms[k] = c->prof_ms[k];
+        launches[k] = c->prof_n[k];
+    }
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_get_counters(dtws_ctx *c, dtws_counters *out) {
+    if (!c || !out) return DTWS_EINVAL;
+    *out = c->last;
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_search(dtws_ctx *c, const float *T, int64_t n, const float *Q, int32_t m, int32_t r,
+                         uint32_t flags, uint64_t seed, void *stream, dtws_match *out) {
+    if (check_series(c, T, n, m) != DTWS_OK || !Q || !out || r < 0) return DTWS_EINVAL;
+    if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE)) return DTWS_EINVAL;
+    if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED) return DTWS_ENOMODEL;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (r > m - 1) r = m - 1;
+    prof_begin(c, flags);
+    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u64((uint64_t *)c->counters, 0, kNumCounters, s)); }
+    { PROF(DTWS_K_STATS); HIPCHK(c, launch_znorm_stats(T, n, m, nullptr, nullptr, c->st_mu, c->st_s, c->st_o, s)); }
+    if (!(flags & DTWS_NO_LOWER_BOUNDS)) {
+        PROF(DTWS_K_ENV);
+        HIPCHK(c, launch_series_env(T, n, r, c->envU, c->envL, s));
+    }
+    int rc = run_query(c, T, n, Q, m, r, flags, seed, 0, s);
+    if (rc != DTWS_OK) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->h_idx, c->res_idx, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_dist, c->res_dist, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_status, c->res_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    rc = fetch_counters(c, n - m + 1, s);
+    if (rc != DTWS_OK) return rc;
+    prof_end(c);
+    out->index = c->h_idx[0];
+    out->distance = c->h_dist[0];
+    out->status = c->h_status[0];
+    out->reserved = 0;
+    return out->status == DTWS_OK ? DTWS_OK : out->status;
+}
+
+DTWS_API int dtws_search_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int64_t *qoff,
+                               const int32_t *mh, const int32_t *rh, int32_t nq, uint32_t flags, uint64_t seed,
+                               void *stream, dtws_match *out) {
+    if (!c || !T || !Qp || !qoff || !mh || !rh || !out || nq < 1 || nq > c->max_q) return DTWS_EINVAL;
+    if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE)) return DTWS_EINVAL;
+    for (int k = 0; k < nq; ++k)
+        if (check_series(c, T, n, mh[k]) != DTWS_OK || rh[k] < 0 || qoff[k] < 0) return DTWS_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    prof_begin(c, flags);
+    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u64((uint64_t *)c->counters, 0, kNumCounters, s)); }
+    int64_t cand = 0;
+    int last_m = -1, last_r = -1;
+    for (int k = 0; k < nq; ++k) {
+        const int m = mh[k];
+        const int r = rh[k] > m - 1 ? m - 1 : rh[k];
+        if (m != last_m) {
+            PROF(DTWS_K_STATS);
+            HIPCHK(c, launch_znorm_stats(T, n, m, nullptr, nullptr, c->st_mu, c->st_s, c->st_o, s));
+        }
+        if (!(flags & DTWS_NO_LOWER_BOUNDS) && r != last_r) {
+            PROF(DTWS_K_ENV);
+            HIPCHK(c, launch_series_env(T, n, r, c->envU, c->envL, s));
+        }
+        last_m = m;
+        last_r = r;
+        const int rc = run_query(c, T, n, Qp + qoff[k], m, r, flags, seed + (uint64_t)k, k, s);
+        if (rc != DTWS_OK) return rc;
+        cand += n - m + 1;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_idx, c->res_idx, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_dist, c->res_dist, sizeof(double) * nq, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_status, c->res_status, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, s));
+    const int rc = fetch_counters(c, cand, s);
+    if (rc != DTWS_OK) return rc;
+    prof_end(c);
+    int worst = DTWS_OK;
+    for (int k = 0; k < nq; ++k) {
+        out[k].index = c->h_idx[k];
+        out[k].distance = c->h_dist[k];
+        out[k].status = c->h_status[k];
+        out[k].reserved = 0;
+        if (out[k].status != DTWS_OK) worst = out[k].status;
+    }
+    return worst;
+}
+
+DTWS_API int dtws_znorm_stats(dtws_ctx *c, const float *T, int64_t n, int32_t m, double *mu, double *sigma,
+                              void *stream) {
+    if (check_series(c, T, n, m) != DTWS_OK || !mu || !sigma) return DTWS_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_znorm_stats(T, n, m, mu, sigma, nullptr, nullptr, nullptr, (hipStream_t)stream));
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_lb_cascade(dtws_ctx *c, const float *T, int64_t n, const float *Q, int32_t m, int32_t r,
+                             float threshold, float *kim, float *kq, float *kd, int32_t *surv, int64_t *n_surv,
+                             void *stream) {
+    if (check_series(c, T, n, m) != DTWS_OK || !Q || r < 0) return DTWS_EINVAL;
+    if (surv && !n_surv) return DTWS_EINVAL;
+    if (!kim && !kq && !kd && !surv) return DTWS_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (r > m - 1) r = m - 1;
+    const QueryBufs b = query_bufs(c, 0);
+    HIPCHK(c, launch_query_prep(Q, m, r, b, s));
+    HIPCHK(c, launch_znorm_stats(T, n, m, nullptr, nullptr, c->st_mu, c->st_s, c->st_o, s));
+    HIPCHK(c, launch_series_env(T, n, r, c->envU, c->envL, s));
+    LbArgs l{};
+    l.T = T;
+    l.first = 0;
+    l.last = n - m + 1;
+    l.m = m;
+    l.qh = b.qpad + kQPad;
+    l.qs = b.qsorted;
+    l.Us = b.Usorted;
+    l.Ls = b.Lsorted;
+    l.order = b.order;
+    l.mu = c->st_mu;
+    l.s = c->st_s;
+    l.o = c->st_o;
+    l.envU = c->envU;
+    l.envL = c->envL;
+    l.fixed_thr = threshold;
+    l.out_kim = kim;
+    l.out_kq = kq;
+    l.out_kd = kd;
+    if (kim || kq || kd) HIPCHK(c, launch_lb(l, 0, c->num_cu, s));
+    if (surv) {
+        HIPCHK(c, launch_fill_u32(c->surv_count, 0, 1, s));
+        l.surv = surv;
+        l.surv_count = c->surv_count;
+        HIPCHK(c, launch_lb(l, 1, c->num_cu, s));
+        uint32_t cnt = 0;
+        HIPCHK(c, hipMemcpyAsync(&cnt, c->surv_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        *n_surv = cnt;
+    }
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_dtw_band(dtws_ctx *c, const float *T, int64_t n, const float *Q, int32_t m, int32_t r,
+                           const int64_t *starts, int64_t count, float abandon_at, float *dist, void *stream) {
+    if (check_series(c, T, n, m) != DTWS_OK || !Q || r < 0 || !starts || !dist || count < 0) return DTWS_EINVAL;
+    if (count == 0) return DTWS_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (r > m - 1) r = m - 1;
+    const QueryBufs b = query_bufs(c, 0);
+    HIPCHK(c, launch_query_prep(Q, m, r, b, s));
+    DtwArgs d{};
+    d.T = T;
+    d.m = m;
+    d.r = r;
+    d.w = 2 * r + 1;
+    d.qpad = b.qpad;
+    d.starts64 = starts;
+    d.count = count;
+    d.n = n;
+    d.single = -1;
+    d.abandon_at = abandon_at;
+    d.dist_out = dist;
+    HIPCHK(c, launch_dtw(d, false, count, c->num_cu, c->gen_rows, c->gen_lanes, s));
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_bsf_update(dtws_ctx *c, uint64_t *keys, const float *d, const int64_t *idx, int64_t count,
+                             void *stream) {
+    if (!c || !keys || !d || !idx || count < 0) return DTWS_EINVAL;
+    if (count == 0) return DTWS_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_bsf_update(keys, d, idx, count, c->num_cu, (hipStream_t)stream));
+    return DTWS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,468 @@
+// Banded DTW (eq. (dtw) with the Sakoe-Chiba band of Section 2.1), the best-so-far update
+// (eq. (bsf)) and the FP64 certification of the near-best candidates.
+//
+// Register kernel (band width 2r+1 <= 16 * kMaxChunks): one lane per candidate.  The DP is swept
+// column by column over the candidate (DTW is symmetric in its operands, so sweeping the
+// candidate index as the outer loop computes the same d(m,m)).  For column j the lane keeps the
+// cells of rows i = j - R + k, k in [0, 16*NC), in a register array a[k], where R = 8*NC - 1 is a
+// compile-time centre (band r <= R); updating in place in ascending k uses a[k] = d(i-1, j-1),
+// a[k+1] = d(i, j-1) and the cell just written below, d(i-1, j):
+//     a[k] <- (q_{j-R+k} - c_j)^2 + min(a[k], a[k+1], a[k-1]_new).
+// Cells with |k - R| > r lie outside the band: the lanes that supply their query values read the
+// sentinel padding instead, so they cost +inf.  With the centre fixed at compile time the start
+// cell d(-1,-1) = 0 sits at a[R] before column 0 and the result d(m-1, m-1) at a[R] after the
+// last column.
+// The query window q_{j-R+k} is the same for every lane of the wave; it is loaded 16 values at
+// a time, one value per lane of each 16-lane row, and broadcast to the row with DPP
+// row_newbcast, so each cell costs one v_sub, one v_min3 and one v_fma.  Rows outside [0, m) and
+// cells above the band read the sentinel query value and cost +inf, which keeps the loop free
+// of branches.  A lane is abandoned when every cell of a column exceeds the threshold: every
+// warping path crosses every column and costs are non-negative.
+#include <utility>
+
+#include "dtws_internal.h"
+
+namespace dtws {
+
+
+
+namespace {
+
+template <int KK>
+__device__ __forceinline__ float row_bcast(float v) {
+    // DPP row_newbcast:KK -- every lane of a 16-lane row reads lane KK of that row; written as
+    // update_dpp(old=0, bound_ctrl) so that the compiler folds it into the consuming v_sub_f32_dpp
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + KK, 0xF, 0xF, true));
+}
+
+template <int I, int N, int NC>
+__device__ __forceinline__ void cell(float (&a)[N], const float (&q)[NC], float c, float &below) {
+    const float diff = row_bcast<(I & 15)>(q[I >> 4]) - c;
+    const float mn = fminf(fminf(a[I], a[I + 1]), below);
+    const float v = fmaf(diff, diff, mn);
+    a[I] = v;
+    below = v;
+}
+
+template <int NC, int... I>
+__device__ __forceinline__ void column_impl(float (&a)[16 * NC + 1], const float (&q)[NC], float c,
+                                            std::integer_sequence<int, I...>) {
+    float below = INFINITY;
+    (cell<I, 16 * NC + 1, NC>(a, q, c, below), ...);
+}
+
+template <int NC>
+__device__ __forceinline__ void column(float (&a)[16 * NC + 1], const float (&q)[NC], float c) {
+    column_impl<NC>(a, q, c, std::make_integer_sequence<int, 16 * NC>{});
+}
+
+__device__ inline unsigned long long wave_add(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Band cells of columns [0, J) of an m x m DP with band r.
+__device__ inline unsigned long long band_cells(int m, int r, int J) {
+    long long cells = (long long)J * (2 * r + 1);
+    const long long lower = J <= r ? (long long)J * r - (long long)J * (J - 1) / 2 : (long long)r * (r + 1) / 2;
+    const long long ex = (long long)J - (m - r);
+    const long long upper = ex > 0 ? ex * (ex + 1) / 2 : 0;
+    return (unsigned long long)(cells - lower - upper);
+}
+
+// Per-lane normalisation of the window at `start`: two-pass FP64 mean and sigma.
+__device__ inline void lane_stats(const float *w, int m, float &mu, float &s, float &o) {
+    double sum = 0.0;
+    for (int j = 0; j < m; ++j) sum += (double)w[j];
+    const double mu64 = sum / m;
+    double v = 0.0;
+    for (int j = 0; j < m; ++j) {
+        const double d = (double)w[j] - mu64;
+        v += d * d;
+    }
+    const double sigma = sqrt(v / m);
+    const double inv = sigma <= kSigmaFlat ? 0.0 : 1.0 / sigma;
+    mu = (float)mu64;
+    s = (float)inv;
+    o = (float)(-(mu64 - (double)mu) * inv);
+}
+
+__device__ inline float load_bsf(const uint64_t *key) {
+    return key_dist(__atomic_load_n(key, __ATOMIC_RELAXED));
+}
+
+}  // namespace
+
+template <int NC, bool SEARCH>
+__global__ __launch_bounds__(256) void k_dtw(DtwArgs a) {
+    constexpr int W = 16 * NC;
+    constexpr int R = 8 * NC - 1;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int64_t count = a.single >= 0 ? 1 : (a.count_dev ? (int64_t)*a.count_dev : a.count);
+    if (a.count_dev && count > a.count) count = a.count;
+    const int m = a.m, r = a.r;
+    const int ql = lane & 15;
+    // per-chunk offset into the padded query: in-band cells read q_{j-R+k}, the others read the
+    // sentinel at the start of the padding (offset + j stays below kQPad for every column)
+    int qoff[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+        const int kpos = 16 * cc + ql;
+        qoff[cc] = (kpos >= R - r && kpos <= R + r) ? kQPad - R + kpos : 0;
+    }
+    const float *qp = a.qpad;
+    unsigned long long n_started = 0, n_aband = 0, n_cells = 0, n_lane_cells = 0;
+
+    for (int64_t base = wave * 64; base < count; base += nwaves * 64) {
+        const int64_t k = base + lane;
+        const bool valid = k < count;
+        int64_t start = 0;
+        bool bad = false;
+        if (valid) {
+            start = a.single >= 0 ? a.single
+                    : a.starts32 ? (int64_t)a.starts32[k]
+                    : a.starts64 ? a.starts64[k] : a.range_first + k;
+            bad = start < 0 || start > a.n - m;
+            if (bad) start = 0;
+        }
+        float mu, s, o;
+        if (a.mu) {
+            mu = a.mu[start];
+            s = a.s[start];
+            o = a.o[start];
+        } else {
+            lane_stats(a.T + start, m, mu, s, o);
+        }
+        float arr[W + 1];
+#pragma unroll
+        for (int x = 0; x <= W; ++x) arr[x] = INFINITY;
+        arr[R] = 0.0f;   // d(-1,-1) of the virtual column before column 0
+        float thr = SEARCH ? threshold_of(load_bsf(a.key)) : a.abandon_at;
+        bool alive = valid && !bad;
+        int jdead = m;
+        const float *Tp = a.T + start;
+        float tcur = Tp[0];
+        float qcur[NC];
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) qcur[cc] = qp[qoff[cc]];
+        int j = 0;
+        for (; j < m; ++j) {
+            const int jn = j + 1 < m ? j + 1 : j;
+            const float tnext = Tp[jn];
+            float qnext[NC];
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) qnext[cc] = qp[qoff[cc] + jn];
+            const float c = fmaf(tcur - mu, s, o);
+            column<NC>(arr, qcur, c);
+            tcur = tnext;
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) qcur[cc] = qnext[cc];
+            if ((j & 15) == 15) {
+                float mn = arr[0];
+#pragma unroll
+                for (int x = 1; x < W; ++x) mn = fminf(mn, arr[x]);
+                if (SEARCH) thr = threshold_of(load_bsf(a.key));
+                if (alive && mn > thr) {
+                    alive = false;
+                    jdead = j + 1;
+                }
+                if (__ballot(alive) == 0) {
+                    ++j;
+                    break;
+                }
+            }
+        }
+        n_lane_cells += (unsigned long long)j * W;
+        const float D = arr[R];
+        if (SEARCH) {
+            if (valid && !bad) {
+                ++n_started;
+                if (!alive) ++n_aband;
+                n_cells += band_cells(m, r, alive ? m : jdead);
+            }
+            if (valid && !bad && alive && D <= thr) {
+                atomicMin((unsigned long long *)a.key, (unsigned long long)pack_key(D, (uint32_t)start));
+                const uint32_t pos = atomicAdd(a.nb_count, 1u);
+                if (pos < (uint32_t)kNearBestCap) {
+                    a.nb_d[pos] = D;
+                    a.nb_idx[pos] = (uint32_t)start;
+                }
+            }
+        } else if (valid) {
+            a.dist_out[k] = bad ? NAN : (alive ? D : INFINITY);
+        }
+    }
+    if (SEARCH && a.counters) {
+        n_started = wave_add(n_started);
+        n_aband = wave_add(n_aband);
+        n_cells = wave_add(n_cells);
+        n_lane_cells = wave_add(n_lane_cells);
+        if (lane == 0) {
+            atomicAdd(&a.counters[4], n_started);
+            atomicAdd(&a.counters[5], n_aband);
+            atomicAdd(&a.counters[6], n_cells);
+            atomicAdd(&a.counters[8], n_lane_cells);
+        }
+    }
+}
+
+// Wide-band fallback (2r+1 > 16 * kMaxChunks): one lane per candidate, rows of the DP in global
+// scratch (two rows of m+1 floats per lane), row-by-row sweep as in eq. (dtw).
+template <bool SEARCH>
+__global__ __launch_bounds__(64) void k_dtw_wide(DtwArgs a, float *rows, int64_t nlanes) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nlanes) return;
+    int64_t count = a.single >= 0 ? 1 : (a.count_dev ? (int64_t)*a.count_dev : a.count);
+    if (a.count_dev && count > a.count) count = a.count;
+    const int m = a.m, r = a.r;
+    const float *qh = a.qpad + kQPad;
+    float *prev = rows + g * 2 * (int64_t)(m + 1), *cur = prev + (m + 1);
+    unsigned long long n_started = 0, n_aband = 0, n_cells = 0;
+    for (int64_t k = g; k < count; k += nlanes) {
+        int64_t start = a.single >= 0 ? a.single
+                        : a.starts32 ? (int64_t)a.starts32[k]
+                        : a.starts64 ? a.starts64[k] : a.range_first + k;
+        if (start < 0 || start > a.n - m) {
+            if (!SEARCH) a.dist_out[k] = NAN;
+            continue;
+        }
+        float mu, s, o;
+        if (a.mu) {
+            mu = a.mu[start];
+            s = a.s[start];
+            o = a.o[start];
+        } else {
+            lane_stats(a.T + start, m, mu, s, o);
+        }
+        const float *Tp = a.T + start;
+        float thr = SEARCH ? threshold_of(load_bsf(a.key)) : a.abandon_at;
+        for (int x = 0; x <= m; ++x) {
+            prev[x] = INFINITY;
+            cur[x] = INFINITY;
+        }
+        prev[0] = 0.0f;
+        bool alive = true;
+        int idead = m;
+        for (int i = 1; i <= m; ++i) {
+            const int jlo = i - r < 1 ? 1 : i - r, jhi = i + r > m ? m : i + r;
+            cur[jlo - 1] = INFINITY;
+            if (jhi + 1 <= m) cur[jhi + 1] = INFINITY;
+            const float qi = qh[i - 1];
+            float rowmin = INFINITY;
+            for (int jj = jlo; jj <= jhi; ++jj) {
+                const float c = fmaf(Tp[jj - 1] - mu, s, o);
+                const float diff = qi - c;
+                const float v = fmaf(diff, diff, fminf(fminf(prev[jj], cur[jj - 1]), prev[jj - 1]));
+                cur[jj] = v;
+                rowmin = fminf(rowmin, v);
+            }
+            float *t = prev;
+            prev = cur;
+            cur = t;
+            if ((i & 15) == 0 && SEARCH) thr = threshold_of(load_bsf(a.key));
+            if (rowmin > thr) {
+                alive = false;
+                idead = i;
+                break;
+            }
+        }
+        const float D = alive ? prev[m] : INFINITY;   // after the last swap, prev holds row m
+        // restore the row roles for the next candidate
+        prev = rows + g * 2 * (int64_t)(m + 1);
+        cur = prev + (m + 1);
+        if (SEARCH) {
+            ++n_started;
+            if (!alive) ++n_aband;
+            n_cells += band_cells(m, r, alive ? m : idead);
+            if (alive && D <= thr) {
+                atomicMin((unsigned long long *)a.key, (unsigned long long)pack_key(D, (uint32_t)start));
+                const uint32_t pos = atomicAdd(a.nb_count, 1u);
+                if (pos < (uint32_t)kNearBestCap) {
+                    a.nb_d[pos] = D;
+                    a.nb_idx[pos] = (uint32_t)start;
+                }
+            }
+        } else {
+            a.dist_out[k] = D;
+        }
+    }
+    if (SEARCH && a.counters) {
+        atomicAdd(&a.counters[4], n_started);
+        atomicAdd(&a.counters[5], n_aband);
+        atomicAdd(&a.counters[6], n_cells);
+        atomicAdd(&a.counters[8], n_cells);
+    }
+}
+
+// ------------------------------------------------------------------ small fills
+// Plain fill kernels instead of hipMemsetAsync, so the same calls can later be captured in a graph.
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ best-so-far update
+__global__ __launch_bounds__(256) void k_bsf_update(uint64_t *keys, const float *d, const int64_t *idx,
+                                                    int64_t count) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < count; base += stride) {
+        const int64_t k = base + threadIdx.x;
+        unsigned long long key = ~0ull;
+        if (k < count) key = pack_key(d[k], (uint32_t)idx[k]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(key, off, 64);
+            key = o < key ? o : key;
+        }
+        if ((threadIdx.x & 63) == 0) atomicMin((unsigned long long *)keys, key);
+    }
+}
+
+// ------------------------------------------------------------------ FP64 certification
+
+
+__global__ __launch_bounds__(256) void k_certify(CertArgs c) {
+    __shared__ double sd[256];
+    __shared__ uint32_t si[256];
+    __shared__ unsigned int s_cert;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_cert = 0;
+    __syncthreads();
+    const float thr = threshold_of(key_dist(*c.key));
+    const uint32_t total = *c.nb_count;
+    const uint32_t cnt = total < (uint32_t)kNearBestCap ? total : (uint32_t)kNearBestCap;
+    const int m = c.m, r = c.r;
+    double *ch = c.scratch + (int64_t)tid * 3 * (m + 1);
+    double *prev = ch + m, *cur = prev + (m + 1);
+    double best = INFINITY;
+    uint32_t bidx = 0xffffffffu;
+    for (uint32_t e = tid; e < cnt; e += blockDim.x) {
+        if (!(c.nb_d[e] <= thr)) continue;
+        atomicAdd(&s_cert, 1u);
+        const uint32_t idx = c.nb_idx[e];
+        const float *wv = c.T + idx;
+        double sum = 0.0;
+        for (int j = 0; j < m; ++j) sum += (double)wv[j];
+        const double mu = sum / m;
+        double v = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double d = (double)wv[j] - mu;
+            v += d * d;
+        }
+        const double sigma = sqrt(v / m);
+        const bool flat = sigma <= kSigmaFlat;
+        for (int j = 0; j < m; ++j) ch[j] = flat ? 0.0 : ((double)wv[j] - mu) / sigma;
+        for (int x = 0; x <= m; ++x) {
+            prev[x] = INFINITY;
+            cur[x] = INFINITY;
+        }
+        prev[0] = 0.0;
+        double *P = prev, *C = cur;
+        for (int i = 1; i <= m; ++i) {
+            const int jlo = i - r < 1 ? 1 : i - r, jhi = i + r > m ? m : i + r;
+            C[jlo - 1] = INFINITY;
+            if (jhi + 1 <= m) C[jhi + 1] = INFINITY;
+            const double qi = c.qhat64[i - 1];
+            for (int jj = jlo; jj <= jhi; ++jj) {
+                const double diff = qi - ch[jj - 1];
+                const double a1 = P[jj], a2 = C[jj - 1], a3 = P[jj - 1];
+                double mn = a1 < a2 ? a1 : a2;
+                mn = mn < a3 ? mn : a3;
+                C[jj] = __dadd_rn(__dmul_rn(diff, diff), mn);
+            }
+            double *t = P;
+            P = C;
+            C = t;
+        }
+        const double d = P[m];
+        if (d < best || (d == best && idx < bidx)) {
+            best = d;
+            bidx = idx;
+        }
+    }
+    sd[tid] = best;
+    si[tid] = bidx;
+    __syncthreads();
+    if (tid == 0) {
+        double bd = INFINITY;
+        uint32_t bi = 0xffffffffu;
+        for (int t = 0; t < (int)blockDim.x; ++t) {
+            if (sd[t] < bd || (sd[t] == bd && si[t] < bi)) {
+                bd = sd[t];
+                bi = si[t];
+            }
+        }
+        *c.res_idx = bi == 0xffffffffu ? -1 : (int64_t)bi;
+        *c.res_dist = bd;
+        *c.res_status = total > (uint32_t)kNearBestCap ? DTWS_EOVERFLOW : (bi == 0xffffffffu ? DTWS_EHIP : DTWS_OK);
+        if (c.counters) atomicAdd(&c.counters[7], (unsigned long long)s_cert);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+template <bool SEARCH>
+static hipError_t launch_dtw_t(const DtwArgs &a, int64_t max_count, int num_cu, float *wide_rows,
+                               int64_t wide_lanes, hipStream_t s) {
+    if (max_count <= 0) return hipSuccess;
+    const int nc = (a.r + 1 + 7) / 8;   // smallest NC with 8*NC - 1 >= r
+    if (nc > kMaxChunks) {
+        int64_t lanes = wide_lanes;
+        if (lanes > max_count) lanes = max_count;
+        const int64_t blocks = (lanes + 63) / 64;
+        hipLaunchKernelGGL(k_dtw_wide<SEARCH>, dim3((unsigned)blocks), dim3(64), 0, s, a, wide_rows, lanes);
+        return hipGetLastError();
+    }
+    int64_t blocks = (max_count + 255) / 256;
+    const int64_t cap = (int64_t)num_cu * 4;
+    if (blocks > cap) blocks = cap;
+    const dim3 g((unsigned)blocks), b(256);
+    switch (nc) {
+#define DTWS_CASE(N) \
+    case N: hipLaunchKernelGGL((k_dtw<N, SEARCH>), g, b, 0, s, a); break;
+        DTWS_CASE(1) DTWS_CASE(2) DTWS_CASE(3) DTWS_CASE(4) DTWS_CASE(5) DTWS_CASE(6) DTWS_CASE(7)
+        DTWS_CASE(8) DTWS_CASE(9) DTWS_CASE(10) DTWS_CASE(11) DTWS_CASE(12) DTWS_CASE(13) DTWS_CASE(14)
+#undef DTWS_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dtw(const DtwArgs &a, bool search, int64_t max_count, int num_cu, float *wide_rows,
+                      int64_t wide_lanes, hipStream_t s) {
+    return search ? launch_dtw_t<true>(a, max_count, num_cu, wide_rows, wide_lanes, s)
+                  : launch_dtw_t<false>(a, max_count, num_cu, wide_rows, wide_lanes, s);
+}
+
+hipError_t launch_bsf_update(uint64_t *keys, const float *d, const int64_t *idx, int64_t count, int num_cu,
+                             hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > num_cu * 8) blocks = num_cu * 8;
+    hipLaunchKernelGGL(k_bsf_update, dim3((unsigned)blocks), dim3(256), 0, s, keys, d, idx, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_certify(const CertArgs &c, hipStream_t s) {
+    hipLaunchKernelGGL(k_certify, dim3(1), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+}  // namespace dtws

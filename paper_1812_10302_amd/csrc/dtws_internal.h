@@ -1,0 +1,161 @@
+// Internal declarations of the dtws library (not installed; include/dtws.h is the interface).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dtws.h"
+
+namespace dtws {
+
+// Row sentinel: a normalised query value this far out makes (q - c)^2 overflow to +inf in FP32,
+// so band cells whose row lies outside [0, m) (or above the band) cost +inf without branches.
+constexpr float kSentinel = 1e20f;
+// Padding of the sentinel-padded query on each side (elements); >= the largest band.
+constexpr int kQPad = 4096 + 64;
+constexpr int kMaxM = 2048;
+// Pruning slack: a bound or partial DTW computed in FP32 is compared with
+// bsf * (1 + kEpsRel) + kEpsAbs so that FP32 rounding can never discard the FP64 best.
+constexpr float kEpsRel = 1.0f / 1024.0f;
+constexpr float kEpsAbs = 1e-6f;
+constexpr double kSigmaFlat = 1e-8;
+// Largest band (2r+1) handled by the register-resident DTW kernel (16-cell chunks).
+constexpr int kMaxChunks = 14;
+constexpr int kNearBestCap = 1 << 16;
+
+__host__ __device__ inline float threshold_of(float bsf) {
+    return bsf * (1.0f + kEpsRel) + kEpsAbs;   // +inf stays +inf
+}
+
+__device__ inline uint64_t pack_key(float d, uint32_t idx) {
+    return (uint64_t(__float_as_uint(d)) << 32) | uint64_t(idx);
+}
+__device__ inline float key_dist(uint64_t k) { return __uint_as_float(uint32_t(k >> 32)); }
+
+// Per-query device buffers, all inside the context's arrays.
+struct QueryBufs {
+    float *qpad;      // [2*kQPad + m] sentinel-padded normalised query (FP32)
+    double *qhat64;   // [m] normalised query (FP64)
+    float *qsorted;   // [m] normalised query in the LB visiting order
+    float *Usorted;   // [m] query envelope (upper) in the LB visiting order
+    float *Lsorted;   // [m] query envelope (lower) in the LB visiting order
+    int32_t *order;   // [m] LB visiting order: positions by decreasing |qhat|
+};
+
+
+// ---------------------------------------------------------------- kernel arguments
+struct LbArgs {
+    const float *T;
+    int64_t first, last;   // candidate range [first, last)
+    int m;
+    const float *qh;       // normalised query, natural order (qpad + kQPad)
+    const float *qs, *Us, *Ls;
+    const int32_t *order;
+    const float *mu, *s, *o;
+    const float *envU, *envL;
+    const uint64_t *key;   // best-so-far key (threshold source) or null
+    float fixed_thr;       // threshold when key is null
+    float *out_kim, *out_kq, *out_kd;
+    int32_t *surv;
+    uint32_t *surv_count;
+    unsigned long long *counters;
+};
+
+struct DtwArgs {
+    const float *T;
+    int m, r, w;                 // r clamped to m-1, w = 2r+1
+    const float *qpad;           // sentinel-padded normalised query
+    const int32_t *starts32;     // candidate starts (search mode) ...
+    const int64_t *starts64;     // ... or explicit starts (stage entry point), else range_first + k
+    int64_t range_first;
+    int64_t n;                   // series length: explicit starts outside [0, n-m] are rejected (NaN out)
+    const uint32_t *count_dev;   // device-side count of starts32 (search mode) or null
+    int64_t count;               // host count, or capacity bound when count_dev is set
+    int64_t single;              // >= 0: evaluate only this start
+    const float *mu, *s, *o;     // per-window normalisation, or null to compute per lane
+    float abandon_at;            // threshold of the stage entry point
+    float *dist_out;             // stage entry point output
+    uint64_t *key;               // search mode: best-so-far key
+    float *nb_d;
+    uint32_t *nb_idx, *nb_count;
+    unsigned long long *counters;
+};
+
+struct CertArgs {
+    const float *T;
+    int m, r;
+    const double *qhat64;
+    const uint64_t *key;
+    const float *nb_d;
+    const uint32_t *nb_idx, *nb_count;
+    double *scratch;    // [256 * 3 * (m + 1)]
+    int64_t *res_idx;
+    double *res_dist;
+    int32_t *res_status;
+    unsigned long long *counters;
+};
+
+// ---------------------------------------------------------------- launchers (stream-ordered)
+hipError_t launch_query_prep(const float *Q, int m, int r, const QueryBufs &b, hipStream_t s);
+hipError_t launch_znorm_stats(const float *T, int64_t n, int m, double *mu, double *sg, float *mu32, float *s32,
+                              float *o32, hipStream_t s);
+hipError_t launch_series_env(const float *T, int64_t n, int r, float *U, float *L, hipStream_t s);
+hipError_t launch_lb(const LbArgs &a, int mode, int num_cu, hipStream_t s);
+hipError_t launch_dtw(const DtwArgs &a, bool search, int64_t max_count, int num_cu, float *wide_rows,
+                      int64_t wide_lanes, hipStream_t s);
+hipError_t launch_bsf_update(uint64_t *keys, const float *d, const int64_t *idx, int64_t count, int num_cu,
+                             hipStream_t s);
+hipError_t launch_certify(const CertArgs &c, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
+// key of an empty best-so-far: distance +inf, index 0xFFFFFFFF
+constexpr uint64_t kEmptyKey = (uint64_t(0x7F800000u) << 32) | 0xFFFFFFFFull;
+
+}  // namespace dtws
+
+// Opaque context (declared in dtws.h).
+struct dtws_ctx {
+    int device = 0;
+    int num_cu = 0;
+    int64_t max_n = 0;
+    int32_t max_m = 0, max_q = 0;
+    // per-query buffers, stride qstride floats / max_m elements
+    int64_t qstride = 0;
+    float *qpad = nullptr;
+    double *qhat64 = nullptr;
+    float *qsorted = nullptr, *Usorted = nullptr, *Lsorted = nullptr;
+    int32_t *order = nullptr;
+    uint64_t *keys = nullptr;             // best-so-far key per query
+    // series-sized scratch
+    float *st_mu = nullptr, *st_s = nullptr, *st_o = nullptr;   // per-candidate normalisation
+    float *envU = nullptr, *envL = nullptr;                     // raw series envelope
+    int32_t *surv = nullptr;              // survivor starts
+    int64_t surv_cap = 0;
+    uint32_t *surv_count = nullptr;
+    // near-best list
+    float *nb_d = nullptr;
+    uint32_t *nb_idx = nullptr;
+    uint32_t *nb_count = nullptr;
+    // certification scratch and results
+    double *cert_rows = nullptr;          // [256 * 2 * (max_m + 1)]
+    int64_t *res_idx = nullptr;           // device [max_q]
+    double *res_dist = nullptr;           // device [max_q]
+    int32_t *res_status = nullptr;        // device [max_q]
+    unsigned long long *counters = nullptr;  // device [8]
+    float *gen_rows = nullptr;            // scratch for the wide-band DTW kernel
+    int64_t gen_lanes = 0;
+    // pinned host staging
+    int64_t *h_idx = nullptr;
+    double *h_dist = nullptr;
+    int32_t *h_status = nullptr;
+    unsigned long long *h_counters = nullptr;
+    dtws_counters last{};
+    // profiling (DTWS_PROFILE): event pairs around launches, class per pair
+    static constexpr int kMaxEvents = 8192;
+    hipEvent_t *ev = nullptr;             // 2 * kMaxEvents events
+    int *ev_class = nullptr;
+    int ev_used = 0;
+    bool profiling = false;
+    double prof_ms[DTWS_K_COUNT] = {0};
+    int64_t prof_n[DTWS_K_COUNT] = {0};
+    char lasterr[256] = {0};
+};

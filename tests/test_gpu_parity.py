@@ -1,0 +1,221 @@
+"""Parity of the HIP path (called through the C ABI) with the CPU oracle, element by element.
+
+Tolerances: FP32 device arithmetic against the FP64 oracle.
+  * window statistics: FP64 on both sides (anchored prefix sums vs two-pass): mu to 1e-12
+    relative to the window's magnitude, sigma to 1e-9 relative.
+  * bounds and FP32 DTW values: |gpu - ref| <= 1e-4 * ref + 1e-5 (FP32 accumulation over at
+    most 2m terms of O(1) size; the distance tolerance stated for the method is 1e-4).
+  * search results: identical index; distance certified in FP64, so within 1e-9 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1812_10302_amd as dtws
+from paper_1812_10302_amd import workloads as W
+from oracle import reference as R
+from oracle import Cascade
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def close_rel(gpu, ref, rtol=1e-4, atol=1e-5):
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    bad = np.abs(gpu - ref) > rtol * np.abs(ref) + atol
+    assert not bad.any(), f"{bad.sum()} mismatches, first at {np.argmax(bad)}: {gpu[bad][:5]} vs {ref[bad][:5]}"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dtws.Context(0, max_n=3_000_000, max_m=2048, max_queries=16)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def casc():
+    return Cascade()
+
+
+@pytest.fixture(scope="module")
+def small_wl():
+    wl = W.single_query_small()
+    D = R.all_distances(wl.T, wl.queries[0], wl.bands[0], chunk=16384)
+    return wl, D
+
+
+# --------------------------------------------------------------------- statistics
+def oracle_stats(T, m, chunk=100_000):
+    N = T.size - m + 1
+    mu = np.empty(N)
+    sg = np.empty(N)
+    for a in range(0, N, chunk):
+        b = min(N, a + chunk)
+        mu[a:b], sg[a:b] = R.window_stats(T[a:b + m - 1], m)
+    return mu, sg
+
+
+@pytest.mark.parametrize("n,m,offset", [(300_000, 128, 0.0), (123_457, 2, 0.0), (50_001, 1500, 0.0),
+                                        (1_000_003, 1024, 2.0e4), (2100, 2048, -7.5)])
+def test_znorm_stats(ctx, n, m, offset):
+    T = (W.random_walk(n, 5) + np.float32(offset)).astype(np.float32)
+    mu, sg = ctx.znorm_stats(dev(T), m)
+    mu_r, sg_r = oracle_stats(T, m)
+    scale = np.maximum(1.0, np.abs(mu_r))
+    assert np.max(np.abs(mu.cpu().numpy() - mu_r) / scale) < 1e-12
+    assert np.all(np.abs(sg.cpu().numpy() - sg_r) <= 1e-9 * sg_r + 1e-12)
+
+
+def test_znorm_stats_flat_windows(ctx):
+    T = W.random_walk(10_000, 6)
+    T[3000:3400] = np.float32(17.25)          # constant stretch: windows inside are flat
+    T[6000:6100] = np.float32(0.0)
+    mu, sg = ctx.znorm_stats(dev(T), 64)
+    mu_r, sg_r = oracle_stats(T, 64)
+    sg = sg.cpu().numpy()
+    flat = sg_r <= R.SIGMA_FLAT
+    assert flat.sum() == (400 - 63) + (100 - 63)
+    assert np.all(sg[flat] <= R.SIGMA_FLAT)
+    assert np.all(np.abs(sg[~flat] - sg_r[~flat]) <= 1e-9 * sg_r[~flat])
+
+
+# --------------------------------------------------------------------- bounds
+@pytest.mark.parametrize("m,r", [(128, 6), (128, 0), (77, 40), (16, 15)])
+def test_lb_values(ctx, m, r):
+    T = W.random_walk(20_011, 9)
+    Q = W.noisy_cut(T, 5_000, m, 0.1, 10)
+    out = ctx.lb_cascade(dev(T), dev(Q), r)
+    kim, kq, kd = (out[k].cpu().numpy() for k in ("kim", "keogh_q", "keogh_d"))
+    N = T.size - m + 1
+    qh = R.znorm(Q)
+    C = R.normalized_windows(T, m, np.arange(N))
+    kim_r = (qh[0] - C[:, 0]) ** 2 + (qh[-1] - C[:, -1]) ** 2
+    close_rel(kim, kim_r)
+    rng = np.random.default_rng(m + r)
+    sample = np.unique(np.concatenate([rng.integers(0, N, 250), [0, 1, N - 2, N - 1], np.arange(4990, 5010)]))
+    kq_r = [R.lb_keogh_q(qh, C[i], r) for i in sample]
+    kd_r = [R.lb_keogh_d_series(T, int(i), m, r, qh) for i in sample]
+    close_rel(kq[sample], kq_r, rtol=2e-4, atol=2e-4)
+    close_rel(kd[sample], kd_r, rtol=2e-4, atol=2e-4)
+
+
+def test_lb_survivors(ctx):
+    T = W.random_walk(50_000, 11)
+    Q = W.noisy_cut(T, 20_000, 128, 0.1, 12)
+    vals = ctx.lb_cascade(dev(T), dev(Q), 6)
+    mx = np.maximum(np.maximum(vals["kim"].cpu().numpy(), vals["keogh_q"].cpu().numpy()),
+                    vals["keogh_d"].cpu().numpy())
+    thr = float(np.quantile(mx, 0.01))
+    out = ctx.lb_cascade(dev(T), dev(Q), 6, values=False, threshold=thr, survivors=True)
+    got = np.sort(out["survivors"].cpu().numpy())
+    want = np.nonzero(mx <= np.float32(thr))[0]
+    np.testing.assert_array_equal(got, want)
+    assert 20_000 in set(got.tolist()) or mx[20_000] > thr
+
+
+# --------------------------------------------------------------------- DTW
+def test_dtw_band_all_candidates_small_workload(ctx, small_wl):
+    wl, D = small_wl
+    N = D.size
+    got = ctx.dtw_band(dev(wl.T), dev(wl.queries[0]), wl.bands[0],
+                       torch.arange(N, dtype=torch.int64, device=DEV)).cpu().numpy()
+    close_rel(got, D)
+
+
+@pytest.mark.parametrize("n,m,r", [(400, 2, 0), (400, 2, 1), (900, 3, 1), (2500, 17, 4), (2000, 100, 0),
+                                   (1500, 100, 99), (1200, 128, 111), (1200, 128, 112), (1100, 300, 150),
+                                   (700, 64, 63), (333, 333, 20)])
+def test_dtw_band_shapes(ctx, n, m, r):
+    T, Q = W.tiny_random(n, m, n + m + r)
+    N = n - m + 1
+    starts = np.arange(N, dtype=np.int64)
+    got = ctx.dtw_band(dev(T), dev(Q), r, dev(starts)).cpu().numpy()
+    ref = R.distances_at(T, Q, r, starts)
+    close_rel(got, ref)
+
+
+def test_dtw_band_abandon_and_invalid_starts(ctx, small_wl):
+    wl, D = small_wl
+    thr = float(np.quantile(D, 0.05))
+    rng = np.random.default_rng(3)
+    starts = rng.integers(0, D.size, 5000)
+    got = ctx.dtw_band(dev(wl.T), dev(wl.queries[0]), wl.bands[0], dev(starts), abandon_at=thr).cpu().numpy()
+    fin = np.isfinite(got)
+    close_rel(got[fin], D[starts[fin]])
+    assert np.all(D[starts[~fin]] > thr * (1 - 1e-5))
+    bad = np.array([-1, D.size, 10 ** 9, 0], dtype=np.int64)
+    g = ctx.dtw_band(dev(wl.T), dev(wl.queries[0]), wl.bands[0], dev(bad)).cpu().numpy()
+    assert np.isnan(g[:3]).all() and np.isfinite(g[3])
+
+
+# --------------------------------------------------------------------- best-so-far
+def test_bsf_update_contention(ctx):
+    rng = np.random.default_rng(4)
+    n = 1 << 20
+    d = rng.choice(np.array([3.5, 1.25, 1.25, 7.0, 2.0], np.float32), n)
+    idx = rng.permutation(n).astype(np.int64) + 17
+    keys = torch.full((1,), -1, dtype=torch.int64, device=DEV)     # all ones = +inf key
+    ctx.bsf_update(keys, dev(d), dev(idx))
+    k = int(keys.cpu().numpy().view(np.uint64)[0])
+    dist, i = dtws.unpack_key(k)
+    assert dist == 1.25 and i == int(idx[d == np.float32(1.25)].min())
+
+
+# --------------------------------------------------------------------- search
+def test_search_single_query_workload(ctx, small_wl):
+    wl, D = small_wl
+    i_ref = int(np.argmin(D))
+    for seed in (0, 1, 2):
+        idx, dist = ctx.search(dev(wl.T), dev(wl.queries[0]), wl.bands[0], seed=seed)
+        assert idx == i_ref
+        assert abs(dist - D[i_ref]) <= 1e-9 * D[i_ref]
+    c = ctx.counters()
+    assert c["candidates"] == D.size and c["certified"] >= 1
+    idx, dist = ctx.search(dev(wl.T), dev(wl.queries[0]), wl.bands[0], flags=dtws.NO_LOWER_BOUNDS)
+    assert idx == i_ref and abs(dist - D[i_ref]) <= 1e-9 * D[i_ref]
+
+
+@pytest.mark.parametrize("n,m,r,seed", [(64, 64, 3, 1), (65, 64, 63, 2), (500, 16, 0, 3), (3000, 40, 4, 4),
+                                        (3000, 200, 30, 5), (2000, 128, 127, 6), (5000, 2, 1, 7),
+                                        (4000, 500, 120, 8)])
+def test_search_small_shapes(ctx, n, m, r, seed):
+    T, Q = W.tiny_random(n, m, seed)
+    i_ref, d_ref = R.best_match(T, Q, r)
+    idx, dist = ctx.search(dev(T), dev(Q), r, seed=seed)
+    assert idx == i_ref, (idx, i_ref, dist, d_ref)
+    assert abs(dist - d_ref) <= 1e-9 * d_ref + 1e-12
+
+
+def test_search_exact_copies_lowest_index(ctx):
+    T, _ = W.tiny_random(5000, 8, 21)
+    T = T.copy()
+    T[4000:4050] = T[1000:1050]       # bit-identical second copy at a higher index
+    T[2500:2550] = T[1000:1050]
+    Q = (T[1000:1050].astype(np.float64) * 0.25 - 1.0).astype(np.float32)
+    idx, dist = ctx.search(dev(T), dev(Q), 5)
+    i_ref, d_ref = R.best_match(T, Q, 5)
+    assert idx == i_ref == 1000
+    assert dist < 1e-9
+
+
+def test_search_batch_equals_single(ctx):
+    T = W.random_walk(200_000, 13)
+    qs, rs = [], []
+    for k, (m, fr) in enumerate([(64, 0.05), (300, 0.1), (128, 0.0), (1000, 0.02), (64, 0.5)]):
+        qs.append(W.noisy_cut(T, 1000 + 37_000 * k, m, 0.1, 40 + k))
+        rs.append(dtws.band(m, fr))
+    Td = dev(T)
+    batch = ctx.search_batch(Td, [dev(q) for q in qs], rs)
+    for q, r, got in zip(qs, rs, batch):
+        single = ctx.search(Td, dev(q), r)
+        assert got[0] == single[0] and got[1] == pytest.approx(single[1], rel=1e-12)
