@@ -85,10 +85,10 @@ QueryBufs query_bufs(dtws_ctx *c, int slot) {
     QueryBufs b;
     b.qpad = c->qpad + (int64_t)slot * c->qstride;
     b.qhat64 = c->qhat64 + (int64_t)slot * c->max_m;
-    b.qsorted = c->qsorted + (int64_t)slot * c->max_m;
-    b.Usorted = c->Usorted + (int64_t)slot * c->max_m;
-    b.Lsorted = c->Lsorted + (int64_t)slot * c->max_m;
-    b.order = c->order + (int64_t)slot * c->max_m;
+    b.qsorted = c->qsorted + (int64_t)slot * c->mstride;
+    b.Usorted = c->Usorted + (int64_t)slot * c->mstride;
+    b.Lsorted = c->Lsorted + (int64_t)slot * c->mstride;
+    b.order = c->order + (int64_t)slot * c->mstride;
     return b;
 }
 
@@ -176,7 +176,7 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
             HIPCHK(c, launch_dtw(ds, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
         }
         a0 = a1;
-        size = size * 4 < c->surv_cap ? size * 4 : c->surv_cap;
+        size *= 16;   // 64K, 1M, then the rest: few launches once the best-so-far is tight
     }
 
     CertArgs ce{};
@@ -189,6 +189,9 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
     ce.nb_idx = c->nb_idx;
     ce.nb_count = c->nb_count;
     ce.scratch = c->cert_rows;
+    ce.cert_idx = c->cert_idx;
+    ce.cert_count = c->cert_count;
+    ce.cert_d = c->cert_d;
     ce.res_idx = c->res_idx + slot;
     ce.res_dist = c->res_dist + slot;
     ce.res_status = c->res_status + slot;
@@ -245,7 +248,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
     (void)hipSetDevice(c->device);
     void *dev[] = {c->qpad, c->qhat64, c->qsorted, c->Usorted, c->Lsorted, c->order, c->keys, c->st_mu,
                    c->st_s, c->st_o, c->envU, c->envL, c->surv, c->surv_count, c->nb_d, c->nb_idx,
-                   c->nb_count, c->cert_rows, c->res_idx, c->res_dist, c->res_status, c->counters, c->gen_rows};
+                   c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_idx, c->res_dist, c->res_status, c->counters, c->gen_rows};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->ev) {
@@ -279,12 +282,13 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
         c->num_cu <= 0)
         c->num_cu = 256;
     c->qstride = 2 * kQPad + max_m;
-    c->surv_cap = max_n < (int64_t(1) << 24) ? max_n : (int64_t(1) << 24);
+    c->surv_cap = max_n;                  // a chunk of any size can keep every survivor
+    c->mstride = ((int64_t)max_m + 15) / 16 * 16;
     c->gen_lanes = 8192;
     const int64_t Q = max_queries;
     bool ok = dalloc(&c->qpad, Q * c->qstride) == hipSuccess && dalloc(&c->qhat64, Q * max_m) == hipSuccess &&
-              dalloc(&c->qsorted, Q * max_m) == hipSuccess && dalloc(&c->Usorted, Q * max_m) == hipSuccess &&
-              dalloc(&c->Lsorted, Q * max_m) == hipSuccess && dalloc(&c->order, Q * max_m) == hipSuccess &&
+              dalloc(&c->qsorted, Q * c->mstride) == hipSuccess && dalloc(&c->Usorted, Q * c->mstride) == hipSuccess &&
+              dalloc(&c->Lsorted, Q * c->mstride) == hipSuccess && dalloc(&c->order, Q * c->mstride) == hipSuccess &&
               dalloc(&c->keys, Q) == hipSuccess && dalloc(&c->st_mu, max_n) == hipSuccess &&
               dalloc(&c->st_s, max_n) == hipSuccess && dalloc(&c->st_o, max_n) == hipSuccess &&
               dalloc(&c->envU, max_n) == hipSuccess && dalloc(&c->envL, max_n) == hipSuccess &&
@@ -292,6 +296,8 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
               dalloc(&c->nb_d, kNearBestCap) == hipSuccess && dalloc(&c->nb_idx, kNearBestCap) == hipSuccess &&
               dalloc(&c->nb_count, 1) == hipSuccess &&
               dalloc(&c->cert_rows, (size_t)256 * 3 * (max_m + 1)) == hipSuccess &&
+              dalloc(&c->cert_idx, kNearBestCap) == hipSuccess && dalloc(&c->cert_count, 1) == hipSuccess &&
+              dalloc(&c->cert_d, kNearBestCap) == hipSuccess &&
               dalloc(&c->res_idx, Q) == hipSuccess && dalloc(&c->res_dist, Q) == hipSuccess &&
               dalloc(&c->res_status, Q) == hipSuccess && dalloc(&c->counters, kNumCounters) == hipSuccess &&
               dalloc(&c->gen_rows, (size_t)c->gen_lanes * 2 * (max_m + 1)) == hipSuccess &&

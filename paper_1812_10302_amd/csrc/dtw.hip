@@ -417,6 +417,131 @@ __global__ __launch_bounds__(256) void k_certify(CertArgs c) {
     }
 }
 
+// ------------------------------------------------------------------ block-parallel certification
+// The qualifying near-best candidates (D32 <= threshold of the final best-so-far) are compacted,
+// then one block per candidate evaluates eq. (dtw) in FP64 along anti-diagonals a = i + j: all
+// cells of one anti-diagonal depend only on the two previous ones, so the block's threads split
+// each anti-diagonal and synchronise between anti-diagonals.  Anti-diagonals are kept in a ring
+// of three row-indexed buffers of length L = r + 4 in LDS, next to the normalised query and
+// candidate (FP64, two-pass statistics as in eq. (Normalization1)).
+constexpr int kCertCap = kNearBestCap;
+constexpr int kCertBlocks = 64;
+constexpr int kCertThreads = 256;
+
+__global__ __launch_bounds__(256) void k_cert_select(CertArgs c) {
+    const float thr = threshold_of(key_dist(*c.key));
+    const uint32_t total = *c.nb_count;
+    const uint32_t cnt = total < (uint32_t)kNearBestCap ? total : (uint32_t)kNearBestCap;
+    for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+        if (c.nb_d[e] <= thr) {
+            const uint32_t pos = atomicAdd(c.cert_count, 1u);
+            if (pos < (uint32_t)kCertCap) c.cert_idx[pos] = c.nb_idx[e];
+        }
+    }
+}
+
+__device__ inline double block_sum64(double v, double *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+    return s;
+}
+
+__global__ __launch_bounds__(kCertThreads) void k_cert_dtw(CertArgs c) {
+    extern __shared__ double sm[];
+    __shared__ double red[kCertThreads / 64];
+    const int m = c.m, r = c.r, L = r + 4;
+    double *qh = sm, *ch = sm + m, *ring = sm + 2 * m;   // ring: 3 x L
+    const uint32_t cnt0 = *c.cert_count;
+    const uint32_t cnt = cnt0 < (uint32_t)kCertCap ? cnt0 : (uint32_t)kCertCap;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int j = tid; j < m; j += nt) qh[j] = c.qhat64[j];
+    for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
+        const uint32_t idx = c.cert_idx[e];
+        const float *wv = c.T + idx;
+        double s = 0.0;
+        for (int j = tid; j < m; j += nt) s += (double)wv[j];
+        const double mu = block_sum64(s, red) / m;
+        double v = 0.0;
+        for (int j = tid; j < m; j += nt) {
+            const double dd = (double)wv[j] - mu;
+            v += dd * dd;
+        }
+        const double sigma = sqrt(block_sum64(v, red) / m);
+        const bool flat = sigma <= kSigmaFlat;
+        for (int j = tid; j < m; j += nt) ch[j] = flat ? 0.0 : ((double)wv[j] - mu) / sigma;
+        __syncthreads();
+        // anti-diagonal a holds rows i in [lo(a), hi(a)]: |2i - a| <= r, 0 <= i, a - i < m
+        for (int a = 0; a <= 2 * (m - 1); ++a) {
+            int lo = (a - r + 1) >> 1;          // ceil((a - r) / 2) for a - r >= -1
+            if (a - r < 0) lo = -((r - a) >> 1);
+            if (lo < a - (m - 1)) lo = a - (m - 1);
+            if (lo < 0) lo = 0;
+            int hi = (a + r) >> 1;
+            if (hi > a) hi = a;
+            if (hi > m - 1) hi = m - 1;
+            double *cur = ring + (a % 3) * L, *p1 = ring + ((a + 2) % 3) * L, *p2 = ring + ((a + 1) % 3) * L;
+            for (int i = lo + tid; i <= hi; i += nt) {
+                const int j = a - i;
+                const double diff = qh[i] - ch[j];
+                double best;
+                if (a == 0) {
+                    best = 0.0;
+                } else {
+                    // predecessors; a cell is readable iff it lies in the band and the grid
+                    const double up = (i >= 1 && (i - 1) - j <= r && j - (i - 1) <= r) ? p1[(i - 1) % L] : INFINITY;
+                    const double left = (j >= 1 && i - (j - 1) <= r && (j - 1) - i <= r) ? p1[i % L] : INFINITY;
+                    const double dg = (i >= 1 && j >= 1) ? p2[(i - 1) % L] : INFINITY;
+                    best = up < left ? up : left;
+                    best = best < dg ? best : dg;
+                }
+                cur[i % L] = __dadd_rn(__dmul_rn(diff, diff), best);
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            c.cert_d[e] = ring[((2 * (m - 1)) % 3) * L + (m - 1) % L];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cert_reduce(CertArgs c) {
+    __shared__ double sd[256];
+    __shared__ uint32_t si[256];
+    const uint32_t cnt0 = *c.cert_count;
+    const uint32_t cnt = cnt0 < (uint32_t)kCertCap ? cnt0 : (uint32_t)kCertCap;
+    double best = INFINITY;
+    uint32_t bidx = 0xffffffffu;
+    for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const double d = c.cert_d[e];
+        const uint32_t idx = c.cert_idx[e];
+        if (d < best || (d == best && idx < bidx)) {
+            best = d;
+            bidx = idx;
+        }
+    }
+    sd[threadIdx.x] = best;
+    si[threadIdx.x] = bidx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 1; t < (int)blockDim.x; ++t)
+            if (sd[t] < best || (sd[t] == best && si[t] < bidx)) {
+                best = sd[t];
+                bidx = si[t];
+            }
+        *c.res_idx = bidx == 0xffffffffu ? -1 : (int64_t)bidx;
+        *c.res_dist = best;
+        const bool overflow = *c.nb_count > (uint32_t)kNearBestCap || cnt0 > (uint32_t)kCertCap;
+        *c.res_status = overflow ? DTWS_EOVERFLOW : (bidx == 0xffffffffu ? DTWS_EHIP : DTWS_OK);
+        if (c.counters) atomicAdd(&c.counters[7], (unsigned long long)cnt);
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 template <bool SEARCH>
 static hipError_t launch_dtw_t(const DtwArgs &a, int64_t max_count, int num_cu, float *wide_rows,
@@ -461,7 +586,18 @@ hipError_t launch_bsf_update(uint64_t *keys, const float *d, const int64_t *idx,
 }
 
 hipError_t launch_certify(const CertArgs &c, hipStream_t s) {
-    hipLaunchKernelGGL(k_certify, dim3(1), dim3(256), 0, s, c);
+    const size_t shm = sizeof(double) * (2 * (size_t)c.m + 3 * (size_t)(c.r + 4));
+    if (shm > 60 * 1024 || !c.cert_idx) {
+        // very wide bands: one thread per candidate with rows in global scratch
+        hipLaunchKernelGGL(k_certify, dim3(1), dim3(256), 0, s, c);
+        return hipGetLastError();
+    }
+    hipError_t e = launch_fill_u32(c.cert_count, 0, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cert_select, dim3(1), dim3(256), 0, s, c);
+    const int threads = c.r < 64 ? 64 : kCertThreads;   // one wave when an anti-diagonal fits in it
+    hipLaunchKernelGGL(k_cert_dtw, dim3(kCertBlocks), dim3(threads), shm, s, c);
+    hipLaunchKernelGGL(k_cert_reduce, dim3(1), dim3(256), 0, s, c);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ constexpr float kEpsAbs = 1e-6f;
 constexpr double kSigmaFlat = 1e-8;
 // Largest band (2r+1) handled by the register-resident DTW kernel (16-cell chunks).
 constexpr int kMaxChunks = 14;
-constexpr int kNearBestCap = 1 << 16;
+constexpr int kNearBestCap = 1 << 20;
 
 __host__ __device__ inline float threshold_of(float bsf) {
     return bsf * (1.0f + kEpsRel) + kEpsAbs;   // +inf stays +inf
@@ -87,7 +87,10 @@ struct CertArgs {
     const uint64_t *key;
     const float *nb_d;
     const uint32_t *nb_idx, *nb_count;
-    double *scratch;    // [256 * 3 * (m + 1)]
+    double *scratch;    // [256 * 3 * (m + 1)] (wide-band fallback)
+    uint32_t *cert_idx; // [1024] compacted qualifying candidates
+    uint32_t *cert_count;
+    double *cert_d;     // [1024] their FP64 distances
     int64_t *res_idx;
     double *res_dist;
     int32_t *res_status;
@@ -120,6 +123,7 @@ struct dtws_ctx {
     int32_t max_m = 0, max_q = 0;
     // per-query buffers, stride qstride floats / max_m elements
     int64_t qstride = 0;
+    int64_t mstride = 0;                  // per-query stride of the 16-padded sorted arrays
     float *qpad = nullptr;
     double *qhat64 = nullptr;
     float *qsorted = nullptr, *Usorted = nullptr, *Lsorted = nullptr;
@@ -137,6 +141,9 @@ struct dtws_ctx {
     uint32_t *nb_count = nullptr;
     // certification scratch and results
     double *cert_rows = nullptr;          // [256 * 2 * (max_m + 1)]
+    uint32_t *cert_idx = nullptr;         // [1024] compacted qualifying candidates
+    uint32_t *cert_count = nullptr;
+    double *cert_d = nullptr;             // [1024]
     int64_t *res_idx = nullptr;           // device [max_q]
     double *res_dist = nullptr;           // device [max_q]
     int32_t *res_status = nullptr;        // device [max_q]

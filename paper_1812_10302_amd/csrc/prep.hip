@@ -113,6 +113,16 @@ __global__ __launch_bounds__(1024) void k_query_prep(const float *__restrict__ Q
         b.Usorted[k] = U[j];
         b.Lsorted[k] = L[j];
     }
+    // Pad to a multiple of 16 with neutral terms so the bound loops run whole blocks of 16: an
+    // infinite query envelope adds nothing to the query-envelope bound, and a NaN query value
+    // adds nothing to the data-envelope bound (max(NaN, x) = x under IEEE maxNum).
+    const int mpad = (m + 15) & ~15;
+    for (int k = m + tid; k < mpad; k += nt) {
+        b.order[k] = 0;
+        b.qsorted[k] = __builtin_nanf("");
+        b.Usorted[k] = INFINITY;
+        b.Lsorted[k] = -INFINITY;
+    }
 }
 
 // ------------------------------------------------------------------ window statistics
