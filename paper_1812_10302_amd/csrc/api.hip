@@ -14,6 +14,8 @@ using namespace dtws;
 namespace {
 
 constexpr int kNumCounters = 16;
+constexpr int64_t kMinBlock = 2048;   // smallest work-item block (sizes the order arrays)
+constexpr int64_t kDefaultBlock = 4096;
 
 void set_err(dtws_ctx *c, hipError_t e, const char *what) {
     if (!c) return;
@@ -217,6 +219,206 @@ int fetch_counters(dtws_ctx *c, int64_t candidates, hipStream_t s) {
     return DTWS_OK;
 }
 
+
+// Batched pipeline (see batch.hip): all queries in rounds over a device work queue.
+int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int64_t *qoff, const int32_t *mh,
+              const int32_t *rh, int nq, uint32_t flags, uint64_t seed, hipStream_t s, dtws_match *out) {
+    const int64_t B = kDefaultBlock;
+    bool same_m = true;
+    int max_m = 0, max_r = 0;
+    int64_t max_nb = 0, cand = 0;
+    bool bucket_used[kMaxChunks + 2] = {false};
+    for (int k = 0; k < nq; ++k) {
+        BatchQ &b = c->h_bq[k];
+        b.qoff = qoff[k];
+        b.m = mh[k];
+        b.r = rh[k] > mh[k] - 1 ? mh[k] - 1 : rh[k];
+        b.N = n - b.m + 1;
+        b.nblocks = (int32_t)((b.N + B - 1) / B);
+        const int nc = (b.r + 8) / 8;
+        b.nc = nc > kMaxChunks ? kMaxChunks + 1 : nc;
+        bucket_used[b.nc] = true;
+        same_m = same_m && b.m == mh[0];
+        max_m = b.m > max_m ? b.m : max_m;
+        max_r = b.r > max_r ? b.r : max_r;
+        max_nb = b.nblocks > max_nb ? b.nblocks : max_nb;
+        cand += b.N;
+    }
+    const size_t cert_shm = sizeof(double) * (2 * (size_t)max_m + 3 * (size_t)(max_r + 4));
+    if ((flags & DTWS_NO_LOWER_BOUNDS) || cert_shm > 60 * 1024) {
+        // outside the batched pipeline's envelope: every query through the plain path
+        dtws_counters sum{};
+        int worst = DTWS_OK;
+        for (int k = 0; k < nq; ++k) {
+            const int rc = dtws_search(c, T, n, Qp + qoff[k], mh[k], rh[k], flags & ~DTWS_ORDER_MASK, seed + k, s, &out[k]);
+            if (rc != DTWS_OK && rc != DTWS_EOVERFLOW) return rc;
+            if (rc != DTWS_OK) worst = rc;
+            const int64_t *src = (const int64_t *)&c->last;
+            int64_t *dst = (int64_t *)&sum;
+            for (size_t f = 0; f < sizeof(dtws_counters) / sizeof(int64_t); ++f) dst[f] += src[f];
+        }
+        c->last = sum;
+        return worst;
+    }
+    prof_begin(c, flags);
+    BatchArgs a{};
+    a.T = T;
+    a.n = n;
+    a.nq = nq;
+    a.block = B;
+    a.max_m = c->max_m;
+    a.bq = c->bq;
+    a.qpad = c->qpad;
+    a.qstride = c->qstride;
+    a.qhat64 = c->qhat64;
+    a.order = c->order;
+    a.Us = c->Usorted;
+    a.Ls = c->Lsorted;
+    a.qs = c->qsorted;
+    a.mstride = c->mstride;
+    a.keys = c->keys;
+    if (same_m) {
+        a.mu = c->st_mu;
+        a.s = c->st_s;
+        a.o = c->st_o;
+    } else {
+        a.P1 = c->P1;
+        a.P2 = c->P2;
+        a.anc = c->anc;
+        a.tot1 = c->tot1;
+        a.tot2 = c->tot2;
+    }
+    a.envU = c->envU;
+    a.envL = c->envL;
+    a.perm = c->perm;
+    a.maxblocks = c->maxblocks;
+    a.heads = c->heads;
+    a.surv_q = c->surv_q;
+    a.surv_i = c->surv_i;
+    a.surv_count = c->surv_count;
+    a.qcnt = c->qcnt;
+    a.overflow = c->overflow;
+    a.surv_cap = c->bsurv_cap;
+    a.sorted = c->sorted;
+    a.qorder = c->qorder;
+    a.wstart = c->wstart;
+    a.seg_off = c->seg_off;
+    a.fill = c->fill;
+    a.bucket_w = c->bucket_w;
+    a.bucket_j = c->bucket_j;
+    a.nb_d = c->nb_d;
+    a.nb_idx = c->nb_idx;
+    a.nb_q = c->nb_q;
+    a.nb_count = c->nb_count;
+    a.cert_idx = c->cert_idx;
+    a.cert_q = c->cert_q;
+    a.cert_count = c->cert_count;
+    a.cert_d = c->cert_d;
+    a.res_idx = c->res_idx;
+    a.res_dist = c->res_dist;
+    a.res_status = c->res_status;
+    a.counters = c->counters;
+    a.wide_rows = c->gen_rows;
+    a.wide_lanes = c->gen_lanes;
+
+    QueryBufs base{};
+    base.qpad = c->qpad;
+    base.qhat64 = c->qhat64;
+    base.qsorted = c->qsorted;
+    base.Usorted = c->Usorted;
+    base.Lsorted = c->Lsorted;
+    base.order = c->order;
+
+    HIPCHK(c, hipMemcpyAsync(c->bq, c->h_bq, sizeof(BatchQ) * nq, hipMemcpyHostToDevice, s));
+    {
+        PROF(DTWS_K_OTHER);
+        HIPCHK(c, launch_fill_u64(c->keys, kEmptyKey, nq, s));
+        HIPCHK(c, launch_fill_u64((uint64_t *)c->counters, 0, kNumCounters, s));
+        HIPCHK(c, launch_fill_u32(c->heads, 0, 8, s));
+        HIPCHK(c, launch_fill_u32(c->nb_count, 0, 1, s));
+        HIPCHK(c, launch_fill_u32(c->cert_count, 0, 1, s));
+        HIPCHK(c, launch_fill_u32(c->overflow, 0, 1, s));
+    }
+    {
+        PROF(DTWS_K_PREP);
+        HIPCHK(c, launch_query_prep_batch(Qp, c->bq, nq, base, c->qstride, c->mstride, c->max_m, s));
+    }
+    {
+        PROF(DTWS_K_STATS);
+        if (same_m)
+            HIPCHK(c, launch_znorm_stats(T, n, max_m, nullptr, nullptr, c->st_mu, c->st_s, c->st_o, s));
+        else
+            HIPCHK(c, launch_prefix(T, n, c->P1, c->P2, c->anc, c->tot1, c->tot2, s));
+    }
+    {
+        PROF(DTWS_K_ENV);   // one data envelope for the largest band: valid (looser) for the others
+        HIPCHK(c, launch_series_env(T, n, max_r, c->envU, c->envL, s));
+    }
+    {
+        PROF(DTWS_K_OTHER);
+        HIPCHK(c, launch_make_perm(a, (flags & DTWS_ORDER_MASK) == DTWS_ORDER_RANDOM ? 1 : 0, seed ^ 0xA5A5ull,
+                                   max_nb, s));
+    }
+    const int dtw_blocks = c->num_cu * 4;
+    auto dtw_round = [&]() -> int {
+        { PROF(DTWS_K_OTHER); HIPCHK(c, launch_segments(a, c->num_cu, s)); }
+        for (int nc = 1; nc <= kMaxChunks + 1; ++nc) {
+            if (!bucket_used[nc]) continue;
+            PROF(DTWS_K_DTW);
+            HIPCHK(c, launch_dtw_bucket(a, !same_m, nc, dtw_blocks, s));
+        }
+        return DTWS_OK;
+    };
+    // round -1: one random candidate per query
+    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_seed_random(a, seed, s)); }
+    int rc = dtw_round();
+    if (rc != DTWS_OK) return rc;
+    // rounds over the work queue: 64K, 1M, 16M candidates per query, then the rest
+    const int64_t targets[4] = {int64_t(1) << 16, (int64_t(1) << 16) + (int64_t(1) << 20),
+                                (int64_t(1) << 16) + (int64_t(1) << 20) + (int64_t(1) << 24), INT64_MAX / 2};
+    int64_t rank_lo = 0;
+    for (int round = 0; round < 4 && rank_lo < max_nb; ++round) {
+        int64_t rank_hi = (targets[round] + B - 1) / B;
+        if (rank_hi > max_nb) rank_hi = max_nb;
+        {
+            PROF(DTWS_K_OTHER);
+            HIPCHK(c, launch_fill_u32(c->surv_count, 0, 1, s));
+            HIPCHK(c, launch_fill_u32(c->qcnt, 0, nq, s));
+        }
+        {
+            PROF(DTWS_K_LB);
+            HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)rank_lo, (int)rank_hi, c->num_cu * 8, s));
+        }
+        rc = dtw_round();
+        if (rc != DTWS_OK) return rc;
+        rank_lo = rank_hi;
+    }
+    { PROF(DTWS_K_CERT); HIPCHK(c, launch_cert_batch(a, max_m, max_r, s)); }
+    HIPCHK(c, hipMemcpyAsync(c->h_idx, c->res_idx, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_dist, c->res_dist, sizeof(double) * nq, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_status, c->res_status, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, s));
+    rc = fetch_counters(c, cand, s);
+    if (rc != DTWS_OK) return rc;
+    prof_end(c);
+    int worst = DTWS_OK;
+    for (int k = 0; k < nq; ++k) {
+        out[k].index = c->h_idx[k];
+        out[k].distance = c->h_dist[k];
+        out[k].status = c->h_status[k];
+        out[k].reserved = 0;
+        if (out[k].status == DTWS_EOVERFLOW) {
+            // survivor or near-best list overflowed: redo this query through the plain path
+            dtws_counters keep = c->last;
+            const int r2 = dtws_search(c, T, n, Qp + qoff[k], mh[k], rh[k], 0, seed + k, s, &out[k]);
+            c->last = keep;
+            if (r2 != DTWS_OK) worst = r2;
+        } else if (out[k].status != DTWS_OK) {
+            worst = out[k].status;
+        }
+    }
+    return worst;
+}
+
 }  // namespace
 
 // ============================================================================ C ABI
@@ -248,7 +450,10 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
     (void)hipSetDevice(c->device);
     void *dev[] = {c->qpad, c->qhat64, c->qsorted, c->Usorted, c->Lsorted, c->order, c->keys, c->st_mu,
                    c->st_s, c->st_o, c->envU, c->envL, c->surv, c->surv_count, c->nb_d, c->nb_idx,
-                   c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_idx, c->res_dist, c->res_status, c->counters, c->gen_rows};
+                   c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_idx, c->res_dist,
+                   c->res_status, c->counters, c->gen_rows, c->bq, c->P1, c->P2, c->anc, c->tot1, c->tot2,
+                   c->perm, c->heads, c->surv_q, c->surv_i, c->sorted, c->qcnt, c->fill, c->overflow,
+                   c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->ev) {
@@ -257,7 +462,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
         delete[] c->ev;
     }
     delete[] c->ev_class;
-    void *host[] = {c->h_idx, c->h_dist, c->h_status, c->h_counters};
+    void *host[] = {c->h_idx, c->h_dist, c->h_status, c->h_counters, c->h_bq};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     delete c;
@@ -305,6 +510,23 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
               hipHostMalloc((void **)&c->h_dist, sizeof(double) * Q, 0) == hipSuccess &&
               hipHostMalloc((void **)&c->h_status, sizeof(int32_t) * Q, 0) == hipSuccess &&
               hipHostMalloc((void **)&c->h_counters, sizeof(unsigned long long) * kNumCounters, 0) == hipSuccess;
+    if (ok) {
+        c->maxblocks = (max_n + kMinBlock - 1) / kMinBlock + 1;
+        const int64_t cap = Q * max_n < (int64_t(1) << 25) ? Q * max_n : (int64_t(1) << 25);
+        c->bsurv_cap = cap;
+        const int64_t nblk = max_n / 4096 + 2;
+        ok = dalloc(&c->bq, Q) == hipSuccess && hipHostMalloc((void **)&c->h_bq, sizeof(BatchQ) * Q, 0) == hipSuccess &&
+             dalloc(&c->P1, max_n + 1) == hipSuccess && dalloc(&c->P2, max_n + 1) == hipSuccess &&
+             dalloc(&c->anc, nblk) == hipSuccess && dalloc(&c->tot1, nblk) == hipSuccess &&
+             dalloc(&c->tot2, nblk) == hipSuccess && dalloc(&c->perm, Q * c->maxblocks) == hipSuccess &&
+             dalloc(&c->heads, 8) == hipSuccess && dalloc(&c->surv_q, cap) == hipSuccess &&
+             dalloc(&c->surv_i, cap) == hipSuccess && dalloc(&c->sorted, cap + 64 * Q) == hipSuccess &&
+             dalloc(&c->qcnt, Q) == hipSuccess && dalloc(&c->fill, Q) == hipSuccess &&
+             dalloc(&c->overflow, 1) == hipSuccess && dalloc(&c->qorder, Q + 1) == hipSuccess &&
+             dalloc(&c->wstart, Q + 1) == hipSuccess && dalloc(&c->bucket_w, 2 * (kMaxChunks + 2)) == hipSuccess &&
+             dalloc(&c->bucket_j, 2 * (kMaxChunks + 2)) == hipSuccess && dalloc(&c->seg_off, Q) == hipSuccess &&
+             dalloc(&c->nb_q, kNearBestCap) == hipSuccess && dalloc(&c->cert_q, kNearBestCap) == hipSuccess;
+    }
     if (ok) {
         c->ev = new (std::nothrow) hipEvent_t[2 * dtws_ctx::kMaxEvents]();
         c->ev_class = new (std::nothrow) int[dtws_ctx::kMaxEvents]();
@@ -370,46 +592,12 @@ DTWS_API int dtws_search_batch(dtws_ctx *c, const float *T, int64_t n, const flo
                                void *stream, dtws_match *out) {
     if (!c || !T || !Qp || !qoff || !mh || !rh || !out || nq < 1 || nq > c->max_q) return DTWS_EINVAL;
     if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE)) return DTWS_EINVAL;
+    if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED) return DTWS_ENOMODEL;
     for (int k = 0; k < nq; ++k)
         if (check_series(c, T, n, mh[k]) != DTWS_OK || rh[k] < 0 || qoff[k] < 0) return DTWS_EINVAL;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
-    prof_begin(c, flags);
-    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u64((uint64_t *)c->counters, 0, kNumCounters, s)); }
-    int64_t cand = 0;
-    int last_m = -1, last_r = -1;
-    for (int k = 0; k < nq; ++k) {
-        const int m = mh[k];
-        const int r = rh[k] > m - 1 ? m - 1 : rh[k];
-        if (m != last_m) {
-            PROF(DTWS_K_STATS);
-            HIPCHK(c, launch_znorm_stats(T, n, m, nullptr, nullptr, c->st_mu, c->st_s, c->st_o, s));
-        }
-        if (!(flags & DTWS_NO_LOWER_BOUNDS) && r != last_r) {
-            PROF(DTWS_K_ENV);
-            HIPCHK(c, launch_series_env(T, n, r, c->envU, c->envL, s));
-        }
-        last_m = m;
-        last_r = r;
-        const int rc = run_query(c, T, n, Qp + qoff[k], m, r, flags, seed + (uint64_t)k, k, s);
-        if (rc != DTWS_OK) return rc;
-        cand += n - m + 1;
-    }
-    HIPCHK(c, hipMemcpyAsync(c->h_idx, c->res_idx, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_dist, c->res_dist, sizeof(double) * nq, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_status, c->res_status, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, s));
-    const int rc = fetch_counters(c, cand, s);
-    if (rc != DTWS_OK) return rc;
-    prof_end(c);
-    int worst = DTWS_OK;
-    for (int k = 0; k < nq; ++k) {
-        out[k].index = c->h_idx[k];
-        out[k].distance = c->h_dist[k];
-        out[k].status = c->h_status[k];
-        out[k].reserved = 0;
-        if (out[k].status != DTWS_OK) worst = out[k].status;
-    }
-    return worst;
+    return run_batch(c, T, n, Qp, qoff, mh, rh, nq, flags, seed, s, out);
 }
 
 DTWS_API int dtws_znorm_stats(dtws_ctx *c, const float *T, int64_t n, int32_t m, double *mu, double *sigma,

@@ -1,0 +1,627 @@
+// Batched search: many queries of different lengths and bands against one series.
+//
+// Work is a device queue of items (query, block of consecutive candidate starts).  Each query's
+// blocks are visited in a per-query order (series order, a seeded permutation, or the learned
+// model's ranking) and in rounds: the first 64K candidates of every query, then the next 1M,
+// the next 16M, then the rest.  A round is one persistent launch of the bound cascade over all
+// queries' items (waves pop items from an atomic head); survivors (query, start) are then
+// counting-sorted into per-query segments padded to whole waves, grouped by DTW band bucket, and
+// one DTW launch per bucket covers every query of that bucket.  The best-so-far of each query
+// lives in device memory throughout (the reduction of Algorithm 1 becomes an atomic minimum on
+// a packed (distance, index) key) and every later round prunes with the tighter values.
+//
+// Window statistics for any query length come from one blocked prefix of the series: FP64 sums
+// of (t - a_b) and (t - a_b)^2 anchored at the first point a_b of each 4096-point block, so a
+// window's sums are a difference of two nearby partial sums (re-anchored when the window crosses
+// one block boundary; m <= 2048 < 4096 crosses at most one).  When all queries share one length
+// the per-window arrays of the statistics pass are used instead.
+#include "device.h"
+
+namespace dtws {
+
+constexpr int kPB = 4096;            // prefix block length (points)
+constexpr int kPrefixThreads = 256;  // 16 points per thread
+
+__device__ inline uint64_t splitmix64_d(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// ------------------------------------------------------------------ blocked prefix
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restrict__ T, int64_t n, double *P1,
+                                                           double *P2, double *anc, double *tot1, double *tot2) {
+    __shared__ double ws1[kPrefixThreads / 64], ws2[kPrefixThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t b = blockIdx.x, x0 = b * kPB;
+    const double a = (double)T[x0];
+    double v1[16], v2[16];
+    double r1 = 0.0, r2 = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int64_t y = x0 + 16 * tid + u;
+        const double d = y < n ? (double)T[y] - a : 0.0;
+        v1[u] = r1;
+        v2[u] = r2;
+        r1 += d;
+        r2 += d * d;
+    }
+    double i1 = r1, i2 = r2;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double y1 = __shfl_up(i1, off, 64), y2 = __shfl_up(i2, off, 64);
+        if (lane >= off) {
+            i1 += y1;
+            i2 += y2;
+        }
+    }
+    if (lane == 63) {
+        ws1[wid] = i1;
+        ws2[wid] = i2;
+    }
+    __syncthreads();
+    double b1 = 0.0, b2 = 0.0, t1 = 0.0, t2 = 0.0;
+    for (int w = 0; w < kPrefixThreads / 64; ++w) {
+        if (w < wid) {
+            b1 += ws1[w];
+            b2 += ws2[w];
+        }
+        t1 += ws1[w];
+        t2 += ws2[w];
+    }
+    b1 += i1 - r1;
+    b2 += i2 - r2;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int64_t y = x0 + 16 * tid + u;
+        if (y <= n) {    // P[n] = sum of the last partial block, read for windows ending at n
+            P1[y] = b1 + v1[u];
+            P2[y] = b2 + v2[u];
+        }
+    }
+    if (tid == 0) {
+        anc[b] = a;
+        tot1[b] = t1;
+        tot2[b] = t2;
+    }
+}
+
+// Mean and population sigma of T[i .. i+m) from the blocked prefix (FP64).  Windows whose prefix
+// difference may have lost relative precision (short windows, heavy cancellation) are recomputed
+// two-pass from the series.
+struct StatsPrefix {
+    const float *T;
+    const double *P1, *P2, *anc, *tot1, *tot2;
+    int m;
+    __device__ void window(int64_t i, double &mu, double &sigma) const {
+        const int64_t e = i + m;
+        const int64_t b0 = i / kPB, b1 = (e - 1) / kPB;
+        double e1, e2;
+        if (e == (b1 + 1) * kPB) {
+            e1 = tot1[b1];
+            e2 = tot2[b1];
+        } else {
+            e1 = P1[e];
+            e2 = P2[e];
+        }
+        double S1, S2;
+        if (b0 == b1) {
+            S1 = e1 - P1[i];
+            S2 = e2 - P2[i];
+        } else {
+            const double delta = anc[b1] - anc[b0];
+            const double c2 = (double)(e - b1 * kPB);
+            S1 = (tot1[b0] - P1[i]) + e1 + c2 * delta;
+            S2 = (tot2[b0] - P2[i]) + e2 + 2.0 * delta * e1 + c2 * delta * delta;
+        }
+        const double md = S1 / m, msq = S2 / m;
+        double var = msq - md * md;
+        mu = anc[b0] + md;
+        if (m <= 64 || !(var > 4e-6 * msq)) {
+            const float *w = T + i;
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += (double)w[j];
+            mu = s / m;
+            double q = 0.0;
+            for (int j = 0; j < m; ++j) {
+                const double d = (double)w[j] - mu;
+                q += d * d;
+            }
+            var = q / m;
+        }
+        sigma = sqrt(var > 0.0 ? var : 0.0);
+    }
+    __device__ void operator()(int64_t i, float &mu32, float &s, float &o) const {
+        double mu, sigma;
+        window(i, mu, sigma);
+        norm_params(mu, sigma, mu32, s, o);
+    }
+};
+
+struct StatsArr {
+    const float *mu, *s, *o;
+    __device__ void operator()(int64_t i, float &m, float &sg, float &off) const {
+        m = mu[i];
+        sg = s[i];
+        off = o[i];
+    }
+};
+
+// ------------------------------------------------------------------ work order
+// Primes above any block count (series < 2^31 points, blocks >= 2048 points): A = p mod nb is
+// then coprime to nb, so k -> (A k + C) mod nb is a permutation.
+__constant__ uint64_t kPrimes[8] = {1000003ull, 1000033ull, 1000037ull, 1000039ull,
+                                    1000081ull, 1000099ull, 1000117ull, 1000121ull};
+
+// mode 0: series order; 1: seeded permutation k -> (A k + C) mod nb with A coprime to nb.
+__global__ void k_make_perm(BatchArgs a, int mode, uint64_t seed) {
+    const int q = blockIdx.y;
+    const BatchQ bq = a.bq[q];
+    const int64_t nb = bq.nblocks;
+    const uint64_t h = splitmix64_d(seed ^ (0x51ED2701ull * (uint64_t)(q + 1)));
+    const uint64_t A = kPrimes[h & 7] % (uint64_t)nb, C = (h >> 8) % (uint64_t)nb;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t v = k;
+        if (mode == 1 && nb > 1) v = (int64_t)((A * (uint64_t)k + C) % (uint64_t)nb);
+        a.perm[(int64_t)q * a.maxblocks + k] = (int32_t)v;
+    }
+}
+
+// Round -1: the best-so-far of every query starts from one seeded random candidate (Algorithm 1).
+__global__ void k_seed_random(BatchArgs a, uint64_t seed) {
+    for (int q = threadIdx.x; q < a.nq; q += blockDim.x) {
+        const int64_t N = a.bq[q].N;
+        a.surv_q[q] = q;
+        a.surv_i[q] = (int32_t)(splitmix64_d(seed + (uint64_t)q) % (uint64_t)N);
+        a.qcnt[q] = 1;
+    }
+    if (threadIdx.x == 0) *a.surv_count = (uint32_t)a.nq;
+}
+
+// ------------------------------------------------------------------ batched bound cascade
+struct EmitBatch {
+    int32_t *surv_q, *surv_i;
+    uint32_t *count, *qcnt, *overflow;
+    int64_t cap;
+    int q;
+    __device__ void operator()(bool alive, int64_t i) const {
+        const uint64_t mask = __ballot(alive);
+        if (!mask) return;
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        const uint32_t pc = (uint32_t)__popcll(mask);
+        uint32_t base = 0;
+        if (lane == leader) {
+            base = atomicAdd(count, pc);
+            if ((int64_t)base + pc > cap) atomicOr(overflow, 1u);
+            else atomicAdd(&qcnt[q], pc);
+        }
+        base = __shfl(base, leader, 64);
+        const int64_t pos = (int64_t)base + __popcll(mask & lanemask_lt());
+        if (alive && (int64_t)base + pc <= cap) {
+            surv_q[pos] = q;
+            surv_i[pos] = (int32_t)i;
+        }
+    }
+};
+
+template <bool PREFIX>
+__global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int rank_lo, int rank_hi) {
+    __shared__ WaveQueue queues[4][2];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t total = (uint32_t)(rank_hi - rank_lo) * (uint32_t)a.nq;
+    CascadeCounts cnt;
+    for (;;) {
+        uint32_t idx = 0;
+        if (lane == 0) idx = atomicAdd(&a.heads[round], 1u);
+        idx = __shfl(idx, 0, 64);
+        if (idx >= total) break;
+        const int k = rank_lo + (int)(idx / (uint32_t)a.nq);
+        const int q = (int)(idx % (uint32_t)a.nq);
+        const BatchQ bq = a.bq[q];
+        if (k >= bq.nblocks) continue;
+        const int64_t blk = a.perm[(int64_t)q * a.maxblocks + k];
+        const int64_t first = blk * a.block;
+        const int64_t last = first + a.block < bq.N ? first + a.block : bq.N;
+        const QView v{a.order + q * a.mstride, a.Us + q * a.mstride, a.Ls + q * a.mstride, a.qs + q * a.mstride,
+                      bq.m, (bq.m + 15) & ~15};
+        const float *qh = a.qpad + q * a.qstride + kQPad;
+        const float thr = threshold_of(load_bsf(a.keys + q));
+        const EmitBatch emit{a.surv_q, a.surv_i, a.surv_count, a.qcnt, a.overflow, a.surv_cap, q};
+        if (PREFIX)
+            cascade(v, a.T, a.envU, a.envL, thr, qh[0], qh[bq.m - 1], first, 64, last, queues[wid][0],
+                    queues[wid][1], StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, bq.m}, emit, cnt);
+        else
+            cascade(v, a.T, a.envU, a.envL, thr, qh[0], qh[bq.m - 1], first, 64, last, queues[wid][0],
+                    queues[wid][1], StatsArr{a.mu, a.s, a.o}, emit, cnt);
+    }
+    if (a.counters) {
+        const unsigned long long c_kim = wave_add_u64(cnt.kim), c_kq = wave_add_u64(cnt.kq),
+                                 c_kd = wave_add_u64(cnt.kd);
+        if (lane == 0) {
+            atomicAdd(&a.counters[1], c_kim);
+            atomicAdd(&a.counters[2], c_kq);
+            atomicAdd(&a.counters[3], c_kd);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ survivor segments
+// Queries in bucket order; each query's survivors get ceil(count / 64) whole waves, so a DTW
+// wave never mixes queries (the query window is broadcast across the wave).  bucket_w[2c] /
+// bucket_w[2c+1] are the wave range of bucket c and bucket_j[2c] / bucket_j[2c+1] its range of
+// positions in qorder / wstart.
+__global__ void k_seg_plan(BatchArgs a) {
+    if (threadIdx.x != 0) return;
+    int32_t off = 0, j = 0;
+    for (int c = 1; c <= kMaxChunks + 1; ++c) {
+        a.bucket_w[2 * c] = off;
+        a.bucket_j[2 * c] = j;
+        for (int q = 0; q < a.nq; ++q) {
+            if (a.bq[q].nc != c) continue;
+            a.qorder[j] = q;
+            a.wstart[j] = off;
+            a.seg_off[q] = (int64_t)off * 64;
+            a.fill[q] = 0;
+            off += (int32_t)((a.qcnt[q] + 63u) / 64u);
+            ++j;
+        }
+        a.bucket_w[2 * c + 1] = off;
+        a.bucket_j[2 * c + 1] = j;
+    }
+    a.wstart[j] = off;
+}
+
+__global__ void k_seg_scatter(BatchArgs a) {
+    if (*a.overflow) return;
+    uint32_t cnt = *a.surv_count;
+    if ((int64_t)cnt > a.surv_cap) cnt = (uint32_t)a.surv_cap;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
+        const int q = a.surv_q[e];
+        const uint32_t p = atomicAdd(&a.fill[q], 1u);
+        a.sorted[a.seg_off[q] + p] = a.surv_i[e];
+    }
+}
+
+// Finds the query of DTW wave w inside a bucket.
+__device__ inline int wave_query(const BatchArgs &a, int c, int64_t w, int32_t &wq0) {
+    int lo = a.bucket_j[2 * c], hi = a.bucket_j[2 * c + 1];   // wstart[lo] <= w < wstart[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.wstart[mid] <= w) lo = mid;
+        else hi = mid;
+    }
+    wq0 = a.wstart[lo];
+    return a.qorder[lo];
+}
+
+template <class Stats>
+__device__ inline void stats_of(const Stats &st, int64_t i, float &mu, float &s, float &o) {
+    st(i, mu, s, o);
+}
+
+// ------------------------------------------------------------------ batched DTW (register kernel)
+template <int NC, bool PREFIX>
+__global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
+    constexpr int W = 16 * NC;
+    if (*a.overflow) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t wlo = a.bucket_w[2 * NC], whi = a.bucket_w[2 * NC + 1];
+    unsigned long long n_started = 0, n_aband = 0, n_cells = 0, n_lane_cells = 0;
+    for (int64_t w = wlo + wave; w < whi; w += nwaves) {
+        int32_t wq0;
+        const int q = wave_query(a, NC, w, wq0);
+        const BatchQ bq = a.bq[q];
+        const int64_t local = (w - wq0) * 64 + lane;
+        const bool valid = local < (int64_t)a.qcnt[q];
+        const int64_t start = valid ? (int64_t)a.sorted[w * 64 + lane] : 0;
+        float mu, s, o;
+        if (PREFIX)
+            StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, bq.m}(start, mu, s, o);
+        else
+            StatsArr{a.mu, a.s, a.o}(start, mu, s, o);
+        bool alive;
+        float D;
+        int jdead, jrun;
+        dtw_lanes<NC>(a.T, start, mu, s, o, a.qpad + q * a.qstride, bq.m, bq.r, valid, a.keys + q, INFINITY,
+                          alive, D, jdead, jrun);
+        n_lane_cells += (unsigned long long)jrun * W;
+        if (valid) {
+            ++n_started;
+            if (jdead < bq.m) ++n_aband;
+            n_cells += band_cells(bq.m, bq.r, jdead);
+            if (alive) {
+                atomicMin((unsigned long long *)(a.keys + q), (unsigned long long)pack_key(D, (uint32_t)start));
+                const uint32_t pos = atomicAdd(a.nb_count, 1u);
+                if (pos < (uint32_t)kNearBestCap) {
+                    a.nb_d[pos] = D;
+                    a.nb_idx[pos] = (uint32_t)start;
+                    a.nb_q[pos] = q;
+                }
+            }
+        }
+    }
+    if (a.counters) {
+        n_started = wave_add(n_started);
+        n_aband = wave_add(n_aband);
+        n_cells = wave_add(n_cells);
+        n_lane_cells = wave_add(n_lane_cells);
+        if (lane == 0) {
+            atomicAdd(&a.counters[4], n_started);
+            atomicAdd(&a.counters[5], n_aband);
+            atomicAdd(&a.counters[6], n_cells);
+            atomicAdd(&a.counters[8], n_lane_cells);
+        }
+    }
+}
+
+// Wide bands (r > 8 * kMaxChunks - 1): one lane per candidate, DP rows in global scratch.
+template <bool PREFIX>
+__global__ __launch_bounds__(64) void k_dtw_batch_wide(BatchArgs a) {
+    constexpr int c = kMaxChunks + 1;
+    if (*a.overflow) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t wave = g >> 6, nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t wlo = a.bucket_w[2 * c], whi = a.bucket_w[2 * c + 1];
+    unsigned long long n_started = 0, n_aband = 0, n_cells = 0;
+    for (int64_t w = wlo + wave; w < whi; w += nwaves) {
+        int32_t wq0;
+        const int q = wave_query(a, c, w, wq0);
+        const BatchQ bq = a.bq[q];
+        const int m = bq.m, r = bq.r;
+        const int64_t local = (w - wq0) * 64 + lane;
+        if (local >= (int64_t)a.qcnt[q]) continue;
+        const int64_t start = a.sorted[w * 64 + lane];
+        float mu, s, o;
+        if (PREFIX)
+            StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, m}(start, mu, s, o);
+        else
+            StatsArr{a.mu, a.s, a.o}(start, mu, s, o);
+        const float *qh = a.qpad + q * a.qstride + kQPad;
+        float *prev = a.wide_rows + g * 2 * (int64_t)(a.max_m + 1), *cur = prev + (a.max_m + 1);
+        const float *Tp = a.T + start;
+        float thr = threshold_of(load_bsf(a.keys + q));
+        for (int x = 0; x <= m; ++x) {
+            prev[x] = INFINITY;
+            cur[x] = INFINITY;
+        }
+        prev[0] = 0.0f;
+        bool alive = true;
+        int idead = m;
+        for (int i = 1; i <= m; ++i) {
+            const int jlo = i - r < 1 ? 1 : i - r, jhi = i + r > m ? m : i + r;
+            cur[jlo - 1] = INFINITY;
+            if (jhi + 1 <= m) cur[jhi + 1] = INFINITY;
+            const float qi = qh[i - 1];
+            float rowmin = INFINITY;
+            for (int jj = jlo; jj <= jhi; ++jj) {
+                const float cc = fmaf(Tp[jj - 1] - mu, s, o);
+                const float diff = qi - cc;
+                const float v = fmaf(diff, diff, fminf(fminf(prev[jj], cur[jj - 1]), prev[jj - 1]));
+                cur[jj] = v;
+                rowmin = fminf(rowmin, v);
+            }
+            float *t = prev;
+            prev = cur;
+            cur = t;
+            if ((i & 15) == 0) thr = threshold_of(load_bsf(a.keys + q));
+            if (rowmin > thr) {
+                alive = false;
+                idead = i;
+                break;
+            }
+        }
+        const float D = prev[m];
+        ++n_started;
+        if (!alive) ++n_aband;
+        n_cells += band_cells(m, r, alive ? m : idead);
+        if (alive && D <= thr) {
+            atomicMin((unsigned long long *)(a.keys + q), (unsigned long long)pack_key(D, (uint32_t)start));
+            const uint32_t pos = atomicAdd(a.nb_count, 1u);
+            if (pos < (uint32_t)kNearBestCap) {
+                a.nb_d[pos] = D;
+                a.nb_idx[pos] = (uint32_t)start;
+                a.nb_q[pos] = q;
+            }
+        }
+    }
+    if (a.counters) {
+        atomicAdd(&a.counters[4], n_started);
+        atomicAdd(&a.counters[5], n_aband);
+        atomicAdd(&a.counters[6], n_cells);
+        atomicAdd(&a.counters[8], n_cells);
+    }
+}
+
+// ------------------------------------------------------------------ batched certification
+__global__ __launch_bounds__(256) void k_cert_select_batch(BatchArgs a) {
+    const uint32_t total = *a.nb_count;
+    const uint32_t cnt = total < (uint32_t)kNearBestCap ? total : (uint32_t)kNearBestCap;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
+        const int q = a.nb_q[e];
+        if (a.nb_d[e] <= threshold_of(load_bsf(a.keys + q))) {
+            const uint32_t pos = atomicAdd(a.cert_count, 1u);
+            if (pos < (uint32_t)kNearBestCap) {
+                a.cert_idx[pos] = a.nb_idx[e];
+                a.cert_q[pos] = q;
+            }
+        }
+    }
+}
+
+__device__ inline double block_sum_d(double v, double *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+    return s;
+}
+
+// One block per qualifying candidate: FP64 DTW along anti-diagonals (cells of one anti-diagonal
+// are independent), three anti-diagonals in an LDS ring of row-indexed buffers of length r + 4.
+__global__ __launch_bounds__(256) void k_cert_dtw_batch(BatchArgs a) {
+    extern __shared__ double sm[];
+    __shared__ double red[4];
+    const uint32_t cnt0 = *a.cert_count;
+    const uint32_t cnt = cnt0 < (uint32_t)kNearBestCap ? cnt0 : (uint32_t)kNearBestCap;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
+        const int q = a.cert_q[e];
+        const BatchQ bq = a.bq[q];
+        const int m = bq.m, r = bq.r, L = r + 4;
+        double *qh = sm, *ch = sm + m, *ring = sm + 2 * m;
+        const double *qsrc = a.qhat64 + (int64_t)q * a.max_m;
+        for (int j = tid; j < m; j += nt) qh[j] = qsrc[j];
+        const float *wv = a.T + a.cert_idx[e];
+        double s = 0.0;
+        for (int j = tid; j < m; j += nt) s += (double)wv[j];
+        const double mu = block_sum_d(s, red) / m;
+        double v = 0.0;
+        for (int j = tid; j < m; j += nt) {
+            const double dd = (double)wv[j] - mu;
+            v += dd * dd;
+        }
+        const double sigma = sqrt(block_sum_d(v, red) / m);
+        const bool flat = sigma <= kSigmaFlat;
+        for (int j = tid; j < m; j += nt) ch[j] = flat ? 0.0 : ((double)wv[j] - mu) / sigma;
+        __syncthreads();
+        for (int d = 0; d <= 2 * (m - 1); ++d) {
+            int lo = (d - r + 1) >> 1;
+            if (d - r < 0) lo = -((r - d) >> 1);
+            if (lo < d - (m - 1)) lo = d - (m - 1);
+            if (lo < 0) lo = 0;
+            int hi = (d + r) >> 1;
+            if (hi > d) hi = d;
+            if (hi > m - 1) hi = m - 1;
+            double *cur = ring + (d % 3) * L, *p1 = ring + ((d + 2) % 3) * L, *p2 = ring + ((d + 1) % 3) * L;
+            for (int i = lo + tid; i <= hi; i += nt) {
+                const int j = d - i;
+                const double diff = qh[i] - ch[j];
+                double best;
+                if (d == 0) {
+                    best = 0.0;
+                } else {
+                    const double up = (i >= 1 && (i - 1) - j <= r && j - (i - 1) <= r) ? p1[(i - 1) % L] : INFINITY;
+                    const double left = (j >= 1 && i - (j - 1) <= r && (j - 1) - i <= r) ? p1[i % L] : INFINITY;
+                    const double dg = (i >= 1 && j >= 1) ? p2[(i - 1) % L] : INFINITY;
+                    best = up < left ? up : left;
+                    best = best < dg ? best : dg;
+                }
+                cur[i % L] = __dadd_rn(__dmul_rn(diff, diff), best);
+            }
+            __syncthreads();
+        }
+        if (tid == 0) a.cert_d[e] = ring[((2 * (m - 1)) % 3) * L + (m - 1) % L];
+        __syncthreads();
+    }
+}
+
+// One block per query: minimum certified distance, lowest index on ties.
+__global__ __launch_bounds__(256) void k_cert_reduce_batch(BatchArgs a) {
+    __shared__ double sd[256];
+    __shared__ uint32_t si[256];
+    const int q = blockIdx.x;
+    const uint32_t cnt0 = *a.cert_count;
+    const uint32_t cnt = cnt0 < (uint32_t)kNearBestCap ? cnt0 : (uint32_t)kNearBestCap;
+    double best = INFINITY;
+    uint32_t bidx = 0xffffffffu;
+    for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+        if (a.cert_q[e] != q) continue;
+        const double d = a.cert_d[e];
+        const uint32_t idx = a.cert_idx[e];
+        if (d < best || (d == best && idx < bidx)) {
+            best = d;
+            bidx = idx;
+        }
+    }
+    sd[threadIdx.x] = best;
+    si[threadIdx.x] = bidx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 1; t < (int)blockDim.x; ++t)
+            if (sd[t] < best || (sd[t] == best && si[t] < bidx)) {
+                best = sd[t];
+                bidx = si[t];
+            }
+        a.res_idx[q] = bidx == 0xffffffffu ? -1 : (int64_t)bidx;
+        a.res_dist[q] = best;
+        const bool overflow = *a.overflow || *a.nb_count > (uint32_t)kNearBestCap ||
+                              *a.cert_count > (uint32_t)kNearBestCap;
+        a.res_status[q] = overflow ? DTWS_EOVERFLOW : (bidx == 0xffffffffu ? DTWS_EHIP : DTWS_OK);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_prefix(const float *T, int64_t n, double *P1, double *P2, double *anc, double *tot1,
+                         double *tot2, hipStream_t s) {
+    const int64_t blocks = (n + kPB - 1) / kPB;
+    hipLaunchKernelGGL(k_prefix, dim3((unsigned)blocks), dim3(kPrefixThreads), 0, s, T, n, P1, P2, anc, tot1, tot2);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_perm(const BatchArgs &a, int mode, uint64_t seed, int64_t max_nblocks, hipStream_t s) {
+    int64_t bx = (max_nblocks + 255) / 256;
+    if (bx > 1024) bx = 1024;
+    hipLaunchKernelGGL(k_make_perm, dim3((unsigned)bx, (unsigned)a.nq), dim3(256), 0, s, a, mode, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_seed_random, dim3(1), dim3(256), 0, s, a, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int blocks,
+                           hipStream_t s) {
+    if (prefix)
+        hipLaunchKernelGGL(k_lb_batch<true>, dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi);
+    else
+        hipLaunchKernelGGL(k_lb_batch<false>, dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_segments(const BatchArgs &a, int num_cu, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_seg_scatter, dim3(num_cu * 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <bool PREFIX>
+static hipError_t launch_dtw_bucket_t(const BatchArgs &a, int nc, int blocks, hipStream_t s) {
+    const dim3 g(blocks), b(256);
+    switch (nc) {
+#define DTWS_BCASE(N) \
+    case N: hipLaunchKernelGGL((k_dtw_batch<N, PREFIX>), g, b, 0, s, a); break;
+        DTWS_BCASE(1) DTWS_BCASE(2) DTWS_BCASE(3) DTWS_BCASE(4) DTWS_BCASE(5) DTWS_BCASE(6) DTWS_BCASE(7)
+        DTWS_BCASE(8) DTWS_BCASE(9) DTWS_BCASE(10) DTWS_BCASE(11) DTWS_BCASE(12) DTWS_BCASE(13) DTWS_BCASE(14)
+#undef DTWS_BCASE
+        case kMaxChunks + 1: {
+            const int64_t wblocks = a.wide_lanes / 64;
+            hipLaunchKernelGGL(k_dtw_batch_wide<PREFIX>, dim3((unsigned)wblocks), dim3(64), 0, s, a);
+            break;
+        }
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dtw_bucket(const BatchArgs &a, bool prefix, int nc, int blocks, hipStream_t s) {
+    return prefix ? launch_dtw_bucket_t<true>(a, nc, blocks, s) : launch_dtw_bucket_t<false>(a, nc, blocks, s);
+}
+
+hipError_t launch_cert_batch(const BatchArgs &a, int max_m, int max_r, hipStream_t s) {
+    hipLaunchKernelGGL(k_cert_select_batch, dim3(16), dim3(256), 0, s, a);
+    const size_t shm = sizeof(double) * (2 * (size_t)max_m + 3 * (size_t)(max_r + 4));
+    hipLaunchKernelGGL(k_cert_dtw_batch, dim3(256), dim3(max_r < 64 ? 64 : 256), shm, s, a);
+    hipLaunchKernelGGL(k_cert_reduce_batch, dim3(a.nq), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace dtws

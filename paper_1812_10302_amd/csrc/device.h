@@ -1,0 +1,365 @@
+// Device helpers shared by the plain and the batched search kernels.
+#pragma once
+#include <utility>
+
+#include "dtws_internal.h"
+
+namespace dtws {
+
+// ---------------------------------------------------------------- wave utilities
+__device__ inline unsigned long long wave_add_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline unsigned long long wave_add(unsigned long long v) { return wave_add_u64(v); }
+
+__device__ inline uint64_t lanemask_lt() {
+    const int lane = threadIdx.x & 63;
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Orders the LDS traffic of one wave (for structures private to a wave).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Query-side arrays never change during a launch: reading them through the constant address
+// space lets the compiler use scalar loads for wave-uniform positions.
+template <class T>
+__device__ __forceinline__ T ldc(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
+__device__ inline float load_bsf(const uint64_t *key) {
+    return key_dist(__atomic_load_n(key, __ATOMIC_RELAXED));
+}
+
+// ---------------------------------------------------------------- bound terms
+// Query side of the bounds: positions in visiting order (decreasing |qhat|), padded with neutral
+// terms to a multiple of 16.
+struct QView {
+    const int32_t *order;
+    const float *Us, *Ls, *qs;
+    int m, mpad;
+};
+
+// One block of 16 query-envelope terms (eq. (LBKeoghEC)) starting at k0, a multiple of 16: all
+// 16 series loads are issued before any use, so a wave waits for one memory round trip.
+__device__ inline float keogh_q_block(const QView &v, const float *Ti, float mu, float s, float o, float kq,
+                                      int k0) {
+    float t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = Ti[ldc(v.order + k0 + u)];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const float c = fmaf(t[u] - mu, s, o);
+        const float e = fmaxf(fmaxf(c - ldc(v.Us + k0 + u), ldc(v.Ls + k0 + u) - c), 0.0f);
+        kq = fmaf(e, e, kq);
+    }
+    return kq;
+}
+
+__device__ inline float keogh_q_terms(const QView &v, const float *Ti, float mu, float s, float o, float kq, int k0,
+                                      int k1, bool early, float thr) {
+    for (int k = k0; k < k1; k += 16) {
+        kq = keogh_q_block(v, Ti, mu, s, o, kq, k);
+        if (early && kq > thr) break;
+    }
+    return kq;
+}
+
+// The query against the data envelope (eq. (LBKeoghEQ)), early abandoning per 16 terms.
+__device__ inline float keogh_d(const QView &v, const float *Ui, const float *Li, float mu, float s, float o,
+                                float thr) {
+    float kd = 0.0f;
+    for (int k0 = 0; k0 < v.mpad; k0 += 16) {
+        float u[16], l[16];
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const int j = ldc(v.order + k0 + w);
+            u[w] = Ui[j];
+            l[w] = Li[j];
+        }
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const float uu = fmaf(u[w] - mu, s, o), ll = fmaf(l[w] - mu, s, o);
+            const float q = ldc(v.qs + k0 + w);
+            const float e = fmaxf(fmaxf(q - uu, ll - q), 0.0f);
+            kd = fmaf(e, e, kd);
+        }
+        if (kd > thr) break;
+    }
+    return kd;
+}
+
+// ---------------------------------------------------------------- wave-private queues
+constexpr int kQCap = 128;   // power of two, >= 2 * 64
+constexpr int kK0 = 16, kK1 = 64;
+
+struct WaveQueue {
+    int32_t idx[kQCap];
+    float kq[kQCap], mu[kQCap], s[kQCap], o[kQCap];
+};
+
+__device__ inline void q_push(WaveQueue &q, uint32_t &tail, bool pred, int32_t i, float kq, float mu, float s,
+                              float o) {
+    const uint64_t mask = __ballot(pred);
+    if (pred) {
+        const uint32_t p = (tail + (uint32_t)__popcll(mask & lanemask_lt())) & (kQCap - 1);
+        q.idx[p] = i;
+        q.kq[p] = kq;
+        q.mu[p] = mu;
+        q.s[p] = s;
+        q.o[p] = o;
+    }
+    tail += (uint32_t)__popcll(mask);
+    wave_sync();
+}
+
+// Pops up to 64 entries (one per lane); returns whether this lane got one.
+__device__ inline bool q_pop(WaveQueue &q, uint32_t &head, uint32_t tail, int32_t &i, float &kq, float &mu,
+                             float &s, float &o) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t avail = tail - head;
+    const uint32_t take = avail < 64u ? avail : 64u;
+    const bool got = (uint32_t)lane < take;
+    const uint32_t p = (head + lane) & (kQCap - 1);
+    if (got) {
+        i = q.idx[p];
+        kq = q.kq[p];
+        mu = q.mu[p];
+        s = q.s[p];
+        o = q.o[p];
+    }
+    head += take;
+    wave_sync();
+    return got;
+}
+
+// ---------------------------------------------------------------- cascade over a candidate range
+struct CascadeCounts {
+    uint32_t kim = 0, kq = 0, kd = 0;
+};
+
+// Runs the bound cascade on groups of 64 consecutive candidates g, g + gstep, ... below `last`
+// (one wave).  Level 0 (coalesced, uniform): LB_KimFL and the first K0 query-envelope terms.
+// Survivors are compacted into the wave's LDS queue q1; full batches of 64 run the terms up to
+// K1 (level 1) and their survivors go to q2, whose full batches run the remaining terms with
+// early abandoning and then the data-envelope bound (level 2, if envU is set).  Candidates that
+// pass everything go to emit(alive, i).  A scheduler that is uniform across the wave serves a
+// full q2 batch first, then a full q1 batch, then a new group, so a queue never holds 64 or more
+// entries when a push can reach it; at the end both queues are drained.
+//   stats(i, mu, s, o): normalisation parameters of candidate i.
+template <class Stats, class Emit>
+__device__ __forceinline__ void cascade(const QView &v, const float *T, const float *envU, const float *envL,
+                                        float thr, float q0, float ql, int64_t g, int64_t gstep, int64_t last,
+                                        WaveQueue &q1, WaveQueue &q2, const Stats &stats, const Emit &emit,
+                                        CascadeCounts &cnt) {
+    const int lane = threadIdx.x & 63;
+    const int m = v.m, mpad = v.mpad;
+    const int K0 = mpad < kK0 ? mpad : kK0, K1 = mpad < kK1 ? mpad : kK1;
+    uint32_t h1 = 0, t1 = 0, h2 = 0, t2 = 0;
+    bool done = false;
+    for (;;) {
+        if (t2 - h2 >= 64u || (done && t2 != h2)) {
+            int32_t i = 0;
+            float kq = 0.f, mu = 0.f, s = 0.f, o = 0.f;
+            const bool got = q_pop(q2, h2, t2, i, kq, mu, s, o);
+            bool alive = got;
+            if (got) {
+                kq = keogh_q_terms(v, T + i, mu, s, o, kq, K1, mpad, true, thr);
+                if (kq > thr) {
+                    alive = false;
+                    ++cnt.kq;
+                }
+            }
+            if (alive && envU) {
+                const float kd = keogh_d(v, envU + i, envL + i, mu, s, o, thr);
+                if (kd > thr) {
+                    alive = false;
+                    ++cnt.kd;
+                }
+            }
+            emit(alive, i);
+            continue;
+        }
+        if (t1 - h1 >= 64u || (done && t1 != h1)) {
+            int32_t i = 0;
+            float kq = 0.f, mu = 0.f, s = 0.f, o = 0.f;
+            const bool got = q_pop(q1, h1, t1, i, kq, mu, s, o);
+            bool alive = got;
+            if (got && K1 > K0) {
+                kq = keogh_q_terms(v, T + i, mu, s, o, kq, K0, K1, false, thr);
+                if (kq > thr) {
+                    alive = false;
+                    ++cnt.kq;
+                }
+            }
+            q_push(q2, t2, alive, i, kq, mu, s, o);
+            continue;
+        }
+        if (done) break;
+        if (g >= last) {
+            done = true;
+            continue;
+        }
+        const int64_t i = g + lane;
+        const bool valid = i < last;
+        const int64_t ii = valid ? i : g;      // idle lanes reuse the group's first start
+        float mu, s, o;
+        stats(ii, mu, s, o);
+        const float *Ti = T + ii;
+        const float c0 = fmaf(Ti[0] - mu, s, o), cl = fmaf(Ti[m - 1] - mu, s, o);
+        const float d0 = q0 - c0, dl = ql - cl;
+        const float kim = fmaf(d0, d0, dl * dl);
+        bool alive = valid && !(kim > thr);
+        if (valid && !alive) ++cnt.kim;
+        float kq = 0.0f;
+        if (__ballot(alive)) {
+            kq = keogh_q_terms(v, Ti, mu, s, o, 0.0f, 0, K0, false, thr);
+            if (alive && kq > thr) {
+                alive = false;
+                ++cnt.kq;
+            }
+        }
+        q_push(q1, t1, alive, (int32_t)ii, kq, mu, s, o);
+        g += gstep;
+    }
+}
+
+// ---------------------------------------------------------------- DTW column machinery
+
+template <int KK>
+__device__ __forceinline__ float row_bcast(float v) {
+    // DPP row_newbcast:KK -- every lane of a 16-lane row reads lane KK of that row; written as
+    // update_dpp(old=0, bound_ctrl) so that the compiler folds it into the consuming v_sub_f32_dpp
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + KK, 0xF, 0xF, true));
+}
+
+template <int I, int N, int NC>
+__device__ __forceinline__ void cell(float (&a)[N], const float (&q)[NC], float c, float &below) {
+    const float diff = row_bcast<(I & 15)>(q[I >> 4]) - c;
+    const float mn = fminf(fminf(a[I], a[I + 1]), below);
+    const float v = fmaf(diff, diff, mn);
+    a[I] = v;
+    below = v;
+}
+
+template <int NC, int... I>
+__device__ __forceinline__ void column_impl(float (&a)[16 * NC + 1], const float (&q)[NC], float c,
+                                            std::integer_sequence<int, I...>) {
+    float below = INFINITY;
+    (cell<I, 16 * NC + 1, NC>(a, q, c, below), ...);
+}
+
+template <int NC>
+__device__ __forceinline__ void column(float (&a)[16 * NC + 1], const float (&q)[NC], float c) {
+    column_impl<NC>(a, q, c, std::make_integer_sequence<int, 16 * NC>{});
+}
+
+
+// Band cells of columns [0, J) of an m x m DP with band r.
+__device__ inline unsigned long long band_cells(int m, int r, int J) {
+    long long cells = (long long)J * (2 * r + 1);
+    const long long lower = J <= r ? (long long)J * r - (long long)J * (J - 1) / 2 : (long long)r * (r + 1) / 2;
+    const long long ex = (long long)J - (m - r);
+    const long long upper = ex > 0 ? ex * (ex + 1) / 2 : 0;
+    return (unsigned long long)(cells - lower - upper);
+}
+
+// Per-lane normalisation of the window at `start`: two-pass FP64 mean and sigma.
+__device__ inline void lane_stats(const float *w, int m, float &mu, float &s, float &o) {
+    double sum = 0.0;
+    for (int j = 0; j < m; ++j) sum += (double)w[j];
+    const double mu64 = sum / m;
+    double v = 0.0;
+    for (int j = 0; j < m; ++j) {
+        const double d = (double)w[j] - mu64;
+        v += d * d;
+    }
+    const double sigma = sqrt(v / m);
+    const double inv = sigma <= kSigmaFlat ? 0.0 : 1.0 / sigma;
+    mu = (float)mu64;
+    s = (float)inv;
+    o = (float)(-(mu64 - (double)mu) * inv);
+}
+
+
+
+// Banded DTW of one candidate per lane (register kernel; see dtw.hip).  qpad: the query's sentinel-padded
+// normalised values; key: best-so-far key read for abandoning (null: use thr0 only).  Returns the
+// distance in D and whether the lane stayed within the threshold; jdead is the number of columns
+// completed before abandoning and jrun the number of columns the wave executed.
+template <int NC>
+__device__ __forceinline__ void dtw_lanes(const float *T, int64_t start, float mu, float s, float o,
+                                          const float *qpad, int m, int r, bool live, const uint64_t *key,
+                                          float thr0, bool &alive, float &D, int &jdead, int &jrun) {
+    constexpr int W = 16 * NC;
+    constexpr int R = 8 * NC - 1;
+    const int ql = threadIdx.x & 15;
+    // per-chunk offset into the padded query: in-band cells read q_{j-R+k}, the others read the
+    // sentinel at the start of the padding (offset + j stays below kQPad for every column)
+    int qoff[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+        const int kpos = 16 * cc + ql;
+        qoff[cc] = (kpos >= R - r && kpos <= R + r) ? kQPad - R + kpos : 0;
+    }
+    float arr[W + 1];
+#pragma unroll
+    for (int x = 0; x <= W; ++x) arr[x] = INFINITY;
+    arr[R] = 0.0f;   // d(-1,-1) of the virtual column before column 0
+    float thr = key ? fminf(thr0, threshold_of(load_bsf(key))) : thr0;
+    alive = live;
+    jdead = m;
+    const float *Tp = T + start;
+    float tcur = Tp[0];
+    float qcur[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) qcur[cc] = qpad[qoff[cc]];
+    int j = 0;
+    for (; j < m; ++j) {
+        const int jn = j + 1 < m ? j + 1 : j;
+        const float tnext = Tp[jn];
+        float qnext[NC];
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) qnext[cc] = qpad[qoff[cc] + jn];
+        const float c = fmaf(tcur - mu, s, o);
+        column<NC>(arr, qcur, c);
+        tcur = tnext;
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) qcur[cc] = qnext[cc];
+        if ((j & 15) == 15) {
+            float mn = arr[0];
+#pragma unroll
+            for (int x = 1; x < W; ++x) mn = fminf(mn, arr[x]);
+            if (key) thr = fminf(thr0, threshold_of(load_bsf(key)));
+            if (alive && mn > thr) {
+                alive = false;
+                jdead = j + 1;
+            }
+            if (__ballot(alive) == 0) {
+                ++j;
+                break;
+            }
+        }
+    }
+    jrun = j;
+    D = arr[R];
+    if (alive && !(D <= thr)) alive = key ? false : alive;   // search mode keeps only improvements
+}
+
+// Normalisation parameters of a candidate from FP64 mean and sigma (eq. (Normalization1)):
+// c_j = fma(T[i+j] - mu32, s, o) with s = 1/sigma (0 for a flat window), o = -(mu - mu32) * s.
+__device__ inline void norm_params(double mu, double sigma, float &mu32, float &s, float &o) {
+    const double inv = sigma <= kSigmaFlat ? 0.0 : 1.0 / sigma;
+    mu32 = (float)mu;
+    s = (float)inv;
+    o = (float)(-(mu - (double)mu32) * inv);
+}
+
+}  // namespace dtws

@@ -20,100 +20,22 @@
 // warping path crosses every column and costs are non-negative.
 #include <utility>
 
-#include "dtws_internal.h"
+#include "device.h"
 
 namespace dtws {
 
 
 
-namespace {
-
-template <int KK>
-__device__ __forceinline__ float row_bcast(float v) {
-    // DPP row_newbcast:KK -- every lane of a 16-lane row reads lane KK of that row; written as
-    // update_dpp(old=0, bound_ctrl) so that the compiler folds it into the consuming v_sub_f32_dpp
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + KK, 0xF, 0xF, true));
-}
-
-template <int I, int N, int NC>
-__device__ __forceinline__ void cell(float (&a)[N], const float (&q)[NC], float c, float &below) {
-    const float diff = row_bcast<(I & 15)>(q[I >> 4]) - c;
-    const float mn = fminf(fminf(a[I], a[I + 1]), below);
-    const float v = fmaf(diff, diff, mn);
-    a[I] = v;
-    below = v;
-}
-
-template <int NC, int... I>
-__device__ __forceinline__ void column_impl(float (&a)[16 * NC + 1], const float (&q)[NC], float c,
-                                            std::integer_sequence<int, I...>) {
-    float below = INFINITY;
-    (cell<I, 16 * NC + 1, NC>(a, q, c, below), ...);
-}
-
-template <int NC>
-__device__ __forceinline__ void column(float (&a)[16 * NC + 1], const float (&q)[NC], float c) {
-    column_impl<NC>(a, q, c, std::make_integer_sequence<int, 16 * NC>{});
-}
-
-__device__ inline unsigned long long wave_add(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Band cells of columns [0, J) of an m x m DP with band r.
-__device__ inline unsigned long long band_cells(int m, int r, int J) {
-    long long cells = (long long)J * (2 * r + 1);
-    const long long lower = J <= r ? (long long)J * r - (long long)J * (J - 1) / 2 : (long long)r * (r + 1) / 2;
-    const long long ex = (long long)J - (m - r);
-    const long long upper = ex > 0 ? ex * (ex + 1) / 2 : 0;
-    return (unsigned long long)(cells - lower - upper);
-}
-
-// Per-lane normalisation of the window at `start`: two-pass FP64 mean and sigma.
-__device__ inline void lane_stats(const float *w, int m, float &mu, float &s, float &o) {
-    double sum = 0.0;
-    for (int j = 0; j < m; ++j) sum += (double)w[j];
-    const double mu64 = sum / m;
-    double v = 0.0;
-    for (int j = 0; j < m; ++j) {
-        const double d = (double)w[j] - mu64;
-        v += d * d;
-    }
-    const double sigma = sqrt(v / m);
-    const double inv = sigma <= kSigmaFlat ? 0.0 : 1.0 / sigma;
-    mu = (float)mu64;
-    s = (float)inv;
-    o = (float)(-(mu64 - (double)mu) * inv);
-}
-
-__device__ inline float load_bsf(const uint64_t *key) {
-    return key_dist(__atomic_load_n(key, __ATOMIC_RELAXED));
-}
-
-}  // namespace
 
 template <int NC, bool SEARCH>
 __global__ __launch_bounds__(256) void k_dtw(DtwArgs a) {
     constexpr int W = 16 * NC;
-    constexpr int R = 8 * NC - 1;
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     int64_t count = a.single >= 0 ? 1 : (a.count_dev ? (int64_t)*a.count_dev : a.count);
     if (a.count_dev && count > a.count) count = a.count;
     const int m = a.m, r = a.r;
-    const int ql = lane & 15;
-    // per-chunk offset into the padded query: in-band cells read q_{j-R+k}, the others read the
-    // sentinel at the start of the padding (offset + j stays below kQPad for every column)
-    int qoff[NC];
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc) {
-        const int kpos = 16 * cc + ql;
-        qoff[cc] = (kpos >= R - r && kpos <= R + r) ? kQPad - R + kpos : 0;
-    }
-    const float *qp = a.qpad;
     unsigned long long n_started = 0, n_aband = 0, n_cells = 0, n_lane_cells = 0;
 
     for (int64_t base = wave * 64; base < count; base += nwaves * 64) {
@@ -136,54 +58,19 @@ __global__ __launch_bounds__(256) void k_dtw(DtwArgs a) {
         } else {
             lane_stats(a.T + start, m, mu, s, o);
         }
-        float arr[W + 1];
-#pragma unroll
-        for (int x = 0; x <= W; ++x) arr[x] = INFINITY;
-        arr[R] = 0.0f;   // d(-1,-1) of the virtual column before column 0
-        float thr = SEARCH ? threshold_of(load_bsf(a.key)) : a.abandon_at;
-        bool alive = valid && !bad;
-        int jdead = m;
-        const float *Tp = a.T + start;
-        float tcur = Tp[0];
-        float qcur[NC];
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) qcur[cc] = qp[qoff[cc]];
-        int j = 0;
-        for (; j < m; ++j) {
-            const int jn = j + 1 < m ? j + 1 : j;
-            const float tnext = Tp[jn];
-            float qnext[NC];
-#pragma unroll
-            for (int cc = 0; cc < NC; ++cc) qnext[cc] = qp[qoff[cc] + jn];
-            const float c = fmaf(tcur - mu, s, o);
-            column<NC>(arr, qcur, c);
-            tcur = tnext;
-#pragma unroll
-            for (int cc = 0; cc < NC; ++cc) qcur[cc] = qnext[cc];
-            if ((j & 15) == 15) {
-                float mn = arr[0];
-#pragma unroll
-                for (int x = 1; x < W; ++x) mn = fminf(mn, arr[x]);
-                if (SEARCH) thr = threshold_of(load_bsf(a.key));
-                if (alive && mn > thr) {
-                    alive = false;
-                    jdead = j + 1;
-                }
-                if (__ballot(alive) == 0) {
-                    ++j;
-                    break;
-                }
-            }
-        }
-        n_lane_cells += (unsigned long long)j * W;
-        const float D = arr[R];
+        bool alive;
+        float D;
+        int jdead, jrun;
+        dtw_lanes<NC>(a.T, start, mu, s, o, a.qpad, m, r, valid && !bad, SEARCH ? a.key : nullptr,
+                      SEARCH ? INFINITY : a.abandon_at, alive, D, jdead, jrun);
+        n_lane_cells += (unsigned long long)jrun * W;
         if (SEARCH) {
             if (valid && !bad) {
                 ++n_started;
-                if (!alive) ++n_aband;
-                n_cells += band_cells(m, r, alive ? m : jdead);
+                if (jdead < m) ++n_aband;
+                n_cells += band_cells(m, r, jdead);
             }
-            if (valid && !bad && alive && D <= thr) {
+            if (valid && !bad && alive) {
                 atomicMin((unsigned long long *)a.key, (unsigned long long)pack_key(D, (uint32_t)start));
                 const uint32_t pos = atomicAdd(a.nb_count, 1u);
                 if (pos < (uint32_t)kNearBestCap) {

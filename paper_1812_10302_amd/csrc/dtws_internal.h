@@ -42,6 +42,15 @@ struct QueryBufs {
 };
 
 
+// Per-query parameters of a batch (device array, one entry per query).
+struct BatchQ {
+    int64_t qoff;      // first element of the query in the packed query array
+    int64_t N;         // candidates n - m + 1
+    int32_t m, r;      // length and band (r clamped to m - 1)
+    int32_t nc;        // DTW bucket: register chunks (1..kMaxChunks), kMaxChunks + 1 = wide band
+    int32_t nblocks;   // work items: ceil(N / block)
+};
+
 // ---------------------------------------------------------------- kernel arguments
 struct LbArgs {
     const float *T;
@@ -97,8 +106,58 @@ struct CertArgs {
     unsigned long long *counters;
 };
 
+struct BatchArgs {
+    const float *T;
+    int64_t n;
+    int nq;
+    int64_t block;             // candidates per work item
+    int max_m;
+    const BatchQ *bq;
+    const float *qpad;         // per query, stride qstride
+    int64_t qstride;
+    const double *qhat64;      // per query, stride max_m
+    const int32_t *order;      // per query, stride mstride (16-padded visiting order)
+    const float *Us, *Ls, *qs;
+    int64_t mstride;
+    uint64_t *keys;            // best-so-far per query
+    // window statistics: per-window arrays (all queries share m) or the blocked prefix
+    const float *mu, *s, *o;
+    const double *P1, *P2, *anc, *tot1, *tot2;
+    const float *envU, *envL;  // data envelope for the largest band of the batch, or null
+    // work queue
+    int32_t *perm;             // per query: block visiting order, stride maxblocks
+    int64_t maxblocks;
+    uint32_t *heads;           // per round
+    // survivors of the bound cascade, then sorted into per-query wave segments
+    int32_t *surv_q, *surv_i;
+    uint32_t *surv_count, *qcnt, *overflow;
+    int64_t surv_cap;
+    int32_t *sorted;
+    int32_t *qorder, *wstart;
+    int64_t *seg_off;
+    uint32_t *fill;
+    int32_t *bucket_w, *bucket_j;
+    // near-best list and certification
+    float *nb_d;
+    uint32_t *nb_idx;
+    int32_t *nb_q;
+    uint32_t *nb_count;
+    uint32_t *cert_idx;
+    int32_t *cert_q;
+    uint32_t *cert_count;
+    double *cert_d;
+    int64_t *res_idx;
+    double *res_dist;
+    int32_t *res_status;
+    unsigned long long *counters;
+    float *wide_rows;
+    int64_t wide_lanes;
+};
+
 // ---------------------------------------------------------------- launchers (stream-ordered)
 hipError_t launch_query_prep(const float *Q, int m, int r, const QueryBufs &b, hipStream_t s);
+hipError_t launch_query_prep_batch(const float *Qp, const BatchQ *bq, int nq, const QueryBufs &base,
+                                  int64_t qstride, int64_t mstride, int64_t m64stride, hipStream_t s);
 hipError_t launch_znorm_stats(const float *T, int64_t n, int m, double *mu, double *sg, float *mu32, float *s32,
                               float *o32, hipStream_t s);
 hipError_t launch_series_env(const float *T, int64_t n, int r, float *U, float *L, hipStream_t s);
@@ -108,6 +167,15 @@ hipError_t launch_dtw(const DtwArgs &a, bool search, int64_t max_count, int num_
 hipError_t launch_bsf_update(uint64_t *keys, const float *d, const int64_t *idx, int64_t count, int num_cu,
                              hipStream_t s);
 hipError_t launch_certify(const CertArgs &c, hipStream_t s);
+hipError_t launch_prefix(const float *T, int64_t n, double *P1, double *P2, double *anc, double *tot1,
+                         double *tot2, hipStream_t s);
+hipError_t launch_make_perm(const BatchArgs &a, int mode, uint64_t seed, int64_t max_nblocks, hipStream_t s);
+hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s);
+hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int blocks,
+                           hipStream_t s);
+hipError_t launch_segments(const BatchArgs &a, int num_cu, hipStream_t s);
+hipError_t launch_dtw_bucket(const BatchArgs &a, bool prefix, int nc, int blocks, hipStream_t s);
+hipError_t launch_cert_batch(const BatchArgs &a, int max_m, int max_r, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
 // key of an empty best-so-far: distance +inf, index 0xFFFFFFFF
@@ -150,6 +218,19 @@ struct dtws_ctx {
     unsigned long long *counters = nullptr;  // device [8]
     float *gen_rows = nullptr;            // scratch for the wide-band DTW kernel
     int64_t gen_lanes = 0;
+    // batched search
+    dtws::BatchQ *bq = nullptr, *h_bq = nullptr;   // device / pinned host, max_q entries
+    double *P1 = nullptr, *P2 = nullptr;     // blocked prefix, max_n + 1 entries
+    double *anc = nullptr, *tot1 = nullptr, *tot2 = nullptr;
+    int32_t *perm = nullptr;
+    int64_t maxblocks = 0;
+    uint32_t *heads = nullptr;
+    int32_t *surv_q = nullptr, *surv_i = nullptr, *sorted = nullptr;
+    int64_t bsurv_cap = 0;
+    uint32_t *qcnt = nullptr, *fill = nullptr, *overflow = nullptr;
+    int32_t *qorder = nullptr, *wstart = nullptr, *bucket_w = nullptr, *bucket_j = nullptr;
+    int64_t *seg_off = nullptr;
+    int32_t *nb_q = nullptr, *cert_q = nullptr;
     // pinned host staging
     int64_t *h_idx = nullptr;
     double *h_dist = nullptr;

@@ -40,7 +40,7 @@ __device__ inline bool before(float ka, int ia, float kb, int ib) {
 }  // namespace
 
 // ------------------------------------------------------------------ query preparation
-__global__ __launch_bounds__(1024) void k_query_prep(const float *__restrict__ Q, int m, int r, QueryBufs b) {
+__device__ void query_prep_body(const float *__restrict__ Q, int m, int r, const QueryBufs &b) {
     __shared__ double red[16];
     __shared__ float qh[kMaxM];
     __shared__ float U[kMaxM], L[kMaxM];
@@ -123,6 +123,26 @@ __global__ __launch_bounds__(1024) void k_query_prep(const float *__restrict__ Q
         b.Usorted[k] = INFINITY;
         b.Lsorted[k] = -INFINITY;
     }
+}
+
+__global__ __launch_bounds__(1024) void k_query_prep(const float *__restrict__ Q, int m, int r, QueryBufs b) {
+    query_prep_body(Q, m, r, b);
+}
+
+// One block per query of a batch: query k is Qp[qoff[k] .. qoff[k] + m_k).
+__global__ __launch_bounds__(1024) void k_query_prep_batch(const float *__restrict__ Qp, const BatchQ *bq,
+                                                           QueryBufs base, int64_t qstride, int64_t mstride,
+                                                           int64_t m64stride) {
+    const int k = blockIdx.x;
+    const BatchQ q = bq[k];
+    QueryBufs b;
+    b.qpad = base.qpad + k * qstride;
+    b.qhat64 = base.qhat64 + k * m64stride;
+    b.qsorted = base.qsorted + k * mstride;
+    b.Usorted = base.Usorted + k * mstride;
+    b.Lsorted = base.Lsorted + k * mstride;
+    b.order = base.order + k * mstride;
+    query_prep_body(Qp + q.qoff, q.m, q.r, b);
 }
 
 // ------------------------------------------------------------------ window statistics
@@ -323,6 +343,12 @@ __global__ __launch_bounds__(kEnvThreads) void k_series_env(const float *__restr
 // ------------------------------------------------------------------ host launchers
 hipError_t launch_query_prep(const float *Q, int m, int r, const QueryBufs &b, hipStream_t s) {
     hipLaunchKernelGGL(k_query_prep, dim3(1), dim3(1024), 0, s, Q, m, r, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_prep_batch(const float *Qp, const BatchQ *bq, int nq, const QueryBufs &base,
+                                  int64_t qstride, int64_t mstride, int64_t m64stride, hipStream_t s) {
+    hipLaunchKernelGGL(k_query_prep_batch, dim3(nq), dim3(1024), 0, s, Qp, bq, base, qstride, mstride, m64stride);
     return hipGetLastError();
 }
 

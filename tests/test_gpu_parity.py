@@ -219,3 +219,49 @@ def test_search_batch_equals_single(ctx):
     for q, r, got in zip(qs, rs, batch):
         single = ctx.search(Td, dev(q), r)
         assert got[0] == single[0] and got[1] == pytest.approx(single[1], rel=1e-12)
+
+
+# --------------------------------------------------------------------- batched search
+def _cascade_refs(casc, T, qs, rs):
+    return [casc.search(T, q, r)[:2] for q, r in zip(qs, rs)]
+
+
+def _check_batch(got, ref):
+    for k, ((gi, gd), (ri, rd)) in enumerate(zip(got, ref)):
+        assert gi == ri, (k, gi, ri, gd, rd)
+        assert abs(gd - rd) <= 1e-9 * rd + 1e-12, (k, gd, rd)
+
+
+def test_batch_mixed_lengths_and_bands(ctx, casc):
+    """Different m per query: window statistics from the blocked prefix; one wide band (r > 111)."""
+    T = W.random_walk(150_001, 31)
+    specs = [(16, 1), (40, 0), (64, 6), (100, 10), (128, 6), (200, 20), (300, 150), (512, 25), (65, 64), (128, 0),
+             (777, 38), (2048, 102)]
+    qs, rs = [], []
+    for k, (m, r) in enumerate(specs):
+        src = (9_973 * (k + 1)) % (T.size - m)
+        qs.append(W.noisy_cut(T, src, m, 0.1, 500 + k) if k % 3 else W.random_walk(m, 600 + k))
+        rs.append(r)
+    got = ctx.search_batch(dev(T), [dev(q) for q in qs], rs)
+    _check_batch(got, _cascade_refs(casc, T, qs, rs))
+
+
+def test_batch_shared_length(ctx, casc):
+    """All queries of one length: per-window statistics arrays shared by the batch."""
+    T = W.random_walk(300_000, 32)
+    qs = [W.noisy_cut(T, 1_000 + 29_000 * k, 128, 0.1, 700 + k) for k in range(10)]
+    rs = [6] * 10
+    got = ctx.search_batch(dev(T), [dev(q) for q in qs], rs)
+    _check_batch(got, _cascade_refs(casc, T, qs, rs))
+
+
+def test_batch_order_invariance(ctx):
+    """Natural order and seeded random block orders give identical results."""
+    T = W.random_walk(400_000, 33)
+    qs = [W.noisy_cut(T, 3_000 + 51_000 * k, m, 0.1, 800 + k) for k, m in enumerate((64, 128, 256, 128, 512))]
+    rs = [3, 6, 12, 0, 25]
+    Td = dev(T)
+    Qd = [dev(q) for q in qs]
+    base = ctx.search_batch(Td, Qd, rs)
+    for seed in (1, 2, 3):
+        assert ctx.search_batch(Td, Qd, rs, flags=dtws.ORDER_RANDOM, seed=seed) == base
