@@ -70,68 +70,80 @@ def main():
     ctx = dtws.Context(0, max_n=wl.T.size, max_m=max(ms), max_queries=nq)
     torch.cuda.synchronize()
 
-    def step(flags=0):
-        res = []
-        for q, r in zip(Qs, rs):
-            res.append(ctx.search(T, q, r, flags=flags, seed=7))
-        return res
+    # ---------------------------------------------------------------- plain: one query at a time
+    def plain_step(flags=0):
+        return [ctx.search(T, q, r, flags=flags, seed=7) for q, r in zip(Qs, rs)]
 
     for _ in range(args.warmup):
-        step()
+        plain_step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     per_query = []
     for _ in range(args.steps):
         for q, r in zip(Qs, rs):
             a = time.perf_counter()
-            out = ctx.search(T, q, r, seed=7)
+            ctx.search(T, q, r, seed=7)
             per_query.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t1) / args.steps / nq
+    plain_results = plain_step()
+
+    # ---------------------------------------------------------------- batched: all queries, graph replay
+    pq = dtws.PackedQueries(Qs)
+    bflags = 0
+
+    def batch_step(flags=0):
+        return ctx.search_batch(T, pq, rs, flags=bflags | flags, seed=7)
+
+    for _ in range(max(1, args.warmup)):
+        batch_step()             # the first call captures the graph
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        results = batch_step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t1
     ms_per_step = elapsed / args.steps * 1e3
     s_per_query = elapsed / args.steps / nq
-    results = step()
-    log("results:", results)
+    log("plain:", plain_results)
+    log("batched:", results)
+    assert [i for i, _ in results] == [i for i, _ in plain_results], "batched and plain disagree"
 
-    # ---------------------------------------------------------------- profiled pass
-    prof_total = {k: [0.0, 0] for k in dtws.KERNEL_CLASSES}
-    cnt_total = {}
-    dtw_cells = 0
-    dtw_lane_cells = 0
-    lb_candidates = 0
+    # ---------------------------------------------------------------- profiled passes
+    def profiled(run):
+        run()
+        p = ctx.profile()
+        return {k: [v[0], v[1]] for k, v in p.items()}, ctx.counters()
+
+    prof_total, cnt_total = {k: [0.0, 0] for k in dtws.KERNEL_CLASSES}, {}
     per_query_prof = []
     if not args.no_profile:
+        prof_total, cnt_total = profiled(lambda: batch_step(dtws.PROFILE))
         for q, r in zip(Qs, rs):
-            ctx.search(T, q, r, flags=dtws.PROFILE, seed=7)
-            p = ctx.profile()
-            c = ctx.counters()
-            per_query_prof.append({"m": int(q.numel()), "r": int(r), "kernel_ms": {k: round(v[0], 4) for k, v in p.items()},
-                                   "counters": c})
-            for k, (t, nl) in p.items():
-                prof_total[k][0] += t
-                prof_total[k][1] += nl
-            for k, v in c.items():
-                cnt_total[k] = cnt_total.get(k, 0) + v
-            dtw_cells += c["dtw_cells"]
-            dtw_lane_cells += c["dtw_lane_cells"]
-            lb_candidates += c["candidates"]
+            kp, c = profiled(lambda: ctx.search(T, q, r, flags=dtws.PROFILE, seed=7))
+            per_query_prof.append({"m": int(q.numel()), "r": int(r),
+                                   "plain_kernel_ms": {k: round(v[0], 4) for k, v in kp.items()}, "counters": c})
+    dtw_cells = cnt_total.get("dtw_cells", 0)
+    dtw_lane_cells = cnt_total.get("dtw_lane_cells", 0)
+    lb_candidates = cnt_total.get("candidates", 0)
     dominant = max(prof_total, key=lambda k: prof_total[k][0])
     roofline = None
     if not args.no_profile:
         t_ms, nl = prof_total[dominant]
         if dominant == "dtw":
             ach = dtw_cells / (t_ms * 1e-3) / 1e9
-            roofline = {"bound": "alu", "kernel": "k_dtw", "achieved": round(ach, 2), "peak": round(DTW_PEAK_GCUPS, 1),
-                        "unit": "GCUPS", "frac": round(ach / DTW_PEAK_GCUPS, 4), "traffic": None,
-                        "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl,
+            roofline = {"bound": "alu", "kernel": "k_dtw_batch", "achieved": round(ach, 2),
+                        "peak": round(DTW_PEAK_GCUPS, 1), "unit": "GCUPS", "frac": round(ach / DTW_PEAK_GCUPS, 4),
+                        "traffic": None, "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl,
                         "issued_frac": round(dtw_lane_cells / (t_ms * 1e-3) / 1e9 / DTW_PEAK_GCUPS, 4)}
         else:
-            # streaming kernels: algorithmic bytes = 4 B of series + 12 B of window statistics per
-            # candidate (lb), 4 B read + 12 B written (stats), 4 B read + 8 B written (env)
-            per_cand = {"lb": 16, "stats": 16, "env": 12}.get(dominant, 16)
+            # streaming kernels: algorithmic bytes per candidate = series point 4 B + window
+            # statistics (prefix: 4 x 8 B; shared-length arrays: 12 B) for the cascade
+            per_cand = {"lb": 36, "stats": 20, "env": 12}.get(dominant, 36)
             ach = lb_candidates * per_cand / (t_ms * 1e-3) / 1e9
-            roofline = {"bound": "hbm", "kernel": f"k_{dominant}", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            roofline = {"bound": "hbm", "kernel": f"k_{dominant}_batch" if dominant == "lb" else f"k_{dominant}",
+                        "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                         "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
 
     # ---------------------------------------------------------------- CPU baseline (oracle)
@@ -163,15 +175,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": int(wl.T.size), "m": ms, "r": rs, "mode": "plain",
+        "config": {"workload": wl.name, "n": int(wl.T.size), "m": ms, "r": rs, "mode": "batched",
                    "note": wl.note},
+        "plain_s_per_query": round(plain_s, 6),
+        "batched_over_plain": round(s_per_query / plain_s, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "per_query_s": [round(float(np.median(per_query[i::nq])), 6) for i in range(nq)],
-        "kernel_ms": {k: [round(v[0], 4), v[1]] for k, v in prof_total.items()},
+        "plain_per_query_s": [round(float(np.median(per_query[i::nq])), 6) for i in range(nq)],
+        "batched_kernel_ms": {k: [round(v[0], 4), v[1]] for k, v in prof_total.items()},
         "dtw_gcups": round(dtw_cells / (prof_total["dtw"][0] * 1e-3) / 1e9, 2) if prof_total["dtw"][0] > 0 else None,
+        "dtw_frac_valu_peak": round(dtw_cells / (prof_total["dtw"][0] * 1e-3) / 1e9 / DTW_PEAK_GCUPS, 4)
+        if prof_total["dtw"][0] > 0 else None,
         "counters": cnt_total,
-        "per_query_profile": per_query_prof,
+        "plain_profile": per_query_prof,
         "results": [[int(i), float(d)] for i, d in results],
     }
     print(json.dumps(out), flush=True)

@@ -64,6 +64,8 @@ enum dtws_status {
 #define DTWS_PROFILE 8u              /* time every kernel with HIP events on the call's stream
                                         (adds an event pair per launch); see dtws_get_profile     */
 
+#define DTWS_NO_GRAPH 16u            /* batched calls: enqueue eagerly instead of replaying a graph */
+
 /* Kernel classes reported by dtws_get_profile. */
 enum dtws_kernel_class {
     DTWS_K_PREP = 0,    /* query normalisation, envelope, visiting order        */

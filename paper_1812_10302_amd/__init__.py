@@ -24,6 +24,7 @@ OK, EINVAL, ENOMEM, ENODEV, EHIP, EOVERFLOW, ENOMODEL = 0, -1, -2, -3, -4, -5, -
 ORDER_NATURAL, ORDER_RANDOM, ORDER_LEARNED = 0, 1, 2
 NO_LOWER_BOUNDS = 4
 PROFILE = 8
+NO_GRAPH = 16
 KERNEL_CLASSES = ("prep", "stats", "env", "lb", "dtw", "cert", "other")
 MAX_M = 2048
 
@@ -128,6 +129,23 @@ def _stream(t):
     return ctypes.c_void_p(_torch().cuda.current_stream(t.device).cuda_stream)
 
 
+class PackedQueries:
+    """Queries packed back to back in one device tensor.  Reusing the same object in repeated
+    batched calls keeps every pointer stable, so the library replays its captured graph."""
+
+    def __init__(self, queries):
+        torch = _torch()
+        qs = [q.reshape(-1) for q in queries]
+        self.packed = torch.cat(qs).contiguous()
+        _dev_f32(self.packed, "queries")
+        self.ms = np.array([q.numel() for q in qs], np.int32)
+        self.offsets = np.zeros(len(qs), np.int64)
+        self.offsets[1:] = np.cumsum(self.ms.astype(np.int64))[:-1]
+
+    def __len__(self):
+        return int(self.ms.size)
+
+
 class Context:
     """A search context on one GPU; owns all device scratch (sized by max_n, max_m, max_queries)."""
 
@@ -173,20 +191,17 @@ class Context:
         return int(out.index), float(out.distance)
 
     def search_batch(self, T, queries, rs, flags: int = ORDER_NATURAL, seed: int = 0):
-        """Best matches of several queries (list of 1-D float32 tensors); returns a list of pairs."""
-        torch = _torch()
+        """Best matches of several queries (a list of 1-D float32 tensors, or PackedQueries) in one
+        batched search; returns a list of (index, distance) pairs."""
         _dev_f32(T, "T")
-        qs = [q.reshape(-1) for q in queries]
-        packed = torch.cat(qs).contiguous()
-        _dev_f32(packed, "queries")
-        nq = len(qs)
-        offs = np.zeros(nq, np.int64)
-        offs[1:] = np.cumsum([q.numel() for q in qs])[:-1]
-        ms = np.array([q.numel() for q in qs], np.int32)
+        pq = queries if isinstance(queries, PackedQueries) else PackedQueries(queries)
+        nq = len(pq)
         rr = np.array([int(x) for x in rs], np.int32)
+        if rr.size != nq:
+            raise ValueError("one band per query")
         out = (Match * nq)()
-        rc = _load().dtws_search_batch(self._h, T.data_ptr(), T.numel(), packed.data_ptr(), offs.ctypes.data,
-                                       ms.ctypes.data, rr.ctypes.data, nq, int(flags), int(seed), _stream(T),
+        rc = _load().dtws_search_batch(self._h, T.data_ptr(), T.numel(), pq.packed.data_ptr(), pq.offsets.ctypes.data,
+                                       pq.ms.ctypes.data, rr.ctypes.data, nq, int(flags), int(seed), _stream(T),
                                        ctypes.cast(out, ctypes.c_void_p))
         self._check(rc, "dtws_search_batch")
         return [(int(o.index), float(o.distance)) for o in out]

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "dtws_internal.h"
 
@@ -221,46 +222,78 @@ int fetch_counters(dtws_ctx *c, int64_t candidates, hipStream_t s) {
 
 
 // Batched pipeline (see batch.hip): all queries in rounds over a device work queue.
-int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int64_t *qoff, const int32_t *mh,
-              const int32_t *rh, int nq, uint32_t flags, uint64_t seed, hipStream_t s, dtws_match *out) {
-    const int64_t B = kDefaultBlock;
-    bool same_m = true;
+struct BatchPlan {
+    bool same_m = true;     // per-window statistics slots (few distinct lengths) instead of the prefix
+    int nm = 0, nr = 0;     // distinct lengths / bands held in slots (nr = 0: one envelope, largest band)
+    int slot_m[8] = {0}, slot_r[8] = {0};
     int max_m = 0, max_r = 0;
-    int64_t max_nb = 0, cand = 0;
+    int64_t max_nb = 0, cand = 0, block = 0;
     bool bucket_used[kMaxChunks + 2] = {false};
+};
+
+BatchPlan plan_batch(dtws_ctx *c, int64_t n, const int64_t *qoff, const int32_t *mh, const int32_t *rh, int nq) {
+    BatchPlan p;
+    p.block = c->block > 0 ? c->block : kDefaultBlock;
     for (int k = 0; k < nq; ++k) {
         BatchQ &b = c->h_bq[k];
         b.qoff = qoff[k];
         b.m = mh[k];
         b.r = rh[k] > mh[k] - 1 ? mh[k] - 1 : rh[k];
         b.N = n - b.m + 1;
-        b.nblocks = (int32_t)((b.N + B - 1) / B);
+        b.nblocks = (int32_t)((b.N + p.block - 1) / p.block);
         const int nc = (b.r + 8) / 8;
         b.nc = nc > kMaxChunks ? kMaxChunks + 1 : nc;
-        bucket_used[b.nc] = true;
-        same_m = same_m && b.m == mh[0];
-        max_m = b.m > max_m ? b.m : max_m;
-        max_r = b.r > max_r ? b.r : max_r;
-        max_nb = b.nblocks > max_nb ? b.nblocks : max_nb;
-        cand += b.N;
+        p.bucket_used[b.nc] = true;
+        p.max_m = b.m > p.max_m ? b.m : p.max_m;
+        p.max_r = b.r > p.max_r ? b.r : p.max_r;
+        p.max_nb = b.nblocks > p.max_nb ? b.nblocks : p.max_nb;
+        p.cand += b.N;
     }
-    const size_t cert_shm = sizeof(double) * (2 * (size_t)max_m + 3 * (size_t)(max_r + 4));
-    if ((flags & DTWS_NO_LOWER_BOUNDS) || cert_shm > 60 * 1024) {
-        // outside the batched pipeline's envelope: every query through the plain path
-        dtws_counters sum{};
-        int worst = DTWS_OK;
-        for (int k = 0; k < nq; ++k) {
-            const int rc = dtws_search(c, T, n, Qp + qoff[k], mh[k], rh[k], flags & ~DTWS_ORDER_MASK, seed + k, s, &out[k]);
-            if (rc != DTWS_OK && rc != DTWS_EOVERFLOW) return rc;
-            if (rc != DTWS_OK) worst = rc;
-            const int64_t *src = (const int64_t *)&c->last;
-            int64_t *dst = (int64_t *)&sum;
-            for (size_t f = 0; f < sizeof(dtws_counters) / sizeof(int64_t); ++f) dst[f] += src[f];
+    // slots for distinct lengths and bands, in order of first appearance
+    bool m_fit = true, r_fit = true;
+    for (int k = 0; k < nq; ++k) {
+        BatchQ &b = c->h_bq[k];
+        int sm = -1, sr = -1;
+        for (int t = 0; t < p.nm; ++t)
+            if (p.slot_m[t] == b.m) sm = t;
+        if (sm < 0 && m_fit) {
+            if (p.nm < c->nslots) {
+                p.slot_m[p.nm] = b.m;
+                sm = p.nm++;
+            } else {
+                m_fit = false;
+            }
         }
-        c->last = sum;
-        return worst;
+        for (int t = 0; t < p.nr; ++t)
+            if (p.slot_r[t] == b.r) sr = t;
+        if (sr < 0 && r_fit) {
+            if (p.nr < c->nslots) {
+                p.slot_r[p.nr] = b.r;
+                sr = p.nr++;
+            } else {
+                r_fit = false;
+            }
+        }
+        b.stat_slot = sm < 0 ? 0 : sm;
+        b.env_slot = sr < 0 ? 0 : sr;
     }
-    prof_begin(c, flags);
+    p.same_m = m_fit;
+    if (!r_fit) {
+        // too many distinct bands: one envelope for the largest band, valid (looser) for all
+        p.nr = 1;
+        p.slot_r[0] = p.max_r;
+        for (int k = 0; k < nq; ++k) c->h_bq[k].env_slot = 0;
+    }
+    return p;
+}
+
+// Enqueues the whole batched search on stream s without any host synchronisation, so the same
+// sequence can be captured into a graph.  Results land in the pinned host staging buffers.
+int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, const float *Qp, int nq,
+                  uint32_t flags, uint64_t seed, hipStream_t s) {
+    const bool same_m = p.same_m;
+    const int max_m = p.max_m, max_r = p.max_r;
+    const int64_t B = p.block, max_nb = p.max_nb;
     BatchArgs a{};
     a.T = T;
     a.n = n;
@@ -290,6 +323,7 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
     }
     a.envU = c->envU;
     a.envL = c->envL;
+    a.slot_stride = c->max_n;
     a.perm = c->perm;
     a.maxblocks = c->maxblocks;
     a.heads = c->heads;
@@ -343,27 +377,33 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
         PROF(DTWS_K_PREP);
         HIPCHK(c, launch_query_prep_batch(Qp, c->bq, nq, base, c->qstride, c->mstride, c->max_m, s));
     }
-    {
+    if (same_m) {
+        for (int t = 0; t < p.nm; ++t) {
+            PROF(DTWS_K_STATS);
+            const int64_t so = (int64_t)t * c->max_n;
+            HIPCHK(c, launch_znorm_stats(T, n, p.slot_m[t], nullptr, nullptr, c->st_mu + so, c->st_s + so,
+                                         c->st_o + so, s));
+        }
+    } else {
         PROF(DTWS_K_STATS);
-        if (same_m)
-            HIPCHK(c, launch_znorm_stats(T, n, max_m, nullptr, nullptr, c->st_mu, c->st_s, c->st_o, s));
-        else
-            HIPCHK(c, launch_prefix(T, n, c->P1, c->P2, c->anc, c->tot1, c->tot2, s));
+        HIPCHK(c, launch_prefix(T, n, c->P1, c->P2, c->anc, c->tot1, c->tot2, s));
     }
-    {
-        PROF(DTWS_K_ENV);   // one data envelope for the largest band: valid (looser) for the others
-        HIPCHK(c, launch_series_env(T, n, max_r, c->envU, c->envL, s));
+    for (int t = 0; t < p.nr; ++t) {
+        PROF(DTWS_K_ENV);
+        const int64_t so = (int64_t)t * c->max_n;
+        HIPCHK(c, launch_series_env(T, n, p.slot_r[t], c->envU + so, c->envL + so, s));
     }
     {
         PROF(DTWS_K_OTHER);
         HIPCHK(c, launch_make_perm(a, (flags & DTWS_ORDER_MASK) == DTWS_ORDER_RANDOM ? 1 : 0, seed ^ 0xA5A5ull,
                                    max_nb, s));
     }
-    const int dtw_blocks = c->num_cu * 4;
+    const int dtw_blocks = c->num_cu * (c->dtw_blocks_per_cu > 0 ? c->dtw_blocks_per_cu : 4);
+    const int lb_blocks = c->num_cu * (c->lb_blocks_per_cu > 0 ? c->lb_blocks_per_cu : 8);
     auto dtw_round = [&]() -> int {
         { PROF(DTWS_K_OTHER); HIPCHK(c, launch_segments(a, c->num_cu, s)); }
         for (int nc = 1; nc <= kMaxChunks + 1; ++nc) {
-            if (!bucket_used[nc]) continue;
+            if (!p.bucket_used[nc]) continue;
             PROF(DTWS_K_DTW);
             HIPCHK(c, launch_dtw_bucket(a, !same_m, nc, dtw_blocks, s));
         }
@@ -387,7 +427,10 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
         }
         {
             PROF(DTWS_K_LB);
-            HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)rank_lo, (int)rank_hi, c->num_cu * 8, s));
+            // early rounds are small: split each block so that many waves share them
+            int parts = round == 0 ? 16 : (round == 1 ? 4 : 1);
+            while (parts > 1 && B / parts < 256) parts /= 2;
+            HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)rank_lo, (int)rank_hi, parts, lb_blocks, s));
         }
         rc = dtw_round();
         if (rc != DTWS_OK) return rc;
@@ -397,15 +440,104 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
     HIPCHK(c, hipMemcpyAsync(c->h_idx, c->res_idx, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(c->h_dist, c->res_dist, sizeof(double) * nq, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(c->h_status, c->res_status, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, s));
-    rc = fetch_counters(c, cand, s);
-    if (rc != DTWS_OK) return rc;
-    prof_end(c);
+    HIPCHK(c, hipMemcpyAsync(c->h_counters, c->counters, sizeof(unsigned long long) * kNumCounters,
+                             hipMemcpyDeviceToHost, s));
+    return DTWS_OK;
+}
+
+void parse_counters(dtws_ctx *c, int64_t candidates) {
+    const unsigned long long *h = c->h_counters;
+    c->last.candidates = candidates;
+    c->last.pruned_kim = (int64_t)h[1];
+    c->last.pruned_keogh_q = (int64_t)h[2];
+    c->last.pruned_keogh_d = (int64_t)h[3];
+    c->last.dtw_started = (int64_t)h[4];
+    c->last.dtw_abandoned = (int64_t)h[5];
+    c->last.dtw_cells = (int64_t)h[6];
+    c->last.certified = (int64_t)h[7];
+    c->last.dtw_lane_cells = (int64_t)h[8];
+}
+
+int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int64_t *qoff, const int32_t *mh,
+              const int32_t *rh, int nq, uint32_t flags, uint64_t seed, hipStream_t s, dtws_match *out) {
+    const BatchPlan p = plan_batch(c, n, qoff, mh, rh, nq);
+    const size_t cert_shm = sizeof(double) * (2 * (size_t)p.max_m + 3 * (size_t)(p.max_r + 4));
+    if ((flags & DTWS_NO_LOWER_BOUNDS) || cert_shm > 60 * 1024) {
+        // outside the batched pipeline's envelope: every query through the plain path
+        dtws_counters sum{};
+        int worst = DTWS_OK;
+        for (int k = 0; k < nq; ++k) {
+            const int rc = dtws_search(c, T, n, Qp + qoff[k], mh[k], rh[k], flags & ~(DTWS_ORDER_MASK | DTWS_NO_GRAPH),
+                                       seed + k, s, &out[k]);
+            if (rc != DTWS_OK && rc != DTWS_EOVERFLOW) return rc;
+            if (rc != DTWS_OK) worst = rc;
+            const int64_t *src = (const int64_t *)&c->last;
+            int64_t *dst = (int64_t *)&sum;
+            for (size_t f = 0; f < sizeof(dtws_counters) / sizeof(int64_t); ++f) dst[f] += src[f];
+        }
+        c->last = sum;
+        return worst;
+    }
+    const bool use_graph = !(flags & (DTWS_PROFILE | DTWS_NO_GRAPH));
+    if (!use_graph) {
+        prof_begin(c, flags);
+        int rc = enqueue_batch(c, p, T, n, Qp, nq, flags, seed, s);
+        if (rc != DTWS_OK) return rc;
+        HIPCHK(c, hipStreamSynchronize(s));
+        prof_end(c);
+    } else {
+        // The graph is rebuilt when anything it bakes in changes: pointers, sizes, flags, seed, the
+        // per-query parameters and the tuning knobs.
+        std::vector<int64_t> sig = {(int64_t)(uintptr_t)T, n, (int64_t)(uintptr_t)Qp, nq, (int64_t)flags,
+                                    (int64_t)seed, p.block, c->lb_blocks_per_cu, c->dtw_blocks_per_cu};
+        for (int k = 0; k < nq; ++k) {
+            sig.push_back(qoff[k]);
+            sig.push_back(mh[k]);
+            sig.push_back(rh[k]);
+        }
+        if (!c->graph_exec || sig != c->graph_sig) {
+            if (c->graph_exec) {
+                (void)hipGraphExecDestroy(c->graph_exec);
+                c->graph_exec = nullptr;
+            }
+            c->profiling = false;
+            HIPCHK(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+            const int rc = enqueue_batch(c, p, T, n, Qp, nq, flags, seed, c->gstream);
+            hipGraph_t g = nullptr;
+            const hipError_t ee = hipStreamEndCapture(c->gstream, &g);
+            if (rc != DTWS_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (ee != hipSuccess) {
+                set_err(c, ee, "hipStreamEndCapture");
+                return DTWS_EHIP;
+            }
+            const hipError_t ie = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) {
+                c->graph_exec = nullptr;
+                set_err(c, ie, "hipGraphInstantiate");
+                return DTWS_EHIP;
+            }
+            c->graph_sig = sig;
+        }
+        // order the graph after the caller's stream, run it, wait for it
+        HIPCHK(c, hipEventRecord(c->gevent, s));
+        HIPCHK(c, hipStreamWaitEvent(c->gstream, c->gevent, 0));
+        HIPCHK(c, hipGraphLaunch(c->graph_exec, c->gstream));
+        HIPCHK(c, hipStreamSynchronize(c->gstream));
+        c->graph_launches++;
+    }
+    parse_counters(c, p.cand);
     int worst = DTWS_OK;
     for (int k = 0; k < nq; ++k) {
         out[k].index = c->h_idx[k];
         out[k].distance = c->h_dist[k];
         out[k].status = c->h_status[k];
         out[k].reserved = 0;
+    }
+    for (int k = 0; k < nq; ++k) {
         if (out[k].status == DTWS_EOVERFLOW) {
             // survivor or near-best list overflowed: redo this query through the plain path
             dtws_counters keep = c->last;
@@ -456,6 +588,9 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
                    c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q};
     for (void *p : dev)
         if (p) (void)hipFree(p);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->gevent) (void)hipEventDestroy(c->gevent);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
     if (c->ev) {
         for (int e = 0; e < 2 * dtws_ctx::kMaxEvents; ++e)
             if (c->ev[e]) (void)hipEventDestroy(c->ev[e]);
@@ -488,15 +623,22 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
         c->num_cu = 256;
     c->qstride = 2 * kQPad + max_m;
     c->surv_cap = max_n;                  // a chunk of any size can keep every survivor
+    {
+        // statistics (12 B) + envelope (8 B) slots of max_n points for distinct lengths / bands of
+        // a batch, up to four, within about 24 GB
+        const int64_t fit = (int64_t)(24e9 / (20.0 * (double)max_n));
+        c->nslots = fit < 1 ? 1 : (fit > 4 ? 4 : (int)fit);
+        if (c->nslots > max_queries) c->nslots = max_queries;
+    }
     c->mstride = ((int64_t)max_m + 15) / 16 * 16;
     c->gen_lanes = 8192;
     const int64_t Q = max_queries;
     bool ok = dalloc(&c->qpad, Q * c->qstride) == hipSuccess && dalloc(&c->qhat64, Q * max_m) == hipSuccess &&
               dalloc(&c->qsorted, Q * c->mstride) == hipSuccess && dalloc(&c->Usorted, Q * c->mstride) == hipSuccess &&
               dalloc(&c->Lsorted, Q * c->mstride) == hipSuccess && dalloc(&c->order, Q * c->mstride) == hipSuccess &&
-              dalloc(&c->keys, Q) == hipSuccess && dalloc(&c->st_mu, max_n) == hipSuccess &&
-              dalloc(&c->st_s, max_n) == hipSuccess && dalloc(&c->st_o, max_n) == hipSuccess &&
-              dalloc(&c->envU, max_n) == hipSuccess && dalloc(&c->envL, max_n) == hipSuccess &&
+              dalloc(&c->keys, Q) == hipSuccess && dalloc(&c->st_mu, c->nslots * max_n) == hipSuccess &&
+              dalloc(&c->st_s, c->nslots * max_n) == hipSuccess && dalloc(&c->st_o, c->nslots * max_n) == hipSuccess &&
+              dalloc(&c->envU, c->nslots * max_n) == hipSuccess && dalloc(&c->envL, c->nslots * max_n) == hipSuccess &&
               dalloc(&c->surv, c->surv_cap) == hipSuccess && dalloc(&c->surv_count, 1) == hipSuccess &&
               dalloc(&c->nb_d, kNearBestCap) == hipSuccess && dalloc(&c->nb_idx, kNearBestCap) == hipSuccess &&
               dalloc(&c->nb_count, 1) == hipSuccess &&
@@ -533,6 +675,8 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
         ok = c->ev && c->ev_class;
         for (int e = 0; ok && e < 2 * dtws_ctx::kMaxEvents; ++e) ok = hipEventCreate(&c->ev[e]) == hipSuccess;
     }
+    if (ok) ok = hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&c->gevent, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         dtws_destroy(c);
@@ -560,7 +704,7 @@ DTWS_API int dtws_get_counters(dtws_ctx *c, dtws_counters *out) {
 DTWS_API int dtws_search(dtws_ctx *c, const float *T, int64_t n, const float *Q, int32_t m, int32_t r,
                          uint32_t flags, uint64_t seed, void *stream, dtws_match *out) {
     if (check_series(c, T, n, m) != DTWS_OK || !Q || !out || r < 0) return DTWS_EINVAL;
-    if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE)) return DTWS_EINVAL;
+    if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE | DTWS_NO_GRAPH)) return DTWS_EINVAL;
     if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED) return DTWS_ENOMODEL;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
@@ -591,7 +735,7 @@ DTWS_API int dtws_search_batch(dtws_ctx *c, const float *T, int64_t n, const flo
                                const int32_t *mh, const int32_t *rh, int32_t nq, uint32_t flags, uint64_t seed,
                                void *stream, dtws_match *out) {
     if (!c || !T || !Qp || !qoff || !mh || !rh || !out || nq < 1 || nq > c->max_q) return DTWS_EINVAL;
-    if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE)) return DTWS_EINVAL;
+    if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE | DTWS_NO_GRAPH)) return DTWS_EINVAL;
     if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED) return DTWS_ENOMODEL;
     for (int k = 0; k < nq; ++k)
         if (check_series(c, T, n, mh[k]) != DTWS_OK || rh[k] < 0 || qoff[k] < 0) return DTWS_EINVAL;

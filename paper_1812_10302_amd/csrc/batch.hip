@@ -94,7 +94,9 @@ struct StatsPrefix {
     const float *T;
     const double *P1, *P2, *anc, *tot1, *tot2;
     int m;
-    __device__ void window(int64_t i, double &mu, double &sigma) const {
+    double inv_m;
+    // mean and variance of window i
+    __device__ void window(int64_t i, double &mu, double &var) const {
         const int64_t e = i + m;
         const int64_t b0 = i / kPB, b1 = (e - 1) / kPB;
         double e1, e2;
@@ -115,8 +117,8 @@ struct StatsPrefix {
             S1 = (tot1[b0] - P1[i]) + e1 + c2 * delta;
             S2 = (tot2[b0] - P2[i]) + e2 + 2.0 * delta * e1 + c2 * delta * delta;
         }
-        const double md = S1 / m, msq = S2 / m;
-        double var = msq - md * md;
+        const double md = S1 * inv_m, msq = S2 * inv_m;
+        var = msq - md * md;
         mu = anc[b0] + md;
         if (m <= 64 || !(var > 4e-6 * msq)) {
             const float *w = T + i;
@@ -130,17 +132,21 @@ struct StatsPrefix {
             }
             var = q / m;
         }
-        sigma = sqrt(var > 0.0 ? var : 0.0);
+        if (!(var > 0.0)) var = 0.0;
     }
+    // The scale is stored in FP32 anyway, so 1/sigma comes from the FP32 reciprocal square root
+    // of the FP64 variance (relative error ~2^-23); flat windows (sigma <= 1e-8) get scale 0.
     __device__ void operator()(int64_t i, float &mu32, float &s, float &o) const {
-        double mu, sigma;
-        window(i, mu, sigma);
-        norm_params(mu, sigma, mu32, s, o);
+        double mu, var;
+        window(i, mu, var);
+        mu32 = (float)mu;
+        s = var <= kSigmaFlat * kSigmaFlat ? 0.0f : rsqrtf((float)var);
+        o = (float)(-(mu - (double)mu32)) * s;
     }
 };
 
 struct StatsArr {
-    const float *mu, *s, *o;
+    const float *mu, *s, *o;   // already offset to the query's statistics slot
     __device__ void operator()(int64_t i, float &m, float &sg, float &off) const {
         m = mu[i];
         sg = s[i];
@@ -206,36 +212,105 @@ struct EmitBatch {
     }
 };
 
+// Work-item source of one wave for one query: consumes the current item group by group, pops the
+// next item when it runs out, and stops (keeping the popped item) at the first item of another
+// query, so the caller can drain the queues before switching query.  Items of round r are
+// (query, rank k, part) in query-major order; part selects one of `parts` equal pieces of the
+// k-th block of the query's visiting order.
+struct ItemSource {
+    const BatchArgs *a;
+    int round, rank_lo, parts;
+    uint32_t per_q, total;
+    int q;                      // query being processed
+    int64_t gnext = 0, gend = 0;  // rest of the current item
+    bool pending = false;       // an item of another query was popped
+    int pq = -1;
+    int64_t pfirst = 0, plast = 0;
+
+    // pops items until one that exists; false when the round is exhausted
+    __device__ bool pop(int &qq, int64_t &first, int64_t &last) {
+        const int lane = threadIdx.x & 63;
+        for (;;) {
+            uint32_t idx = 0;
+            if (lane == 0) idx = atomicAdd(&a->heads[round], 1u);
+            idx = __builtin_amdgcn_readfirstlane(idx);   // wave-uniform: item state stays in SGPRs
+            if (idx >= total) return false;
+            qq = (int)(idx / per_q);
+            const uint32_t rest = idx % per_q;
+            const int k = rank_lo + (int)(rest / (uint32_t)parts);
+            const int part = (int)(rest % (uint32_t)parts);
+            const BatchQ bq = a->bq[qq];
+            if (k >= bq.nblocks) continue;
+            const int64_t blk = a->perm[(int64_t)qq * a->maxblocks + k];
+            const int64_t piece = a->block / parts;
+            first = blk * a->block + part * piece;
+            if (first >= bq.N) continue;
+            last = first + piece < bq.N ? first + piece : bq.N;
+            return true;
+        }
+    }
+
+    __device__ bool next(int64_t &g, int64_t &last) {
+        if (gnext >= gend) {
+            int qq;
+            int64_t f, l;
+            if (!pop(qq, f, l)) return false;
+            if (qq != q) {
+                pending = true;
+                pq = qq;
+                pfirst = f;
+                plast = l;
+                return false;
+            }
+            gnext = f;
+            gend = l;
+        }
+        g = gnext;
+        last = gend;
+        gnext += 64;
+        return true;
+    }
+};
+
 template <bool PREFIX>
-__global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int rank_lo, int rank_hi) {
+__global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int rank_lo, int rank_hi, int parts) {
     __shared__ WaveQueue queues[4][2];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const uint32_t total = (uint32_t)(rank_hi - rank_lo) * (uint32_t)a.nq;
+    ItemSource src{&a, round, rank_lo, parts, (uint32_t)(rank_hi - rank_lo) * (uint32_t)parts, 0u, -1};
+    src.total = src.per_q * (uint32_t)a.nq;
     CascadeCounts cnt;
+    int q;
+    int64_t f, l;
+    if (!src.pop(q, f, l)) goto finish;
     for (;;) {
-        uint32_t idx = 0;
-        if (lane == 0) idx = atomicAdd(&a.heads[round], 1u);
-        idx = __shfl(idx, 0, 64);
-        if (idx >= total) break;
-        const int k = rank_lo + (int)(idx / (uint32_t)a.nq);
-        const int q = (int)(idx % (uint32_t)a.nq);
-        const BatchQ bq = a.bq[q];
-        if (k >= bq.nblocks) continue;
-        const int64_t blk = a.perm[(int64_t)q * a.maxblocks + k];
-        const int64_t first = blk * a.block;
-        const int64_t last = first + a.block < bq.N ? first + a.block : bq.N;
-        const QView v{a.order + q * a.mstride, a.Us + q * a.mstride, a.Ls + q * a.mstride, a.qs + q * a.mstride,
-                      bq.m, (bq.m + 15) & ~15};
-        const float *qh = a.qpad + q * a.qstride + kQPad;
-        const float thr = threshold_of(load_bsf(a.keys + q));
-        const EmitBatch emit{a.surv_q, a.surv_i, a.surv_count, a.qcnt, a.overflow, a.surv_cap, q};
-        if (PREFIX)
-            cascade(v, a.T, a.envU, a.envL, thr, qh[0], qh[bq.m - 1], first, 64, last, queues[wid][0],
-                    queues[wid][1], StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, bq.m}, emit, cnt);
-        else
-            cascade(v, a.T, a.envU, a.envL, thr, qh[0], qh[bq.m - 1], first, 64, last, queues[wid][0],
-                    queues[wid][1], StatsArr{a.mu, a.s, a.o}, emit, cnt);
+        src.q = q;
+        src.gnext = f;
+        src.gend = l;
+        src.pending = false;
+        {
+            const BatchQ bq = a.bq[q];
+            const QView v{a.order + q * a.mstride, a.Us + q * a.mstride, a.Ls + q * a.mstride,
+                          a.qs + q * a.mstride, bq.m, (bq.m + 15) & ~15};
+            const float *qh = a.qpad + q * a.qstride + kQPad;
+            const float thr = threshold_of(load_bsf(a.keys + q));
+            const EmitBatch emit{a.surv_q, a.surv_i, a.surv_count, a.qcnt, a.overflow, a.surv_cap, q};
+            const float *eU = a.envU ? a.envU + bq.env_slot * a.slot_stride : nullptr;
+            const float *eL = a.envU ? a.envL + bq.env_slot * a.slot_stride : nullptr;
+            if (PREFIX) {
+                cascade(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, queues[wid][0], queues[wid][1],
+                        StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, bq.m, 1.0 / bq.m}, emit, cnt);
+            } else {
+                const int64_t so = bq.stat_slot * a.slot_stride;
+                cascade(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, queues[wid][0], queues[wid][1],
+                        StatsArr{a.mu + so, a.s + so, a.o + so}, emit, cnt);
+            }
+        }
+        if (!src.pending) break;
+        q = src.pq;
+        f = src.pfirst;
+        l = src.plast;
     }
+finish:
     if (a.counters) {
         const unsigned long long c_kim = wave_add_u64(cnt.kim), c_kq = wave_add_u64(cnt.kq),
                                  c_kd = wave_add_u64(cnt.kd);
@@ -277,10 +352,26 @@ __global__ void k_seg_scatter(BatchArgs a) {
     if (*a.overflow) return;
     uint32_t cnt = *a.surv_count;
     if ((int64_t)cnt > a.surv_cap) cnt = (uint32_t)a.surv_cap;
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
-        const int q = a.surv_q[e];
-        const uint32_t p = atomicAdd(&a.fill[q], 1u);
-        a.sorted[a.seg_off[q] + p] = a.surv_i[e];
+    const int lane = threadIdx.x & 63;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < cnt; base += stride) {
+        const uint32_t e = base + lane;
+        const bool valid = e < cnt;
+        const int q = valid ? a.surv_q[e] : -1;
+        // one atomic per distinct query among the wave's 64 entries
+        uint64_t pending = __ballot(valid);
+        uint32_t pos = 0;
+        while (pending) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int q0 = __shfl(q, leader, 64);
+            const uint64_t peers = __ballot(valid && q == q0);
+            uint32_t b0 = 0;
+            if (lane == leader) b0 = atomicAdd(&a.fill[q0], (uint32_t)__popcll(peers));
+            b0 = __shfl(b0, leader, 64);
+            if (valid && q == q0) pos = b0 + (uint32_t)__popcll(peers & lanemask_lt());
+            pending &= ~peers;
+        }
+        if (valid) a.sorted[a.seg_off[q] + pos] = a.surv_i[e];
     }
 }
 
@@ -319,10 +410,12 @@ __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
         const bool valid = local < (int64_t)a.qcnt[q];
         const int64_t start = valid ? (int64_t)a.sorted[w * 64 + lane] : 0;
         float mu, s, o;
-        if (PREFIX)
-            StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, bq.m}(start, mu, s, o);
-        else
-            StatsArr{a.mu, a.s, a.o}(start, mu, s, o);
+        if (PREFIX) {
+            StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, bq.m, 1.0 / bq.m}(start, mu, s, o);
+        } else {
+            const int64_t so = bq.stat_slot * a.slot_stride;
+            StatsArr{a.mu + so, a.s + so, a.o + so}(start, mu, s, o);
+        }
         bool alive;
         float D;
         int jdead, jrun;
@@ -377,10 +470,12 @@ __global__ __launch_bounds__(64) void k_dtw_batch_wide(BatchArgs a) {
         if (local >= (int64_t)a.qcnt[q]) continue;
         const int64_t start = a.sorted[w * 64 + lane];
         float mu, s, o;
-        if (PREFIX)
-            StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, m}(start, mu, s, o);
-        else
-            StatsArr{a.mu, a.s, a.o}(start, mu, s, o);
+        if (PREFIX) {
+            StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, m, 1.0 / m}(start, mu, s, o);
+        } else {
+            const int64_t so = bq.stat_slot * a.slot_stride;
+            StatsArr{a.mu + so, a.s + so, a.o + so}(start, mu, s, o);
+        }
         const float *qh = a.qpad + q * a.qstride + kQPad;
         float *prev = a.wide_rows + g * 2 * (int64_t)(a.max_m + 1), *cur = prev + (a.max_m + 1);
         const float *Tp = a.T + start;
@@ -555,6 +650,7 @@ __global__ __launch_bounds__(256) void k_cert_reduce_batch(BatchArgs a) {
         const bool overflow = *a.overflow || *a.nb_count > (uint32_t)kNearBestCap ||
                               *a.cert_count > (uint32_t)kNearBestCap;
         a.res_status[q] = overflow ? DTWS_EOVERFLOW : (bidx == 0xffffffffu ? DTWS_EHIP : DTWS_OK);
+        if (a.counters && q == 0) atomicAdd(&a.counters[7], (unsigned long long)cnt);
     }
 }
 
@@ -578,12 +674,12 @@ hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int blocks,
-                           hipStream_t s) {
+hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
+                           int blocks, hipStream_t s) {
     if (prefix)
-        hipLaunchKernelGGL(k_lb_batch<true>, dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi);
+        hipLaunchKernelGGL(k_lb_batch<true>, dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
     else
-        hipLaunchKernelGGL(k_lb_batch<false>, dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi);
+        hipLaunchKernelGGL(k_lb_batch<false>, dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
     return hipGetLastError();
 }
 

@@ -145,8 +145,9 @@ struct CascadeCounts {
     uint32_t kim = 0, kq = 0, kd = 0;
 };
 
-// Runs the bound cascade on groups of 64 consecutive candidates g, g + gstep, ... below `last`
-// (one wave).  Level 0 (coalesced, uniform): LB_KimFL and the first K0 query-envelope terms.
+// Runs the bound cascade (one wave) on groups of 64 consecutive candidates handed out by
+// src.next(g, last): the group starts at g, starts at or beyond `last` are idle lanes; next()
+// returns false when the source is exhausted.  Level 0 (coalesced, uniform): LB_KimFL and the first K0 query-envelope terms.
 // Survivors are compacted into the wave's LDS queue q1; full batches of 64 run the terms up to
 // K1 (level 1) and their survivors go to q2, whose full batches run the remaining terms with
 // early abandoning and then the data-envelope bound (level 2, if envU is set).  Candidates that
@@ -154,11 +155,10 @@ struct CascadeCounts {
 // full q2 batch first, then a full q1 batch, then a new group, so a queue never holds 64 or more
 // entries when a push can reach it; at the end both queues are drained.
 //   stats(i, mu, s, o): normalisation parameters of candidate i.
-template <class Stats, class Emit>
+template <class Stats, class Emit, class Source>
 __device__ __forceinline__ void cascade(const QView &v, const float *T, const float *envU, const float *envL,
-                                        float thr, float q0, float ql, int64_t g, int64_t gstep, int64_t last,
-                                        WaveQueue &q1, WaveQueue &q2, const Stats &stats, const Emit &emit,
-                                        CascadeCounts &cnt) {
+                                        float thr, float q0, float ql, Source &src, WaveQueue &q1, WaveQueue &q2,
+                                        const Stats &stats, const Emit &emit, CascadeCounts &cnt) {
     const int lane = threadIdx.x & 63;
     const int m = v.m, mpad = v.mpad;
     const int K0 = mpad < kK0 ? mpad : kK0, K1 = mpad < kK1 ? mpad : kK1;
@@ -203,7 +203,8 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
             continue;
         }
         if (done) break;
-        if (g >= last) {
+        int64_t g, last;
+        if (!src.next(g, last)) {
             done = true;
             continue;
         }
@@ -227,9 +228,20 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
             }
         }
         q_push(q1, t1, alive, (int32_t)ii, kq, mu, s, o);
-        g += gstep;
     }
 }
+
+// Group source over [first, last) with a fixed stride (grid-stride loop of the plain kernel).
+struct StrideSource {
+    int64_t g, step, end;
+    __device__ bool next(int64_t &gg, int64_t &last) {
+        if (g >= end) return false;
+        gg = g;
+        last = end;
+        g += step;
+        return true;
+    }
+};
 
 // ---------------------------------------------------------------- DTW column machinery
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/dtws.h"
 
 namespace dtws {
@@ -49,6 +51,8 @@ struct BatchQ {
     int32_t m, r;      // length and band (r clamped to m - 1)
     int32_t nc;        // DTW bucket: register chunks (1..kMaxChunks), kMaxChunks + 1 = wide band
     int32_t nblocks;   // work items: ceil(N / block)
+    int32_t stat_slot; // per-window statistics slot (distinct lengths), when not using the prefix
+    int32_t env_slot;  // data-envelope slot (distinct bands, or the batch's largest band)
 };
 
 // ---------------------------------------------------------------- kernel arguments
@@ -123,7 +127,8 @@ struct BatchArgs {
     // window statistics: per-window arrays (all queries share m) or the blocked prefix
     const float *mu, *s, *o;
     const double *P1, *P2, *anc, *tot1, *tot2;
-    const float *envU, *envL;  // data envelope for the largest band of the batch, or null
+    const float *envU, *envL;  // data envelopes (slot per distinct band), or null
+    int64_t slot_stride;       // elements per statistics / envelope slot
     // work queue
     int32_t *perm;             // per query: block visiting order, stride maxblocks
     int64_t maxblocks;
@@ -171,8 +176,8 @@ hipError_t launch_prefix(const float *T, int64_t n, double *P1, double *P2, doub
                          double *tot2, hipStream_t s);
 hipError_t launch_make_perm(const BatchArgs &a, int mode, uint64_t seed, int64_t max_nblocks, hipStream_t s);
 hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s);
-hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int blocks,
-                           hipStream_t s);
+hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
+                           int blocks, hipStream_t s);
 hipError_t launch_segments(const BatchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_dtw_bucket(const BatchArgs &a, bool prefix, int nc, int blocks, hipStream_t s);
 hipError_t launch_cert_batch(const BatchArgs &a, int max_m, int max_r, hipStream_t s);
@@ -199,7 +204,8 @@ struct dtws_ctx {
     uint64_t *keys = nullptr;             // best-so-far key per query
     // series-sized scratch
     float *st_mu = nullptr, *st_s = nullptr, *st_o = nullptr;   // per-candidate normalisation
-    float *envU = nullptr, *envL = nullptr;                     // raw series envelope
+    float *envU = nullptr, *envL = nullptr;                     // raw series envelope(s)
+    int nslots = 1;                       // statistics / envelope slots of max_n elements each
     int32_t *surv = nullptr;              // survivor starts
     int64_t surv_cap = 0;
     uint32_t *surv_count = nullptr;
@@ -231,6 +237,15 @@ struct dtws_ctx {
     int32_t *qorder = nullptr, *wstart = nullptr, *bucket_w = nullptr, *bucket_j = nullptr;
     int64_t *seg_off = nullptr;
     int32_t *nb_q = nullptr, *cert_q = nullptr;
+    // graph of the last batched call, its signature, and the stream it runs on
+    hipStream_t gstream = nullptr;
+    hipEvent_t gevent = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<int64_t> graph_sig;
+    int64_t graph_launches = 0;
+    // tuning knobs (0 = default): candidates per work item, launch widths per compute unit
+    int64_t block = 0;
+    int lb_blocks_per_cu = 0, dtw_blocks_per_cu = 0;
     // pinned host staging
     int64_t *h_idx = nullptr;
     double *h_dist = nullptr;

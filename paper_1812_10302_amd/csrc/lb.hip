@@ -76,8 +76,9 @@ __global__ __launch_bounds__(256) void k_lb_prune(LbArgs a, QView v) {
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const float thr = a.key ? threshold_of(load_bsf(a.key)) : a.fixed_thr;
     CascadeCounts cnt;
-    cascade(v, a.T, a.envU, a.envL, thr, a.qh[0], a.qh[a.m - 1], a.first + wave * 64, nwaves * 64, a.last,
-            queues[wid][0], queues[wid][1], StatsArrays{a.mu, a.s, a.o}, EmitList{a.surv, a.surv_count}, cnt);
+    StrideSource src{a.first + wave * 64, nwaves * 64, a.last};
+    cascade(v, a.T, a.envU, a.envL, thr, a.qh[0], a.qh[a.m - 1], src, queues[wid][0], queues[wid][1],
+            StatsArrays{a.mu, a.s, a.o}, EmitList{a.surv, a.surv_count}, cnt);
     if (a.counters) {
         const unsigned long long c_kim = wave_add_u64(cnt.kim), c_kq = wave_add_u64(cnt.kq),
                                  c_kd = wave_add_u64(cnt.kd);

@@ -265,3 +265,19 @@ def test_batch_order_invariance(ctx):
     base = ctx.search_batch(Td, Qd, rs)
     for seed in (1, 2, 3):
         assert ctx.search_batch(Td, Qd, rs, flags=dtws.ORDER_RANDOM, seed=seed) == base
+
+
+def test_batch_graph_replays_match_eager(ctx, casc):
+    """The batched pipeline replays a captured graph when called again with the same inputs; every
+    replay, with eager work in between, must equal the eagerly enqueued result and the oracle."""
+    T = W.random_walk(250_000, 34)
+    qs = [W.noisy_cut(T, 5_000 + 40_000 * k, m, 0.1, 900 + k) for k, m in enumerate((96, 256, 640))]
+    rs = [4, 12, 32]
+    Td = dev(T)
+    pq = dtws.PackedQueries([dev(q) for q in qs])
+    eager = ctx.search_batch(Td, pq, rs, flags=dtws.NO_GRAPH)
+    _check_batch(eager, _cascade_refs(casc, T, qs, rs))
+    for rep in range(4):
+        assert ctx.search_batch(Td, pq, rs) == eager, rep
+        ctx.search(Td, dev(qs[rep % 3]), rs[rep % 3])            # eager work between replays
+        torch.cuda.synchronize()
