@@ -75,7 +75,8 @@ enum dtws_kernel_class {
     DTWS_K_DTW = 4,     /* banded DTW (including the best-so-far update)         */
     DTWS_K_CERT = 5,    /* FP64 certification                                    */
     DTWS_K_OTHER = 6,   /* fills and bookkeeping                                 */
-    DTWS_K_COUNT = 7
+    DTWS_K_SCORE = 7,   /* learned ordering: features, network, block order      */
+    DTWS_K_COUNT = 8
 };
 
 /* Result of one search: 0-based start and its squared z-normalised DTW
@@ -192,6 +193,47 @@ DTWS_API int dtws_dtw_band(dtws_ctx *ctx, const float *T_dev, int64_t n, const f
  * d_dev must be non-negative (or +inf), idx_dev in [0, 2^32). */
 DTWS_API int dtws_bsf_update(dtws_ctx *ctx, uint64_t *keys_dev, const float *d_dev, const int64_t *idx_dev,
                              int64_t count, void *stream);
+
+/* ------------------------------------------------- learned block ordering
+ * Not part of the paper's method: a network scores blocks of candidates so that
+ * DTWS_ORDER_LEARNED visits the most promising blocks first; the bounds and the
+ * exact DTW still decide, so results equal those of the natural order.
+ * Model: y = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3, x = (16-segment PAA of
+ * the normalised query, 16-segment PAA of the normalised candidate), segment t
+ * of a length-m window = positions [floor(t m / 16), floor((t+1) m / 16)),
+ * trained on y* = log1p(DTW / m).  Products in bfloat16 on the matrix cores
+ * with FP32 accumulation; FP32 master parameters; Adam (beta 0.9 / 0.999,
+ * eps 1e-8).  Parameters: one flat FP32 vector of DTWS_MODEL_PARAMS values in
+ * the order W1 (32 x 256, row = input), b1 (256), W2 (256 x 256, row = layer-1
+ * unit), b2 (256), w3 (256), b3 (1). */
+#define DTWS_MODEL_PARAMS 74497
+#define DTWS_MODEL_MAX_ROWS 65536   /* rows per dtws_model_grad / dtws_model_train_step */
+
+/* He-normal initialisation from a seed (counter-based; deterministic). */
+DTWS_API int dtws_model_init(dtws_ctx *ctx, uint64_t seed);
+
+/* Copy the FP32 parameters out of / into the context (count = DTWS_MODEL_PARAMS).
+ * Setting resets the Adam state.  Blocking. */
+DTWS_API int dtws_model_get(dtws_ctx *ctx, float *params_host, int64_t count);
+DTWS_API int dtws_model_set(dtws_ctx *ctx, const float *params_host, int64_t count);
+
+/* Predictions y_dev[rows] for feature rows X_dev[rows][32] (FP32). */
+DTWS_API int dtws_model_forward(dtws_ctx *ctx, const float *X_dev, int64_t rows, float *y_dev, void *stream);
+
+/* Gradient of the mean squared error against targets t_dev[rows] (rows <=
+ * DTWS_MODEL_MAX_ROWS) into grad_dev[DTWS_MODEL_PARAMS]; the loss to *loss_host
+ * when not NULL (blocking then). */
+DTWS_API int dtws_model_grad(dtws_ctx *ctx, const float *X_dev, const float *t_dev, int64_t rows, float *grad_dev,
+                             float *loss_host, void *stream);
+
+/* One Adam step with learning rate lr on a batch of rows (<= DTWS_MODEL_MAX_ROWS). */
+DTWS_API int dtws_model_train_step(dtws_ctx *ctx, const float *X_dev, const float *t_dev, int64_t rows, float lr,
+                                   float *loss_host, void *stream);
+
+/* 16-segment PAA of the z-normalised windows T[s .. s+m) for s in starts_dev[count]
+ * into out_dev[count][16] (FP32; NaN rows for starts outside [0, n-m]). */
+DTWS_API int dtws_paa(dtws_ctx *ctx, const float *T_dev, int64_t n, int32_t m, const int64_t *starts_dev,
+                      int64_t count, float *out_dev, void *stream);
 
 #ifdef __cplusplus
 }

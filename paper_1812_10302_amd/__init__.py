@@ -25,7 +25,9 @@ ORDER_NATURAL, ORDER_RANDOM, ORDER_LEARNED = 0, 1, 2
 NO_LOWER_BOUNDS = 4
 PROFILE = 8
 NO_GRAPH = 16
-KERNEL_CLASSES = ("prep", "stats", "env", "lb", "dtw", "cert", "other")
+KERNEL_CLASSES = ("prep", "stats", "env", "lb", "dtw", "cert", "other", "score")
+MODEL_PARAMS = 74497
+MODEL_MAX_ROWS = 65536
 MAX_M = 2048
 
 COUNTER_FIELDS = ("candidates", "pruned_kim", "pruned_keogh_q", "pruned_keogh_d", "dtw_started",
@@ -81,6 +83,13 @@ def _load():
         "dtws_lb_cascade": ([P, P, I64, P, I32, I32, F32, P, P, P, P, ctypes.POINTER(I64), P], ctypes.c_int),
         "dtws_dtw_band": ([P, P, I64, P, I32, I32, P, I64, F32, P, P], ctypes.c_int),
         "dtws_bsf_update": ([P, P, P, P, I64, P], ctypes.c_int),
+        "dtws_model_init": ([P, U64], ctypes.c_int),
+        "dtws_model_get": ([P, P, I64], ctypes.c_int),
+        "dtws_model_set": ([P, P, I64], ctypes.c_int),
+        "dtws_model_forward": ([P, P, I64, P, P], ctypes.c_int),
+        "dtws_model_grad": ([P, P, P, I64, P, P, P], ctypes.c_int),
+        "dtws_model_train_step": ([P, P, P, I64, F32, P, P], ctypes.c_int),
+        "dtws_paa": ([P, P, I64, I32, P, I64, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -269,6 +278,56 @@ class Context:
                                    starts.data_ptr(), starts.numel(), float(abandon_at), out.data_ptr(),
                                    _stream(T))
         self._check(rc, "dtws_dtw_band")
+        return out[:starts.numel()]
+
+    # ------------------------------------------------------------------ ordering network
+    def model_init(self, seed: int = 0):
+        self._check(_load().dtws_model_init(self._h, int(seed)), "dtws_model_init")
+
+    def model_get(self) -> np.ndarray:
+        out = np.empty(MODEL_PARAMS, np.float32)
+        self._check(_load().dtws_model_get(self._h, out.ctypes.data, MODEL_PARAMS), "dtws_model_get")
+        return out
+
+    def model_set(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != MODEL_PARAMS:
+            raise ValueError(f"expected {MODEL_PARAMS} parameters")
+        self._check(_load().dtws_model_set(self._h, p.ctypes.data, MODEL_PARAMS), "dtws_model_set")
+
+    def model_forward(self, X):
+        """Predictions for feature rows X (float32 CUDA tensor, rows x 32)."""
+        torch = _torch()
+        X = X.contiguous()
+        y = torch.empty(max(X.shape[0], 1), dtype=torch.float32, device=X.device)
+        self._check(_load().dtws_model_forward(self._h, X.data_ptr(), X.shape[0], y.data_ptr(), _stream(X)),
+                    "dtws_model_forward")
+        return y[:X.shape[0]]
+
+    def model_grad(self, X, t):
+        """(gradient of the mean squared error as a CUDA tensor, loss)."""
+        torch = _torch()
+        X, t = X.contiguous(), t.contiguous()
+        g = torch.empty(MODEL_PARAMS, dtype=torch.float32, device=X.device)
+        loss = ctypes.c_float(0.0)
+        self._check(_load().dtws_model_grad(self._h, X.data_ptr(), t.data_ptr(), X.shape[0], g.data_ptr(),
+                                            ctypes.byref(loss), _stream(X)), "dtws_model_grad")
+        return g, float(loss.value)
+
+    def model_train_step(self, X, t, lr: float, want_loss: bool = True):
+        loss = ctypes.c_float(0.0)
+        self._check(_load().dtws_model_train_step(self._h, X.data_ptr(), t.data_ptr(), X.shape[0], float(lr),
+                                                  ctypes.byref(loss) if want_loss else None, _stream(X)),
+                    "dtws_model_train_step")
+        return float(loss.value) if want_loss else None
+
+    def paa(self, T, m: int, starts):
+        """16-segment PAA of the normalised windows T[s:s+m] (rows x 16 float32 CUDA tensor)."""
+        torch = _torch()
+        _dev_f32(T, "T")
+        out = torch.empty((max(starts.numel(), 1), 16), dtype=torch.float32, device=T.device)
+        self._check(_load().dtws_paa(self._h, T.data_ptr(), T.numel(), int(m), starts.data_ptr(), starts.numel(),
+                                     out.data_ptr(), _stream(T)), "dtws_paa")
         return out[:starts.numel()]
 
     def bsf_update(self, keys, d, idx):

@@ -393,7 +393,35 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         const int64_t so = (int64_t)t * c->max_n;
         HIPCHK(c, launch_series_env(T, n, p.slot_r[t], c->envU + so, c->envL + so, s));
     }
-    {
+    if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED) {
+        // visiting order from the ordering network: blocks by ascending predicted distance
+        PROF(DTWS_K_SCORE);
+        ScoreArgs sa{};
+        sa.K = kScoreSamples;
+        sa.qpaa = c->qpaa;
+        sa.cpaa = c->cpaa;
+        sa.score = c->score;
+        sa.cpaa_stride = c->cpaa_stride;
+        sa.row_off = c->row_off;
+        sa.cpaa_slot = c->cpaa_slot;
+        int64_t rows = 0;
+        for (int k = 0; k < nq; ++k) {
+            c->h_row_off[k] = rows;
+            rows += (int64_t)c->h_bq[k].nblocks * kScoreSamples;
+            c->h_cpaa_slot[k] = same_m ? c->h_bq[k].stat_slot : -1;
+        }
+        c->h_row_off[nq] = rows;
+        sa.total_rows = rows;
+        sa.ncpaa = same_m ? p.nm : 0;
+        for (int t = 0; t < sa.ncpaa; ++t) {
+            sa.cpaa_m[t] = p.slot_m[t];
+            sa.cpaa_N[t] = n - p.slot_m[t] + 1;
+            sa.cpaa_nblocks[t] = (sa.cpaa_N[t] + B - 1) / B;
+        }
+        HIPCHK(c, hipMemcpyAsync(c->row_off, c->h_row_off, sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(c->cpaa_slot, c->h_cpaa_slot, sizeof(int32_t) * nq, hipMemcpyHostToDevice, s));
+        HIPCHK(c, mlp_order_blocks(c->mlp, a, sa, s));
+    } else {
         PROF(DTWS_K_OTHER);
         HIPCHK(c, launch_make_perm(a, (flags & DTWS_ORDER_MASK) == DTWS_ORDER_RANDOM ? 1 : 0, seed ^ 0xA5A5ull,
                                    max_nb, s));
@@ -585,7 +613,11 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
                    c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_idx, c->res_dist,
                    c->res_status, c->counters, c->gen_rows, c->bq, c->P1, c->P2, c->anc, c->tot1, c->tot2,
                    c->perm, c->heads, c->surv_q, c->surv_i, c->sorted, c->qcnt, c->fill, c->overflow,
-                   c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q};
+                   c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q,
+                   c->mlp.theta, c->mlp.grad, c->mlp.adam_m, c->mlp.adam_v, c->mlp.W1T, c->mlp.W2T, c->mlp.W2b,
+                   c->mlp.Xb, c->mlp.XbT, c->mlp.H1b, c->mlp.H1T, c->mlp.dA2b, c->mlp.dA2T, c->mlp.dA1T,
+                   c->mlp.C1, c->mlp.C2, c->mlp.y, c->mlp.dy, c->mlp.loss, c->mlp.Xf, c->qpaa, c->cpaa,
+                   c->score, c->row_off, c->cpaa_slot};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -597,7 +629,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
         delete[] c->ev;
     }
     delete[] c->ev_class;
-    void *host[] = {c->h_idx, c->h_dist, c->h_status, c->h_counters, c->h_bq};
+    void *host[] = {c->h_idx, c->h_dist, c->h_status, c->h_counters, c->h_bq, c->h_row_off, c->h_cpaa_slot};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     delete c;
@@ -670,6 +702,26 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&c->nb_q, kNearBestCap) == hipSuccess && dalloc(&c->cert_q, kNearBestCap) == hipSuccess;
     }
     if (ok) {
+        MlpBufs &b = c->mlp;
+        const int64_t R = kMlpChunk;
+        c->cpaa_stride = c->maxblocks * kScoreSamples * 16;
+        ok = dalloc(&b.theta, kModelParams) == hipSuccess && dalloc(&b.grad, kModelParams) == hipSuccess &&
+             dalloc(&b.adam_m, kModelParams) == hipSuccess && dalloc(&b.adam_v, kModelParams) == hipSuccess &&
+             dalloc(&b.W1T, 256 * 32) == hipSuccess && dalloc(&b.W2T, 256 * 256) == hipSuccess &&
+             dalloc(&b.W2b, 256 * 256) == hipSuccess && dalloc(&b.Xb, R * 32) == hipSuccess &&
+             dalloc(&b.XbT, R * 32) == hipSuccess && dalloc(&b.H1b, R * 256) == hipSuccess &&
+             dalloc(&b.H1T, R * 256) == hipSuccess && dalloc(&b.dA2b, R * 256) == hipSuccess &&
+             dalloc(&b.dA2T, R * 256) == hipSuccess && dalloc(&b.dA1T, R * 256) == hipSuccess &&
+             dalloc(&b.C1, R * 256) == hipSuccess && dalloc(&b.C2, R * 256) == hipSuccess &&
+             dalloc(&b.y, R) == hipSuccess && dalloc(&b.dy, R) == hipSuccess && dalloc(&b.loss, 1) == hipSuccess &&
+             dalloc(&b.Xf, R * 32) == hipSuccess && dalloc(&c->qpaa, Q * 16) == hipSuccess &&
+             dalloc(&c->cpaa, c->nslots * c->cpaa_stride) == hipSuccess &&
+             dalloc(&c->score, Q * c->maxblocks) == hipSuccess && dalloc(&c->row_off, Q + 1) == hipSuccess &&
+             dalloc(&c->cpaa_slot, Q) == hipSuccess &&
+             hipHostMalloc((void **)&c->h_row_off, sizeof(int64_t) * (Q + 1), 0) == hipSuccess &&
+             hipHostMalloc((void **)&c->h_cpaa_slot, sizeof(int32_t) * Q, 0) == hipSuccess;
+    }
+    if (ok) {
         c->ev = new (std::nothrow) hipEvent_t[2 * dtws_ctx::kMaxEvents]();
         c->ev_class = new (std::nothrow) int[dtws_ctx::kMaxEvents]();
         ok = c->ev && c->ev_class;
@@ -736,12 +788,93 @@ DTWS_API int dtws_search_batch(dtws_ctx *c, const float *T, int64_t n, const flo
                                void *stream, dtws_match *out) {
     if (!c || !T || !Qp || !qoff || !mh || !rh || !out || nq < 1 || nq > c->max_q) return DTWS_EINVAL;
     if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE | DTWS_NO_GRAPH)) return DTWS_EINVAL;
-    if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED) return DTWS_ENOMODEL;
+    if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED && !c->has_model) return DTWS_ENOMODEL;
     for (int k = 0; k < nq; ++k)
         if (check_series(c, T, n, mh[k]) != DTWS_OK || rh[k] < 0 || qoff[k] < 0) return DTWS_EINVAL;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     return run_batch(c, T, n, Qp, qoff, mh, rh, nq, flags, seed, s, out);
+}
+
+DTWS_API int dtws_model_init(dtws_ctx *c, uint64_t seed) {
+    if (!c) return DTWS_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, mlp_init(c->mlp, seed, nullptr));
+    HIPCHK(c, hipStreamSynchronize(nullptr));
+    c->has_model = true;
+    c->model_step = 0;
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_model_get(dtws_ctx *c, float *params, int64_t count) {
+    if (!c || !params || count != kModelParams) return DTWS_EINVAL;
+    if (!c->has_model) return DTWS_ENOMODEL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpy(params, c->mlp.theta, sizeof(float) * kModelParams, hipMemcpyDeviceToHost));
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_model_set(dtws_ctx *c, const float *params, int64_t count) {
+    if (!c || !params || count != kModelParams) return DTWS_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpy(c->mlp.theta, params, sizeof(float) * kModelParams, hipMemcpyHostToDevice));
+    HIPCHK(c, launch_fill_u32((uint32_t *)c->mlp.adam_m, 0, kModelParams, nullptr));
+    HIPCHK(c, launch_fill_u32((uint32_t *)c->mlp.adam_v, 0, kModelParams, nullptr));
+    HIPCHK(c, mlp_refresh(c->mlp, nullptr));
+    HIPCHK(c, hipStreamSynchronize(nullptr));
+    c->has_model = true;
+    c->model_step = 0;
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_model_forward(dtws_ctx *c, const float *X, int64_t rows, float *y, void *stream) {
+    if (!c || !X || !y || rows < 0) return DTWS_EINVAL;
+    if (!c->has_model) return DTWS_ENOMODEL;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t r0 = 0; r0 < rows; r0 += kMlpChunk) {
+        const int64_t R = rows - r0 < kMlpChunk ? rows - r0 : kMlpChunk;
+        HIPCHK(c, mlp_forward(c->mlp, X + r0 * 32, R, y + r0, false, s));
+    }
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_model_grad(dtws_ctx *c, const float *X, const float *t, int64_t rows, float *grad, float *loss,
+                             void *stream) {
+    if (!c || !X || !t || !grad || rows < 1 || rows > kMaxTrainRows) return DTWS_EINVAL;
+    if (!c->has_model) return DTWS_ENOMODEL;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, mlp_backward(c->mlp, X, t, rows, s));
+    HIPCHK(c, hipMemcpyAsync(grad, c->mlp.grad, sizeof(float) * kModelParams, hipMemcpyDeviceToDevice, s));
+    if (loss) {
+        HIPCHK(c, hipMemcpyAsync(loss, c->mlp.loss, sizeof(float), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_model_train_step(dtws_ctx *c, const float *X, const float *t, int64_t rows, float lr, float *loss,
+                                   void *stream) {
+    if (!c || !X || !t || rows < 1 || rows > kMaxTrainRows || !(lr > 0.0f)) return DTWS_EINVAL;
+    if (!c->has_model) return DTWS_ENOMODEL;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, mlp_backward(c->mlp, X, t, rows, s));
+    HIPCHK(c, mlp_adam(c->mlp, ++c->model_step, lr, s));
+    if (loss) {
+        HIPCHK(c, hipMemcpyAsync(loss, c->mlp.loss, sizeof(float), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_paa(dtws_ctx *c, const float *T, int64_t n, int32_t m, const int64_t *starts, int64_t count,
+                      float *out, void *stream) {
+    if (!c || !T || !starts || !out || count < 0 || m < 2 || m > c->max_m || n < m) return DTWS_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_paa(T, n, m, starts, count, out, (hipStream_t)stream));
+    return DTWS_OK;
 }
 
 DTWS_API int dtws_znorm_stats(dtws_ctx *c, const float *T, int64_t n, int32_t m, double *mu, double *sigma,

@@ -159,6 +159,33 @@ struct BatchArgs {
     int64_t wide_lanes;
 };
 
+// ---------------------------------------------------------------- ordering network
+constexpr int64_t kModelParams = 32 * 256 + 256 + 256 * 256 + 256 + 256 + 1;
+constexpr int64_t kOffW1 = 0, kOffb1 = 32 * 256, kOffW2 = kOffb1 + 256, kOffb2 = kOffW2 + 256 * 256,
+                  kOffw3 = kOffb2 + 256, kOffb3 = kOffw3 + 256;
+constexpr int64_t kMlpChunk = 1 << 18;   // rows per forward pass (workspace size)
+constexpr int kScoreSamples = 4;         // sampled starts scored per block
+constexpr int64_t kMaxTrainRows = 1 << 16;  // rows per gradient / training step
+
+struct MlpBufs {
+    float *theta, *grad, *adam_m, *adam_v;   // FP32 master parameters, gradient, Adam moments
+    uint16_t *W1T, *W2T, *W2b;               // bfloat16 weight copies
+    uint16_t *Xb, *XbT, *H1b, *H1T, *dA2b, *dA2T, *dA1T;
+    float *C1, *C2, *y, *dy, *loss, *Xf;
+};
+
+struct ScoreArgs {
+    int K;
+    int64_t total_rows;
+    float *qpaa, *cpaa, *score;
+    int64_t cpaa_stride;
+    int ncpaa;
+    int cpaa_m[8];
+    int64_t cpaa_N[8], cpaa_nblocks[8];
+    const int64_t *row_off;
+    const int32_t *cpaa_slot;
+};
+
 // ---------------------------------------------------------------- launchers (stream-ordered)
 hipError_t launch_query_prep(const float *Q, int m, int r, const QueryBufs &b, hipStream_t s);
 hipError_t launch_query_prep_batch(const float *Qp, const BatchQ *bq, int nq, const QueryBufs &base,
@@ -181,6 +208,14 @@ hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_
 hipError_t launch_segments(const BatchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_dtw_bucket(const BatchArgs &a, bool prefix, int nc, int blocks, hipStream_t s);
 hipError_t launch_cert_batch(const BatchArgs &a, int max_m, int max_r, hipStream_t s);
+hipError_t mlp_init(const MlpBufs &b, uint64_t seed, hipStream_t s);
+hipError_t mlp_refresh(const MlpBufs &b, hipStream_t s);
+hipError_t mlp_forward(const MlpBufs &b, const float *X, int64_t R, float *y, bool train, hipStream_t s);
+hipError_t mlp_backward(const MlpBufs &b, const float *X, const float *t, int64_t R, hipStream_t s);
+hipError_t mlp_adam(const MlpBufs &b, int step, float lr, hipStream_t s);
+hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArgs &sa, hipStream_t s);
+hipError_t launch_paa(const float *T, int64_t n, int m, const int64_t *starts, int64_t count, float *out,
+                      hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
 // key of an empty best-so-far: distance +inf, index 0xFFFFFFFF
@@ -246,6 +281,14 @@ struct dtws_ctx {
     // tuning knobs (0 = default): candidates per work item, launch widths per compute unit
     int64_t block = 0;
     int lb_blocks_per_cu = 0, dtw_blocks_per_cu = 0;
+    // ordering network
+    dtws::MlpBufs mlp{};
+    bool has_model = false;
+    int model_step = 0;
+    float *qpaa = nullptr, *cpaa = nullptr, *score = nullptr;
+    int64_t *row_off = nullptr, *h_row_off = nullptr;
+    int32_t *cpaa_slot = nullptr, *h_cpaa_slot = nullptr;
+    int64_t cpaa_stride = 0;
     // pinned host staging
     int64_t *h_idx = nullptr;
     double *h_dist = nullptr;

@@ -1,0 +1,462 @@
+// Learned block ordering: a small network that predicts log1p(DTW / m) of a candidate from the
+// 16-segment PAA of the normalised query and of the normalised candidate.  It is not part of the
+// paper's method and never decides a result: its scores only order the work items, the exact
+// lower bounds and the exact DTW still prune and decide.
+//
+// Network 32 -> 256 -> 256 -> 1 with ReLU; products in bfloat16 on the matrix cores with FP32
+// accumulation (v_mfma_f32_16x16x32_bf16), FP32 master parameters, Adam in FP32.
+// Parameters are one flat FP32 vector: W1 (32 x 256, row = input), b1, W2 (256 x 256, row =
+// layer-1 unit), b2, w3 (256), b3.  bfloat16 copies: W1T (256 x 32), W2T (256 x 256, row = layer-2
+// unit) for the forward products and W2 (row-major) for the backward product.
+//
+// Rounding points (the CPU reference rounds at the same places): the inputs, W1, W2, the layer-1
+// activations, and the back-propagated pre-activation gradients before they enter a product.
+#include "device.h"
+
+namespace dtws {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> bfloat16 bits, round to nearest, ties to even.
+__device__ inline uint16_t f2bf(float x) {
+    const uint32_t u = __float_as_uint(x);
+    const uint32_t lsb = (u >> 16) & 1u;
+    return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ------------------------------------------------------------------ BF16 GEMM on the matrix cores
+// C[M x N] (FP32, row stride ldc) = A[M x K] * B[K x N], with A row-major (row stride lda, K
+// contiguous) and B given transposed, BT[N x K] row-major (row stride ldb).  M % 16 == 0,
+// N % 64 == 0, K % 32 == 0, strides multiples of 8.  One wave per 16 x 64 output tile.
+// Operand layout of v_mfma_f32_16x16x32_bf16 (16 x 32 by 32 x 16): lane l supplies A row l % 16
+// and B column l % 16, each with k = 8 * (l / 16) .. + 7; the accumulator lane l holds column
+// l % 16, rows 4 * (l / 16) .. + 3.
+__global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ A, int64_t lda,
+                                                    const uint16_t *__restrict__ BT, int64_t ldb,
+                                                    float *__restrict__ C, int64_t ldc, int M, int N, int K) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t tiles_m = M / 16, tiles = tiles_m * (N / 64);
+    if (wave >= tiles) return;
+    const int64_t tm = wave % tiles_m, tn = wave / tiles_m;
+    const int r = lane & 15, kq = 8 * (lane >> 4);
+    f32x4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *arow = A + (tm * 16 + r) * lda + kq;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const bf16x8 a = *(const bf16x8 *)(arow + k0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const bf16x8 b = *(const bf16x8 *)(BT + (tn * 64 + 16 * c + r) * ldb + k0 + kq);
+            acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) C[(tm * 16 + 4 * (lane >> 4) + t) * ldc + tn * 64 + 16 * c + r] = acc[c][t];
+}
+
+// ------------------------------------------------------------------ elementwise pieces
+// X (FP32 R x 32, rows >= R are zero padding) -> bfloat16 row-major and transposed (32 x Rp).
+__global__ void k_mlp_x(const float *X, int64_t R, int64_t Rp, uint16_t *Xb, uint16_t *XbT) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= Rp * 32) return;
+    const int64_t r = e / 32, k = e % 32;
+    const uint16_t v = r < R ? f2bf(X[r * 32 + k]) : 0;
+    Xb[e] = v;
+    if (XbT) XbT[k * Rp + r] = v;
+}
+
+// Layer 1 epilogue: H1 = relu(C1 + b1) -> bfloat16 row-major (and transposed, for training).
+__global__ void k_mlp_act1(const float *C1, const float *b1, int64_t Rp, uint16_t *H1b, uint16_t *H1T) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= Rp * 256) return;
+    const int64_t r = e / 256, n = e % 256;
+    const float h = fmaxf(C1[e] + b1[n], 0.0f);
+    const uint16_t v = f2bf(h);
+    H1b[e] = v;
+    if (H1T) H1T[n * Rp + r] = v;
+}
+
+// Layer 2 epilogue and head, one wave per row: H2 = relu(C2 + b2) (written back into C2 when
+// training), y = H2 . w3 + b3.
+__global__ void k_mlp_head(float *C2, const float *b2, const float *w3, const float *b3, int64_t R, float *y,
+                           bool keep) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= R) return;
+    float acc = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int n = lane + 64 * u;
+        const float h = fmaxf(C2[row * 256 + n] + b2[n], 0.0f);
+        if (keep) C2[row * 256 + n] = h;
+        acc = fmaf(h, w3[n], acc);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) y[row] = acc + b3[0];
+}
+
+// Loss and output gradient: dy = 2 (y - t) / R (zero for padding rows), loss = mean (y - t)^2;
+// dA2 = dy * w3 * [H2 > 0] -> bfloat16 row-major and transposed.
+__global__ void k_mlp_bwd_head(const float *y, const float *t, const float *H2, const float *w3, int64_t R, int64_t Rp,
+                               float *dy, uint16_t *dA2b, uint16_t *dA2T, float *loss) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= Rp * 256) return;
+    const int64_t r = e / 256, n = e % 256;
+    const float d = r < R ? 2.0f * (y[r] - t[r]) / (float)R : 0.0f;
+    if (n == 0) {
+        dy[r] = d;
+        if (r < R) atomicAdd(loss, (y[r] - t[r]) * (y[r] - t[r]) / (float)R);
+    }
+    const float g = r < R && H2[e] > 0.0f ? d * w3[n] : 0.0f;
+    const uint16_t v = f2bf(g);
+    dA2b[e] = v;
+    dA2T[n * Rp + r] = v;
+}
+
+// dA1 = dH1 * [H1 > 0] -> bfloat16 transposed.
+__global__ void k_mlp_bwd1(const float *dH1, const uint16_t *H1b, int64_t Rp, uint16_t *dA1T) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= Rp * 256) return;
+    const int64_t r = e / 256, n = e % 256;
+    const float g = bf2f(H1b[e]) > 0.0f ? dH1[e] : 0.0f;
+    dA1T[n * Rp + r] = f2bf(g);
+}
+
+// Column sums over the R rows for the bias gradients and the head weights (FP32, unrounded):
+// db1[n] = sum dH1*[H1>0], db2[n] = sum dy*w3[n]*[H2>0], dw3[n] = sum dy*H2, db3 = sum dy.
+__global__ __launch_bounds__(256) void k_mlp_colsums(const float *dH1, const uint16_t *H1b, const float *H2,
+                                                     const float *dy, const float *w3, int64_t R, float *g_b1,
+                                                     float *g_b2, float *g_w3, float *g_b3) {
+    const int n = threadIdx.x;
+    float s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+    for (int64_t r = 0; r < R; ++r) {
+        const int64_t e = r * 256 + n;
+        if (bf2f(H1b[e]) > 0.0f) s1 += dH1[e];
+        const float h2 = H2[e];
+        if (h2 > 0.0f) s2 += dy[r] * w3[n];
+        s3 = fmaf(dy[r], h2, s3);
+        if (n == 0) s4 += dy[r];
+    }
+    g_b1[n] = s1;
+    g_b2[n] = s2;
+    g_w3[n] = s3;
+    if (n == 0) g_b3[0] = s4;
+}
+
+// Adam with bias correction on the FP32 master parameters.
+__global__ void k_adam(float *theta, const float *g, float *m, float *v, int64_t count, float lr, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// bfloat16 copies of the weights: W1T[n][k] = W1[k][n], W2T[n][h] = W2[h][n], W2b = W2.
+__global__ void k_mlp_refresh(const float *W1, const float *W2, uint16_t *W1T, uint16_t *W2T, uint16_t *W2b) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < 32 * 256) {
+        const int64_t k = e / 256, n = e % 256;
+        W1T[n * 32 + k] = f2bf(W1[e]);
+    }
+    if (e < 256 * 256) {
+        const int64_t h = e / 256, n = e % 256;
+        const uint16_t b = f2bf(W2[e]);
+        W2T[n * 256 + h] = b;
+        W2b[e] = b;
+    }
+}
+
+// Counter-based He-normal initialisation (Box-Muller on splitmix64 draws); zero biases.
+__device__ inline uint64_t mix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__global__ void k_mlp_init(float *theta, uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int64_t oW1 = 0, ob1 = 32 * 256, oW2 = ob1 + 256, ob2 = oW2 + 65536, ow3 = ob2 + 256, ob3 = ow3 + 256;
+    if (i > ob3) return;
+    float scale = 0.0f;
+    if (i < ob1) scale = sqrtf(2.0f / 32.0f);
+    else if (i >= oW2 && i < ob2) scale = sqrtf(2.0f / 256.0f);
+    else if (i >= ow3 && i < ob3) scale = sqrtf(1.0f / 256.0f);
+    (void)oW1;
+    const uint64_t h1 = mix64(seed ^ (uint64_t)(2 * i)), h2 = mix64(seed ^ (uint64_t)(2 * i + 1));
+    const float u1 = ((h1 >> 40) + 1) * (1.0f / 16777217.0f), u2 = (h2 >> 40) * (1.0f / 16777216.0f);
+    const float z = sqrtf(-2.0f * logf(u1)) * cosf(6.283185307179586f * u2);
+    theta[i] = scale * z;
+}
+
+// ------------------------------------------------------------------ PAA features
+// 16-segment PAA of the z-normalised window T[s .. s+m): segment t covers [floor(t m / 16),
+// floor((t+1) m / 16)); mean and population sigma two-pass in FP64 (sigma <= 1e-8: all zero).
+// One thread per window; out[k * 16 + t].
+__device__ inline void paa16(const float *w, int m, float *out16) {
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s += (double)w[j];
+    const double mu = s / m;
+    double v = 0.0;
+    for (int j = 0; j < m; ++j) {
+        const double d = (double)w[j] - mu;
+        v += d * d;
+    }
+    const double sigma = sqrt(v / m);
+    const double inv = sigma <= kSigmaFlat ? 0.0 : 1.0 / sigma;
+    for (int t = 0; t < 16; ++t) {
+        const int a = (t * m) / 16, b = ((t + 1) * m) / 16;
+        double ss = 0.0;
+        for (int j = a; j < b; ++j) ss += (double)w[j];
+        out16[t] = (float)((ss / (b - a) - mu) * inv);
+    }
+}
+
+__global__ void k_paa(const float *T, int64_t n, int m, const int64_t *starts, int64_t count, float *out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int64_t s = starts[k];
+    float f[16];
+    if (s < 0 || s > n - m) {
+        for (int t = 0; t < 16; ++t) out[k * 16 + t] = NAN;
+        return;
+    }
+    paa16(T + s, m, f);
+    for (int t = 0; t < 16; ++t) out[k * 16 + t] = f[t];
+}
+
+// ------------------------------------------------------------------ block scoring and order
+// Sampled start j of block b: b * block + j * (block / K), clamped to the last candidate.
+__device__ inline int64_t sample_start(int64_t blk, int j, int64_t block, int K, int64_t N) {
+    const int64_t s = blk * block + (int64_t)j * (block / K);
+    return s < N ? s : N - 1;
+}
+
+// Query PAA from the FP64 normalised query: qpaa[q * 16 + t].
+__global__ void k_query_paa(const BatchArgs a, float *qpaa) {
+    const int q = blockIdx.x, t = threadIdx.x;
+    if (t >= 16) return;
+    const int m = a.bq[q].m;
+    const double *x = a.qhat64 + (int64_t)q * a.max_m;
+    const int lo = (t * m) / 16, hi = ((t + 1) * m) / 16;
+    double s = 0.0;
+    for (int j = lo; j < hi; ++j) s += x[j];
+    qpaa[q * 16 + t] = (float)(s / (hi - lo));
+}
+
+// Candidate PAA of every sampled start of a length-m query (shared by queries of that length).
+__global__ void k_cand_paa(const float *T, int64_t N, int m, int64_t nblocks, int64_t block, int K, float *cpaa) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nblocks * K) return;
+    const int64_t s = sample_start(row / K, (int)(row % K), block, K, N);
+    float f[16];
+    paa16(T + s, m, f);
+    for (int t = 0; t < 16; ++t) cpaa[row * 16 + t] = f[t];
+}
+
+// Feature rows [row0, row0 + R) of the batch: row = row_off[q] + blk * K + j ->
+// (query PAA of q, candidate PAA of its sampled start); candidates from the shared per-length
+// table when cpaa_slot[q] >= 0, else computed here.
+__global__ void k_score_rows(const BatchArgs a, const float *qpaa, const float *cpaa, const int64_t *row_off,
+                             const int32_t *cpaa_slot, int64_t cpaa_stride, int K, int64_t row0, int64_t R, float *X) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= R) return;
+    const int64_t row = row0 + k;
+    int lo = 0, hi = a.nq;   // row_off[lo] <= row < row_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (row_off[mid] <= row) lo = mid;
+        else hi = mid;
+    }
+    const int q = lo;
+    const int64_t local = row - row_off[q];
+    const BatchQ bq = a.bq[q];
+    float *x = X + k * 32;
+    for (int t = 0; t < 16; ++t) x[t] = qpaa[q * 16 + t];
+    if (cpaa_slot[q] >= 0) {
+        const float *c = cpaa + cpaa_slot[q] * cpaa_stride + local * 16;
+        for (int t = 0; t < 16; ++t) x[16 + t] = c[t];
+    } else {
+        paa16(a.T + sample_start(local / K, (int)(local % K), a.block, K, bq.N), bq.m, x + 16);
+    }
+}
+
+// score of a block = minimum predicted value over its K sampled starts
+__global__ void k_block_min(const float *y, int64_t R, int K, int64_t row0, float *score) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b * K >= R) return;
+    float s = INFINITY;
+    for (int j = 0; j < K; ++j) s = fminf(s, y[b * K + j]);
+    score[row0 / K + b] = s;
+}
+
+// Visiting order of a query's blocks by ascending score: counting sort into 2048 buckets between
+// the minimum and maximum score (order inside a bucket is unspecified; it affects speed only).
+constexpr int kOrderBuckets = 2048;
+__global__ __launch_bounds__(1024) void k_block_order(const BatchArgs a, const float *score, const int64_t *row_off,
+                                                      int K) {
+    __shared__ uint32_t hist[kOrderBuckets];
+    __shared__ float lo_s[32], hi_s[32];
+    const int q = blockIdx.x, tid = threadIdx.x;
+    const int64_t nb = a.bq[q].nblocks;
+    const float *sc = score + row_off[q] / K;
+    float lo = INFINITY, hi = -INFINITY;
+    for (int64_t b = tid; b < nb; b += blockDim.x) {
+        const float v = sc[b];
+        if (v == v) {
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, off, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, off, 64));
+    }
+    if ((tid & 63) == 0) {
+        lo_s[tid >> 6] = lo;
+        hi_s[tid >> 6] = hi;
+    }
+    for (int k = tid; k < kOrderBuckets; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
+    lo = INFINITY;
+    hi = -INFINITY;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        lo = fminf(lo, lo_s[w]);
+        hi = fmaxf(hi, hi_s[w]);
+    }
+    const float scale = hi > lo ? (kOrderBuckets - 1) / (hi - lo) : 0.0f;
+    auto bucket = [&](float v) -> int {
+        if (!(v == v)) return kOrderBuckets - 1;
+        int k = (int)((v - lo) * scale);
+        return k < 0 ? 0 : (k >= kOrderBuckets ? kOrderBuckets - 1 : k);
+    };
+    for (int64_t b = tid; b < nb; b += blockDim.x) atomicAdd(&hist[bucket(sc[b])], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < kOrderBuckets; ++k) {
+            const uint32_t c = hist[k];
+            hist[k] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    int32_t *perm = a.perm + (int64_t)q * a.maxblocks;
+    for (int64_t b = tid; b < nb; b += blockDim.x) {
+        const uint32_t pos = atomicAdd(&hist[bucket(sc[b])], 1u);
+        perm[pos] = (int32_t)b;
+    }
+}
+
+// ------------------------------------------------------------------ host side
+hipError_t mlp_gemm(const uint16_t *A, int64_t lda, const uint16_t *BT, int64_t ldb, float *C, int64_t ldc, int M, int N,
+                    int K, hipStream_t s) {
+    const int64_t waves = (int64_t)(M / 16) * (N / 64);
+    const int64_t blocks = (waves + 3) / 4;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)blocks), dim3(256), 0, s, A, lda, BT, ldb, C, ldc, M, N, K);
+    return hipGetLastError();
+}
+
+static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t mlp_refresh(const MlpBufs &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_refresh, dim3(nblk(65536)), dim3(256), 0, s, b.theta, b.theta + kOffW2, b.W1T, b.W2T,
+                       b.W2b);
+    return hipGetLastError();
+}
+
+hipError_t mlp_init(const MlpBufs &b, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_init, dim3(nblk(kModelParams)), dim3(256), 0, s, b.theta, seed);
+    hipError_t e = launch_fill_u32((uint32_t *)b.adam_m, 0, kModelParams, s);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)b.adam_v, 0, kModelParams, s);
+    if (e == hipSuccess) e = mlp_refresh(b, s);
+    return e;
+}
+
+// Forward pass on R rows (R <= kMlpChunk).  Training keeps the transposed operands and H2.
+hipError_t mlp_forward(const MlpBufs &b, const float *X, int64_t R, float *y, bool train, hipStream_t s) {
+    const int64_t Rp = (R + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_mlp_x, dim3(nblk(Rp * 32)), dim3(256), 0, s, X, R, Rp, b.Xb, train ? b.XbT : nullptr);
+    hipError_t e = mlp_gemm(b.Xb, 32, b.W1T, 32, b.C1, 256, (int)Rp, 256, 32, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_act1, dim3(nblk(Rp * 256)), dim3(256), 0, s, b.C1, b.theta + kOffb1, Rp, b.H1b,
+                       train ? b.H1T : nullptr);
+    e = mlp_gemm(b.H1b, 256, b.W2T, 256, b.C2, 256, (int)Rp, 256, 256, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_head, dim3(nblk(Rp * 64)), dim3(256), 0, s, b.C2, b.theta + kOffb2, b.theta + kOffw3,
+                       b.theta + kOffb3, Rp, y, train);
+    return hipGetLastError();
+}
+
+// Gradient of the mean squared error on R rows into b.grad (and the loss into b.loss).
+hipError_t mlp_backward(const MlpBufs &b, const float *X, const float *t, int64_t R, hipStream_t s) {
+    const int64_t Rp = (R + 63) / 64 * 64;
+    hipError_t e = mlp_forward(b, X, R, b.y, true, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32((uint32_t *)b.loss, 0, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_bwd_head, dim3(nblk(Rp * 256)), dim3(256), 0, s, b.y, t, b.C2, b.theta + kOffw3, R, Rp,
+                       b.dy, b.dA2b, b.dA2T, b.loss);
+    // dH1 = dA2 W2^T  (B^T of this product is W2 itself, row-major)
+    e = mlp_gemm(b.dA2b, 256, b.W2b, 256, b.C1, 256, (int)Rp, 256, 256, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_bwd1, dim3(nblk(Rp * 256)), dim3(256), 0, s, b.C1, b.H1b, Rp, b.dA1T);
+    // dW2 = H1^T dA2, dW1 = X^T dA1 (products over the rows)
+    e = mlp_gemm(b.H1T, Rp, b.dA2T, Rp, b.grad + kOffW2, 256, 256, 256, (int)Rp, s);
+    if (e != hipSuccess) return e;
+    e = mlp_gemm(b.XbT, Rp, b.dA1T, Rp, b.grad + kOffW1, 256, 32, 256, (int)Rp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_colsums, dim3(1), dim3(256), 0, s, b.C1, b.H1b, b.C2, b.dy, b.theta + kOffw3, R,
+                       b.grad + kOffb1, b.grad + kOffb2, b.grad + kOffw3, b.grad + kOffb3);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(const MlpBufs &b, int step, float lr, hipStream_t s) {
+    const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(kModelParams)), dim3(256), 0, s, b.theta, b.grad, b.adam_m, b.adam_v,
+                       (int64_t)kModelParams, lr, c1, c2);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = mlp_refresh(b, s);
+    return e;
+}
+
+// Scores every block of every query of the batch and writes the visiting order into a.perm.
+hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArgs &sa, hipStream_t s) {
+    hipLaunchKernelGGL(k_query_paa, dim3(a.nq), dim3(64), 0, s, a, sa.qpaa);
+    for (int t = 0; t < sa.ncpaa; ++t) {
+        const int64_t rows = sa.cpaa_nblocks[t] * sa.K;
+        hipLaunchKernelGGL(k_cand_paa, dim3(nblk(rows)), dim3(256), 0, s, a.T, sa.cpaa_N[t], sa.cpaa_m[t],
+                           sa.cpaa_nblocks[t], a.block, sa.K, sa.cpaa + t * sa.cpaa_stride);
+    }
+    const int64_t chunk = kMlpChunk / sa.K * sa.K;
+    for (int64_t r0 = 0; r0 < sa.total_rows; r0 += chunk) {
+        const int64_t R = sa.total_rows - r0 < chunk ? sa.total_rows - r0 : chunk;
+        hipLaunchKernelGGL(k_score_rows, dim3(nblk(R)), dim3(256), 0, s, a, sa.qpaa, sa.cpaa, sa.row_off,
+                           sa.cpaa_slot, sa.cpaa_stride, sa.K, r0, R, b.Xf);
+        hipError_t e = mlp_forward(b, b.Xf, R, b.y, false, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_block_min, dim3(nblk(R / sa.K)), dim3(256), 0, s, b.y, R, sa.K, r0, sa.score);
+    }
+    hipLaunchKernelGGL(k_block_order, dim3(a.nq), dim3(1024), 0, s, a, sa.score, sa.row_off, sa.K);
+    return hipGetLastError();
+}
+
+hipError_t launch_paa(const float *T, int64_t n, int m, const int64_t *starts, int64_t count, float *out,
+                      hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_paa, dim3(nblk(count)), dim3(256), 0, s, T, n, m, starts, count, out);
+    return hipGetLastError();
+}
+
+}  // namespace dtws

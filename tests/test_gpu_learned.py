@@ -1,0 +1,122 @@
+"""GPU checks of the learned block ordering against the FP64 reference (oracle/mlp.py).
+
+Tolerances: the reference rounds to bfloat16 at the same points as the kernels, so the remaining
+differences are FP32-vs-FP64 accumulation and the occasional bfloat16 rounding of an activation
+that falls on the other side of a rounding boundary; forward values agree to ~1e-3 relative and
+gradients to ~1e-2 in relative L2 norm per parameter block.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1812_10302_amd as dtws
+from paper_1812_10302_amd import proposal
+from paper_1812_10302_amd import workloads as W
+from oracle import mlp as M
+from oracle import reference as R
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dtws.Context(0, max_n=3_000_000, max_m=2048, max_queries=16)
+    yield c
+    c.close()
+
+
+def _random_problem(seed, rows):
+    rng = np.random.default_rng(seed)
+    theta = M.init_params(seed).astype(np.float32).astype(np.float64)
+    theta[M.N_PARAMS - 1] = 0.3
+    theta[32 * 256:32 * 256 + 256] = rng.normal(0, 0.1, 256)          # non-zero b1
+    X = rng.normal(0, 1, (rows, 32)).astype(np.float32)
+    t = rng.normal(0, 1, rows).astype(np.float32)
+    return theta, X, t
+
+
+def _blocks(v):
+    out, k = {}, 0
+    for name, shape in M.SHAPES:
+        size = int(np.prod(shape))
+        out[name] = v[k:k + size]
+        k += size
+    return out
+
+
+def test_paa_matches_oracle(ctx):
+    T = W.random_walk(50_000, 41)
+    T[20_000:20_400] = np.float32(3.5)                                   # flat windows
+    for m in (16, 100, 256, 1000):
+        starts = np.array([0, 7, 19_990 if m <= 400 else 19_000, 20_000, T.size - m], np.int64)
+        got = ctx.paa(dev(T), m, dev(starts)).cpu().numpy()
+        want = np.array([M.paa(R.znorm(T[s:s + m])) for s in starts])
+        np.testing.assert_allclose(got, want, rtol=1e-5, atol=1e-6)
+    bad = ctx.paa(dev(T), 64, dev(np.array([-1, T.size], np.int64))).cpu().numpy()
+    assert np.isnan(bad).all()
+
+
+@pytest.mark.parametrize("rows", [1, 64, 200, 4096])
+def test_forward_matches_reference(ctx, rows):
+    theta, X, _ = _random_problem(rows, rows)
+    ctx.model_set(theta.astype(np.float32))
+    y = ctx.model_forward(dev(X)).cpu().numpy()
+    want, _ = M.forward(theta, X.astype(np.float64), bf16_ops=True)
+    np.testing.assert_allclose(y, want, rtol=2e-3, atol=2e-3 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("rows", [64, 333, 4096])
+def test_gradients_match_reference(ctx, rows):
+    theta, X, t = _random_problem(100 + rows, rows)
+    ctx.model_set(theta.astype(np.float32))
+    g, loss = ctx.model_grad(dev(X), dev(t))
+    want_loss, want = M.loss_and_grads(theta, X.astype(np.float64), t.astype(np.float64), bf16_ops=True)
+    assert loss == pytest.approx(want_loss, rel=2e-3)
+    got_b, want_b = _blocks(g.cpu().numpy().astype(np.float64)), _blocks(want)
+    for name, _ in M.SHAPES:
+        err = np.linalg.norm(got_b[name] - want_b[name]) / max(np.linalg.norm(want_b[name]), 1e-12)
+        assert err < 2e-2, (name, err)
+
+
+def test_adam_step_matches_reference(ctx):
+    theta, X, t = _random_problem(7, 512)
+    ctx.model_set(theta.astype(np.float32))
+    g, _ = ctx.model_grad(dev(X), dev(t))
+    ctx.model_train_step(dev(X), dev(t), 1e-3)
+    got = ctx.model_get().astype(np.float64)
+    want, _, _ = M.adam(theta.astype(np.float32).astype(np.float64), g.cpu().numpy().astype(np.float64),
+                        np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS), 1, 1e-3)
+    np.testing.assert_allclose(got, want, rtol=1e-5, atol=1e-6)
+
+
+def test_training_reduces_loss(ctx):
+    T = W.sinusoid_mix(1_000_000, 51)
+    X, Y = proposal.make_pairs(ctx, T, 128, 6, 100, 400, seed=52)
+    curve = proposal.train(ctx, X, Y, epochs=6, batch=2048, lr=2e-3, seed=53)
+    assert curve[-1] < 0.5 * curve[0], curve
+
+
+def test_learned_order_identical_results_and_gain(ctx):
+    """Same best matches under natural, random and learned block orders; the trained ordering
+    reaches a tight best-so-far earlier and starts fewer DTW cells than the natural order."""
+    train_T = W.sinusoid_mix(2_000_000, 61)
+    X, Y = proposal.make_pairs(ctx, train_T, 256, 12, 300, 500, seed=62)
+    proposal.train(ctx, X, Y, epochs=4, batch=4096, lr=1e-3, seed=63)
+    T = W.sinusoid_mix(2_500_000, 64)
+    wl = W.mixed_queries(T, nq=12, m=256, seed=65)
+    Td = dev(T)
+    pq = dtws.PackedQueries([dev(q) for q in wl.queries])
+    res, cells = {}, {}
+    for name, flag in (("natural", dtws.ORDER_NATURAL), ("random", dtws.ORDER_RANDOM),
+                       ("learned", dtws.ORDER_LEARNED)):
+        res[name] = ctx.search_batch(Td, pq, wl.bands, flags=flag | dtws.NO_GRAPH, seed=5)
+        cells[name] = ctx.counters()["dtw_cells"]
+    assert res["learned"] == res["natural"] == res["random"]
+    print("DTW cells by order:", cells)
+    assert cells["learned"] < cells["natural"]
