@@ -2,7 +2,9 @@
 
 One step = the whole search path (window statistics, data envelope, bound cascade, banded DTW
 with the device best-so-far, FP64 certification) for every query of the workload, with the
-series already resident in HBM.  Default workload: float32 random walk of n = 1e8 points and
+series already resident in HBM.  The timed path is the batched search with the learned block
+order (one graph replay per step); the plain per-query search and the batched search in series
+order are timed beside it.  The ordering network is trained before timing (seeded).  Default workload: float32 random walk of n = 1e8 points and
 three queries (m = 128, 512, 1024, cut from the series plus N(0, 0.1) noise, band 5%).
 
 Prints one JSON line.  value = seconds per query (lower is better).  The roofline object is
@@ -48,6 +50,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="series points for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--train-n", type=int, default=10_000_000, help="training series length (ordering network)")
+    ap.add_argument("--train-pairs", type=int, default=999_000)
+    ap.add_argument("--train-epochs", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search shards by "
@@ -88,26 +93,48 @@ def main():
     plain_s = (time.perf_counter() - t1) / args.steps / nq
     plain_results = plain_step()
 
+    # ---------------------------------------------------------------- ordering network (untimed)
+    from paper_1812_10302_amd import proposal
+    t0 = time.time()
+    train_T = W.random_walk(args.train_n, 8)
+    Xs, Ys = [], []
+    for k, (m, r) in enumerate(zip(ms, rs)):
+        X, Y = proposal.make_pairs(ctx, train_T, m, r, args.train_pairs // (1000 * nq), 1000, seed=80 + k)
+        Xs.append(X)
+        Ys.append(Y)
+    curve = proposal.train(ctx, torch.cat(Xs).contiguous(), torch.cat(Ys).contiguous(), epochs=args.train_epochs,
+                           seed=9, log=log)
+    train_s = time.time() - t0
+    log(f"ordering network trained in {train_s:.1f}s, loss {curve[0]:.4f} -> {curve[-1]:.4f}")
+
     # ---------------------------------------------------------------- batched: all queries, graph replay
     pq = dtws.PackedQueries(Qs)
-    bflags = 0
 
-    def batch_step(flags=0):
-        return ctx.search_batch(T, pq, rs, flags=bflags | flags, seed=7)
+    def batch_step(order, flags=0):
+        return ctx.search_batch(T, pq, rs, flags=order | flags, seed=7)
 
-    for _ in range(max(1, args.warmup)):
-        batch_step()             # the first call captures the graph
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        results = batch_step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t1
-    ms_per_step = elapsed / args.steps * 1e3
-    s_per_query = elapsed / args.steps / nq
+    def time_batched(order):
+        for _ in range(max(1, args.warmup)):
+            batch_step(order)        # the first call captures the graph
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            res = batch_step(order)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) / args.steps, res
+
+    natural_step_s, natural_results = time_batched(dtws.ORDER_NATURAL)
+    elapsed_step, results = time_batched(dtws.ORDER_LEARNED)
+    ms_per_step = elapsed_step * 1e3
+    s_per_query = elapsed_step / nq
     log("plain:", plain_results)
-    log("batched:", results)
+    log("batched natural:", natural_results)
+    log("batched learned:", results)
+    assert results == natural_results, "learned and natural orders disagree"
     assert [i for i, _ in results] == [i for i, _ in plain_results], "batched and plain disagree"
+
+    def batch_step_learned(flags=0):
+        return batch_step(dtws.ORDER_LEARNED, flags)
 
     # ---------------------------------------------------------------- profiled passes
     def profiled(run):
@@ -118,7 +145,7 @@ def main():
     prof_total, cnt_total = {k: [0.0, 0] for k in dtws.KERNEL_CLASSES}, {}
     per_query_prof = []
     if not args.no_profile:
-        prof_total, cnt_total = profiled(lambda: batch_step(dtws.PROFILE))
+        prof_total, cnt_total = profiled(lambda: batch_step_learned(dtws.PROFILE))
         for q, r in zip(Qs, rs):
             kp, c = profiled(lambda: ctx.search(T, q, r, flags=dtws.PROFILE, seed=7))
             per_query_prof.append({"m": int(q.numel()), "r": int(r),
@@ -175,8 +202,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": int(wl.T.size), "m": ms, "r": rs, "mode": "batched",
+        "config": {"workload": wl.name, "n": int(wl.T.size), "m": ms, "r": rs, "mode": "batched+learned",
                    "note": wl.note},
+        "batched_natural_s_per_query": round(natural_step_s / nq, 6),
+        "ordering_network": {"train_series": f"random walk n={args.train_n} seed 8", "pairs": int(sum(x.shape[0] for x in Xs)),
+                             "epochs": args.train_epochs, "loss_curve": [round(v, 5) for v in curve],
+                             "train_s": round(train_s, 2)},
         "plain_s_per_query": round(plain_s, 6),
         "batched_over_plain": round(s_per_query / plain_s, 4),
         "roofline": roofline,
