@@ -52,7 +52,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--train-n", type=int, default=10_000_000, help="training series length (ordering network)")
     ap.add_argument("--train-pairs", type=int, default=999_000)
-    ap.add_argument("--train-epochs", type=int, default=3)
+    ap.add_argument("--train-epochs", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search shards by "
@@ -99,7 +99,9 @@ def main():
     train_T = W.random_walk(args.train_n, 8)
     Xs, Ys = [], []
     for k, (m, r) in enumerate(zip(ms, rs)):
-        X, Y = proposal.make_pairs(ctx, train_T, m, r, args.train_pairs // (1000 * nq), 1000, seed=80 + k)
+        rows_per_query = args.train_n // 1024 + 320
+        X, Y = proposal.make_pairs(ctx, train_T, m, r, max(1, args.train_pairs // (rows_per_query * nq)),
+                                   seed=80 + k)
         Xs.append(X)
         Ys.append(Y)
     curve = proposal.train(ctx, torch.cat(Xs).contiguous(), torch.cat(Ys).contiguous(), epochs=args.train_epochs,

@@ -106,7 +106,7 @@ typedef struct {
 
 /* Create a context on HIP device `device` able to search series of up to
  * max_n points (max_n < 2^31) with queries of up to max_m points (2 <= max_m
- * <= 4096) and batches of up to max_queries queries.  Allocates all device
+ * <= 2048) and batches of up to max_queries queries.  Allocates all device
  * scratch (roughly 24 bytes per series point plus small per-query buffers).
  * Returns DTWS_ENODEV when no HIP device is present. */
 DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_queries, dtws_ctx **out);
@@ -135,7 +135,7 @@ DTWS_API int dtws_get_profile(dtws_ctx *ctx, double *ms_host, int64_t *launches_
 /* ------------------------------------------------------------------ search */
 
 /* Best match of one query (Section 2.1 best-match definition; Algorithm 1
- * in its single-fragment form, Section 4.2's single-node variant).
+ * with the whole series as one fragment, Section 3.1, i.e. one node).
  *   T_dev[n] float32 series, Q_dev[m] float32 query, band r (clamped to m-1),
  *   flags: DTWS_ORDER_* and DTWS_NO_LOWER_BOUNDS, seed: picks the random
  *   candidate whose DTW initialises the best-so-far (Algorithm 1, the random
@@ -201,7 +201,7 @@ DTWS_API int dtws_bsf_update(dtws_ctx *ctx, uint64_t *keys_dev, const float *d_d
  * Model: y = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3, x = (16-segment PAA of
  * the normalised query, 16-segment PAA of the normalised candidate), segment t
  * of a length-m window = positions [floor(t m / 16), floor((t+1) m / 16)),
- * trained on y* = log1p(DTW / m).  Products in bfloat16 on the matrix cores
+ * trained on y* = log(DTW / m + 1e-4) (the training recipe is the caller's).  Products in bfloat16 on the matrix cores
  * with FP32 accumulation; FP32 master parameters; Adam (beta 0.9 / 0.999,
  * eps 1e-8).  Parameters: one flat FP32 vector of DTWS_MODEL_PARAMS values in
  * the order W1 (32 x 256, row = input), b1 (256), W2 (256 x 256, row = layer-1
@@ -229,6 +229,19 @@ DTWS_API int dtws_model_grad(dtws_ctx *ctx, const float *X_dev, const float *t_d
 /* One Adam step with learning rate lr on a batch of rows (<= DTWS_MODEL_MAX_ROWS). */
 DTWS_API int dtws_model_train_step(dtws_ctx *ctx, const float *X_dev, const float *t_dev, int64_t rows, float lr,
                                    float *loss_host, void *stream);
+
+/* Proposals that the learned order scores (DTWS_ORDER_LEARNED).  The candidates
+ * 0 .. n-m are cut into quarter blocks of block/4 starts (block: 4096); the
+ * proposal of a quarter is its start whose 16-segment PAA is nearest (squared
+ * Euclidean, FP32, lowest start on ties) to the query's, among every ps-th start
+ * of the quarter, ps = max(1, m/64) for m >= 128 and 1 below.  Row k (quarter k)
+ * gets starts_dev[k] (-1 for a quarter past the last candidate) and X_dev[k][32] =
+ * (query PAA, candidate PAA), the network's input.  rows = 4 * ceil((n-m+1) /
+ * 4096) is written to *rows_out; with starts_dev and X_dev both NULL nothing else
+ * happens, else max_rows must be >= rows (DTWS_EINVAL otherwise).  Uses the
+ * context's workspace (calls on one context must not overlap); blocking. */
+DTWS_API int dtws_propose(dtws_ctx *ctx, const float *T_dev, int64_t n, const float *Q_dev, int32_t m,
+                          int64_t *starts_dev, float *X_dev, int64_t max_rows, int64_t *rows_out, void *stream);
 
 /* 16-segment PAA of the z-normalised windows T[s .. s+m) for s in starts_dev[count]
  * into out_dev[count][16] (FP32; NaN rows for starts outside [0, n-m]). */

@@ -8,8 +8,8 @@ bounds and exact DTW decide every result.  Its inputs are Piecewise Aggregate Ap
 candidate, segment s covering positions [floor(s*m/16), floor((s+1)*m/16)).
 
 Network: y = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3 with x in R^32 (query PAA, then
-candidate PAA), hidden widths 256 and 256.  Loss: mean squared error against the target
-y* = log1p(DTW / m).  Parameters are kept as one flat FP32 vector in the order
+candidate PAA), hidden widths 256 and 256.  Loss: mean squared error against given targets (the
+training recipe uses log(DTW / m + 1e-4)).  Parameters are kept as one flat FP32 vector in the order
 W1 (32 x 256, row = input), b1 (256), W2 (256 x 256, row = layer-1 unit), b2 (256), w3 (256), b3 (1).
 
 With bf16=True the reference rounds to bfloat16 exactly where the GPU kernels do: the inputs x,
@@ -59,6 +59,35 @@ def paa(xhat, segments: int = 16) -> np.ndarray:
     m = x.size
     b = [(s * m) // segments for s in range(segments + 1)]
     return np.array([x[b[s]:b[s + 1]].mean() for s in range(segments)])
+
+
+def proposals(T, Q, block: int = 4096, quarters: int = 4):
+    """The candidates the learned order scores: the candidates 0 .. n-m are cut into quarter blocks
+    of block/quarters starts; within each, every ps-th start (ps = m // 64 for m >= 128, else 1)
+    is compared with the query by the squared Euclidean distance of their PAAs (both windows
+    z-normalised, flat ones to zero), and the nearest is proposed, the lowest start on ties.
+    Returns (starts, distances) per quarter; -1 / inf past the last candidate."""
+    from .reference import normalized_windows, znorm
+    T = np.asarray(T, dtype=np.float64)
+    m = len(Q)
+    N = T.size - m + 1
+    ps = m // 64 if m >= 128 else 1
+    qp = paa(znorm(Q))
+    quarter = block // quarters
+    rows = -(-N // block) * quarters
+    starts = np.full(rows, -1, dtype=np.int64)
+    dists = np.full(rows, np.inf)
+    for k in range(rows):
+        lo, hi = k * quarter, min((k + 1) * quarter, N)
+        if lo >= hi:
+            continue
+        cand = np.arange(lo, hi, ps)
+        C = normalized_windows(T, m, cand)
+        F = np.stack([C[:, (t * m) // 16:((t + 1) * m) // 16].mean(axis=1) for t in range(16)], axis=1)
+        d = ((F - qp) ** 2).sum(axis=1)
+        j = int(np.argmin(d))
+        starts[k], dists[k] = cand[j], d[j]
+    return starts, dists
 
 
 def forward(theta, X, bf16_ops: bool = False):

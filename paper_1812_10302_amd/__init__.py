@@ -90,6 +90,7 @@ def _load():
         "dtws_model_grad": ([P, P, P, I64, P, P, P], ctypes.c_int),
         "dtws_model_train_step": ([P, P, P, I64, F32, P, P], ctypes.c_int),
         "dtws_paa": ([P, P, I64, I32, P, I64, P, P], ctypes.c_int),
+        "dtws_propose": ([P, P, I64, P, I32, P, P, I64, ctypes.POINTER(I64), P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -329,6 +330,21 @@ class Context:
         self._check(_load().dtws_paa(self._h, T.data_ptr(), T.numel(), int(m), starts.data_ptr(), starts.numel(),
                                      out.data_ptr(), _stream(T)), "dtws_paa")
         return out[:starts.numel()]
+
+    def propose(self, T, Q):
+        """Proposals of every quarter block for query Q: (starts int64, features rows x 32)."""
+        torch = _torch()
+        _dev_f32(T, "T")
+        _dev_f32(Q, "Q")
+        rows = ctypes.c_int64(0)
+        lib = _load()
+        self._check(lib.dtws_propose(self._h, T.data_ptr(), T.numel(), Q.data_ptr(), Q.numel(), None, None, 0,
+                                     ctypes.byref(rows), _stream(T)), "dtws_propose")
+        starts = torch.empty(max(rows.value, 1), dtype=torch.int64, device=T.device)
+        X = torch.empty((max(rows.value, 1), 32), dtype=torch.float32, device=T.device)
+        self._check(lib.dtws_propose(self._h, T.data_ptr(), T.numel(), Q.data_ptr(), Q.numel(), starts.data_ptr(),
+                                     X.data_ptr(), rows.value, ctypes.byref(rows), _stream(T)), "dtws_propose")
+        return starts[:rows.value], X[:rows.value]
 
     def bsf_update(self, keys, d, idx):
         """Atomically lower keys[0] to the minimum packed (distance, index) key."""

@@ -228,6 +228,7 @@ struct BatchPlan {
     int slot_m[8] = {0}, slot_r[8] = {0};
     int max_m = 0, max_r = 0;
     int64_t max_nb = 0, cand = 0, block = 0;
+    int64_t score_rows = 0;   // proposals of the learned order (kScoreSamples per block)
     bool bucket_used[kMaxChunks + 2] = {false};
 };
 
@@ -248,7 +249,12 @@ BatchPlan plan_batch(dtws_ctx *c, int64_t n, const int64_t *qoff, const int32_t 
         p.max_r = b.r > p.max_r ? b.r : p.max_r;
         p.max_nb = b.nblocks > p.max_nb ? b.nblocks : p.max_nb;
         p.cand += b.N;
+        // rows of the learned order; the pinned copy is refreshed on every call because a graph
+        // replay reads it
+        c->h_row_off[k] = p.score_rows;
+        p.score_rows += (int64_t)b.nblocks * kScoreSamples;
     }
+    c->h_row_off[nq] = p.score_rows;
     // slots for distinct lengths and bands, in order of first appearance
     bool m_fit = true, r_fit = true;
     for (int k = 0; k < nq; ++k) {
@@ -393,33 +399,26 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         const int64_t so = (int64_t)t * c->max_n;
         HIPCHK(c, launch_series_env(T, n, p.slot_r[t], c->envU + so, c->envL + so, s));
     }
-    if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED) {
-        // visiting order from the ordering network: blocks by ascending predicted distance
+    const bool learned = (flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED;
+    ScoreArgs sa{};
+    if (learned) {
+        // visiting order from the ordering network: blocks by ascending predicted distance of their
+        // proposals (the blocked prefix gives every window's PAA)
         PROF(DTWS_K_SCORE);
-        ScoreArgs sa{};
+        if (same_m) HIPCHK(c, launch_prefix(T, n, c->P1, c->P2, c->anc, c->tot1, c->tot2, s));
         sa.K = kScoreSamples;
         sa.qpaa = c->qpaa;
-        sa.cpaa = c->cpaa;
         sa.score = c->score;
-        sa.cpaa_stride = c->cpaa_stride;
+        sa.sstart = c->sstart;
+        sa.bstart = c->bstart;
         sa.row_off = c->row_off;
-        sa.cpaa_slot = c->cpaa_slot;
-        int64_t rows = 0;
-        for (int k = 0; k < nq; ++k) {
-            c->h_row_off[k] = rows;
-            rows += (int64_t)c->h_bq[k].nblocks * kScoreSamples;
-            c->h_cpaa_slot[k] = same_m ? c->h_bq[k].stat_slot : -1;
-        }
-        c->h_row_off[nq] = rows;
-        sa.total_rows = rows;
-        sa.ncpaa = same_m ? p.nm : 0;
-        for (int t = 0; t < sa.ncpaa; ++t) {
-            sa.cpaa_m[t] = p.slot_m[t];
-            sa.cpaa_N[t] = n - p.slot_m[t] + 1;
-            sa.cpaa_nblocks[t] = (sa.cpaa_N[t] + B - 1) / B;
-        }
+        sa.P1 = c->P1;
+        sa.P2 = c->P2;
+        sa.anc = c->anc;
+        sa.tot1 = c->tot1;
+        sa.tot2 = c->tot2;
+        sa.total_rows = p.score_rows;
         HIPCHK(c, hipMemcpyAsync(c->row_off, c->h_row_off, sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, s));
-        HIPCHK(c, hipMemcpyAsync(c->cpaa_slot, c->h_cpaa_slot, sizeof(int32_t) * nq, hipMemcpyHostToDevice, s));
         HIPCHK(c, mlp_order_blocks(c->mlp, a, sa, s));
     } else {
         PROF(DTWS_K_OTHER);
@@ -437,8 +436,13 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         }
         return DTWS_OK;
     };
-    // round -1: one random candidate per query
-    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_seed_random(a, seed, s)); }
+    // round -1: the best-so-far starts from one random candidate per query (Algorithm 1), or from
+    // the proposals of the best-scored blocks under the learned order
+    {
+        PROF(DTWS_K_OTHER);
+        if (learned) HIPCHK(c, launch_seed_learned(a, sa, s));
+        else HIPCHK(c, launch_seed_random(a, seed, s));
+    }
     int rc = dtw_round();
     if (rc != DTWS_OK) return rc;
     // rounds over the work queue: 64K, 1M, 16M candidates per query, then the rest
@@ -616,8 +620,8 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
                    c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q,
                    c->mlp.theta, c->mlp.grad, c->mlp.adam_m, c->mlp.adam_v, c->mlp.W1T, c->mlp.W2T, c->mlp.W2b,
                    c->mlp.Xb, c->mlp.XbT, c->mlp.H1b, c->mlp.H1T, c->mlp.dA2b, c->mlp.dA2T, c->mlp.dA1T,
-                   c->mlp.C1, c->mlp.C2, c->mlp.y, c->mlp.dy, c->mlp.loss, c->mlp.Xf, c->qpaa, c->cpaa,
-                   c->score, c->row_off, c->cpaa_slot};
+                   c->mlp.C1, c->mlp.C2, c->mlp.y, c->mlp.dy, c->mlp.loss, c->mlp.Xf, c->mlp.part, c->qpaa,
+                   c->score, c->sstart, c->bstart, c->row_off};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -629,7 +633,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
         delete[] c->ev;
     }
     delete[] c->ev_class;
-    void *host[] = {c->h_idx, c->h_dist, c->h_status, c->h_counters, c->h_bq, c->h_row_off, c->h_cpaa_slot};
+    void *host[] = {c->h_idx, c->h_dist, c->h_status, c->h_counters, c->h_bq, c->h_row_off};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     delete c;
@@ -686,7 +690,8 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
               hipHostMalloc((void **)&c->h_counters, sizeof(unsigned long long) * kNumCounters, 0) == hipSuccess;
     if (ok) {
         c->maxblocks = (max_n + kMinBlock - 1) / kMinBlock + 1;
-        const int64_t cap = Q * max_n < (int64_t(1) << 25) ? Q * max_n : (int64_t(1) << 25);
+        int64_t cap = Q * max_n < (int64_t(1) << 25) ? Q * max_n : (int64_t(1) << 25);
+        if (cap < Q * kSeedCands) cap = Q * kSeedCands;   // round -1 of the learned order
         c->bsurv_cap = cap;
         const int64_t nblk = max_n / 4096 + 2;
         ok = dalloc(&c->bq, Q) == hipSuccess && hipHostMalloc((void **)&c->h_bq, sizeof(BatchQ) * Q, 0) == hipSuccess &&
@@ -704,7 +709,6 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
     if (ok) {
         MlpBufs &b = c->mlp;
         const int64_t R = kMlpChunk;
-        c->cpaa_stride = c->maxblocks * kScoreSamples * 16;
         ok = dalloc(&b.theta, kModelParams) == hipSuccess && dalloc(&b.grad, kModelParams) == hipSuccess &&
              dalloc(&b.adam_m, kModelParams) == hipSuccess && dalloc(&b.adam_v, kModelParams) == hipSuccess &&
              dalloc(&b.W1T, 256 * 32) == hipSuccess && dalloc(&b.W2T, 256 * 256) == hipSuccess &&
@@ -714,12 +718,11 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&b.dA2T, R * 256) == hipSuccess && dalloc(&b.dA1T, R * 256) == hipSuccess &&
              dalloc(&b.C1, R * 256) == hipSuccess && dalloc(&b.C2, R * 256) == hipSuccess &&
              dalloc(&b.y, R) == hipSuccess && dalloc(&b.dy, R) == hipSuccess && dalloc(&b.loss, 1) == hipSuccess &&
-             dalloc(&b.Xf, R * 32) == hipSuccess && dalloc(&c->qpaa, Q * 16) == hipSuccess &&
-             dalloc(&c->cpaa, c->nslots * c->cpaa_stride) == hipSuccess &&
-             dalloc(&c->score, Q * c->maxblocks) == hipSuccess && dalloc(&c->row_off, Q + 1) == hipSuccess &&
-             dalloc(&c->cpaa_slot, Q) == hipSuccess &&
-             hipHostMalloc((void **)&c->h_row_off, sizeof(int64_t) * (Q + 1), 0) == hipSuccess &&
-             hipHostMalloc((void **)&c->h_cpaa_slot, sizeof(int32_t) * Q, 0) == hipSuccess;
+             dalloc(&b.Xf, R * 32) == hipSuccess && dalloc(&b.part, (int64_t)kColsumGroups * 4 * 256) == hipSuccess &&
+             dalloc(&c->qpaa, Q * 16) == hipSuccess && dalloc(&c->sstart, R) == hipSuccess &&
+             dalloc(&c->score, Q * c->maxblocks) == hipSuccess && dalloc(&c->bstart, Q * c->maxblocks) == hipSuccess &&
+             dalloc(&c->row_off, Q + 1) == hipSuccess &&
+             hipHostMalloc((void **)&c->h_row_off, sizeof(int64_t) * (Q + 1), 0) == hipSuccess;
     }
     if (ok) {
         c->ev = new (std::nothrow) hipEvent_t[2 * dtws_ctx::kMaxEvents]();
@@ -874,6 +877,52 @@ DTWS_API int dtws_paa(dtws_ctx *c, const float *T, int64_t n, int32_t m, const i
     if (!c || !T || !starts || !out || count < 0 || m < 2 || m > c->max_m || n < m) return DTWS_EINVAL;
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_paa(T, n, m, starts, count, out, (hipStream_t)stream));
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_propose(dtws_ctx *c, const float *T, int64_t n, const float *Q, int32_t m, int64_t *starts,
+                         float *X, int64_t max_rows, int64_t *rows_out, void *stream) {
+    if (check_series(c, T, n, m) != DTWS_OK || !rows_out) return DTWS_EINVAL;
+    const int64_t B = c->block > 0 ? c->block : kDefaultBlock;
+    const int64_t N = n - m + 1, nb = (N + B - 1) / B, rows = nb * kScoreSamples;
+    *rows_out = rows;
+    if (!starts && !X) return DTWS_OK;
+    if (!Q || !starts || !X || max_rows < rows) return DTWS_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, launch_query_prep(Q, m, 0, query_bufs(c, 0), s));
+    HIPCHK(c, launch_prefix(T, n, c->P1, c->P2, c->anc, c->tot1, c->tot2, s));
+    BatchQ &bq = c->h_bq[0];
+    bq = BatchQ{};
+    bq.m = m;
+    bq.N = N;
+    bq.nblocks = (int32_t)nb;
+    c->h_row_off[0] = 0;
+    c->h_row_off[1] = rows;
+    HIPCHK(c, hipMemcpyAsync(c->bq, c->h_bq, sizeof(BatchQ), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->row_off, c->h_row_off, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
+    BatchArgs a{};
+    a.T = T;
+    a.n = n;
+    a.nq = 1;
+    a.block = B;
+    a.max_m = c->max_m;
+    a.bq = c->bq;
+    a.qhat64 = c->qhat64;
+    ScoreArgs sa{};
+    sa.K = kScoreSamples;
+    sa.total_rows = rows;
+    sa.qpaa = c->qpaa;
+    sa.sstart = c->sstart;
+    sa.row_off = c->row_off;
+    sa.P1 = c->P1;
+    sa.P2 = c->P2;
+    sa.anc = c->anc;
+    sa.tot1 = c->tot1;
+    sa.tot2 = c->tot2;
+    HIPCHK(c, launch_propose(a, sa, X, starts, s));
+    // the staging entries are read by the copies above before the call returns
+    HIPCHK(c, hipStreamSynchronize(s));
     return DTWS_OK;
 }
 

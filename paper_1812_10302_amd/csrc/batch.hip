@@ -19,7 +19,6 @@
 
 namespace dtws {
 
-constexpr int kPB = 4096;            // prefix block length (points)
 constexpr int kPrefixThreads = 256;  // 16 points per thread
 
 __device__ inline uint64_t splitmix64_d(uint64_t x) {

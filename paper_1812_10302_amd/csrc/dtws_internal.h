@@ -164,26 +164,30 @@ constexpr int64_t kModelParams = 32 * 256 + 256 + 256 * 256 + 256 + 256 + 1;
 constexpr int64_t kOffW1 = 0, kOffb1 = 32 * 256, kOffW2 = kOffb1 + 256, kOffb2 = kOffW2 + 256 * 256,
                   kOffw3 = kOffb2 + 256, kOffb3 = kOffw3 + 256;
 constexpr int64_t kMlpChunk = 1 << 18;   // rows per forward pass (workspace size)
-constexpr int kScoreSamples = 4;         // sampled starts scored per block
+constexpr int kScoreSamples = 4;         // proposals scored per block (one per quarter block)
+constexpr int kSeedCands = 64;           // best-scored proposals per query that seed the best-so-far (one wave)
+constexpr int kColsumGroups = 128;       // row groups of the bias-gradient reduction
 constexpr int64_t kMaxTrainRows = 1 << 16;  // rows per gradient / training step
+constexpr int kPB = 4096;                // blocked prefix: block length (points)
 
 struct MlpBufs {
     float *theta, *grad, *adam_m, *adam_v;   // FP32 master parameters, gradient, Adam moments
     uint16_t *W1T, *W2T, *W2b;               // bfloat16 weight copies
     uint16_t *Xb, *XbT, *H1b, *H1T, *dA2b, *dA2T, *dA1T;
     float *C1, *C2, *y, *dy, *loss, *Xf;
+    float *part;                             // kColsumGroups x 4 x 256 partial column sums
 };
 
+// Scoring of a batch: row (q, blk, j) = row_off[q] + blk * K + j is the proposal of quarter j
+// of block blk of query q; score and bstart are indexed by row_off[q] / K + blk.
 struct ScoreArgs {
     int K;
     int64_t total_rows;
-    float *qpaa, *cpaa, *score;
-    int64_t cpaa_stride;
-    int ncpaa;
-    int cpaa_m[8];
-    int64_t cpaa_N[8], cpaa_nblocks[8];
-    const int64_t *row_off;
-    const int32_t *cpaa_slot;
+    float *qpaa, *score;
+    int32_t *sstart;           // start of each row of the current chunk (-1: empty quarter)
+    int32_t *bstart;           // start of the best-scored proposal of each block
+    const int64_t *row_off;    // per query, nq + 1 entries
+    const double *P1, *P2, *anc, *tot1, *tot2;   // blocked prefix of the series
 };
 
 // ---------------------------------------------------------------- launchers (stream-ordered)
@@ -214,6 +218,8 @@ hipError_t mlp_forward(const MlpBufs &b, const float *X, int64_t R, float *y, bo
 hipError_t mlp_backward(const MlpBufs &b, const float *X, const float *t, int64_t R, hipStream_t s);
 hipError_t mlp_adam(const MlpBufs &b, int step, float lr, hipStream_t s);
 hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArgs &sa, hipStream_t s);
+hipError_t launch_seed_learned(const BatchArgs &a, const ScoreArgs &sa, hipStream_t s);
+hipError_t launch_propose(const BatchArgs &a, const ScoreArgs &sa, float *X, int64_t *starts, hipStream_t s);
 hipError_t launch_paa(const float *T, int64_t n, int m, const int64_t *starts, int64_t count, float *out,
                       hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
@@ -285,10 +291,9 @@ struct dtws_ctx {
     dtws::MlpBufs mlp{};
     bool has_model = false;
     int model_step = 0;
-    float *qpaa = nullptr, *cpaa = nullptr, *score = nullptr;
+    float *qpaa = nullptr, *score = nullptr;
+    int32_t *sstart = nullptr, *bstart = nullptr;
     int64_t *row_off = nullptr, *h_row_off = nullptr;
-    int32_t *cpaa_slot = nullptr, *h_cpaa_slot = nullptr;
-    int64_t cpaa_stride = 0;
     // pinned host staging
     int64_t *h_idx = nullptr;
     double *h_dist = nullptr;

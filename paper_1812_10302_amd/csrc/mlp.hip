@@ -131,18 +131,39 @@ __global__ void k_mlp_bwd1(const float *dH1, const uint16_t *H1b, int64_t Rp, ui
 
 // Column sums over the R rows for the bias gradients and the head weights (FP32, unrounded):
 // db1[n] = sum dH1*[H1>0], db2[n] = sum dy*w3[n]*[H2>0], dw3[n] = sum dy*H2, db3 = sum dy.
-__global__ __launch_bounds__(256) void k_mlp_colsums(const float *dH1, const uint16_t *H1b, const float *H2,
-                                                     const float *dy, const float *w3, int64_t R, float *g_b1,
-                                                     float *g_b2, float *g_w3, float *g_b3) {
-    const int n = threadIdx.x;
+// Two passes with a fixed summation order: kColsumGroups row groups into part, then part summed.
+__global__ __launch_bounds__(256) void k_mlp_colsums_part(const float *dH1, const uint16_t *H1b, const float *H2,
+                                                          const float *dy, const float *w3, int64_t R, float *part) {
+    const int n = threadIdx.x, g = blockIdx.x;
+    const int64_t r0 = R * g / kColsumGroups, r1 = R * (g + 1) / kColsumGroups;
+    const float w = w3[n];
     float s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
-    for (int64_t r = 0; r < R; ++r) {
+    for (int64_t r = r0; r < r1; ++r) {
         const int64_t e = r * 256 + n;
+        const float d = dy[r];
         if (bf2f(H1b[e]) > 0.0f) s1 += dH1[e];
         const float h2 = H2[e];
-        if (h2 > 0.0f) s2 += dy[r] * w3[n];
-        s3 = fmaf(dy[r], h2, s3);
-        if (n == 0) s4 += dy[r];
+        if (h2 > 0.0f) s2 += d * w;
+        s3 = fmaf(d, h2, s3);
+        s4 += d;
+    }
+    float *p = part + (int64_t)g * 4 * 256;
+    p[n] = s1;
+    p[256 + n] = s2;
+    p[512 + n] = s3;
+    p[768 + n] = s4;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_colsums(const float *part, float *g_b1, float *g_b2, float *g_w3,
+                                                     float *g_b3) {
+    const int n = threadIdx.x;
+    float s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+    for (int g = 0; g < kColsumGroups; ++g) {
+        const float *p = part + (int64_t)g * 4 * 256;
+        s1 += p[n];
+        s2 += p[256 + n];
+        s3 += p[512 + n];
+        s4 += p[768 + n];
     }
     g_b1[n] = s1;
     g_b2[n] = s2;
@@ -236,12 +257,6 @@ __global__ void k_paa(const float *T, int64_t n, int m, const int64_t *starts, i
 }
 
 // ------------------------------------------------------------------ block scoring and order
-// Sampled start j of block b: b * block + j * (block / K), clamped to the last candidate.
-__device__ inline int64_t sample_start(int64_t blk, int j, int64_t block, int K, int64_t N) {
-    const int64_t s = blk * block + (int64_t)j * (block / K);
-    return s < N ? s : N - 1;
-}
-
 // Query PAA from the FP64 normalised query: qpaa[q * 16 + t].
 __global__ void k_query_paa(const BatchArgs a, float *qpaa) {
     const int q = blockIdx.x, t = threadIdx.x;
@@ -254,50 +269,144 @@ __global__ void k_query_paa(const BatchArgs a, float *qpaa) {
     qpaa[q * 16 + t] = (float)(s / (hi - lo));
 }
 
-// Candidate PAA of every sampled start of a length-m query (shared by queries of that length).
-__global__ void k_cand_paa(const float *T, int64_t N, int m, int64_t nblocks, int64_t block, int K, float *cpaa) {
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= nblocks * K) return;
-    const int64_t s = sample_start(row / K, (int)(row % K), block, K, N);
-    float f[16];
-    paa16(T + s, m, f);
-    for (int t = 0; t < 16; ++t) cpaa[row * 16 + t] = f[t];
-}
+// Sums over a window from the blocked prefix (P1[x], P2[x]: sums of (T - anc[b]) and its square
+// over [b * kPB, x) for x in block b).  Relative to the anchor of the window's first block b0;
+// windows are at most 2048 points, so they end at most one block later.
+struct PrefixView {
+    const double *P1, *P2, *anc, *tot1, *tot2;
+    // sum of (T[y] - anc[b0]) over [b0 * kPB, x)
+    __device__ double s1(int64_t x, int64_t b0, double delta) const {
+        const int64_t e0 = (b0 + 1) * kPB;
+        if (x < e0) return P1[x];
+        const int64_t lx = x - e0;
+        return tot1[b0] + (lx ? P1[x] + (double)lx * delta : 0.0);
+    }
+    // sum of (T[y] - anc[b0])^2 over [b0 * kPB, x)
+    __device__ double s2(int64_t x, int64_t b0, double delta) const {
+        const int64_t e0 = (b0 + 1) * kPB;
+        if (x < e0) return P2[x];
+        const int64_t lx = x - e0;
+        return tot2[b0] + (lx ? P2[x] + 2.0 * delta * P1[x] + (double)lx * delta * delta : 0.0);
+    }
+    // 16-segment PAA of the z-normalised window T[i .. i+m) (segment t: [floor(t m/16),
+    // floor((t+1) m/16))); all zero for a flat window
+    __device__ void paa(int64_t i, int m, float *out) const {
+        const int64_t b0 = i / kPB;
+        const double delta = (i + m) > (b0 + 1) * kPB ? anc[b0 + 1] - anc[b0] : 0.0;
+        const double base = P1[i];
+        const double S1 = s1(i + m, b0, delta) - base, S2 = s2(i + m, b0, delta) - P2[i];
+        const double md = S1 / m, var = S2 / m - md * md;
+        const float inv = var > kSigmaFlat * kSigmaFlat ? (float)(1.0 / sqrt(var)) : 0.0f;
+        double prev = base;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int lo = (t * m) >> 4, hi = ((t + 1) * m) >> 4;
+            const double cur = s1(i + hi, b0, delta);
+            out[t] = (float)((cur - prev) / (hi - lo) - md) * inv;
+            prev = cur;
+        }
+    }
+};
 
-// Feature rows [row0, row0 + R) of the batch: row = row_off[q] + blk * K + j ->
-// (query PAA of q, candidate PAA of its sampled start); candidates from the shared per-length
-// table when cpaa_slot[q] >= 0, else computed here.
-__global__ void k_score_rows(const BatchArgs a, const float *qpaa, const float *cpaa, const int64_t *row_off,
-                             const int32_t *cpaa_slot, int64_t cpaa_stride, int K, int64_t row0, int64_t R, float *X) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Proposals: row (q, blk, j) covers the starts [blk * B + j * B / K, + B / K) of query q.  One wave
+// per row evaluates every ps-th start, ps = max(1, m / 64), and keeps the one whose PAA is nearest
+// (squared Euclidean) to the query's PAA, lowest start on ties.  Its features (query PAA, then
+// candidate PAA) go to X and its start to sstart; an empty quarter gets start -1 and zero features.
+__global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreArgs sa, int64_t row0, int64_t R,
+                                                 float *X) {
+    const int lane = threadIdx.x & 63;
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (k >= R) return;
     const int64_t row = row0 + k;
     int lo = 0, hi = a.nq;   // row_off[lo] <= row < row_off[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (row_off[mid] <= row) lo = mid;
+        if (sa.row_off[mid] <= row) lo = mid;
         else hi = mid;
     }
-    const int q = lo;
-    const int64_t local = row - row_off[q];
+    const int q = __builtin_amdgcn_readfirstlane(lo);
+    const int64_t local = row - sa.row_off[q];
     const BatchQ bq = a.bq[q];
+    const int m = bq.m;
+    const int64_t quarter = a.block / sa.K;
+    const int64_t first = (local / sa.K) * a.block + (local % sa.K) * quarter;
+    const int64_t last = first + quarter < bq.N ? first + quarter : bq.N;
     float *x = X + k * 32;
-    for (int t = 0; t < 16; ++t) x[t] = qpaa[q * 16 + t];
-    if (cpaa_slot[q] >= 0) {
-        const float *c = cpaa + cpaa_slot[q] * cpaa_stride + local * 16;
-        for (int t = 0; t < 16; ++t) x[16 + t] = c[t];
-    } else {
-        paa16(a.T + sample_start(local / K, (int)(local % K), a.block, K, bq.N), bq.m, x + 16);
+    if (first >= last) {
+        if (lane < 32) x[lane] = 0.0f;
+        if (lane == 0) sa.sstart[k] = -1;
+        return;
     }
+    float qp[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) qp[t] = sa.qpaa[q * 16 + t];
+    const PrefixView pv{sa.P1, sa.P2, sa.anc, sa.tot1, sa.tot2};
+    const int64_t ps = m >= 128 ? m >> 6 : 1;
+    uint64_t best = ~0ull;
+    for (int64_t i = first + lane * ps; i < last; i += 64 * ps) {
+        float f[16];
+        pv.paa(i, m, f);
+        float d = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const float e = f[t] - qp[t];
+            d = fmaf(e, e, d);
+        }
+        const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)i;
+        best = key < best ? key : best;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(best, off, 64);
+        best = o < best ? o : best;
+    }
+    const int64_t i = (int64_t)(uint32_t)best;
+    if (lane < 16) {
+        float f[16];
+        pv.paa(i, m, f);
+        float v = f[0];
+#pragma unroll
+        for (int t = 1; t < 16; ++t)
+            if (lane == t) v = f[t];
+        x[16 + lane] = v;
+    } else if (lane < 32) {
+        x[lane - 16] = qp[lane - 16];
+    }
+    if (lane == 0) sa.sstart[k] = (int32_t)i;
 }
 
-// score of a block = minimum predicted value over its K sampled starts
-__global__ void k_block_min(const float *y, int64_t R, int K, int64_t row0, float *score) {
+// Score of a block = minimum predicted value over its proposals; bstart = that proposal's start.
+__global__ void k_block_min(const float *y, const int32_t *sstart, int64_t R, int K, int64_t row0, float *score,
+                            int32_t *bstart) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b * K >= R) return;
-    float s = INFINITY;
-    for (int j = 0; j < K; ++j) s = fminf(s, y[b * K + j]);
+    float s = NAN;
+    int32_t st = -1;
+    for (int j = 0; j < K; ++j) {
+        const int32_t sj = sstart[b * K + j];
+        const float v = y[b * K + j];
+        if (sj >= 0 && (st < 0 || v < s)) {
+            s = v;
+            st = sj;
+        }
+    }
     score[row0 / K + b] = s;
+    bstart[row0 / K + b] = st;
+}
+
+// Round -1 of the learned order: the best-so-far of every query starts from the proposals of its
+// kSeedCands best-scored blocks (repeating the last when a query has fewer blocks).
+__global__ void k_seed_learned(BatchArgs a, const int32_t *bstart, const int64_t *row_off, int K) {
+    for (int q = threadIdx.x; q < a.nq; q += blockDim.x) {
+        const int64_t nb = a.bq[q].nblocks;
+        for (int k = 0; k < kSeedCands; ++k) {
+            const int64_t blk = a.perm[(int64_t)q * a.maxblocks + (k < nb ? k : nb - 1)];
+            a.surv_q[q * kSeedCands + k] = q;
+            a.surv_i[q * kSeedCands + k] = bstart[row_off[q] / K + blk];
+        }
+        a.qcnt[q] = kSeedCands;
+    }
+    if (threadIdx.x == 0) *a.surv_count = (uint32_t)(a.nq * kSeedCands);
 }
 
 // Visiting order of a query's blocks by ascending score: counting sort into 2048 buckets between
@@ -417,8 +526,10 @@ hipError_t mlp_backward(const MlpBufs &b, const float *X, const float *t, int64_
     if (e != hipSuccess) return e;
     e = mlp_gemm(b.XbT, Rp, b.dA1T, Rp, b.grad + kOffW1, 256, 32, 256, (int)Rp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mlp_colsums, dim3(1), dim3(256), 0, s, b.C1, b.H1b, b.C2, b.dy, b.theta + kOffw3, R,
-                       b.grad + kOffb1, b.grad + kOffb2, b.grad + kOffw3, b.grad + kOffb3);
+    hipLaunchKernelGGL(k_mlp_colsums_part, dim3(kColsumGroups), dim3(256), 0, s, b.C1, b.H1b, b.C2, b.dy,
+                       b.theta + kOffw3, R, b.part);
+    hipLaunchKernelGGL(k_mlp_colsums, dim3(1), dim3(256), 0, s, b.part, b.grad + kOffb1, b.grad + kOffb2,
+                       b.grad + kOffw3, b.grad + kOffb3);
     return hipGetLastError();
 }
 
@@ -434,21 +545,38 @@ hipError_t mlp_adam(const MlpBufs &b, int step, float lr, hipStream_t s) {
 // Scores every block of every query of the batch and writes the visiting order into a.perm.
 hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArgs &sa, hipStream_t s) {
     hipLaunchKernelGGL(k_query_paa, dim3(a.nq), dim3(64), 0, s, a, sa.qpaa);
-    for (int t = 0; t < sa.ncpaa; ++t) {
-        const int64_t rows = sa.cpaa_nblocks[t] * sa.K;
-        hipLaunchKernelGGL(k_cand_paa, dim3(nblk(rows)), dim3(256), 0, s, a.T, sa.cpaa_N[t], sa.cpaa_m[t],
-                           sa.cpaa_nblocks[t], a.block, sa.K, sa.cpaa + t * sa.cpaa_stride);
-    }
     const int64_t chunk = kMlpChunk / sa.K * sa.K;
     for (int64_t r0 = 0; r0 < sa.total_rows; r0 += chunk) {
         const int64_t R = sa.total_rows - r0 < chunk ? sa.total_rows - r0 : chunk;
-        hipLaunchKernelGGL(k_score_rows, dim3(nblk(R)), dim3(256), 0, s, a, sa.qpaa, sa.cpaa, sa.row_off,
-                           sa.cpaa_slot, sa.cpaa_stride, sa.K, r0, R, b.Xf);
+        hipLaunchKernelGGL(k_propose, dim3(nblk(R * 64)), dim3(256), 0, s, a, sa, r0, R, b.Xf);
         hipError_t e = mlp_forward(b, b.Xf, R, b.y, false, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_block_min, dim3(nblk(R / sa.K)), dim3(256), 0, s, b.y, R, sa.K, r0, sa.score);
+        hipLaunchKernelGGL(k_block_min, dim3(nblk(R / sa.K)), dim3(256), 0, s, b.y, sa.sstart, R, sa.K, r0, sa.score,
+                           sa.bstart);
     }
     hipLaunchKernelGGL(k_block_order, dim3(a.nq), dim3(1024), 0, s, a, sa.score, sa.row_off, sa.K);
+    return hipGetLastError();
+}
+
+__global__ void k_widen_starts(const int32_t *s32, int64_t R, int64_t *s64) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < R) s64[k] = s32[k];
+}
+
+// Proposals of every quarter block of the batch's first query: features into X (rows x 32) and
+// starts into starts (rows), rows = sa.total_rows.
+hipError_t launch_propose(const BatchArgs &a, const ScoreArgs &sa, float *X, int64_t *starts, hipStream_t s) {
+    hipLaunchKernelGGL(k_query_paa, dim3(a.nq), dim3(64), 0, s, a, sa.qpaa);
+    for (int64_t r0 = 0; r0 < sa.total_rows; r0 += kMlpChunk) {
+        const int64_t R = sa.total_rows - r0 < kMlpChunk ? sa.total_rows - r0 : kMlpChunk;
+        hipLaunchKernelGGL(k_propose, dim3(nblk(R * 64)), dim3(256), 0, s, a, sa, r0, R, X + r0 * 32);
+        hipLaunchKernelGGL(k_widen_starts, dim3(nblk(R)), dim3(256), 0, s, sa.sstart, R, starts + r0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_learned(const BatchArgs &a, const ScoreArgs &sa, hipStream_t s) {
+    hipLaunchKernelGGL(k_seed_learned, dim3(1), dim3(256), 0, s, a, sa.bstart, sa.row_off, sa.K);
     return hipGetLastError();
 }
 

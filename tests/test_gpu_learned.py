@@ -95,9 +95,38 @@ def test_adam_step_matches_reference(ctx):
     np.testing.assert_allclose(got, want, rtol=1e-5, atol=1e-6)
 
 
+def test_proposals_match_oracle(ctx):
+    """Per quarter block, the GPU proposal lies on the stride grid of its quarter and is (within
+    the FP32 error of the PAA distance) the oracle's nearest start; features = (query PAA,
+    candidate PAA).  Shapes: stride 2 / 1 / 4, a ragged last block, a flat stretch, and a window
+    that crosses the 4096-point blocks of the prefix."""
+    for n, m, seed in ((70_001, 128, 21), (50_000, 100, 22), (66_000, 300, 23)):
+        T = W.random_walk(n, seed)
+        T[20_000:21_500] = T[20_000]                       # flat windows (PAA all zero)
+        Q = W.noisy_cut(T, 12_345, m, 0.1, seed + 100)
+        st, X = ctx.propose(dev(T), dev(Q))
+        st, X = st.cpu().numpy(), X.cpu().numpy().astype(np.float64)
+        ost, od = M.proposals(T, Q)
+        assert st.shape == ost.shape
+        np.testing.assert_array_equal(st >= 0, ost >= 0)
+        v = st >= 0
+        k = np.nonzero(v)[0]
+        ps = m // 64 if m >= 128 else 1
+        assert np.all(st[v] % ps == 0) and np.all(st[v] // 1024 == k)
+        qp = M.paa(R.znorm(Q))
+        C = R.normalized_windows(T, m, st[v])
+        F = np.stack([C[:, (t * m) // 16:((t + 1) * m) // 16].mean(axis=1) for t in range(16)], axis=1)
+        d_gpu = ((F - qp) ** 2).sum(axis=1)
+        assert np.all(d_gpu <= od[v] + 2e-4 * (1.0 + od[v])), np.max(d_gpu - od[v])
+        assert np.mean(st[v] == ost[v]) > 0.95
+        np.testing.assert_allclose(X[v, :16], np.broadcast_to(qp, (k.size, 16)), atol=2e-5)
+        np.testing.assert_allclose(X[v, 16:], F, atol=2e-4)
+        np.testing.assert_array_equal(X[~v], 0.0)
+
+
 def test_training_reduces_loss(ctx):
     T = W.sinusoid_mix(1_000_000, 51)
-    X, Y = proposal.make_pairs(ctx, T, 128, 6, 100, 400, seed=52)
+    X, Y = proposal.make_pairs(ctx, T, 128, 6, 40, seed=52)
     curve = proposal.train(ctx, X, Y, epochs=6, batch=2048, lr=2e-3, seed=53)
     assert curve[-1] < 0.5 * curve[0], curve
 
@@ -106,8 +135,8 @@ def test_learned_order_identical_results_and_gain(ctx):
     """Same best matches under natural, random and learned block orders; the trained ordering
     reaches a tight best-so-far earlier and starts fewer DTW cells than the natural order."""
     train_T = W.sinusoid_mix(2_000_000, 61)
-    X, Y = proposal.make_pairs(ctx, train_T, 256, 12, 300, 500, seed=62)
-    proposal.train(ctx, X, Y, epochs=4, batch=4096, lr=1e-3, seed=63)
+    X, Y = proposal.make_pairs(ctx, train_T, 256, 12, 120, seed=62)
+    proposal.train(ctx, X, Y, epochs=10, batch=4096, lr=1e-3, seed=63)
     T = W.sinusoid_mix(2_500_000, 64)
     wl = W.mixed_queries(T, nq=12, m=256, seed=65)
     Td = dev(T)

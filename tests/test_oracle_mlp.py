@@ -69,3 +69,36 @@ def test_adam_first_step_is_signed_lr():
     g = np.array([0.3, -5.0, 1e-3])
     new, m, v = M.adam(theta, g, np.zeros(3), np.zeros(3), 1, 0.01)
     np.testing.assert_allclose(new, theta - 0.01 * np.sign(g), rtol=1e-4)
+
+
+def test_proposals_planted_copy_flat_series_and_tail():
+    """Proposals: a planted affine copy of the query on the stride grid is proposed by its quarter
+    at distance 0; the result is invariant to an affine change of the series; on a flat series
+    every PAA is zero, so each quarter proposes its first start (lowest start on ties); quarters
+    past the last candidate are empty."""
+    from paper_1812_10302_amd import workloads as W
+    rng = np.random.default_rng(11)
+    T = W.random_walk(9000, 12).astype(np.float64)
+    for m, p in ((128, 5002), (100, 3333), (300, 2048)):
+        Q = 2.5 * T[p:p + m] - 7.0
+        st, d = M.proposals(T, Q, block=1024)
+        ps = m // 64 if m >= 128 else 1
+        assert p % ps == 0
+        k = p // 256
+        assert st[k] == p and d[k] < 1e-20, (m, st[k], d[k])
+        N = T.size - m + 1
+        assert st.size == -(-N // 1024) * 4
+        valid = st >= 0
+        assert np.all(st[valid] // 256 == np.nonzero(valid)[0])
+        assert np.all(st[valid] % ps == 0)
+        np.testing.assert_array_equal(valid, np.arange(st.size) * 256 < N)
+        st2, d2 = M.proposals(0.5 * T + 100.0, Q, block=1024)
+        np.testing.assert_array_equal(st2, st)
+        np.testing.assert_allclose(d2, d, rtol=1e-9, atol=1e-12)
+    flat = np.full(3000, 4.0)
+    Q = rng.normal(0, 1, 64)
+    st, d = M.proposals(flat, Q, block=1024)
+    N = flat.size - 64 + 1
+    want = np.where(np.arange(st.size) * 256 < N, np.arange(st.size) * 256, -1)
+    np.testing.assert_array_equal(st, want)
+    assert np.allclose(d[st >= 0], (M.paa(np.asarray(Q - Q.mean()) / Q.std()) ** 2).sum())
