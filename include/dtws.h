@@ -194,6 +194,39 @@ DTWS_API int dtws_dtw_band(dtws_ctx *ctx, const float *T_dev, int64_t n, const f
 DTWS_API int dtws_bsf_update(dtws_ctx *ctx, uint64_t *keys_dev, const float *d_dev, const int64_t *idx_dev,
                              int64_t count, void *stream);
 
+/* ---------------------------------------------------------------- schedule
+ * How the work is cut and launched; no field changes a result.  dtws_set_schedule
+ * takes 0 in block / lb_blocks_per_cu / dtw_blocks_per_cu and -1 in diag_max
+ * for the defaults; dtws_get_schedule reports the values in effect. */
+typedef struct {
+    int64_t block;             /* candidates per work item of the batched search:
+                                  2048, 4096 (default), 8192 or 16384 */
+    int32_t lb_blocks_per_cu;  /* bound-cascade workgroups per compute unit, 1..64 (8) */
+    int32_t dtw_blocks_per_cu; /* one-lane-per-candidate DTW workgroups per compute
+                                  unit, 1..64 (4) */
+    int32_t diag_max;          /* a DTW round with at most this many candidates runs one
+                                  wave per candidate along anti-diagonals instead of one
+                                  lane per candidate (bands r <= 255; 0 = never; 8192) */
+    int32_t band_lanes;        /* dtws_dtw_band: 1 = one lane per candidate (default),
+                                  64 = one wave per candidate (r <= 255) */
+} dtws_schedule;
+
+DTWS_API int dtws_get_schedule(dtws_ctx *ctx, dtws_schedule *out_host);
+/* DTWS_EINVAL (nothing changed) when a field is outside the ranges above. */
+DTWS_API int dtws_set_schedule(dtws_ctx *ctx, const dtws_schedule *s_host);
+
+/* Autotuner: runs dtws_search_batch on the given batch (arguments as there;
+ * DTWS_PROFILE is ignored) under candidate schedules, by coordinate descent over
+ * diag_max, block, lb_blocks_per_cu and dtw_blocks_per_cu starting from the current
+ * schedule; each candidate is called once untimed (graph capture) and then `reps`
+ * times (1..100) timed on the host clock.  All candidates must return identical
+ * matches (DTWS_EHIP otherwise, schedule unchanged).  Installs the fastest, writes
+ * it to *best_host and its mean time per call (ms) to *best_ms_host.  Blocking. */
+DTWS_API int dtws_autotune_batch(dtws_ctx *ctx, const float *T_dev, int64_t n, const float *Q_packed_dev,
+                                 const int64_t *q_offsets_host, const int32_t *m_host, const int32_t *r_host,
+                                 int32_t nq, uint32_t flags, uint64_t seed, void *stream, int32_t reps,
+                                 dtws_schedule *best_host, double *best_ms_host);
+
 /* ------------------------------------------------- learned block ordering
  * Not part of the paper's method: a network scores blocks of candidates so that
  * DTWS_ORDER_LEARNED visits the most promising blocks first; the bounds and the

@@ -43,6 +43,14 @@ class Counters(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in COUNTER_FIELDS]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int64), ("lb_blocks_per_cu", ctypes.c_int32),
+                ("dtw_blocks_per_cu", ctypes.c_int32), ("diag_max", ctypes.c_int32), ("band_lanes", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 class DtwsError(RuntimeError):
     def __init__(self, code: int, what: str, detail: str = ""):
         self.code = code
@@ -91,6 +99,10 @@ def _load():
         "dtws_model_train_step": ([P, P, P, I64, F32, P, P], ctypes.c_int),
         "dtws_paa": ([P, P, I64, I32, P, I64, P, P], ctypes.c_int),
         "dtws_propose": ([P, P, I64, P, I32, P, P, I64, ctypes.POINTER(I64), P], ctypes.c_int),
+        "dtws_get_schedule": ([P, ctypes.POINTER(Schedule)], ctypes.c_int),
+        "dtws_set_schedule": ([P, ctypes.POINTER(Schedule)], ctypes.c_int),
+        "dtws_autotune_batch": ([P, P, I64, P, P, P, P, I32, U32, U64, P, I32, ctypes.POINTER(Schedule),
+                                 ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -345,6 +357,37 @@ class Context:
         self._check(lib.dtws_propose(self._h, T.data_ptr(), T.numel(), Q.data_ptr(), Q.numel(), starts.data_ptr(),
                                      X.data_ptr(), rows.value, ctypes.byref(rows), _stream(T)), "dtws_propose")
         return starts[:rows.value], X[:rows.value]
+
+    def get_schedule(self) -> dict:
+        """Launch schedule in effect (block, lb_blocks_per_cu, dtw_blocks_per_cu, diag_max, band_lanes)."""
+        sc = Schedule()
+        self._check(_load().dtws_get_schedule(self._h, ctypes.byref(sc)), "dtws_get_schedule")
+        return sc.as_dict()
+
+    def set_schedule(self, **fields):
+        """Change some schedule fields (the others keep their current values)."""
+        cur = self.get_schedule()
+        unknown = set(fields) - set(cur)
+        if unknown:
+            raise ValueError(f"unknown schedule fields {sorted(unknown)}")
+        cur.update(fields)
+        sc = Schedule(**cur)
+        self._check(_load().dtws_set_schedule(self._h, ctypes.byref(sc)), "dtws_set_schedule")
+
+    def autotune_batch(self, T, queries, rs, flags: int = ORDER_NATURAL, seed: int = 0, reps: int = 3):
+        """Pick and install the fastest schedule for this batch; returns (schedule dict, ms per call)."""
+        _dev_f32(T, "T")
+        pq = queries if isinstance(queries, PackedQueries) else PackedQueries(queries)
+        rr = np.array([int(x) for x in rs], np.int32)
+        if rr.size != len(pq):
+            raise ValueError("one band per query")
+        sc = Schedule()
+        ms = ctypes.c_double(0.0)
+        self._check(_load().dtws_autotune_batch(self._h, T.data_ptr(), T.numel(), pq.packed.data_ptr(),
+                                                pq.offsets.ctypes.data, pq.ms.ctypes.data, rr.ctypes.data,
+                                                len(pq), int(flags), int(seed), _stream(T), int(reps),
+                                                ctypes.byref(sc), ctypes.byref(ms)), "dtws_autotune_batch")
+        return sc.as_dict(), float(ms.value)
 
     def bsf_update(self, keys, d, idx):
         """Atomically lower keys[0] to the minimum packed (distance, index) key."""

@@ -17,6 +17,9 @@ namespace {
 constexpr int kNumCounters = 16;
 constexpr int64_t kMinBlock = 2048;   // smallest work-item block (sizes the order arrays)
 constexpr int64_t kDefaultBlock = 4096;
+constexpr int kDefaultDiagMax = 8192;  // rounds with at most this many survivors: one wave per candidate
+
+int diag_max_of(const dtws_ctx *c) { return c->diag_max >= 0 ? c->diag_max : kDefaultDiagMax; }
 
 void set_err(dtws_ctx *c, hipError_t e, const char *what) {
     if (!c) return;
@@ -129,13 +132,16 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
     d.nb_count = c->nb_count;
     d.counters = c->counters;
     d.abandon_at = INFINITY;
+    const bool diag = r <= kDiagMaxBand;
+    d.diag_max = diag ? (uint32_t)diag_max_of(c) : 0u;
 
     // best-so-far from one seeded random candidate (Algorithm 1, before the main loop)
     {
         DtwArgs d0 = d;
         d0.single = (int64_t)(splitmix64(seed) % (uint64_t)N);
         PROF(DTWS_K_DTW);
-        HIPCHK(c, launch_dtw(d0, true, 1, c->num_cu, c->gen_rows, c->gen_lanes, s));
+        if (diag) HIPCHK(c, launch_dtw_diag_list(d0, true, 1, s));
+        else HIPCHK(c, launch_dtw(d0, true, 1, c->num_cu, c->gen_rows, c->gen_lanes, s));
     }
 
     LbArgs l{};
@@ -176,7 +182,9 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
             ds.count_dev = c->surv_count;
             ds.count = a1 - a0;
             PROF(DTWS_K_DTW);
+            // both schedules are enqueued; the device-side survivor count picks the one that runs
             HIPCHK(c, launch_dtw(ds, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
+            if (ds.diag_max > 0) HIPCHK(c, launch_dtw_diag_list(ds, true, c->num_cu * 4, s));
         }
         a0 = a1;
         size *= 16;   // 64K, 1M, then the rest: few launches once the best-so-far is tight
@@ -360,6 +368,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     a.counters = c->counters;
     a.wide_rows = c->gen_rows;
     a.wide_lanes = c->gen_lanes;
+    a.diag_max = p.max_r <= kDiagMaxBand ? (uint32_t)diag_max_of(c) : 0u;
 
     QueryBufs base{};
     base.qpad = c->qpad;
@@ -433,6 +442,10 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
             if (!p.bucket_used[nc]) continue;
             PROF(DTWS_K_DTW);
             HIPCHK(c, launch_dtw_bucket(a, !same_m, nc, dtw_blocks, s));
+        }
+        if (a.diag_max > 0) {
+            PROF(DTWS_K_DTW);
+            HIPCHK(c, launch_dtw_diag(a, !same_m, c->num_cu * 4, s));
         }
         return DTWS_OK;
     };
@@ -521,7 +534,7 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
         // The graph is rebuilt when anything it bakes in changes: pointers, sizes, flags, seed, the
         // per-query parameters and the tuning knobs.
         std::vector<int64_t> sig = {(int64_t)(uintptr_t)T, n, (int64_t)(uintptr_t)Qp, nq, (int64_t)flags,
-                                    (int64_t)seed, p.block, c->lb_blocks_per_cu, c->dtw_blocks_per_cu};
+                                    (int64_t)seed, p.block, c->lb_blocks_per_cu, c->dtw_blocks_per_cu, c->diag_max};
         for (int k = 0; k < nq; ++k) {
             sig.push_back(qoff[k]);
             sig.push_back(mh[k]);
@@ -1001,7 +1014,12 @@ DTWS_API int dtws_dtw_band(dtws_ctx *c, const float *T, int64_t n, const float *
     d.single = -1;
     d.abandon_at = abandon_at;
     d.dist_out = dist;
-    HIPCHK(c, launch_dtw(d, false, count, c->num_cu, c->gen_rows, c->gen_lanes, s));
+    if (c->band_lanes == 64 && r <= kDiagMaxBand) {
+        const int64_t blocks = (count + 1) / 2;
+        HIPCHK(c, launch_dtw_diag_list(d, false, (int)(blocks < c->num_cu * 8 ? blocks : c->num_cu * 8), s));
+    } else {
+        HIPCHK(c, launch_dtw(d, false, count, c->num_cu, c->gen_rows, c->gen_lanes, s));
+    }
     return DTWS_OK;
 }
 

@@ -15,7 +15,7 @@
 // window's sums are a difference of two nearby partial sums (re-anchored when the window crosses
 // one block boundary; m <= 2048 < 4096 crosses at most one).  When all queries share one length
 // the per-window arrays of the statistics pass are used instead.
-#include "device.h"
+#include "batch_stats.h"
 
 namespace dtws {
 
@@ -85,73 +85,6 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
         tot2[b] = t2;
     }
 }
-
-// Mean and population sigma of T[i .. i+m) from the blocked prefix (FP64).  Windows whose prefix
-// difference may have lost relative precision (short windows, heavy cancellation) are recomputed
-// two-pass from the series.
-struct StatsPrefix {
-    const float *T;
-    const double *P1, *P2, *anc, *tot1, *tot2;
-    int m;
-    double inv_m;
-    // mean and variance of window i
-    __device__ void window(int64_t i, double &mu, double &var) const {
-        const int64_t e = i + m;
-        const int64_t b0 = i / kPB, b1 = (e - 1) / kPB;
-        double e1, e2;
-        if (e == (b1 + 1) * kPB) {
-            e1 = tot1[b1];
-            e2 = tot2[b1];
-        } else {
-            e1 = P1[e];
-            e2 = P2[e];
-        }
-        double S1, S2;
-        if (b0 == b1) {
-            S1 = e1 - P1[i];
-            S2 = e2 - P2[i];
-        } else {
-            const double delta = anc[b1] - anc[b0];
-            const double c2 = (double)(e - b1 * kPB);
-            S1 = (tot1[b0] - P1[i]) + e1 + c2 * delta;
-            S2 = (tot2[b0] - P2[i]) + e2 + 2.0 * delta * e1 + c2 * delta * delta;
-        }
-        const double md = S1 * inv_m, msq = S2 * inv_m;
-        var = msq - md * md;
-        mu = anc[b0] + md;
-        if (m <= 64 || !(var > 4e-6 * msq)) {
-            const float *w = T + i;
-            double s = 0.0;
-            for (int j = 0; j < m; ++j) s += (double)w[j];
-            mu = s / m;
-            double q = 0.0;
-            for (int j = 0; j < m; ++j) {
-                const double d = (double)w[j] - mu;
-                q += d * d;
-            }
-            var = q / m;
-        }
-        if (!(var > 0.0)) var = 0.0;
-    }
-    // The scale is stored in FP32 anyway, so 1/sigma comes from the FP32 reciprocal square root
-    // of the FP64 variance (relative error ~2^-23); flat windows (sigma <= 1e-8) get scale 0.
-    __device__ void operator()(int64_t i, float &mu32, float &s, float &o) const {
-        double mu, var;
-        window(i, mu, var);
-        mu32 = (float)mu;
-        s = var <= kSigmaFlat * kSigmaFlat ? 0.0f : rsqrtf((float)var);
-        o = (float)(-(mu - (double)mu32)) * s;
-    }
-};
-
-struct StatsArr {
-    const float *mu, *s, *o;   // already offset to the query's statistics slot
-    __device__ void operator()(int64_t i, float &m, float &sg, float &off) const {
-        m = mu[i];
-        sg = s[i];
-        off = o[i];
-    }
-};
 
 // ------------------------------------------------------------------ work order
 // Primes above any block count (series < 2^31 points, blocks >= 2048 points): A = p mod nb is
@@ -395,7 +328,7 @@ __device__ inline void stats_of(const Stats &st, int64_t i, float &mu, float &s,
 template <int NC, bool PREFIX>
 __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
     constexpr int W = 16 * NC;
-    if (*a.overflow) return;
+    if (*a.overflow || *a.surv_count <= a.diag_max) return;
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -454,7 +387,7 @@ __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
 template <bool PREFIX>
 __global__ __launch_bounds__(64) void k_dtw_batch_wide(BatchArgs a) {
     constexpr int c = kMaxChunks + 1;
-    if (*a.overflow) return;
+    if (*a.overflow || *a.surv_count <= a.diag_max) return;
     const int lane = threadIdx.x & 63;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t wave = g >> 6, nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -713,8 +646,13 @@ hipError_t launch_dtw_bucket(const BatchArgs &a, bool prefix, int nc, int blocks
 
 hipError_t launch_cert_batch(const BatchArgs &a, int max_m, int max_r, hipStream_t s) {
     hipLaunchKernelGGL(k_cert_select_batch, dim3(16), dim3(256), 0, s, a);
-    const size_t shm = sizeof(double) * (2 * (size_t)max_m + 3 * (size_t)(max_r + 4));
-    hipLaunchKernelGGL(k_cert_dtw_batch, dim3(256), dim3(max_r < 64 ? 64 : 256), shm, s, a);
+    if (max_r <= kDiagMaxBand) {
+        hipError_t e = launch_cert_diag(a, 256, s);
+        if (e != hipSuccess) return e;
+    } else {
+        const size_t shm = sizeof(double) * (2 * (size_t)max_m + 3 * (size_t)(max_r + 4));
+        hipLaunchKernelGGL(k_cert_dtw_batch, dim3(256), dim3(max_r < 64 ? 64 : 256), shm, s, a);
+    }
     hipLaunchKernelGGL(k_cert_reduce_batch, dim3(a.nq), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -35,6 +35,7 @@ __global__ __launch_bounds__(256) void k_dtw(DtwArgs a) {
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     int64_t count = a.single >= 0 ? 1 : (a.count_dev ? (int64_t)*a.count_dev : a.count);
     if (a.count_dev && count > a.count) count = a.count;
+    if (SEARCH && a.count_dev && count <= (int64_t)a.diag_max) return;   // the one-wave kernel's round
     const int m = a.m, r = a.r;
     unsigned long long n_started = 0, n_aband = 0, n_cells = 0, n_lane_cells = 0;
 
@@ -104,6 +105,7 @@ __global__ __launch_bounds__(64) void k_dtw_wide(DtwArgs a, float *rows, int64_t
     if (g >= nlanes) return;
     int64_t count = a.single >= 0 ? 1 : (a.count_dev ? (int64_t)*a.count_dev : a.count);
     if (a.count_dev && count > a.count) count = a.count;
+    if (SEARCH && a.count_dev && count <= (int64_t)a.diag_max) return;   // the one-wave kernel's round
     const int m = a.m, r = a.r;
     const float *qh = a.qpad + kQPad;
     float *prev = rows + g * 2 * (int64_t)(m + 1), *cur = prev + (m + 1);
@@ -482,8 +484,12 @@ hipError_t launch_certify(const CertArgs &c, hipStream_t s) {
     hipError_t e = launch_fill_u32(c.cert_count, 0, 1, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cert_select, dim3(1), dim3(256), 0, s, c);
-    const int threads = c.r < 64 ? 64 : kCertThreads;   // one wave when an anti-diagonal fits in it
-    hipLaunchKernelGGL(k_cert_dtw, dim3(kCertBlocks), dim3(threads), shm, s, c);
+    if (c.r <= kDiagMaxBand) {
+        e = launch_cert_diag_list(c, kCertBlocks, s);   // one wave per candidate along anti-diagonals
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_cert_dtw, dim3(kCertBlocks), dim3(kCertThreads), shm, s, c);
+    }
     hipLaunchKernelGGL(k_cert_reduce, dim3(1), dim3(256), 0, s, c);
     return hipGetLastError();
 }

@@ -86,6 +86,7 @@ struct DtwArgs {
     int64_t single;              // >= 0: evaluate only this start
     const float *mu, *s, *o;     // per-window normalisation, or null to compute per lane
     float abandon_at;            // threshold of the stage entry point
+    uint32_t diag_max;           // search rounds of at most this many survivors: one wave per candidate
     float *dist_out;             // stage entry point output
     uint64_t *key;               // search mode: best-so-far key
     float *nb_d;
@@ -157,6 +158,7 @@ struct BatchArgs {
     unsigned long long *counters;
     float *wide_rows;
     int64_t wide_lanes;
+    uint32_t diag_max;         // rounds with at most this many survivors use one wave per candidate
 };
 
 // ---------------------------------------------------------------- ordering network
@@ -220,6 +222,12 @@ hipError_t mlp_adam(const MlpBufs &b, int step, float lr, hipStream_t s);
 hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArgs &sa, hipStream_t s);
 hipError_t launch_seed_learned(const BatchArgs &a, const ScoreArgs &sa, hipStream_t s);
 hipError_t launch_propose(const BatchArgs &a, const ScoreArgs &sa, float *X, int64_t *starts, hipStream_t s);
+constexpr int kDiagMaxBand = 255;        // widest band of the one-wave-per-candidate kernels
+size_t diag_lds_bytes(int max_m, bool fp64);
+hipError_t launch_dtw_diag(const BatchArgs &a, bool prefix, int blocks, hipStream_t s);
+hipError_t launch_cert_diag(const BatchArgs &a, int blocks, hipStream_t s);
+hipError_t launch_dtw_diag_list(const DtwArgs &a, bool search, int blocks, hipStream_t s);
+hipError_t launch_cert_diag_list(const CertArgs &c, int blocks, hipStream_t s);
 hipError_t launch_paa(const float *T, int64_t n, int m, const int64_t *starts, int64_t count, float *out,
                       hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
@@ -287,6 +295,8 @@ struct dtws_ctx {
     // tuning knobs (0 = default): candidates per work item, launch widths per compute unit
     int64_t block = 0;
     int lb_blocks_per_cu = 0, dtw_blocks_per_cu = 0;
+    int diag_max = -1;   // survivors per round below which DTW runs one wave per candidate (-1: default)
+    int band_lanes = 1;  // dtws_dtw_band: 1 = one lane per candidate, 64 = one wave per candidate
     // ordering network
     dtws::MlpBufs mlp{};
     bool has_model = false;

@@ -1,0 +1,122 @@
+// Launch schedule of a context and the autotuner that picks it.
+//
+// None of the knobs changes a result: the block size only cuts the work queue differently, the
+// launch widths only change how many workgroups share it, and the two DTW schedules (one lane per
+// candidate, or one wave per candidate along anti-diagonals) compute the same recurrence.  The
+// autotuner therefore checks that every schedule it times returns identical matches.
+#include <chrono>
+#include <vector>
+
+#include "dtws_internal.h"
+
+namespace {
+
+constexpr int64_t kBlocks[] = {2048, 4096, 8192, 16384};
+constexpr int32_t kDiagMaxes[] = {0, 1024, 8192, 65536};
+constexpr int32_t kLbWidths[] = {4, 8, 16, 32};
+constexpr int32_t kDtwWidths[] = {2, 4, 8};
+
+bool valid_block(int64_t b) {
+    if (b == 0) return true;
+    for (int64_t x : kBlocks)
+        if (b == x) return true;
+    return false;
+}
+
+bool same(const std::vector<dtws_match> &a, const std::vector<dtws_match> &b) {
+    for (size_t k = 0; k < a.size(); ++k)
+        if (a[k].index != b[k].index || a[k].distance != b[k].distance || a[k].status != b[k].status) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+DTWS_API int dtws_get_schedule(dtws_ctx *c, dtws_schedule *out) {
+    if (!c || !out) return DTWS_EINVAL;
+    out->block = c->block > 0 ? c->block : 4096;
+    out->lb_blocks_per_cu = c->lb_blocks_per_cu > 0 ? c->lb_blocks_per_cu : 8;
+    out->dtw_blocks_per_cu = c->dtw_blocks_per_cu > 0 ? c->dtw_blocks_per_cu : 4;
+    out->diag_max = c->diag_max >= 0 ? c->diag_max : 8192;
+    out->band_lanes = c->band_lanes;
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_set_schedule(dtws_ctx *c, const dtws_schedule *s) {
+    if (!c || !s) return DTWS_EINVAL;
+    if (!valid_block(s->block) || s->lb_blocks_per_cu < 0 || s->lb_blocks_per_cu > 64 || s->dtw_blocks_per_cu < 0 ||
+        s->dtw_blocks_per_cu > 64 || s->diag_max < -1 || s->diag_max > (1 << 24) ||
+        (s->band_lanes != 1 && s->band_lanes != 64))
+        return DTWS_EINVAL;
+    c->block = s->block;
+    c->lb_blocks_per_cu = s->lb_blocks_per_cu;
+    c->dtw_blocks_per_cu = s->dtw_blocks_per_cu;
+    c->diag_max = s->diag_max;
+    c->band_lanes = s->band_lanes;
+    return DTWS_OK;
+}
+
+DTWS_API int dtws_autotune_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int64_t *qoff,
+                                 const int32_t *mh, const int32_t *rh, int32_t nq, uint32_t flags, uint64_t seed,
+                                 void *stream, int32_t reps, dtws_schedule *best_out, double *best_ms_out) {
+    if (!c || !best_out || !best_ms_out || reps < 1 || reps > 100 || nq < 1 || nq > c->max_q) return DTWS_EINVAL;
+    flags &= ~(uint32_t)DTWS_PROFILE;
+    dtws_schedule start{};
+    dtws_get_schedule(c, &start);
+    std::vector<dtws_match> ref(nq), got(nq);
+    // one untimed call (it captures the graph), then `reps` timed calls
+    auto run = [&](const dtws_schedule &sc, std::vector<dtws_match> &out, double &ms) -> int {
+        int rc = dtws_set_schedule(c, &sc);
+        if (rc != DTWS_OK) return rc;
+        rc = dtws_search_batch(c, T, n, Qp, qoff, mh, rh, nq, flags, seed, stream, out.data());
+        if (rc != DTWS_OK) return rc;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int k = 0; k < reps; ++k) {
+            rc = dtws_search_batch(c, T, n, Qp, qoff, mh, rh, nq, flags, seed, stream, out.data());
+            if (rc != DTWS_OK) return rc;
+        }
+        ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
+        return DTWS_OK;
+    };
+    dtws_schedule best = start;
+    double best_ms = 0.0;
+    int rc = run(best, ref, best_ms);
+    // coordinate descent: each knob in turn over its candidate values, keeping the fastest
+    for (int knob = 0; knob < 4 && rc == DTWS_OK; ++knob) {
+        const int count = knob == 0 ? 4 : knob == 1 ? 4 : knob == 2 ? 4 : 3;
+        const dtws_schedule base = best;
+        for (int v = 0; v < count && rc == DTWS_OK; ++v) {
+            dtws_schedule t = base;
+            if (knob == 0) t.diag_max = kDiagMaxes[v];
+            else if (knob == 1) t.block = kBlocks[v];
+            else if (knob == 2) t.lb_blocks_per_cu = kLbWidths[v];
+            else t.dtw_blocks_per_cu = kDtwWidths[v];
+            if (t.diag_max == base.diag_max && t.block == base.block && t.lb_blocks_per_cu == base.lb_blocks_per_cu &&
+                t.dtw_blocks_per_cu == base.dtw_blocks_per_cu)
+                continue;
+            double ms = 0.0;
+            rc = run(t, got, ms);
+            if (rc != DTWS_OK) break;
+            if (!same(ref, got)) {
+                snprintf(c->lasterr, sizeof(c->lasterr), "autotune: schedules returned different matches");
+                rc = DTWS_EHIP;
+                break;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+    }
+    if (rc != DTWS_OK) {
+        dtws_set_schedule(c, &start);
+        return rc;
+    }
+    dtws_set_schedule(c, &best);
+    *best_out = best;
+    *best_ms_out = best_ms;
+    return DTWS_OK;
+}
+
+}  // extern "C"

@@ -281,3 +281,89 @@ def test_batch_graph_replays_match_eager(ctx, casc):
         assert ctx.search_batch(Td, pq, rs) == eager, rep
         ctx.search(Td, dev(qs[rep % 3]), rs[rep % 3])            # eager work between replays
         torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------- schedules
+@pytest.mark.parametrize("n,m,r", [(400, 2, 0), (400, 2, 1), (900, 3, 2), (2500, 17, 4), (2000, 100, 0),
+                                   (3000, 130, 63), (3000, 130, 64), (2000, 300, 127), (2100, 300, 128),
+                                   (1500, 400, 255), (4200, 2048, 102), (2048, 2048, 255), (1200, 256, 255)])
+def test_dtw_band_wave_schedule(ctx, n, m, r):
+    """One wave per candidate along anti-diagonals (odd / even bands, one to four slot registers,
+    r = 0, r = m - 1 clamped, n = m) against the oracle, and against the lane schedule."""
+    T, Q = W.tiny_random(n, m, 7 * n + m + r)
+    N = n - m + 1
+    starts = np.arange(0, N, max(1, N // 600), dtype=np.int64)
+    ref = R.distances_at(T, Q, r, starts)
+    try:
+        ctx.set_schedule(band_lanes=64)
+        got = ctx.dtw_band(dev(T), dev(Q), r, dev(starts)).cpu().numpy()
+    finally:
+        ctx.set_schedule(band_lanes=1)
+    close_rel(got, ref)
+    lane = ctx.dtw_band(dev(T), dev(Q), r, dev(starts)).cpu().numpy()
+    close_rel(got, lane)
+
+
+def test_dtw_band_wave_schedule_abandon_and_invalid(ctx, small_wl):
+    wl, D = small_wl
+    thr = float(np.quantile(D, 0.05))
+    starts = np.random.default_rng(5).integers(0, D.size, 3000)
+    try:
+        ctx.set_schedule(band_lanes=64)
+        got = ctx.dtw_band(dev(wl.T), dev(wl.queries[0]), wl.bands[0], dev(starts), abandon_at=thr).cpu().numpy()
+        bad = np.array([-1, D.size, 5], dtype=np.int64)
+        g = ctx.dtw_band(dev(wl.T), dev(wl.queries[0]), wl.bands[0], dev(bad)).cpu().numpy()
+    finally:
+        ctx.set_schedule(band_lanes=1)
+    fin = np.isfinite(got)
+    close_rel(got[fin], D[starts[fin]])
+    assert np.all(D[starts[~fin]] > thr * (1 - 1e-5))
+    assert np.all(fin[D[starts] <= thr * 0.999])
+    assert np.isnan(g[:2]).all() and abs(g[2] - D[5]) <= 1e-4 * D[5] + 1e-5
+
+
+def test_schedules_give_identical_results(ctx, casc):
+    """Every DTW schedule (lane only, wave only, the default split) and every block size returns
+    the oracle's matches, for the plain and the batched search."""
+    T = W.random_walk(200_003, 35)
+    specs = [(64, 3), (128, 6), (200, 20), (300, 150), (512, 25), (1000, 255), (777, 0)]
+    qs = [W.noisy_cut(T, 7_000 + 27_000 * k, m, 0.1, 950 + k) if k % 2 == 0 else W.random_walk(m, 960 + k)
+          for k, (m, r) in enumerate(specs)]
+    rs = [r for _, r in specs]
+    ref = _cascade_refs(casc, T, qs, rs)
+    Td = dev(T)
+    Qd = [dev(q) for q in qs]
+    default = ctx.get_schedule()
+    try:
+        for sched in ({"diag_max": 0}, {"diag_max": 1 << 24}, {"diag_max": 8192, "block": 2048},
+                      {"diag_max": 64, "block": 16384, "lb_blocks_per_cu": 2, "dtw_blocks_per_cu": 1}):
+            ctx.set_schedule(**sched)
+            _check_batch(ctx.search_batch(Td, Qd, rs), ref)
+            _check_batch([ctx.search(Td, q, r, seed=3) for q, r in zip(Qd, rs)], ref)
+    finally:
+        ctx.set_schedule(**default)
+
+
+def test_set_schedule_rejects_bad_fields(ctx):
+    default = ctx.get_schedule()
+    for bad in ({"block": 3000}, {"diag_max": -2}, {"band_lanes": 2}, {"lb_blocks_per_cu": 65}):
+        with pytest.raises(dtws.DtwsError):
+            ctx.set_schedule(**bad)
+        assert ctx.get_schedule() == default
+
+
+def test_autotune_installs_a_candidate_schedule(ctx, casc):
+    T = W.random_walk(300_000, 36)
+    qs = [W.noisy_cut(T, 11_000 + 61_000 * k, m, 0.1, 970 + k) for k, m in enumerate((128, 256, 512))]
+    rs = [6, 12, 25]
+    default = ctx.get_schedule()
+    try:
+        pq = dtws.PackedQueries([dev(q) for q in qs])
+        best, ms = ctx.autotune_batch(dev(T), pq, rs, reps=2)
+        assert ms > 0
+        assert best["block"] in (2048, 4096, 8192, 16384) and best["diag_max"] in (0, 1024, 8192, 65536)
+        assert best["lb_blocks_per_cu"] in (4, 8, 16, 32) and best["dtw_blocks_per_cu"] in (2, 4, 8)
+        assert ctx.get_schedule() == best
+        _check_batch(ctx.search_batch(dev(T), pq, rs), _cascade_refs(casc, T, qs, rs))
+    finally:
+        ctx.set_schedule(**default)
