@@ -126,6 +126,10 @@ def main():
         return (time.perf_counter() - t1) / args.steps, res
 
     natural_step_s, natural_results = time_batched(dtws.ORDER_NATURAL)
+    # launch schedule for the learned batch picked by the library's autotuner (untimed)
+    t0 = time.time()
+    schedule, tune_ms = ctx.autotune_batch(T, pq, rs, flags=dtws.ORDER_LEARNED, seed=7, reps=3)
+    log(f"autotuned schedule {schedule} ({tune_ms:.2f} ms per batch, tuning took {time.time() - t0:.1f}s)")
     elapsed_step, results = time_batched(dtws.ORDER_LEARNED)
     ms_per_step = elapsed_step * 1e3
     s_per_query = elapsed_step / nq
@@ -210,6 +214,7 @@ def main():
         "ordering_network": {"train_series": f"random walk n={args.train_n} seed 8", "pairs": int(sum(x.shape[0] for x in Xs)),
                              "epochs": args.train_epochs, "loss_curve": [round(v, 5) for v in curve],
                              "train_s": round(train_s, 2)},
+        "schedule": schedule,
         "plain_s_per_query": round(plain_s, 6),
         "batched_over_plain": round(s_per_query / plain_s, 4),
         "roofline": roofline,

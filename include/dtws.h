@@ -206,9 +206,17 @@ typedef struct {
                                   unit, 1..64 (4) */
     int32_t diag_max;          /* a DTW round with at most this many candidates runs one
                                   wave per candidate along anti-diagonals instead of one
-                                  lane per candidate (bands r <= 255; 0 = never; 8192) */
-    int32_t band_lanes;        /* dtws_dtw_band: 1 = one lane per candidate (default),
-                                  64 = one wave per candidate (r <= 255) */
+                                  lane per candidate (bands r <= 255; 0 = never; 16384).
+                                  Bands 112 <= r <= 255 always run one wave per candidate */
+    int32_t band_lanes;        /* dtws_dtw_band: 0 = automatic (default: one wave per
+                                  candidate for r <= 255 when count <= diag_max or r >= 112,
+                                  else one lane), 1 = one lane per candidate, 64 = one wave
+                                  per candidate (r <= 255) */
+    int32_t stats_prefix;      /* batched search, window statistics: 0 = per-length arrays
+                                  when the batch has few distinct lengths (default), 1 =
+                                  always from the blocked prefix of the series */
+    int32_t data_envelope;     /* batched search: 1 = the cascade's data-envelope bound
+                                  (default), 0 = skip it (no envelope pass) */
 } dtws_schedule;
 
 DTWS_API int dtws_get_schedule(dtws_ctx *ctx, dtws_schedule *out_host);
@@ -217,8 +225,8 @@ DTWS_API int dtws_set_schedule(dtws_ctx *ctx, const dtws_schedule *s_host);
 
 /* Autotuner: runs dtws_search_batch on the given batch (arguments as there;
  * DTWS_PROFILE is ignored) under candidate schedules, by coordinate descent over
- * diag_max, block, lb_blocks_per_cu and dtw_blocks_per_cu starting from the current
- * schedule; each candidate is called once untimed (graph capture) and then `reps`
+ * diag_max, block, lb_blocks_per_cu, dtw_blocks_per_cu, stats_prefix and
+ * data_envelope starting from the current schedule; each candidate is called once untimed (graph capture) and then `reps`
  * times (1..100) timed on the host clock.  All candidates must return identical
  * matches (DTWS_EHIP otherwise, schedule unchanged).  Installs the fastest, writes
  * it to *best_host and its mean time per call (ms) to *best_ms_host.  Blocking. */

@@ -17,7 +17,7 @@ namespace {
 constexpr int kNumCounters = 16;
 constexpr int64_t kMinBlock = 2048;   // smallest work-item block (sizes the order arrays)
 constexpr int64_t kDefaultBlock = 4096;
-constexpr int kDefaultDiagMax = 8192;  // rounds with at most this many survivors: one wave per candidate
+constexpr int kDefaultDiagMax = 16384;  // rounds with at most this many survivors: one wave per candidate
 
 int diag_max_of(const dtws_ctx *c) { return c->diag_max >= 0 ? c->diag_max : kDefaultDiagMax; }
 
@@ -132,8 +132,9 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
     d.nb_count = c->nb_count;
     d.counters = c->counters;
     d.abandon_at = INFINITY;
+    // one wave per candidate for small rounds, and always for bands wider than the register kernel
     const bool diag = r <= kDiagMaxBand;
-    d.diag_max = diag ? (uint32_t)diag_max_of(c) : 0u;
+    d.diag_max = !diag ? 0u : (2 * r + 1 > 16 * kMaxChunks ? 0xFFFFFFFFu : (uint32_t)diag_max_of(c));
 
     // best-so-far from one seeded random candidate (Algorithm 1, before the main loop)
     {
@@ -291,7 +292,7 @@ BatchPlan plan_batch(dtws_ctx *c, int64_t n, const int64_t *qoff, const int32_t 
         b.stat_slot = sm < 0 ? 0 : sm;
         b.env_slot = sr < 0 ? 0 : sr;
     }
-    p.same_m = m_fit;
+    p.same_m = m_fit && !c->stats_prefix;
     if (!r_fit) {
         // too many distinct bands: one envelope for the largest band, valid (looser) for all
         p.nr = 1;
@@ -335,8 +336,8 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         a.tot1 = c->tot1;
         a.tot2 = c->tot2;
     }
-    a.envU = c->envU;
-    a.envL = c->envL;
+    a.envU = c->data_envelope ? c->envU : nullptr;
+    a.envL = c->data_envelope ? c->envL : nullptr;
     a.slot_stride = c->max_n;
     a.perm = c->perm;
     a.maxblocks = c->maxblocks;
@@ -369,6 +370,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     a.wide_rows = c->gen_rows;
     a.wide_lanes = c->gen_lanes;
     a.diag_max = p.max_r <= kDiagMaxBand ? (uint32_t)diag_max_of(c) : 0u;
+    a.diag_wide = p.max_r <= kDiagMaxBand;
 
     QueryBufs base{};
     base.qpad = c->qpad;
@@ -403,7 +405,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         PROF(DTWS_K_STATS);
         HIPCHK(c, launch_prefix(T, n, c->P1, c->P2, c->anc, c->tot1, c->tot2, s));
     }
-    for (int t = 0; t < p.nr; ++t) {
+    for (int t = 0; t < p.nr && c->data_envelope; ++t) {
         PROF(DTWS_K_ENV);
         const int64_t so = (int64_t)t * c->max_n;
         HIPCHK(c, launch_series_env(T, n, p.slot_r[t], c->envU + so, c->envL + so, s));
@@ -443,7 +445,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
             PROF(DTWS_K_DTW);
             HIPCHK(c, launch_dtw_bucket(a, !same_m, nc, dtw_blocks, s));
         }
-        if (a.diag_max > 0) {
+        if (a.diag_max > 0 || a.diag_wide) {
             PROF(DTWS_K_DTW);
             HIPCHK(c, launch_dtw_diag(a, !same_m, c->num_cu * 4, s));
         }
@@ -534,7 +536,8 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
         // The graph is rebuilt when anything it bakes in changes: pointers, sizes, flags, seed, the
         // per-query parameters and the tuning knobs.
         std::vector<int64_t> sig = {(int64_t)(uintptr_t)T, n, (int64_t)(uintptr_t)Qp, nq, (int64_t)flags,
-                                    (int64_t)seed, p.block, c->lb_blocks_per_cu, c->dtw_blocks_per_cu, c->diag_max};
+                                    (int64_t)seed, p.block, c->lb_blocks_per_cu, c->dtw_blocks_per_cu, c->diag_max,
+                                    c->stats_prefix, c->data_envelope};
         for (int k = 0; k < nq; ++k) {
             sig.push_back(qoff[k]);
             sig.push_back(mh[k]);
@@ -1014,7 +1017,10 @@ DTWS_API int dtws_dtw_band(dtws_ctx *c, const float *T, int64_t n, const float *
     d.single = -1;
     d.abandon_at = abandon_at;
     d.dist_out = dist;
-    if (c->band_lanes == 64 && r <= kDiagMaxBand) {
+    const bool wave = r <= kDiagMaxBand &&
+                      (c->band_lanes == 64 ||
+                       (c->band_lanes == 0 && (2 * r + 1 > 16 * kMaxChunks || count <= diag_max_of(c))));
+    if (wave) {
         const int64_t blocks = (count + 1) / 2;
         HIPCHK(c, launch_dtw_diag_list(d, false, (int)(blocks < c->num_cu * 8 ? blocks : c->num_cu * 8), s));
     } else {

@@ -307,18 +307,6 @@ __global__ void k_seg_scatter(BatchArgs a) {
     }
 }
 
-// Finds the query of DTW wave w inside a bucket.
-__device__ inline int wave_query(const BatchArgs &a, int c, int64_t w, int32_t &wq0) {
-    int lo = a.bucket_j[2 * c], hi = a.bucket_j[2 * c + 1];   // wstart[lo] <= w < wstart[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.wstart[mid] <= w) lo = mid;
-        else hi = mid;
-    }
-    wq0 = a.wstart[lo];
-    return a.qorder[lo];
-}
-
 template <class Stats>
 __device__ inline void stats_of(const Stats &st, int64_t i, float &mu, float &s, float &o) {
     st(i, mu, s, o);
@@ -631,6 +619,7 @@ static hipError_t launch_dtw_bucket_t(const BatchArgs &a, int nc, int blocks, hi
         DTWS_BCASE(8) DTWS_BCASE(9) DTWS_BCASE(10) DTWS_BCASE(11) DTWS_BCASE(12) DTWS_BCASE(13) DTWS_BCASE(14)
 #undef DTWS_BCASE
         case kMaxChunks + 1: {
+            if (a.diag_wide) break;   // the one-wave-per-candidate kernel takes this bucket
             const int64_t wblocks = a.wide_lanes / 64;
             hipLaunchKernelGGL(k_dtw_batch_wide<PREFIX>, dim3((unsigned)wblocks), dim3(64), 0, s, a);
             break;

@@ -72,4 +72,16 @@ struct StatsArr {
     }
 };
 
+// Query of wave w of DTW bucket c in the survivor segments (segments are query-major).
+__device__ inline int wave_query(const BatchArgs &a, int c, int64_t w, int32_t &wq0) {
+    int lo = a.bucket_j[2 * c], hi = a.bucket_j[2 * c + 1];   // wstart[lo] <= w < wstart[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.wstart[mid] <= w) lo = mid;
+        else hi = mid;
+    }
+    wq0 = a.wstart[lo];
+    return a.qorder[lo];
+}
+
 }  // namespace dtws

@@ -156,15 +156,19 @@ __device__ F diag_dtw(const F *qb, const F *cb, int m, int r, const uint64_t *ke
     return lane_value(res, s0 & 63);
 }
 
-// Band cells (|i - j| <= r, 0 <= i, j < m) with i + j <= dl.
+// Band cells (|i - j| <= r, 0 <= i, j < m) with i + j <= dl, summed over the wave's lanes (one
+// anti-diagonal per lane and step); every lane gets the total.
 __device__ inline unsigned long long band_cells_upto(int m, int r, long long dl) {
     unsigned long long n = 0;
-    for (int i = 0; i < m; ++i) {
-        long long lo = i - r < 0 ? 0 : i - r, hi = i + r > m - 1 ? m - 1 : i + r;
-        if (hi > dl - i) hi = dl - i;
+    for (long long d = threadIdx.x & 63; d <= dl; d += 64) {
+        long long lo = (d - r + 1) >> 1, hi = (d + r) >> 1;   // ceil((d-r)/2), floor((d+r)/2)
+        if (lo < 0) lo = 0;
+        if (lo < d - (m - 1)) lo = d - (m - 1);
+        if (hi > m - 1) hi = m - 1;
+        if (hi > d) hi = d;
         if (hi >= lo) n += (unsigned long long)(hi - lo + 1);
     }
-    return n;
+    return wave_add_u64(n);
 }
 
 template <int CPL, bool ABANDON, typename F>
@@ -196,17 +200,32 @@ __global__ __launch_bounds__(128) void k_dtw_diag(BatchArgs a) {
     extern __shared__ float lds_f[];
     if (*a.overflow) return;
     const uint32_t count = *a.surv_count;
-    if (count > a.diag_max) return;
+    // small rounds: every survivor here; large rounds: only the wide-band bucket (112 <= r <= 255),
+    // read from its sorted segments, the other buckets go to the lane-per-candidate kernels
+    const bool all = count <= a.diag_max;
+    if (!all && !a.diag_wide) return;
+    constexpr int cw = kMaxChunks + 1;
+    const int64_t glo = all ? 0 : (int64_t)a.bucket_w[2 * cw] * 64;
+    const int64_t ghi = all ? (int64_t)count : (int64_t)a.bucket_w[2 * cw + 1] * 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     float *qb = lds_f + (int64_t)wid * (2 * a.max_m + kDiagPad) + kDiagPadQLo;
     float *cb = qb + a.max_m + kDiagPadQHi + kDiagPadCLo;
     unsigned long long n_started = 0, n_aband = 0, n_cells = 0, n_lane_cells = 0;
-    for (int64_t w = wave; w < (int64_t)count; w += nwaves) {
+    for (int64_t g = glo + wave; g < ghi; g += nwaves) {
         // wave-uniform values in scalar registers keep the diagonal loop uniform
-        const int q = __builtin_amdgcn_readfirstlane(a.surv_q[w]);
-        const int64_t start = __builtin_amdgcn_readfirstlane(a.surv_i[w]);
+        int q;
+        int64_t start;
+        if (all) {
+            q = __builtin_amdgcn_readfirstlane(a.surv_q[g]);
+            start = __builtin_amdgcn_readfirstlane(a.surv_i[g]);
+        } else {
+            int32_t wq0;
+            q = __builtin_amdgcn_readfirstlane(wave_query(a, cw, g >> 6, wq0));
+            if (((g >> 6) - wq0) * 64 + (g & 63) >= (int64_t)a.qcnt[q]) continue;
+            start = __builtin_amdgcn_readfirstlane(a.sorted[g]);
+        }
         const BatchQ bq = a.bq[q];
         const int m = __builtin_amdgcn_readfirstlane(bq.m), r = __builtin_amdgcn_readfirstlane(bq.r);
         float mu, s, o;
@@ -232,7 +251,7 @@ __global__ __launch_bounds__(128) void k_dtw_diag(BatchArgs a) {
         ++n_started;
         n_lane_cells += (unsigned long long)pairs * 2 * 64 * cpl;
         if (!alive) ++n_aband;
-        if (a.counters && lane == 0) n_cells += band_cells_upto(m, r, 2LL * pairs - 1 - (r & 1));
+        if (a.counters) n_cells += band_cells_upto(m, r, 2LL * pairs - 1 - (r & 1));
         if (alive && D <= threshold_of(load_bsf(a.keys + q)) && lane == 0) {
             atomicMin((unsigned long long *)(a.keys + q), (unsigned long long)pack_key(D, (uint32_t)start));
             const uint32_t pos = atomicAdd(a.nb_count, 1u);
@@ -364,7 +383,7 @@ __global__ __launch_bounds__(128) void k_dtw_diag_list(DtwArgs a) {
             ++n_started;
             n_lane_cells += (unsigned long long)pairs * 2 * 64 * ((r >> 6) + 1);
             if (!alive) ++n_aband;
-            if (a.counters && lane == 0) n_cells += band_cells_upto(m, r, 2LL * pairs - 1 - (r & 1));
+            if (a.counters) n_cells += band_cells_upto(m, r, 2LL * pairs - 1 - (r & 1));
             if (alive && D <= threshold_of(load_bsf(a.key)) && lane == 0) {
                 atomicMin((unsigned long long *)a.key, (unsigned long long)pack_key(D, (uint32_t)start));
                 const uint32_t pos = atomicAdd(a.nb_count, 1u);

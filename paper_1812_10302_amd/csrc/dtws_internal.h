@@ -159,6 +159,7 @@ struct BatchArgs {
     float *wide_rows;
     int64_t wide_lanes;
     uint32_t diag_max;         // rounds with at most this many survivors use one wave per candidate
+    bool diag_wide;            // bands 112..255 always use one wave per candidate
 };
 
 // ---------------------------------------------------------------- ordering network
@@ -296,7 +297,9 @@ struct dtws_ctx {
     int64_t block = 0;
     int lb_blocks_per_cu = 0, dtw_blocks_per_cu = 0;
     int diag_max = -1;   // survivors per round below which DTW runs one wave per candidate (-1: default)
-    int band_lanes = 1;  // dtws_dtw_band: 1 = one lane per candidate, 64 = one wave per candidate
+    int band_lanes = 0;  // dtws_dtw_band: 0 = automatic, 1 = one lane per candidate, 64 = one wave per candidate
+    int stats_prefix = 0;   // batched: 1 = window statistics always from the blocked prefix
+    int data_envelope = 1;  // batched: 0 = skip the data-envelope bound
     // ordering network
     dtws::MlpBufs mlp{};
     bool has_model = false;

@@ -289,20 +289,21 @@ struct PrefixView {
         return tot2[b0] + (lx ? P2[x] + 2.0 * delta * P1[x] + (double)lx * delta * delta : 0.0);
     }
     // 16-segment PAA of the z-normalised window T[i .. i+m) (segment t: [floor(t m/16),
-    // floor((t+1) m/16))); all zero for a flat window
-    __device__ void paa(int64_t i, int m, float *out) const {
+    // floor((t+1) m/16)), inv_len[t] = 1 / its length, inv_m = 1 / m); all zero for a flat window.
+    // Sums are FP64 differences of the prefix; the means and the scaling run in FP32.
+    __device__ void paa(int64_t i, int m, double inv_m, const float (&inv_len)[16], float *out) const {
         const int64_t b0 = i / kPB;
         const double delta = (i + m) > (b0 + 1) * kPB ? anc[b0 + 1] - anc[b0] : 0.0;
         const double base = P1[i];
         const double S1 = s1(i + m, b0, delta) - base, S2 = s2(i + m, b0, delta) - P2[i];
-        const double md = S1 / m, var = S2 / m - md * md;
-        const float inv = var > kSigmaFlat * kSigmaFlat ? (float)(1.0 / sqrt(var)) : 0.0f;
+        const double md = S1 * inv_m, var = S2 * inv_m - md * md;
+        const float inv = var > kSigmaFlat * kSigmaFlat ? rsqrtf((float)var) : 0.0f;
+        const float mdf = (float)md;
         double prev = base;
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
-            const int lo = (t * m) >> 4, hi = ((t + 1) * m) >> 4;
-            const double cur = s1(i + hi, b0, delta);
-            out[t] = (float)((cur - prev) / (hi - lo) - md) * inv;
+            const double cur = s1(i + (((t + 1) * m) >> 4), b0, delta);
+            out[t] = ((float)(cur - prev) * inv_len[t] - mdf) * inv;
             prev = cur;
         }
     }
@@ -337,15 +338,19 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
         if (lane == 0) sa.sstart[k] = -1;
         return;
     }
-    float qp[16];
+    float qp[16], inv_len[16];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) qp[t] = sa.qpaa[q * 16 + t];
+    for (int t = 0; t < 16; ++t) {
+        qp[t] = sa.qpaa[q * 16 + t];
+        inv_len[t] = 1.0f / (float)((((t + 1) * m) >> 4) - ((t * m) >> 4));
+    }
+    const double inv_m = 1.0 / m;
     const PrefixView pv{sa.P1, sa.P2, sa.anc, sa.tot1, sa.tot2};
     const int64_t ps = m >= 128 ? m >> 6 : 1;
     uint64_t best = ~0ull;
     for (int64_t i = first + lane * ps; i < last; i += 64 * ps) {
         float f[16];
-        pv.paa(i, m, f);
+        pv.paa(i, m, inv_m, inv_len, f);
         float d = 0.0f;
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
@@ -363,7 +368,7 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
     const int64_t i = (int64_t)(uint32_t)best;
     if (lane < 16) {
         float f[16];
-        pv.paa(i, m, f);
+        pv.paa(i, m, inv_m, inv_len, f);
         float v = f[0];
 #pragma unroll
         for (int t = 1; t < 16; ++t)

@@ -5,6 +5,7 @@
 // candidate, or one wave per candidate along anti-diagonals) compute the same recurrence.  The
 // autotuner therefore checks that every schedule it times returns identical matches.
 #include <chrono>
+#include <cstring>
 #include <vector>
 
 #include "dtws_internal.h"
@@ -12,9 +13,11 @@
 namespace {
 
 constexpr int64_t kBlocks[] = {2048, 4096, 8192, 16384};
-constexpr int32_t kDiagMaxes[] = {0, 1024, 8192, 65536};
+constexpr int32_t kDiagMaxes[] = {0, 2048, 16384, 65536};
 constexpr int32_t kLbWidths[] = {4, 8, 16, 32};
 constexpr int32_t kDtwWidths[] = {2, 4, 8};
+constexpr int kKnobs = 6;
+constexpr int kKnobValues[kKnobs] = {4, 4, 4, 3, 2, 2};
 
 bool valid_block(int64_t b) {
     if (b == 0) return true;
@@ -38,8 +41,10 @@ DTWS_API int dtws_get_schedule(dtws_ctx *c, dtws_schedule *out) {
     out->block = c->block > 0 ? c->block : 4096;
     out->lb_blocks_per_cu = c->lb_blocks_per_cu > 0 ? c->lb_blocks_per_cu : 8;
     out->dtw_blocks_per_cu = c->dtw_blocks_per_cu > 0 ? c->dtw_blocks_per_cu : 4;
-    out->diag_max = c->diag_max >= 0 ? c->diag_max : 8192;
+    out->diag_max = c->diag_max >= 0 ? c->diag_max : 16384;
     out->band_lanes = c->band_lanes;
+    out->stats_prefix = c->stats_prefix;
+    out->data_envelope = c->data_envelope;
     return DTWS_OK;
 }
 
@@ -47,13 +52,16 @@ DTWS_API int dtws_set_schedule(dtws_ctx *c, const dtws_schedule *s) {
     if (!c || !s) return DTWS_EINVAL;
     if (!valid_block(s->block) || s->lb_blocks_per_cu < 0 || s->lb_blocks_per_cu > 64 || s->dtw_blocks_per_cu < 0 ||
         s->dtw_blocks_per_cu > 64 || s->diag_max < -1 || s->diag_max > (1 << 24) ||
-        (s->band_lanes != 1 && s->band_lanes != 64))
+        (s->band_lanes != 0 && s->band_lanes != 1 && s->band_lanes != 64) || (s->stats_prefix != 0 && s->stats_prefix != 1) ||
+        (s->data_envelope != 0 && s->data_envelope != 1))
         return DTWS_EINVAL;
     c->block = s->block;
     c->lb_blocks_per_cu = s->lb_blocks_per_cu;
     c->dtw_blocks_per_cu = s->dtw_blocks_per_cu;
     c->diag_max = s->diag_max;
     c->band_lanes = s->band_lanes;
+    c->stats_prefix = s->stats_prefix;
+    c->data_envelope = s->data_envelope;
     return DTWS_OK;
 }
 
@@ -62,7 +70,8 @@ DTWS_API int dtws_autotune_batch(dtws_ctx *c, const float *T, int64_t n, const f
                                  void *stream, int32_t reps, dtws_schedule *best_out, double *best_ms_out) {
     if (!c || !best_out || !best_ms_out || reps < 1 || reps > 100 || nq < 1 || nq > c->max_q) return DTWS_EINVAL;
     flags &= ~(uint32_t)DTWS_PROFILE;
-    dtws_schedule start{};
+    dtws_schedule start;
+    memset(&start, 0, sizeof(start));
     dtws_get_schedule(c, &start);
     std::vector<dtws_match> ref(nq), got(nq);
     // one untimed call (it captures the graph), then `reps` timed calls
@@ -83,18 +92,20 @@ DTWS_API int dtws_autotune_batch(dtws_ctx *c, const float *T, int64_t n, const f
     double best_ms = 0.0;
     int rc = run(best, ref, best_ms);
     // coordinate descent: each knob in turn over its candidate values, keeping the fastest
-    for (int knob = 0; knob < 4 && rc == DTWS_OK; ++knob) {
-        const int count = knob == 0 ? 4 : knob == 1 ? 4 : knob == 2 ? 4 : 3;
+    for (int knob = 0; knob < kKnobs && rc == DTWS_OK; ++knob) {
         const dtws_schedule base = best;
-        for (int v = 0; v < count && rc == DTWS_OK; ++v) {
-            dtws_schedule t = base;
-            if (knob == 0) t.diag_max = kDiagMaxes[v];
-            else if (knob == 1) t.block = kBlocks[v];
-            else if (knob == 2) t.lb_blocks_per_cu = kLbWidths[v];
-            else t.dtw_blocks_per_cu = kDtwWidths[v];
-            if (t.diag_max == base.diag_max && t.block == base.block && t.lb_blocks_per_cu == base.lb_blocks_per_cu &&
-                t.dtw_blocks_per_cu == base.dtw_blocks_per_cu)
-                continue;
+        for (int v = 0; v < kKnobValues[knob] && rc == DTWS_OK; ++v) {
+            dtws_schedule t;
+            memcpy(&t, &base, sizeof(t));
+            switch (knob) {
+            case 0: t.diag_max = kDiagMaxes[v]; break;
+            case 1: t.block = kBlocks[v]; break;
+            case 2: t.lb_blocks_per_cu = kLbWidths[v]; break;
+            case 3: t.dtw_blocks_per_cu = kDtwWidths[v]; break;
+            case 4: t.stats_prefix = v; break;
+            default: t.data_envelope = 1 - v; break;
+            }
+            if (memcmp(&t, &base, sizeof(t)) == 0) continue;
             double ms = 0.0;
             rc = run(t, got, ms);
             if (rc != DTWS_OK) break;

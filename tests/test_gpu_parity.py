@@ -297,10 +297,11 @@ def test_dtw_band_wave_schedule(ctx, n, m, r):
     try:
         ctx.set_schedule(band_lanes=64)
         got = ctx.dtw_band(dev(T), dev(Q), r, dev(starts)).cpu().numpy()
-    finally:
         ctx.set_schedule(band_lanes=1)
+        lane = ctx.dtw_band(dev(T), dev(Q), r, dev(starts)).cpu().numpy()
+    finally:
+        ctx.set_schedule(band_lanes=0)
     close_rel(got, ref)
-    lane = ctx.dtw_band(dev(T), dev(Q), r, dev(starts)).cpu().numpy()
     close_rel(got, lane)
 
 
@@ -314,7 +315,7 @@ def test_dtw_band_wave_schedule_abandon_and_invalid(ctx, small_wl):
         bad = np.array([-1, D.size, 5], dtype=np.int64)
         g = ctx.dtw_band(dev(wl.T), dev(wl.queries[0]), wl.bands[0], dev(bad)).cpu().numpy()
     finally:
-        ctx.set_schedule(band_lanes=1)
+        ctx.set_schedule(band_lanes=0)
     fin = np.isfinite(got)
     close_rel(got[fin], D[starts[fin]])
     assert np.all(D[starts[~fin]] > thr * (1 - 1e-5))
@@ -336,7 +337,8 @@ def test_schedules_give_identical_results(ctx, casc):
     default = ctx.get_schedule()
     try:
         for sched in ({"diag_max": 0}, {"diag_max": 1 << 24}, {"diag_max": 8192, "block": 2048},
-                      {"diag_max": 64, "block": 16384, "lb_blocks_per_cu": 2, "dtw_blocks_per_cu": 1}):
+                      {"diag_max": 64, "block": 16384, "lb_blocks_per_cu": 2, "dtw_blocks_per_cu": 1},
+                      {"diag_max": 8192, "block": 4096, "stats_prefix": 1, "data_envelope": 0}):
             ctx.set_schedule(**sched)
             _check_batch(ctx.search_batch(Td, Qd, rs), ref)
             _check_batch([ctx.search(Td, q, r, seed=3) for q, r in zip(Qd, rs)], ref)
@@ -346,7 +348,8 @@ def test_schedules_give_identical_results(ctx, casc):
 
 def test_set_schedule_rejects_bad_fields(ctx):
     default = ctx.get_schedule()
-    for bad in ({"block": 3000}, {"diag_max": -2}, {"band_lanes": 2}, {"lb_blocks_per_cu": 65}):
+    for bad in ({"block": 3000}, {"diag_max": -2}, {"band_lanes": 2}, {"lb_blocks_per_cu": 65},
+                {"stats_prefix": 2}, {"data_envelope": -1}):
         with pytest.raises(dtws.DtwsError):
             ctx.set_schedule(**bad)
         assert ctx.get_schedule() == default
@@ -361,8 +364,9 @@ def test_autotune_installs_a_candidate_schedule(ctx, casc):
         pq = dtws.PackedQueries([dev(q) for q in qs])
         best, ms = ctx.autotune_batch(dev(T), pq, rs, reps=2)
         assert ms > 0
-        assert best["block"] in (2048, 4096, 8192, 16384) and best["diag_max"] in (0, 1024, 8192, 65536)
+        assert best["block"] in (2048, 4096, 8192, 16384) and best["diag_max"] in (0, 2048, 16384, 65536)
         assert best["lb_blocks_per_cu"] in (4, 8, 16, 32) and best["dtw_blocks_per_cu"] in (2, 4, 8)
+        assert best["stats_prefix"] in (0, 1) and best["data_envelope"] in (0, 1)
         assert ctx.get_schedule() == best
         _check_batch(ctx.search_batch(dev(T), pq, rs), _cascade_refs(casc, T, qs, rs))
     finally:
