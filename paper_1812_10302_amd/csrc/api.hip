@@ -330,11 +330,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         a.s = c->st_s;
         a.o = c->st_o;
     } else {
-        a.P1 = c->P1;
-        a.P2 = c->P2;
-        a.anc = c->anc;
-        a.tot1 = c->tot1;
-        a.tot2 = c->tot2;
+        a.pre = Prefix{c->PP, c->anc, c->tot};
     }
     a.envU = c->data_envelope ? c->envU : nullptr;
     a.envL = c->data_envelope ? c->envL : nullptr;
@@ -403,7 +399,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         }
     } else {
         PROF(DTWS_K_STATS);
-        HIPCHK(c, launch_prefix(T, n, c->P1, c->P2, c->anc, c->tot1, c->tot2, s));
+        HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s));
     }
     for (int t = 0; t < p.nr && c->data_envelope; ++t) {
         PROF(DTWS_K_ENV);
@@ -416,18 +412,14 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         // visiting order from the ordering network: blocks by ascending predicted distance of their
         // proposals (the blocked prefix gives every window's PAA)
         PROF(DTWS_K_SCORE);
-        if (same_m) HIPCHK(c, launch_prefix(T, n, c->P1, c->P2, c->anc, c->tot1, c->tot2, s));
+        if (same_m) HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s));
         sa.K = kScoreSamples;
         sa.qpaa = c->qpaa;
         sa.score = c->score;
         sa.sstart = c->sstart;
         sa.bstart = c->bstart;
         sa.row_off = c->row_off;
-        sa.P1 = c->P1;
-        sa.P2 = c->P2;
-        sa.anc = c->anc;
-        sa.tot1 = c->tot1;
-        sa.tot2 = c->tot2;
+        sa.pre = Prefix{c->PP, c->anc, c->tot};
         sa.total_rows = p.score_rows;
         HIPCHK(c, hipMemcpyAsync(c->row_off, c->h_row_off, sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, s));
         HIPCHK(c, mlp_order_blocks(c->mlp, a, sa, s));
@@ -631,7 +623,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
     void *dev[] = {c->qpad, c->qhat64, c->qsorted, c->Usorted, c->Lsorted, c->order, c->keys, c->st_mu,
                    c->st_s, c->st_o, c->envU, c->envL, c->surv, c->surv_count, c->nb_d, c->nb_idx,
                    c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_idx, c->res_dist,
-                   c->res_status, c->counters, c->gen_rows, c->bq, c->P1, c->P2, c->anc, c->tot1, c->tot2,
+                   c->res_status, c->counters, c->gen_rows, c->bq, c->PP, c->anc, c->tot,
                    c->perm, c->heads, c->surv_q, c->surv_i, c->sorted, c->qcnt, c->fill, c->overflow,
                    c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q,
                    c->mlp.theta, c->mlp.grad, c->mlp.adam_m, c->mlp.adam_v, c->mlp.W1T, c->mlp.W2T, c->mlp.W2b,
@@ -711,9 +703,8 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
         c->bsurv_cap = cap;
         const int64_t nblk = max_n / 4096 + 2;
         ok = dalloc(&c->bq, Q) == hipSuccess && hipHostMalloc((void **)&c->h_bq, sizeof(BatchQ) * Q, 0) == hipSuccess &&
-             dalloc(&c->P1, max_n + 1) == hipSuccess && dalloc(&c->P2, max_n + 1) == hipSuccess &&
-             dalloc(&c->anc, nblk) == hipSuccess && dalloc(&c->tot1, nblk) == hipSuccess &&
-             dalloc(&c->tot2, nblk) == hipSuccess && dalloc(&c->perm, Q * c->maxblocks) == hipSuccess &&
+             dalloc(&c->PP, max_n + 1) == hipSuccess && dalloc(&c->anc, nblk) == hipSuccess &&
+             dalloc(&c->tot, nblk) == hipSuccess && dalloc(&c->perm, Q * c->maxblocks) == hipSuccess &&
              dalloc(&c->heads, 8) == hipSuccess && dalloc(&c->surv_q, cap) == hipSuccess &&
              dalloc(&c->surv_i, cap) == hipSuccess && dalloc(&c->sorted, cap + 64 * Q) == hipSuccess &&
              dalloc(&c->qcnt, Q) == hipSuccess && dalloc(&c->fill, Q) == hipSuccess &&
@@ -907,7 +898,7 @@ DTWS_API int dtws_propose(dtws_ctx *c, const float *T, int64_t n, const float *Q
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, launch_query_prep(Q, m, 0, query_bufs(c, 0), s));
-    HIPCHK(c, launch_prefix(T, n, c->P1, c->P2, c->anc, c->tot1, c->tot2, s));
+    HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s));
     BatchQ &bq = c->h_bq[0];
     bq = BatchQ{};
     bq.m = m;
@@ -931,11 +922,7 @@ DTWS_API int dtws_propose(dtws_ctx *c, const float *T, int64_t n, const float *Q
     sa.qpaa = c->qpaa;
     sa.sstart = c->sstart;
     sa.row_off = c->row_off;
-    sa.P1 = c->P1;
-    sa.P2 = c->P2;
-    sa.anc = c->anc;
-    sa.tot1 = c->tot1;
-    sa.tot2 = c->tot2;
+    sa.pre = Prefix{c->PP, c->anc, c->tot};
     HIPCHK(c, launch_propose(a, sa, X, starts, s));
     // the staging entries are read by the copies above before the call returns
     HIPCHK(c, hipStreamSynchronize(s));

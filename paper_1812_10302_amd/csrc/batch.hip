@@ -29,8 +29,13 @@ __device__ inline uint64_t splitmix64_d(uint64_t x) {
 }
 
 // ------------------------------------------------------------------ blocked prefix
-__global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restrict__ T, int64_t n, double *P1,
-                                                           double *P2, double *anc, double *tot1, double *tot2) {
+// One workgroup per block of kPB points: each thread scans 16 consecutive points in FP64, the
+// workgroup scans the thread totals, and the results leave through LDS in two halves so that the
+// stores are coalesced.
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restrict__ T, int64_t n, double2 *PP,
+                                                           double *anc, double2 *tot) {
+    constexpr int kHalf = kPB / 2, kPad = 16 + 1;           // 16 entries per thread, one spare
+    __shared__ double2 stage[kPrefixThreads / 2 * kPad];
     __shared__ double ws1[kPrefixThreads / 64], ws2[kPrefixThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t b = blockIdx.x, x0 = b * kPB;
@@ -71,18 +76,29 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
     }
     b1 += i1 - r1;
     b2 += i2 - r2;
+    const int64_t lim = n + 1 - x0;   // entries [x0, n] exist
+    for (int h = 0; h < 2; ++h) {
+        const int owner = tid - h * (kPrefixThreads / 2);
+        if (owner >= 0 && owner < kPrefixThreads / 2) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int64_t y = x0 + 16 * tid + u;
-        if (y <= n) {    // P[n] = sum of the last partial block, read for windows ending at n
-            P1[y] = b1 + v1[u];
-            P2[y] = b2 + v2[u];
+            for (int u = 0; u < 16; ++u) stage[owner * kPad + u] = make_double2(b1 + v1[u], b2 + v2[u]);
         }
+        __syncthreads();
+        for (int e = tid; e < kHalf; e += kPrefixThreads) {
+            const int64_t x = (int64_t)h * kHalf + e;
+            if (x < lim) PP[x0 + x] = stage[(e >> 4) * kPad + (e & 15)];
+        }
+        __syncthreads();
     }
     if (tid == 0) {
         anc[b] = a;
-        tot1[b] = t1;
-        tot2[b] = t2;
+        tot[b] = make_double2(t1, t2);
+        if (b == (int64_t)gridDim.x - 1) {
+            // sentinels: the entry past the last block, and PP[n] when n ends a block
+            anc[b + 1] = a;
+            tot[b + 1] = make_double2(0.0, 0.0);
+            if (x0 + kPB == n) PP[n] = make_double2(0.0, 0.0);
+        }
     }
 }
 
@@ -230,7 +246,7 @@ __global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int ra
             const float *eL = a.envU ? a.envL + bq.env_slot * a.slot_stride : nullptr;
             if (PREFIX) {
                 cascade(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, queues[wid][0], queues[wid][1],
-                        StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, bq.m, 1.0 / bq.m}, emit, cnt);
+                        StatsPrefix{a.T, a.pre, bq.m, 1.0 / bq.m}, emit, cnt);
             } else {
                 const int64_t so = bq.stat_slot * a.slot_stride;
                 cascade(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, queues[wid][0], queues[wid][1],
@@ -331,7 +347,7 @@ __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
         const int64_t start = valid ? (int64_t)a.sorted[w * 64 + lane] : 0;
         float mu, s, o;
         if (PREFIX) {
-            StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, bq.m, 1.0 / bq.m}(start, mu, s, o);
+            StatsPrefix{a.T, a.pre, bq.m, 1.0 / bq.m}(start, mu, s, o);
         } else {
             const int64_t so = bq.stat_slot * a.slot_stride;
             StatsArr{a.mu + so, a.s + so, a.o + so}(start, mu, s, o);
@@ -391,7 +407,7 @@ __global__ __launch_bounds__(64) void k_dtw_batch_wide(BatchArgs a) {
         const int64_t start = a.sorted[w * 64 + lane];
         float mu, s, o;
         if (PREFIX) {
-            StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, m, 1.0 / m}(start, mu, s, o);
+            StatsPrefix{a.T, a.pre, m, 1.0 / m}(start, mu, s, o);
         } else {
             const int64_t so = bq.stat_slot * a.slot_stride;
             StatsArr{a.mu + so, a.s + so, a.o + so}(start, mu, s, o);
@@ -575,10 +591,9 @@ __global__ __launch_bounds__(256) void k_cert_reduce_batch(BatchArgs a) {
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_prefix(const float *T, int64_t n, double *P1, double *P2, double *anc, double *tot1,
-                         double *tot2, hipStream_t s) {
+hipError_t launch_prefix(const float *T, int64_t n, double2 *PP, double *anc, double2 *tot, hipStream_t s) {
     const int64_t blocks = (n + kPB - 1) / kPB;
-    hipLaunchKernelGGL(k_prefix, dim3((unsigned)blocks), dim3(kPrefixThreads), 0, s, T, n, P1, P2, anc, tot1, tot2);
+    hipLaunchKernelGGL(k_prefix, dim3((unsigned)blocks), dim3(kPrefixThreads), 0, s, T, n, PP, anc, tot);
     return hipGetLastError();
 }
 

@@ -10,34 +10,26 @@ namespace dtws {
 // two-pass from the series.
 struct StatsPrefix {
     const float *T;
-    const double *P1, *P2, *anc, *tot1, *tot2;
+    Prefix pre;
     int m;
     double inv_m;
-    // mean and variance of window i
+    // mean and variance of window i (m <= 2048 < kPB: the window ends in its first block or the next)
     __device__ void window(int64_t i, double &mu, double &var) const {
         const int64_t e = i + m;
-        const int64_t b0 = i / kPB, b1 = (e - 1) / kPB;
-        double e1, e2;
-        if (e == (b1 + 1) * kPB) {
-            e1 = tot1[b1];
-            e2 = tot2[b1];
-        } else {
-            e1 = P1[e];
-            e2 = P2[e];
+        const int64_t b0 = i / kPB, e0 = (b0 + 1) * kPB;
+        const double2 p0 = pre.PP[i], pe = pre.PP[e];
+        double S1 = pe.x - p0.x, S2 = pe.y - p0.y;
+        if (e >= e0) {
+            const double2 t = pre.tot[b0];
+            const double delta = pre.anc[b0 + 1] - pre.anc[b0];
+            const double c2 = (double)(e - e0);
+            S1 = (t.x - p0.x) + pe.x + c2 * delta;
+            S2 = (t.y - p0.y) + pe.y + 2.0 * delta * pe.x + c2 * delta * delta;
         }
-        double S1, S2;
-        if (b0 == b1) {
-            S1 = e1 - P1[i];
-            S2 = e2 - P2[i];
-        } else {
-            const double delta = anc[b1] - anc[b0];
-            const double c2 = (double)(e - b1 * kPB);
-            S1 = (tot1[b0] - P1[i]) + e1 + c2 * delta;
-            S2 = (tot2[b0] - P2[i]) + e2 + 2.0 * delta * e1 + c2 * delta * delta;
-        }
+        const double a0 = pre.anc[b0];
         const double md = S1 * inv_m, msq = S2 * inv_m;
         var = msq - md * md;
-        mu = anc[b0] + md;
+        mu = a0 + md;
         if (m <= 64 || !(var > 4e-6 * msq)) {
             const float *w = T + i;
             double s = 0.0;

@@ -230,7 +230,7 @@ __global__ __launch_bounds__(128) void k_dtw_diag(BatchArgs a) {
         const int m = __builtin_amdgcn_readfirstlane(bq.m), r = __builtin_amdgcn_readfirstlane(bq.r);
         float mu, s, o;
         if (PREFIX) {
-            StatsPrefix{a.T, a.P1, a.P2, a.anc, a.tot1, a.tot2, m, 1.0 / m}(start, mu, s, o);
+            StatsPrefix{a.T, a.pre, m, 1.0 / m}(start, mu, s, o);
         } else {
             const int64_t so = bq.stat_slot * a.slot_stride;
             StatsArr{a.mu + so, a.s + so, a.o + so}(start, mu, s, o);

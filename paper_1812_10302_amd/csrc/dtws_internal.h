@@ -44,6 +44,16 @@ struct QueryBufs {
 };
 
 
+// Blocked prefix of the series: blocks of kPB points, anchor anc[b] = T[b * kPB]; for x in block b,
+// PP[x] = (sum, sum of squares) of (T[y] - anc[b]) over [b * kPB, x) and tot[b] the same over the
+// whole block.  One entry past the last block (anchor repeated, zero sums) and PP[n] exist, so
+// readers may touch them without a test.
+struct Prefix {
+    const double2 *PP;
+    const double *anc;
+    const double2 *tot;
+};
+
 // Per-query parameters of a batch (device array, one entry per query).
 struct BatchQ {
     int64_t qoff;      // first element of the query in the packed query array
@@ -127,7 +137,7 @@ struct BatchArgs {
     uint64_t *keys;            // best-so-far per query
     // window statistics: per-window arrays (all queries share m) or the blocked prefix
     const float *mu, *s, *o;
-    const double *P1, *P2, *anc, *tot1, *tot2;
+    Prefix pre;
     const float *envU, *envL;  // data envelopes (slot per distinct band), or null
     int64_t slot_stride;       // elements per statistics / envelope slot
     // work queue
@@ -190,7 +200,7 @@ struct ScoreArgs {
     int32_t *sstart;           // start of each row of the current chunk (-1: empty quarter)
     int32_t *bstart;           // start of the best-scored proposal of each block
     const int64_t *row_off;    // per query, nq + 1 entries
-    const double *P1, *P2, *anc, *tot1, *tot2;   // blocked prefix of the series
+    Prefix pre;                // blocked prefix of the series
 };
 
 // ---------------------------------------------------------------- launchers (stream-ordered)
@@ -206,8 +216,7 @@ hipError_t launch_dtw(const DtwArgs &a, bool search, int64_t max_count, int num_
 hipError_t launch_bsf_update(uint64_t *keys, const float *d, const int64_t *idx, int64_t count, int num_cu,
                              hipStream_t s);
 hipError_t launch_certify(const CertArgs &c, hipStream_t s);
-hipError_t launch_prefix(const float *T, int64_t n, double *P1, double *P2, double *anc, double *tot1,
-                         double *tot2, hipStream_t s);
+hipError_t launch_prefix(const float *T, int64_t n, double2 *PP, double *anc, double2 *tot, hipStream_t s);
 hipError_t launch_make_perm(const BatchArgs &a, int mode, uint64_t seed, int64_t max_nblocks, hipStream_t s);
 hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s);
 hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
@@ -276,8 +285,9 @@ struct dtws_ctx {
     int64_t gen_lanes = 0;
     // batched search
     dtws::BatchQ *bq = nullptr, *h_bq = nullptr;   // device / pinned host, max_q entries
-    double *P1 = nullptr, *P2 = nullptr;     // blocked prefix, max_n + 1 entries
-    double *anc = nullptr, *tot1 = nullptr, *tot2 = nullptr;
+    double2 *PP = nullptr;                   // blocked prefix, max_n + 1 entries
+    double *anc = nullptr;
+    double2 *tot = nullptr;
     int32_t *perm = nullptr;
     int64_t maxblocks = 0;
     uint32_t *heads = nullptr;

@@ -269,43 +269,39 @@ __global__ void k_query_paa(const BatchArgs a, float *qpaa) {
     qpaa[q * 16 + t] = (float)(s / (hi - lo));
 }
 
-// Sums over a window from the blocked prefix (P1[x], P2[x]: sums of (T - anc[b]) and its square
-// over [b * kPB, x) for x in block b).  Relative to the anchor of the window's first block b0;
-// windows are at most 2048 points, so they end at most one block later.
+// PAA of windows from the blocked prefix (see Prefix).  Windows are at most 2048 points, so they
+// end in their first block or the next; every lookup is unconditional (the prefix has sentinels
+// past its last block), so the loads of one window issue back to back.
 struct PrefixView {
-    const double *P1, *P2, *anc, *tot1, *tot2;
-    // sum of (T[y] - anc[b0]) over [b0 * kPB, x)
-    __device__ double s1(int64_t x, int64_t b0, double delta) const {
-        const int64_t e0 = (b0 + 1) * kPB;
-        if (x < e0) return P1[x];
-        const int64_t lx = x - e0;
-        return tot1[b0] + (lx ? P1[x] + (double)lx * delta : 0.0);
-    }
-    // sum of (T[y] - anc[b0])^2 over [b0 * kPB, x)
-    __device__ double s2(int64_t x, int64_t b0, double delta) const {
-        const int64_t e0 = (b0 + 1) * kPB;
-        if (x < e0) return P2[x];
-        const int64_t lx = x - e0;
-        return tot2[b0] + (lx ? P2[x] + 2.0 * delta * P1[x] + (double)lx * delta * delta : 0.0);
-    }
+    Prefix pre;
     // 16-segment PAA of the z-normalised window T[i .. i+m) (segment t: [floor(t m/16),
     // floor((t+1) m/16)), inv_len[t] = 1 / its length, inv_m = 1 / m); all zero for a flat window.
     // Sums are FP64 differences of the prefix; the means and the scaling run in FP32.
     __device__ void paa(int64_t i, int m, double inv_m, const float (&inv_len)[16], float *out) const {
-        const int64_t b0 = i / kPB;
-        const double delta = (i + m) > (b0 + 1) * kPB ? anc[b0 + 1] - anc[b0] : 0.0;
-        const double base = P1[i];
-        const double S1 = s1(i + m, b0, delta) - base, S2 = s2(i + m, b0, delta) - P2[i];
+        const int64_t b0 = i / kPB, e0 = (b0 + 1) * kPB;
+        const double delta = pre.anc[b0 + 1] - pre.anc[b0];
+        const double2 t = pre.tot[b0];
+        double2 p[17];
+#pragma unroll
+        for (int k = 0; k <= 16; ++k) p[k] = pre.PP[i + ((k * m) >> 4)];
+        // sums relative to anc[b0] from the block start to x: P(x) in block b0, else the whole
+        // block b0 plus P(x) re-anchored
+        double g[17];
+#pragma unroll
+        for (int k = 0; k <= 16; ++k) {
+            const int64_t x = i + ((k * m) >> 4);
+            const double lx = (double)(x - e0);
+            g[k] = x < e0 ? p[k].x : t.x + p[k].x + lx * delta;
+        }
+        const int64_t xe = i + m;
+        const double lxe = (double)(xe - e0);
+        const double g2 = xe < e0 ? p[16].y : t.y + p[16].y + 2.0 * delta * p[16].x + lxe * delta * delta;
+        const double S1 = g[16] - g[0], S2 = g2 - p[0].y;
         const double md = S1 * inv_m, var = S2 * inv_m - md * md;
         const float inv = var > kSigmaFlat * kSigmaFlat ? rsqrtf((float)var) : 0.0f;
         const float mdf = (float)md;
-        double prev = base;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const double cur = s1(i + (((t + 1) * m) >> 4), b0, delta);
-            out[t] = ((float)(cur - prev) * inv_len[t] - mdf) * inv;
-            prev = cur;
-        }
+        for (int k = 0; k < 16; ++k) out[k] = ((float)(g[k + 1] - g[k]) * inv_len[k] - mdf) * inv;
     }
 };
 
@@ -345,7 +341,7 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
         inv_len[t] = 1.0f / (float)((((t + 1) * m) >> 4) - ((t * m) >> 4));
     }
     const double inv_m = 1.0 / m;
-    const PrefixView pv{sa.P1, sa.P2, sa.anc, sa.tot1, sa.tot2};
+    const PrefixView pv{sa.pre};
     const int64_t ps = m >= 128 ? m >> 6 : 1;
     uint64_t best = ~0ull;
     for (int64_t i = first + lane * ps; i < last; i += 64 * ps) {
