@@ -18,15 +18,15 @@ struct StatsPrefix {
         const int64_t e = i + m;
         const int64_t b0 = i / kPB, e0 = (b0 + 1) * kPB;
         const double2 p0 = pre.PP[i], pe = pre.PP[e];
-        double S1 = pe.x - p0.x, S2 = pe.y - p0.y;
-        if (e >= e0) {
-            const double2 t = pre.tot[b0];
-            const double delta = pre.anc[b0 + 1] - pre.anc[b0];
-            const double c2 = (double)(e - e0);
-            S1 = (t.x - p0.x) + pe.x + c2 * delta;
-            S2 = (t.y - p0.y) + pe.y + 2.0 * delta * pe.x + c2 * delta * delta;
-        }
+        // a window that ends in the next block: whole block b0 plus the re-anchored part (branch
+        // free; the lookups past the last block hit sentinels)
+        const bool cross = e >= e0;
+        const double2 t = pre.tot[b0];
         const double a0 = pre.anc[b0];
+        const double delta = cross ? pre.anc[b0 + 1] - a0 : 0.0;
+        const double c2 = (double)(e - e0);
+        const double S1 = cross ? (t.x - p0.x) + pe.x + c2 * delta : pe.x - p0.x;
+        const double S2 = cross ? (t.y - p0.y) + pe.y + 2.0 * delta * pe.x + c2 * delta * delta : pe.y - p0.y;
         const double md = S1 * inv_m, msq = S2 * inv_m;
         var = msq - md * md;
         mu = a0 + md;

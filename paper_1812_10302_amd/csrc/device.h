@@ -98,7 +98,7 @@ __device__ inline float keogh_d(const QView &v, const float *Ui, const float *Li
 
 // ---------------------------------------------------------------- wave-private queues
 constexpr int kQCap = 128;   // power of two, >= 2 * 64
-constexpr int kK0 = 16, kK1 = 64;
+constexpr int kK1 = 64;   // query-envelope terms of level 1
 
 struct WaveQueue {
     int32_t idx[kQCap];
@@ -147,9 +147,10 @@ struct CascadeCounts {
 
 // Runs the bound cascade (one wave) on groups of 64 consecutive candidates handed out by
 // src.next(g, last): the group starts at g, starts at or beyond `last` are idle lanes; next()
-// returns false when the source is exhausted.  Level 0 (coalesced, uniform): LB_KimFL and the first K0 query-envelope terms.
-// Survivors are compacted into the wave's LDS queue q1; full batches of 64 run the terms up to
-// K1 (level 1) and their survivors go to q2, whose full batches run the remaining terms with
+// returns false when the source is exhausted.  Level 0 (coalesced, uniform): LB_KimFL only.
+// Survivors are compacted into the wave's LDS queue q1; full batches of 64 run the first K1
+// query-envelope terms, 16 at a time with early abandoning (level 1), and their survivors go to
+// q2, whose full batches run the remaining terms with
 // early abandoning and then the data-envelope bound (level 2, if envU is set).  Candidates that
 // pass everything go to emit(alive, i).  A scheduler that is uniform across the wave serves a
 // full q2 batch first, then a full q1 batch, then a new group, so a queue never holds 64 or more
@@ -161,7 +162,7 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
                                         const Stats &stats, const Emit &emit, CascadeCounts &cnt) {
     const int lane = threadIdx.x & 63;
     const int m = v.m, mpad = v.mpad;
-    const int K0 = mpad < kK0 ? mpad : kK0, K1 = mpad < kK1 ? mpad : kK1;
+    const int K1 = mpad < kK1 ? mpad : kK1;
     uint32_t h1 = 0, t1 = 0, h2 = 0, t2 = 0;
     bool done = false;
     for (;;) {
@@ -192,8 +193,8 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
             float kq = 0.f, mu = 0.f, s = 0.f, o = 0.f;
             const bool got = q_pop(q1, h1, t1, i, kq, mu, s, o);
             bool alive = got;
-            if (got && K1 > K0) {
-                kq = keogh_q_terms(v, T + i, mu, s, o, kq, K0, K1, false, thr);
+            if (got) {
+                kq = keogh_q_terms(v, T + i, mu, s, o, 0.0f, 0, K1, true, thr);
                 if (kq > thr) {
                     alive = false;
                     ++cnt.kq;
@@ -217,17 +218,9 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
         const float c0 = fmaf(Ti[0] - mu, s, o), cl = fmaf(Ti[m - 1] - mu, s, o);
         const float d0 = q0 - c0, dl = ql - cl;
         const float kim = fmaf(d0, d0, dl * dl);
-        bool alive = valid && !(kim > thr);
+        const bool alive = valid && !(kim > thr);
         if (valid && !alive) ++cnt.kim;
-        float kq = 0.0f;
-        if (__ballot(alive)) {
-            kq = keogh_q_terms(v, Ti, mu, s, o, 0.0f, 0, K0, false, thr);
-            if (alive && kq > thr) {
-                alive = false;
-                ++cnt.kq;
-            }
-        }
-        q_push(q1, t1, alive, (int32_t)ii, kq, mu, s, o);
+        q_push(q1, t1, alive, (int32_t)ii, 0.0f, mu, s, o);
     }
 }
 

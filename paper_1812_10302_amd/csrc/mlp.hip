@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
     const int q = __builtin_amdgcn_readfirstlane(lo);
     const int64_t local = row - sa.row_off[q];
     const BatchQ bq = a.bq[q];
-    const int m = bq.m;
+    const int m = __builtin_amdgcn_readfirstlane(bq.m);
     const int64_t quarter = a.block / sa.K;
     const int64_t first = (local / sa.K) * a.block + (local % sa.K) * quarter;
     const int64_t last = first + quarter < bq.N ? first + quarter : bq.N;
@@ -344,17 +344,63 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
     const PrefixView pv{sa.pre};
     const int64_t ps = m >= 128 ? m >> 6 : 1;
     uint64_t best = ~0ull;
-    for (int64_t i = first + lane * ps; i < last; i += 64 * ps) {
-        float f[16];
-        pv.paa(i, m, inv_m, inv_len, f);
-        float d = 0.0f;
+    if ((m & 63) == 0) {
+        // m = 64 ps: the sampled starts and every segment boundary lie on the grid of step ps, so
+        // the 64 starts of a group need the prefix at 128 grid points only, staged once in LDS
+        // (re-anchored to the block of the group's first start)
+        __shared__ double2 grid[4][128];
+        double2 *gw = grid[threadIdx.x >> 6];
+        const float inv_seg = 16.0f / (float)m;
+        for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
+            const int64_t b0 = g0 / kPB, e0 = (b0 + 1) * kPB;
+            const double2 tb = sa.pre.tot[b0];
+            const double a0 = sa.pre.anc[b0], delta = sa.pre.anc[b0 + 1] - a0;
+            wave_sync();
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const float e = f[t] - qp[t];
-            d = fmaf(e, e, d);
+            for (int h = 0; h < 2; ++h) {
+                int64_t x = g0 + ps * (lane + 64 * h);
+                x = x < a.n ? x : a.n;   // points past the series only serve idle lanes
+                const double2 p = sa.pre.PP[x];
+                const bool cross = x >= e0;
+                const double lx = (double)(x - e0);
+                double2 gv;
+                gv.x = cross ? tb.x + p.x + lx * delta : p.x;
+                gv.y = cross ? tb.y + p.y + 2.0 * delta * p.x + lx * delta * delta : p.y;
+                gw[lane + 64 * h] = gv;
+            }
+            wave_sync();
+            const int64_t i = g0 + lane * ps;
+            if (i < last) {
+                const double2 w0 = gw[lane], w1 = gw[lane + 64];
+                const double md = (w1.x - w0.x) * inv_m, var = (w1.y - w0.y) * inv_m - md * md;
+                const float inv = var > kSigmaFlat * kSigmaFlat ? rsqrtf((float)var) : 0.0f;
+                const float mdf = (float)md;
+                double prev = w0.x;
+                float d = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const double cur = gw[lane + 4 * (t + 1)].x;
+                    const float e = ((float)(cur - prev) * inv_seg - mdf) * inv - qp[t];
+                    d = fmaf(e, e, d);
+                    prev = cur;
+                }
+                const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)i;
+                best = key < best ? key : best;
+            }
         }
-        const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)i;
-        best = key < best ? key : best;
+    } else {
+        for (int64_t i = first + lane * ps; i < last; i += 64 * ps) {
+            float f[16];
+            pv.paa(i, m, inv_m, inv_len, f);
+            float d = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const float e = f[t] - qp[t];
+                d = fmaf(e, e, d);
+            }
+            const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)i;
+            best = key < best ? key : best;
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {

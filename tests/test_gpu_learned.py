@@ -98,9 +98,11 @@ def test_adam_step_matches_reference(ctx):
 def test_proposals_match_oracle(ctx):
     """Per quarter block, the GPU proposal lies on the stride grid of its quarter and is (within
     the FP32 error of the PAA distance) the oracle's nearest start; features = (query PAA,
-    candidate PAA).  Shapes: stride 2 / 1 / 4, a ragged last block, a flat stretch, and a window
-    that crosses the 4096-point blocks of the prefix."""
-    for n, m, seed in ((70_001, 128, 21), (50_000, 100, 22), (66_000, 300, 23)):
+    candidate PAA).  Shapes: strides 1 to 32, lengths on and off the 64-multiple grid of the
+    staged path, a ragged last block, a flat stretch, and windows that cross the 4096-point blocks
+    of the prefix."""
+    for n, m, seed in ((70_001, 128, 21), (50_000, 100, 22), (66_000, 300, 23), (60_000, 64, 24),
+                       (80_000, 256, 25), (70_000, 2048, 26)):
         T = W.random_walk(n, seed)
         T[20_000:21_500] = T[20_000]                       # flat windows (PAA all zero)
         Q = W.noisy_cut(T, 12_345, m, 0.1, seed + 100)
