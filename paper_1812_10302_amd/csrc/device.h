@@ -97,7 +97,7 @@ __device__ inline float keogh_d(const QView &v, const float *Ui, const float *Li
 }
 
 // ---------------------------------------------------------------- wave-private queues
-constexpr int kQCap = 128;   // power of two, >= 2 * 64
+constexpr int kQCap = 256;   // power of two, >= 3 * 64 (a level-0 step pushes two groups)
 constexpr int kK1 = 64;   // query-envelope terms of level 1
 
 struct WaveQueue {
@@ -147,14 +147,17 @@ struct CascadeCounts {
 
 // Runs the bound cascade (one wave) on groups of 64 consecutive candidates handed out by
 // src.next(g, last): the group starts at g, starts at or beyond `last` are idle lanes; next()
-// returns false when the source is exhausted.  Level 0 (coalesced, uniform): LB_KimFL only.
-// Survivors are compacted into the wave's LDS queue q1; full batches of 64 run the first K1
-// query-envelope terms, 16 at a time with early abandoning (level 1), and their survivors go to
+// returns false when the source is exhausted.  Level 0 (coalesced, uniform, two groups per step):
+// LB_KimFL, plus the first 16 query-envelope terms for a group in which more than half survive
+// it.  Survivors are compacted into the wave's LDS queue q1; full batches of 64 run the
+// query-envelope terms up to K1, 16 at a time with early abandoning (level 1), and their
+// survivors go to
 // q2, whose full batches run the remaining terms with
 // early abandoning and then the data-envelope bound (level 2, if envU is set).  Candidates that
 // pass everything go to emit(alive, i).  A scheduler that is uniform across the wave serves a
-// full q2 batch first, then a full q1 batch, then a new group, so a queue never holds 64 or more
-// entries when a push can reach it; at the end both queues are drained.
+// full q2 batch first, then a full q1 batch, then new groups: q2 holds fewer than 64 entries when
+// level 1 pushes up to 64 into it, and q1 fewer than 64 when level 0 pushes up to two groups (128)
+// into it, which kQCap accommodates; at the end both queues are drained.
 //   stats(i, mu, s, o): normalisation parameters of candidate i.
 template <class Stats, class Emit, class Source>
 __device__ __forceinline__ void cascade(const QView &v, const float *T, const float *envU, const float *envL,
@@ -194,7 +197,14 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
             const bool got = q_pop(q1, h1, t1, i, kq, mu, s, o);
             bool alive = got;
             if (got) {
-                kq = keogh_q_terms(v, T + i, mu, s, o, 0.0f, 0, K1, true, thr);
+                // entries with kq < 0 have no term done yet, the others the first 16; the first
+                // block runs for the whole batch when any entry needs it, so the term position
+                // stays wave-uniform (scalar loads of the query side)
+                if (__ballot(kq < 0.0f)) {
+                    const float k16 = keogh_q_block(v, T + i, mu, s, o, 0.0f, 0);
+                    if (kq < 0.0f) kq = k16;
+                }
+                kq = keogh_q_terms(v, T + i, mu, s, o, kq, 16, K1, true, thr);
                 if (kq > thr) {
                     alive = false;
                     ++cnt.kq;
@@ -204,23 +214,51 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
             continue;
         }
         if (done) break;
-        int64_t g, last;
-        if (!src.next(g, last)) {
+        // two groups per step: the loads of both are in flight together
+        int64_t gA, lastA, gB, lastB;
+        if (!src.next(gA, lastA)) {
             done = true;
             continue;
         }
-        const int64_t i = g + lane;
-        const bool valid = i < last;
-        const int64_t ii = valid ? i : g;      // idle lanes reuse the group's first start
-        float mu, s, o;
-        stats(ii, mu, s, o);
-        const float *Ti = T + ii;
-        const float c0 = fmaf(Ti[0] - mu, s, o), cl = fmaf(Ti[m - 1] - mu, s, o);
-        const float d0 = q0 - c0, dl = ql - cl;
-        const float kim = fmaf(d0, d0, dl * dl);
-        const bool alive = valid && !(kim > thr);
-        if (valid && !alive) ++cnt.kim;
-        q_push(q1, t1, alive, (int32_t)ii, 0.0f, mu, s, o);
+        const bool hasB = src.next(gB, lastB);
+        if (!hasB) {
+            gB = gA;
+            lastB = gA;
+        }
+        const int64_t iA = gA + lane, iB = gB + lane;
+        const bool vA = iA < lastA, vB = iB < lastB;
+        const int64_t iiA = vA ? iA : gA, iiB = vB ? iB : gA;   // idle lanes reuse a valid start
+        float muA, sA, oA, muB, sB, oB;
+        stats(iiA, muA, sA, oA);
+        stats(iiB, muB, sB, oB);
+        const float a0 = T[iiA], al = T[iiA + m - 1], b0 = T[iiB], bl = T[iiB + m - 1];
+        const float dA0 = q0 - fmaf(a0 - muA, sA, oA), dAl = ql - fmaf(al - muA, sA, oA);
+        const float dB0 = q0 - fmaf(b0 - muB, sB, oB), dBl = ql - fmaf(bl - muB, sB, oB);
+        const bool aliveA = vA && !(fmaf(dA0, dA0, dAl * dAl) > thr);
+        const bool aliveB = vB && !(fmaf(dB0, dB0, dBl * dBl) > thr);
+        if (vA && !aliveA) ++cnt.kim;
+        if (vB && !aliveB) ++cnt.kim;
+        // a group where LB_Kim pruned little runs the first 16 query-envelope terms right here on
+        // coalesced lanes; otherwise its survivors enter the queue with no term done (kq = -1)
+        float kqA = -1.0f, kqB = -1.0f;
+        bool keepA = aliveA, keepB = aliveB;
+        if (__popcll(__ballot(aliveA)) > 32) {
+            kqA = keogh_q_block(v, T + iiA, muA, sA, oA, 0.0f, 0);
+            if (aliveA && kqA > thr) {
+                keepA = false;
+                ++cnt.kq;
+            }
+        }
+        if (__popcll(__ballot(aliveB)) > 32) {
+            kqB = keogh_q_block(v, T + iiB, muB, sB, oB, 0.0f, 0);
+            if (aliveB && kqB > thr) {
+                keepB = false;
+                ++cnt.kq;
+            }
+        }
+        q_push(q1, t1, keepA, (int32_t)iiA, kqA, muA, sA, oA);
+        q_push(q1, t1, keepB, (int32_t)iiB, kqB, muB, sB, oB);
+        if (!hasB) done = true;
     }
 }
 
