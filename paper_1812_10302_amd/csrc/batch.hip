@@ -198,6 +198,28 @@ struct ItemSource {
         }
     }
 
+    // the rest of the current item as one run, or the next item of this query
+    __device__ bool next_run(int64_t &g, int64_t &last) {
+        if (gnext >= gend) {
+            int qq;
+            int64_t f, l;
+            if (!pop(qq, f, l)) return false;
+            if (qq != q) {
+                pending = true;
+                pq = qq;
+                pfirst = f;
+                plast = l;
+                return false;
+            }
+            gnext = f;
+            gend = l;
+        }
+        g = gnext;
+        last = gend;
+        gnext = gend;
+        return true;
+    }
+
     __device__ bool next(int64_t &g, int64_t &last) {
         if (gnext >= gend) {
             int qq;

@@ -9,32 +9,41 @@ namespace dtws {
 // difference may have lost relative precision (short windows, heavy cancellation) are recomputed
 // two-pass from the series.
 struct StatsPrefix {
+    static constexpr bool kRuns = true;   // the cascade may walk items as chains (see cascade)
     const float *T;
     Prefix pre;
     int m;
     double inv_m;
-    // mean and variance of window i (m <= 2048 < kPB: the window ends in its first block or the next)
-    __device__ void window(int64_t i, double &mu, double &var) const {
+    // Sums of (T - a0) and of its square over window i, a0 = the anchor of the window's first block
+    // (m <= 2048 < kPB: the window ends in its first block or the next; branch free, the lookups
+    // past the last block hit sentinels).
+    __device__ void sums(int64_t i, double &a0, double &S1, double &S2) const {
+        sums_from(i, pre.PP[i], pre.PP[i + m], a0, S1, S2);
+    }
+    // the same from the prefix entries p0 = PP[i] and pe = PP[i + m]
+    __device__ void sums_from(int64_t i, double2 p0, double2 pe, double &a0, double &S1, double &S2) const {
         const int64_t e = i + m;
         const int64_t b0 = i / kPB, e0 = (b0 + 1) * kPB;
-        const double2 p0 = pre.PP[i], pe = pre.PP[e];
-        // a window that ends in the next block: whole block b0 plus the re-anchored part (branch
-        // free; the lookups past the last block hit sentinels)
         const bool cross = e >= e0;
         const double2 t = pre.tot[b0];
-        const double a0 = pre.anc[b0];
+        a0 = pre.anc[b0];
         const double delta = cross ? pre.anc[b0 + 1] - a0 : 0.0;
         const double c2 = (double)(e - e0);
-        const double S1 = cross ? (t.x - p0.x) + pe.x + c2 * delta : pe.x - p0.x;
-        const double S2 = cross ? (t.y - p0.y) + pe.y + 2.0 * delta * pe.x + c2 * delta * delta : pe.y - p0.y;
+        S1 = cross ? (t.x - p0.x) + pe.x + c2 * delta : pe.x - p0.x;
+        S2 = cross ? (t.y - p0.y) + pe.y + 2.0 * delta * pe.x + c2 * delta * delta : pe.y - p0.y;
+    }
+    // Normalisation parameters from anchored sums.  Windows whose sums may have lost relative
+    // precision (short windows, heavy cancellation) are recomputed two-pass from the series.  The
+    // scale is stored in FP32 anyway, so 1/sigma comes from the FP32 reciprocal square root of the
+    // FP64 variance (relative error ~2^-23); flat windows (sigma <= 1e-8) get scale 0.
+    __device__ void finish(int64_t i, double a0, double S1, double S2, float &mu32, float &s, float &o) const {
         const double md = S1 * inv_m, msq = S2 * inv_m;
-        var = msq - md * md;
-        mu = a0 + md;
+        double var = msq - md * md, mu = a0 + md;
         if (m <= 64 || !(var > 4e-6 * msq)) {
             const float *w = T + i;
-            double s = 0.0;
-            for (int j = 0; j < m; ++j) s += (double)w[j];
-            mu = s / m;
+            double sm = 0.0;
+            for (int j = 0; j < m; ++j) sm += (double)w[j];
+            mu = sm / m;
             double q = 0.0;
             for (int j = 0; j < m; ++j) {
                 const double d = (double)w[j] - mu;
@@ -43,19 +52,19 @@ struct StatsPrefix {
             var = q / m;
         }
         if (!(var > 0.0)) var = 0.0;
-    }
-    // The scale is stored in FP32 anyway, so 1/sigma comes from the FP32 reciprocal square root
-    // of the FP64 variance (relative error ~2^-23); flat windows (sigma <= 1e-8) get scale 0.
-    __device__ void operator()(int64_t i, float &mu32, float &s, float &o) const {
-        double mu, var;
-        window(i, mu, var);
         mu32 = (float)mu;
         s = var <= kSigmaFlat * kSigmaFlat ? 0.0f : rsqrtf((float)var);
         o = (float)(-(mu - (double)mu32)) * s;
     }
+    __device__ void operator()(int64_t i, float &mu32, float &s, float &o) const {
+        double a0, S1, S2;
+        sums(i, a0, S1, S2);
+        finish(i, a0, S1, S2, mu32, s, o);
+    }
 };
 
 struct StatsArr {
+    static constexpr bool kRuns = false;
     const float *mu, *s, *o;   // already offset to the query's statistics slot
     __device__ void operator()(int64_t i, float &m, float &sg, float &off) const {
         m = mu[i];

@@ -149,7 +149,9 @@ struct CascadeCounts {
 // src.next(g, last): the group starts at g, starts at or beyond `last` are idle lanes; next()
 // returns false when the source is exhausted.  Level 0 (coalesced, uniform, two groups per step):
 // LB_KimFL, plus the first 16 query-envelope terms for a group in which more than half survive
-// it.  Survivors are compacted into the wave's LDS queue q1; full batches of 64 run the
+// it.  With Stats::kRuns and m a multiple of 64 the source hands out whole items (src.next_run)
+// that level 0 walks as chains of groups m apart, carrying the prefix entries from one group to
+// the next, so the window statistics cost one prefix lookup per candidate.  Survivors are compacted into the wave's LDS queue q1; full batches of 64 run the
 // query-envelope terms up to K1, 16 at a time with early abandoning (level 1), and their
 // survivors go to
 // q2, whose full batches run the remaining terms with
@@ -168,6 +170,16 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
     const int K1 = mpad < kK1 ? mpad : kK1;
     uint32_t h1 = 0, t1 = 0, h2 = 0, t2 = 0;
     bool done = false;
+    // chain mode (Stats::kRuns, m a multiple of 64): the current item [cf, clast) is walked as m / 64
+    // chains; chain j visits the groups cf + 64 j + t m, t = 0, 1, ..., so the prefix entry at the
+    // end of a group's windows is the one at the start of the chain's next group (carried in
+    // cnext); two chains advance per step
+    const bool chains = Stats::kRuns && (m & 63) == 0;
+    int64_t cf = 0, clast = 0, cg = 0;
+    int cj = 0, cJ = m >> 6;
+    bool citem = false, cfresh = true;
+    double2 ccarry[2];
+    ccarry[0] = ccarry[1] = make_double2(0.0, 0.0);
     for (;;) {
         if (t2 - h2 >= 64u || (done && t2 != h2)) {
             int32_t i = 0;
@@ -214,6 +226,57 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
             continue;
         }
         if (done) break;
+        if constexpr (Stats::kRuns) {
+            if (chains) {
+                if (!citem) {
+                    if (!src.next_run(cf, clast)) {
+                        done = true;
+                        continue;
+                    }
+                    citem = true;
+                    cj = 0;
+                    cg = cf;
+                    cfresh = true;
+                }
+                // chains cj and cj + 1 (if it exists) at the same step t: groups cg and cg + 64
+                const bool two = cj + 1 < cJ;
+                int64_t ii[2];
+                bool valid[2];
+                double2 pe[2];
+                float c0v[2], clv[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int64_t i = cg + 64 * h + lane;
+                    valid[h] = (h == 0 || two) && i < clast;
+                    ii[h] = valid[h] ? i : cf;
+                    pe[h] = stats.pre.PP[ii[h] + m];
+                    c0v[h] = T[ii[h]];
+                    clv[h] = T[ii[h] + m - 1];
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double2 p0 = cfresh ? stats.pre.PP[ii[h]] : ccarry[h];
+                    ccarry[h] = pe[h];
+                    double a0, S1, S2;
+                    stats.sums_from(ii[h], p0, pe[h], a0, S1, S2);
+                    float mu = 0.0f, s = 0.0f, o = 0.0f;
+                    if (valid[h]) stats.finish(ii[h], a0, S1, S2, mu, s, o);
+                    const float d0 = q0 - fmaf(c0v[h] - mu, s, o), dl = ql - fmaf(clv[h] - mu, s, o);
+                    const bool alive = valid[h] && !(fmaf(d0, d0, dl * dl) > thr);
+                    if (valid[h] && !alive) ++cnt.kim;
+                    q_push(q1, t1, alive, (int32_t)ii[h], -1.0f, mu, s, o);
+                }
+                cfresh = false;
+                cg += m;
+                if (cg >= clast) {
+                    cj += two ? 2 : 1;
+                    cg = cf + 64 * cj;
+                    cfresh = true;
+                    if (cj >= cJ || cg >= clast) citem = false;
+                }
+                continue;
+            }
+        }
         // two groups per step: the loads of both are in flight together
         int64_t gA, lastA, gB, lastB;
         if (!src.next(gA, lastA)) {

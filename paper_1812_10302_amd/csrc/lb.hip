@@ -22,6 +22,7 @@ QView make_view(const LbArgs &a) {
 }
 
 struct StatsArrays {
+    static constexpr bool kRuns = false;
     const float *mu, *s, *o;
     __device__ void operator()(int64_t i, float &m, float &sg, float &off) const {
         m = mu[i];
