@@ -36,6 +36,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 over the library sources, to tell whether recorded counters still describe them."""
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1812_10302_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(src, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()
+
+
+def traffic_of(kernel: str, launches: int, algorithmic: float):
+    """HBM bytes per launch of `kernel` recorded from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (see the
+    profiles folder), or None when none is recorded for the current sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    cur = kernel_source_hash()
+    for line in open(path):
+        if line.startswith("| `" + kernel + "`"):
+            cols = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+            # | kernel | sources sha256 | bytes per launch (calibrated) | ...
+            if cols[1] == cur:
+                return float(cols[2])
+    return None
+
+
 def cells(m: int, r: int) -> int:
     r = min(r, m - 1)
     return m * (2 * r + 1) - r * (r + 1)
@@ -53,6 +81,12 @@ def main():
     ap.add_argument("--train-n", type=int, default=10_000_000, help="training series length (ordering network)")
     ap.add_argument("--train-pairs", type=int, default=999_000)
     ap.add_argument("--train-epochs", type=int, default=20)
+    ap.add_argument("--only-learned", action="store_true",
+                    help="time only the batched search in learned order (profiling runs)")
+    ap.add_argument("--schedule", default="",
+                    help="comma-separated schedule fields (k=v) to use instead of the autotuner")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after timing, copy this many MiB on the device (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search shards by "
@@ -79,19 +113,21 @@ def main():
     def plain_step(flags=0):
         return [ctx.search(T, q, r, flags=flags, seed=7) for q, r in zip(Qs, rs)]
 
-    for _ in range(args.warmup):
-        plain_step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
     per_query = []
-    for _ in range(args.steps):
-        for q, r in zip(Qs, rs):
-            a = time.perf_counter()
-            ctx.search(T, q, r, seed=7)
-            per_query.append(time.perf_counter() - a)
-    torch.cuda.synchronize()
-    plain_s = (time.perf_counter() - t1) / args.steps / nq
-    plain_results = plain_step()
+    plain_s, plain_results = None, None
+    if not args.only_learned:
+        for _ in range(args.warmup):
+            plain_step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            for q, r in zip(Qs, rs):
+                a = time.perf_counter()
+                ctx.search(T, q, r, seed=7)
+                per_query.append(time.perf_counter() - a)
+        torch.cuda.synchronize()
+        plain_s = (time.perf_counter() - t1) / args.steps / nq
+        plain_results = plain_step()
 
     # ---------------------------------------------------------------- ordering network (untimed)
     from paper_1812_10302_amd import proposal
@@ -125,19 +161,34 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t1) / args.steps, res
 
-    natural_step_s, natural_results = time_batched(dtws.ORDER_NATURAL)
-    # launch schedule for the learned batch picked by the library's autotuner (untimed)
-    t0 = time.time()
-    schedule, tune_ms = ctx.autotune_batch(T, pq, rs, flags=dtws.ORDER_LEARNED, seed=7, reps=3)
-    log(f"autotuned schedule {schedule} ({tune_ms:.2f} ms per batch, tuning took {time.time() - t0:.1f}s)")
+    natural_step_s, natural_results = (None, None) if args.only_learned else time_batched(dtws.ORDER_NATURAL)
+    if args.schedule:
+        ctx.set_schedule(**{k: int(v) for k, v in (kv.split("=") for kv in args.schedule.split(","))})
+        schedule = ctx.get_schedule()
+        log(f"schedule {schedule} (given)")
+    else:
+        # launch schedule for the learned batch picked by the library's autotuner (untimed)
+        t0 = time.time()
+        schedule, tune_ms = ctx.autotune_batch(T, pq, rs, flags=dtws.ORDER_LEARNED, seed=7, reps=3)
+        log(f"autotuned schedule {schedule} ({tune_ms:.2f} ms per batch, tuning took {time.time() - t0:.1f}s)")
     elapsed_step, results = time_batched(dtws.ORDER_LEARNED)
     ms_per_step = elapsed_step * 1e3
     s_per_query = elapsed_step / nq
     log("plain:", plain_results)
     log("batched natural:", natural_results)
     log("batched learned:", results)
-    assert results == natural_results, "learned and natural orders disagree"
-    assert [i for i, _ in results] == [i for i, _ in plain_results], "batched and plain disagree"
+    if not args.only_learned:
+        assert results == natural_results, "learned and natural orders disagree"
+        assert [i for i, _ in results] == [i for i, _ in plain_results], "batched and plain disagree"
+    if args.copy_calibration_mib > 0:
+        # a plain device copy of known size: its HBM counters calibrate the traffic of the others
+        nb = args.copy_calibration_mib << 20
+        src_buf = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst_buf = torch.empty_like(src_buf)
+        torch.cuda.synchronize()
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        del src_buf, dst_buf
 
     def batch_step_learned(flags=0):
         return batch_step(dtws.ORDER_LEARNED, flags)
@@ -152,32 +203,58 @@ def main():
     per_query_prof = []
     if not args.no_profile:
         prof_total, cnt_total = profiled(lambda: batch_step_learned(dtws.PROFILE))
-        for q, r in zip(Qs, rs):
+        for q, r in ([] if args.only_learned else zip(Qs, rs)):
             kp, c = profiled(lambda: ctx.search(T, q, r, flags=dtws.PROFILE, seed=7))
             per_query_prof.append({"m": int(q.numel()), "r": int(r),
                                    "plain_kernel_ms": {k: round(v[0], 4) for k, v in kp.items()}, "counters": c})
     dtw_cells = cnt_total.get("dtw_cells", 0)
-    dtw_lane_cells = cnt_total.get("dtw_lane_cells", 0)
     lb_candidates = cnt_total.get("candidates", 0)
-    dominant = max(prof_total, key=lambda k: prof_total[k][0])
     roofline = None
     if not args.no_profile:
+        dominant = max(prof_total, key=lambda k: prof_total[k][0])
         t_ms, nl = prof_total[dominant]
-        if dominant == "dtw":
-            ach = dtw_cells / (t_ms * 1e-3) / 1e9
-            roofline = {"bound": "alu", "kernel": "k_dtw_batch", "achieved": round(ach, 2),
-                        "peak": round(DTW_PEAK_GCUPS, 1), "unit": "GCUPS", "frac": round(ach / DTW_PEAK_GCUPS, 4),
-                        "traffic": None, "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl,
-                        "issued_frac": round(dtw_lane_cells / (t_ms * 1e-3) / 1e9 / DTW_PEAK_GCUPS, 4)}
+        if dominant == "lb":
+            # per candidate the cascade must read its series point (4 B) and its window statistics:
+            # one (sum, sum of squares) prefix entry (16 B) or the three per-window values (12 B)
+            per_cand = 20 if schedule["stats_prefix"] else 16
+            kernel = "k_lb_batch<true>" if schedule["stats_prefix"] else "k_lb_batch"
+            units = lb_candidates
+        elif dominant == "stats":
+            # blocked prefix: read 4 B, write 16 B per series point (one pass for the batch)
+            per_cand, kernel, units = 20, "k_prefix", wl.T.size
         else:
-            # streaming kernels: algorithmic bytes per candidate = series point 4 B + window
-            # statistics (prefix: 4 x 8 B; shared-length arrays: 12 B) for the cascade
-            per_cand = {"lb": 36, "stats": 20, "env": 12}.get(dominant, 36)
-            ach = lb_candidates * per_cand / (t_ms * 1e-3) / 1e9
-            roofline = {"bound": "hbm", "kernel": f"k_{dominant}_batch" if dominant == "lb" else f"k_{dominant}",
-                        "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                        "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
+            per_cand, kernel, units = None, f"class {dominant}", None
+        if per_cand is not None:
+            ach = units * per_cand / (t_ms * 1e-3) / 1e9
+            roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "traffic": traffic_of(kernel, nl, units * per_cand / max(nl, 1)),
+                        "algorithmic_bytes_per_launch": round(units * per_cand / max(nl, 1)),
+                        "bytes_per_unit": per_cand, "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
+        else:
+            roofline = {"bound": "latency", "kernel": kernel, "achieved": None, "peak": None, "unit": None,
+                        "frac": None, "traffic": None, "avg_launch_ms": round(t_ms / max(nl, 1), 4),
+                        "launches": nl}
+
+    # ---------------------------------------------------------------- DTW kernel throughput
+    # exact banded DTW (no abandoning) of many random candidates per query shape, default schedule:
+    # the rate of the DTW kernel itself, which the pruned search above hardly exercises
+    dtw_rate = []
+    if not args.no_profile:
+        rng = np.random.default_rng(11)
+        for q, m, r in zip(Qs, ms, rs):
+            count = (1 << 20) if m <= 256 else (1 << 18)
+            st = torch.from_numpy(rng.integers(0, wl.T.size - m + 1, count)).to(dev)
+            ctx.dtw_band(T, q, r, st)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                ctx.dtw_band(T, q, r, st)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 3
+            g = count * cells(m, r) / dt / 1e9
+            dtw_rate.append({"m": m, "r": r, "candidates": count, "ms": round(dt * 1e3, 3), "gcups": round(g, 1),
+                             "frac_valu_peak": round(g / DTW_PEAK_GCUPS, 4)})
 
     # ---------------------------------------------------------------- CPU baseline (oracle)
     cpu = None
@@ -210,19 +287,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "n": int(wl.T.size), "m": ms, "r": rs, "mode": "batched+learned",
                    "note": wl.note},
-        "batched_natural_s_per_query": round(natural_step_s / nq, 6),
+        "batched_natural_s_per_query": round(natural_step_s / nq, 6) if natural_step_s else None,
         "ordering_network": {"train_series": f"random walk n={args.train_n} seed 8", "pairs": int(sum(x.shape[0] for x in Xs)),
                              "epochs": args.train_epochs, "loss_curve": [round(v, 5) for v in curve],
                              "train_s": round(train_s, 2)},
         "schedule": schedule,
-        "plain_s_per_query": round(plain_s, 6),
-        "batched_over_plain": round(s_per_query / plain_s, 4),
+        "plain_s_per_query": round(plain_s, 6) if plain_s else None,
+        "batched_over_plain": round(s_per_query / plain_s, 4) if plain_s else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "plain_per_query_s": [round(float(np.median(per_query[i::nq])), 6) for i in range(nq)],
+        "plain_per_query_s": [round(float(np.median(per_query[i::nq])), 6) for i in range(nq)] if per_query else None,
         "batched_kernel_ms": {k: [round(v[0], 4), v[1]] for k, v in prof_total.items()},
-        "dtw_gcups": round(dtw_cells / (prof_total["dtw"][0] * 1e-3) / 1e9, 2) if prof_total["dtw"][0] > 0 else None,
-        "dtw_frac_valu_peak": round(dtw_cells / (prof_total["dtw"][0] * 1e-3) / 1e9 / DTW_PEAK_GCUPS, 4)
+        "dtw_throughput": dtw_rate,
+        "dtw_gcups": max((d["gcups"] for d in dtw_rate), default=None),
+        "dtw_frac_valu_peak": max((d["frac_valu_peak"] for d in dtw_rate), default=None),
+        "search_dtw_gcups": round(dtw_cells / (prof_total["dtw"][0] * 1e-3) / 1e9, 2)
         if prof_total["dtw"][0] > 0 else None,
         "counters": cnt_total,
         "plain_profile": per_query_prof,

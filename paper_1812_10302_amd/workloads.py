@@ -154,3 +154,50 @@ def tiny_random(n: int, m: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     T = np.cumsum(rng.standard_normal(n)).astype(np.float32)
     Q = np.cumsum(rng.standard_normal(m)).astype(np.float32)
     return T, Q
+
+
+def motif_shapes(m: int = 1024) -> list[np.ndarray]:
+    """Ten z-normalised shapes of length m: five random walks (seeds 100..104) and five sums of
+    two or three sinusoids and Gaussian bumps (seeds 200..204)."""
+    out = []
+    for k in range(5):
+        out.append(random_walk(m, 100 + k).astype(np.float64))
+    t = np.arange(m, dtype=np.float64)
+    for k in range(5):
+        rng = np.random.default_rng(200 + k)
+        x = np.zeros(m)
+        for _ in range(int(rng.integers(2, 4))):
+            if rng.random() < 0.5:
+                x += rng.uniform(0.5, 2.0) * np.sin(2 * math.pi * t / rng.uniform(m / 8, m) + rng.uniform(0, 2 * math.pi))
+            else:
+                c, w = rng.uniform(0, m), rng.uniform(m / 40, m / 6)
+                x += rng.uniform(1.0, 4.0) * np.exp(-0.5 * ((t - c) / w) ** 2)
+        out.append(x)
+    return [(x - x.mean()) / x.std() for x in out]
+
+
+def planted_motifs(n: int = 1_000_000_000, m: int = 1024, copies: int = 100, seed: int = 0) -> Workload:
+    """Random walk of n points (seed) with copies x 10 planted motifs: shape k = motif_shapes()[k]
+    is written at non-overlapping seeded starts p as T[p + j] = T[p] + a S_k[j] + N(0, 0.1),
+    a ~ U[0.5, 5].  Queries (128): a_q S_{q mod 10} + N(0, 0.1), band 10% of m.  Workload.src
+    holds, per query, the shape index; the plant positions and shapes are in note."""
+    shapes = motif_shapes(m)
+    T = random_walk(n, seed)
+    rng = np.random.default_rng(300)
+    total = copies * len(shapes)
+    seg = (n - m) // total
+    pos = np.arange(total, dtype=np.int64) * seg + rng.integers(0, seg - m, total)
+    kind = rng.permutation(np.repeat(np.arange(len(shapes)), copies))
+    amp = rng.uniform(0.5, 5.0, total)
+    for p, k, a in zip(pos, kind, amp):
+        noise = rng.normal(0.0, 0.1, m)
+        T[p:p + m] = (float(T[p]) + a * shapes[k] + noise).astype(np.float32)
+    qrng = np.random.default_rng(500)
+    qs, rs, src = [], [], []
+    for q in range(128):
+        a = qrng.uniform(0.5, 5.0)
+        qs.append((a * shapes[q % 10] + np.random.default_rng(400 + q).normal(0.0, 0.1, m)).astype(np.float32))
+        rs.append(band(m, 0.10))
+        src.append(q % 10)
+    wl = Workload(f"motifs{n}_128q_m{m}", T, qs, rs, src, {"positions": pos, "shapes": kind})
+    return wl

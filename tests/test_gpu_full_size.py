@@ -1,0 +1,153 @@
+"""Parity at the full workload sizes, through the C ABI, in the configuration the benchmark times.
+
+Where the FP64 cascade oracle (oracle/cascade.c, all host threads) finishes in seconds it gives the
+exact answer; elsewhere the checks are properties that hold at any size, computed by the oracle one
+candidate at a time: the returned distance is the FP64 DTW at the returned start, and no other
+candidate examined (the query's source position, seeded random starts) is better.
+
+  * random walk n = 1e8, queries m = 128/512/1024 (5% band): exact, plain and batched (series
+    order and learned order);
+  * the same series, 256 queries m ~ U{64..2048}, band 0-10%: properties for all, exact for the
+    two cheapest, learned order = series order;
+  * sinusoid/random-walk mixture n = 1e8, 64 queries m = 256 (r = 12): properties, exact for two;
+  * random walk n = 1e9 with 1000 planted motifs, 128 queries m = 1024 (r = 102): properties, and
+    the answers are reported against the planted positions of each query's shape.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1812_10302_amd as dtws
+from paper_1812_10302_amd import proposal
+from paper_1812_10302_amd import workloads as W
+from oracle import Cascade
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def casc():
+    return Cascade()
+
+
+@pytest.fixture(scope="module")
+def rw():
+    wl = W.three_queries_large(100_000_000)
+    return wl, dev(wl.T)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dtws.Context(0, max_n=100_000_000, max_m=2048, max_queries=256)
+    yield c
+    c.close()
+
+
+def train_order(ctx, T_train, shapes, queries_per_shape=24, epochs=12, seed=90):
+    Xs, Ys = [], []
+    for k, (m, r) in enumerate(shapes):
+        X, Y = proposal.make_pairs(ctx, T_train, m, r, queries_per_shape, seed=seed + k)
+        Xs.append(X)
+        Ys.append(Y)
+    proposal.train(ctx, torch.cat(Xs).contiguous(), torch.cat(Ys).contiguous(), epochs=epochs, seed=seed)
+
+
+def check_properties(casc, T, queries, rs, got, sources=None, samples=64, seed=0):
+    """got[k] = (index, distance) must be the FP64 DTW at that start, and no better than any
+    sampled start or the query's source (ties: the returned start is the lowest)."""
+    rng = np.random.default_rng(seed)
+    for k, (q, r) in enumerate(zip(queries, rs)):
+        i, d = got[k]
+        N = T.size - q.size + 1
+        at = casc.dtw_starts(T, q, r, np.array([i]))[0]
+        assert abs(at - d) <= 1e-9 * max(d, 1e-300), (k, i, d, at)
+        starts = rng.integers(0, N, samples)
+        if sources is not None and sources[k] >= 0:
+            s = sources[k]
+            starts = np.concatenate([starts, np.arange(max(0, s - 3), min(N, s + 4))])
+        dd = casc.dtw_starts(T, q, r, starts)
+        assert np.all(dd >= d * (1 - 1e-12)), (k, d, float(dd.min()))
+        tie = dd == d
+        assert np.all(starts[tie] >= i), (k, i, starts[tie])
+
+
+def check_exact(got, ref):
+    for k, ((gi, gd), (ri, rd)) in enumerate(zip(got, ref)):
+        assert gi == ri, (k, gi, ri, gd, rd)
+        assert abs(gd - rd) <= 1e-9 * rd + 1e-12, (k, gd, rd)
+
+
+def test_random_walk_1e8_three_queries_exact(ctx, rw, casc):
+    wl, Td = rw
+    ref = [casc.search(wl.T, q, r)[:2] for q, r in zip(wl.queries, wl.bands)]
+    Qd = [dev(q) for q in wl.queries]
+    plain = [ctx.search(Td, q, r, seed=7) for q, r in zip(Qd, wl.bands)]
+    check_exact(plain, ref)
+    pq = dtws.PackedQueries(Qd)
+    check_exact(ctx.search_batch(Td, pq, wl.bands), ref)
+    train_order(ctx, W.random_walk(10_000_000, 8), list(zip([q.size for q in wl.queries], wl.bands)))
+    check_exact(ctx.search_batch(Td, pq, wl.bands, flags=dtws.ORDER_LEARNED, seed=7), ref)
+
+
+def test_random_walk_1e8_256_mixed_queries(ctx, rw, casc):
+    wl, Td = rw
+    b = W.batched_queries(wl.T, 256, seed=6)
+    pq = dtws.PackedQueries([dev(q) for q in b.queries])
+    natural = ctx.search_batch(Td, pq, b.bands)
+    train_order(ctx, W.random_walk(10_000_000, 8), [(128, 6), (512, 25), (1024, 51), (2048, 102)],
+                queries_per_shape=12, epochs=8)
+    learned = ctx.search_batch(Td, pq, b.bands, flags=dtws.ORDER_LEARNED, seed=3)
+    assert learned == natural
+    check_properties(casc, wl.T, b.queries, b.bands, natural, b.sources, samples=32, seed=1)
+    cost = [q.size * (2 * r + 1) for q, r in zip(b.queries, b.bands)]
+    for k in np.argsort(cost)[:2]:
+        check_exact([natural[k]], [casc.search(wl.T, b.queries[k], b.bands[k])[:2]])
+    for k in (0, 200):
+        check_exact([ctx.search(Td, dev(b.queries[k]), b.bands[k], seed=5)], [natural[k]])
+
+
+def test_mixture_1e8_64_queries(ctx, casc):
+    T = W.sinusoid_mix(100_000_000, 7)
+    wl = W.mixed_queries(T, 64, 256, seed=9000)
+    Td = dev(T)
+    pq = dtws.PackedQueries([dev(q) for q in wl.queries])
+    natural = ctx.search_batch(Td, pq, wl.bands)
+    train_order(ctx, W.sinusoid_mix(10_000_000, 8), [(256, 12)], queries_per_shape=96)
+    learned = ctx.search_batch(Td, pq, wl.bands, flags=dtws.ORDER_LEARNED, seed=3)
+    assert learned == natural
+    check_properties(casc, T, wl.queries, wl.bands, natural, wl.sources, samples=64, seed=2)
+    for k in (0, 40):
+        check_exact([natural[k]], [casc.search(T, wl.queries[k], wl.bands[k])[:2]])
+
+
+def test_random_walk_1e9_planted_motifs(casc):
+    wl = W.planted_motifs(1_000_000_000)
+    c = dtws.Context(0, max_n=wl.T.size, max_m=1024, max_queries=128)
+    try:
+        Td = dev(wl.T)
+        pq = dtws.PackedQueries([dev(q) for q in wl.queries])
+        train_order(c, W.random_walk(10_000_000, 8), [(1024, 102)], queries_per_shape=48, epochs=10)
+        learned = c.search_batch(Td, pq, wl.bands, flags=dtws.ORDER_LEARNED, seed=3)
+        check_properties(casc, wl.T, wl.queries, wl.bands, learned, None, samples=16, seed=3)
+        check_exact([c.search(Td, dev(wl.queries[k]), wl.bands[k], seed=5) for k in (0, 77)],
+                    [learned[0], learned[77]])
+        # expected, not guaranteed: each answer is a planted copy of the query's own shape
+        pos, kind = wl.note["positions"], wl.note["shapes"]
+        hits = 0
+        for k, (i, _) in enumerate(learned):
+            near = np.abs(pos - i) <= 16
+            hits += bool(np.any(kind[near] == wl.sources[k]))
+        print(f"answers at a planted copy of the query's shape: {hits}/{len(learned)}")
+        assert hits >= int(0.9 * len(learned))
+        del Td
+    finally:
+        c.close()
+        torch.cuda.empty_cache()
