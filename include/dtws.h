@@ -217,6 +217,10 @@ typedef struct {
                                   always from the blocked prefix of the series */
     int32_t data_envelope;     /* batched search: 1 = the cascade's data-envelope bound
                                   (default), 0 = skip it (no envelope pass) */
+    int32_t rounds;            /* batched search: bound-cascade / DTW rounds over the work
+                                  queue, per query 64K, 1M, 16M candidates then the rest (4,
+                                  default), 1M then the rest (2), or all at once (1) */
+    int32_t reserved;          /* 0 */
 } dtws_schedule;
 
 DTWS_API int dtws_get_schedule(dtws_ctx *ctx, dtws_schedule *out_host);
@@ -225,8 +229,8 @@ DTWS_API int dtws_set_schedule(dtws_ctx *ctx, const dtws_schedule *s_host);
 
 /* Autotuner: runs dtws_search_batch on the given batch (arguments as there;
  * DTWS_PROFILE is ignored) under candidate schedules, by coordinate descent over
- * diag_max, block, lb_blocks_per_cu, dtw_blocks_per_cu, stats_prefix and
- * data_envelope starting from the current schedule; each candidate is called once untimed (graph capture) and then `reps`
+ * diag_max, block, lb_blocks_per_cu, dtw_blocks_per_cu, stats_prefix,
+ * data_envelope and rounds starting from the current schedule; each candidate is called once untimed (graph capture) and then `reps`
  * times (1..100) timed on the host clock.  All candidates must return identical
  * matches (DTWS_EHIP otherwise, schedule unchanged).  Installs the fastest, writes
  * it to *best_host and its mean time per call (ms) to *best_ms_host.  Blocking. */

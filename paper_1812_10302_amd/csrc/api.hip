@@ -452,11 +452,14 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     }
     int rc = dtw_round();
     if (rc != DTWS_OK) return rc;
-    // rounds over the work queue: 64K, 1M, 16M candidates per query, then the rest
-    const int64_t targets[4] = {int64_t(1) << 16, (int64_t(1) << 16) + (int64_t(1) << 20),
-                                (int64_t(1) << 16) + (int64_t(1) << 20) + (int64_t(1) << 24), INT64_MAX / 2};
+    // rounds over the work queue (candidates per query, cumulative): 64K, 1M, 16M, then the rest;
+    // with fewer rounds (schedule) 1M then the rest, or everything at once
+    const int64_t k64 = int64_t(1) << 16, k1m = int64_t(1) << 20, k16m = int64_t(1) << 24, all = INT64_MAX / 2;
+    const int nrounds = c->rounds == 1 ? 1 : (c->rounds == 2 ? 2 : 4);
+    const int64_t t4[4] = {k64, k64 + k1m, k64 + k1m + k16m, all}, t2[2] = {k1m, all}, t1[1] = {all};
+    const int64_t *targets = nrounds == 4 ? t4 : (nrounds == 2 ? t2 : t1);
     int64_t rank_lo = 0;
-    for (int round = 0; round < 4 && rank_lo < max_nb; ++round) {
+    for (int round = 0; round < nrounds && rank_lo < max_nb; ++round) {
         int64_t rank_hi = (targets[round] + B - 1) / B;
         if (rank_hi > max_nb) rank_hi = max_nb;
         {
@@ -466,8 +469,9 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         }
         {
             PROF(DTWS_K_LB);
-            // early rounds are small: split each block so that many waves share them
-            int parts = round == 0 ? 16 : (round == 1 ? 4 : 1);
+            // small rounds: split each block so that many waves share them
+            const int64_t size = (rank_hi - rank_lo) * B;
+            int parts = size <= k64 ? 16 : (size <= 2 * k1m ? 4 : 1);
             while (parts > 1 && B / parts < 256) parts /= 2;
             HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)rank_lo, (int)rank_hi, parts, lb_blocks, s));
         }
@@ -529,7 +533,7 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
         // per-query parameters and the tuning knobs.
         std::vector<int64_t> sig = {(int64_t)(uintptr_t)T, n, (int64_t)(uintptr_t)Qp, nq, (int64_t)flags,
                                     (int64_t)seed, p.block, c->lb_blocks_per_cu, c->dtw_blocks_per_cu, c->diag_max,
-                                    c->stats_prefix, c->data_envelope};
+                                    c->stats_prefix, c->data_envelope, c->rounds};
         for (int k = 0; k < nq; ++k) {
             sig.push_back(qoff[k]);
             sig.push_back(mh[k]);

@@ -25,12 +25,16 @@ struct StatsPrefix {
         const int64_t e = i + m;
         const int64_t b0 = i / kPB, e0 = (b0 + 1) * kPB;
         const bool cross = e >= e0;
+        // unconditional loads (the entry past the last block exists), selected afterwards
         const double2 t = pre.tot[b0];
         a0 = pre.anc[b0];
-        const double delta = cross ? pre.anc[b0 + 1] - a0 : 0.0;
+        const double a1 = pre.anc[b0 + 1];
+        const double delta = cross ? a1 - a0 : 0.0;
         const double c2 = (double)(e - e0);
-        S1 = cross ? (t.x - p0.x) + pe.x + c2 * delta : pe.x - p0.x;
-        S2 = cross ? (t.y - p0.y) + pe.y + 2.0 * delta * pe.x + c2 * delta * delta : pe.y - p0.y;
+        const double cS1 = (t.x - p0.x) + pe.x + c2 * delta;
+        const double cS2 = (t.y - p0.y) + pe.y + 2.0 * delta * pe.x + c2 * delta * delta;
+        S1 = cross ? cS1 : pe.x - p0.x;
+        S2 = cross ? cS2 : pe.y - p0.y;
     }
     // Normalisation parameters from anchored sums.  Windows whose sums may have lost relative
     // precision (short windows, heavy cancellation) are recomputed two-pass from the series.  The

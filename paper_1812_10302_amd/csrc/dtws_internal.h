@@ -310,6 +310,7 @@ struct dtws_ctx {
     int band_lanes = 0;  // dtws_dtw_band: 0 = automatic, 1 = one lane per candidate, 64 = one wave per candidate
     int stats_prefix = 0;   // batched: 1 = window statistics always from the blocked prefix
     int data_envelope = 1;  // batched: 0 = skip the data-envelope bound
+    int rounds = 4;         // batched: rounds over the work queue (4, 2 or 1)
     // ordering network
     dtws::MlpBufs mlp{};
     bool has_model = false;

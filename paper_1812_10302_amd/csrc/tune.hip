@@ -16,8 +16,9 @@ constexpr int64_t kBlocks[] = {2048, 4096, 8192, 16384};
 constexpr int32_t kDiagMaxes[] = {0, 2048, 16384, 65536};
 constexpr int32_t kLbWidths[] = {4, 8, 16, 32};
 constexpr int32_t kDtwWidths[] = {2, 4, 8};
-constexpr int kKnobs = 6;
-constexpr int kKnobValues[kKnobs] = {4, 4, 4, 3, 2, 2};
+constexpr int32_t kRounds[] = {4, 2, 1};
+constexpr int kKnobs = 7;
+constexpr int kKnobValues[kKnobs] = {4, 4, 4, 3, 2, 2, 3};
 
 bool valid_block(int64_t b) {
     if (b == 0) return true;
@@ -45,6 +46,8 @@ DTWS_API int dtws_get_schedule(dtws_ctx *c, dtws_schedule *out) {
     out->band_lanes = c->band_lanes;
     out->stats_prefix = c->stats_prefix;
     out->data_envelope = c->data_envelope;
+    out->rounds = c->rounds;
+    out->reserved = 0;
     return DTWS_OK;
 }
 
@@ -53,7 +56,7 @@ DTWS_API int dtws_set_schedule(dtws_ctx *c, const dtws_schedule *s) {
     if (!valid_block(s->block) || s->lb_blocks_per_cu < 0 || s->lb_blocks_per_cu > 64 || s->dtw_blocks_per_cu < 0 ||
         s->dtw_blocks_per_cu > 64 || s->diag_max < -1 || s->diag_max > (1 << 24) ||
         (s->band_lanes != 0 && s->band_lanes != 1 && s->band_lanes != 64) || (s->stats_prefix != 0 && s->stats_prefix != 1) ||
-        (s->data_envelope != 0 && s->data_envelope != 1))
+        (s->data_envelope != 0 && s->data_envelope != 1) || (s->rounds != 1 && s->rounds != 2 && s->rounds != 4))
         return DTWS_EINVAL;
     c->block = s->block;
     c->lb_blocks_per_cu = s->lb_blocks_per_cu;
@@ -62,6 +65,7 @@ DTWS_API int dtws_set_schedule(dtws_ctx *c, const dtws_schedule *s) {
     c->band_lanes = s->band_lanes;
     c->stats_prefix = s->stats_prefix;
     c->data_envelope = s->data_envelope;
+    c->rounds = s->rounds;
     return DTWS_OK;
 }
 
@@ -103,7 +107,8 @@ DTWS_API int dtws_autotune_batch(dtws_ctx *c, const float *T, int64_t n, const f
             case 2: t.lb_blocks_per_cu = kLbWidths[v]; break;
             case 3: t.dtw_blocks_per_cu = kDtwWidths[v]; break;
             case 4: t.stats_prefix = v; break;
-            default: t.data_envelope = 1 - v; break;
+            case 5: t.data_envelope = 1 - v; break;
+            default: t.rounds = kRounds[v]; break;
             }
             if (memcmp(&t, &base, sizeof(t)) == 0) continue;
             double ms = 0.0;

@@ -338,7 +338,8 @@ def test_schedules_give_identical_results(ctx, casc):
     try:
         for sched in ({"diag_max": 0}, {"diag_max": 1 << 24}, {"diag_max": 8192, "block": 2048},
                       {"diag_max": 64, "block": 16384, "lb_blocks_per_cu": 2, "dtw_blocks_per_cu": 1},
-                      {"diag_max": 8192, "block": 4096, "stats_prefix": 1, "data_envelope": 0}):
+                      {"diag_max": 8192, "block": 4096, "stats_prefix": 1, "data_envelope": 0},
+                      {"rounds": 1, "block": 8192}, {"rounds": 2, "stats_prefix": 1}):
             ctx.set_schedule(**sched)
             _check_batch(ctx.search_batch(Td, Qd, rs), ref)
             _check_batch([ctx.search(Td, q, r, seed=3) for q, r in zip(Qd, rs)], ref)
@@ -349,7 +350,7 @@ def test_schedules_give_identical_results(ctx, casc):
 def test_set_schedule_rejects_bad_fields(ctx):
     default = ctx.get_schedule()
     for bad in ({"block": 3000}, {"diag_max": -2}, {"band_lanes": 2}, {"lb_blocks_per_cu": 65},
-                {"stats_prefix": 2}, {"data_envelope": -1}):
+                {"stats_prefix": 2}, {"data_envelope": -1}, {"rounds": 3}):
         with pytest.raises(dtws.DtwsError):
             ctx.set_schedule(**bad)
         assert ctx.get_schedule() == default
@@ -366,7 +367,7 @@ def test_autotune_installs_a_candidate_schedule(ctx, casc):
         assert ms > 0
         assert best["block"] in (2048, 4096, 8192, 16384) and best["diag_max"] in (0, 2048, 16384, 65536)
         assert best["lb_blocks_per_cu"] in (4, 8, 16, 32) and best["dtw_blocks_per_cu"] in (2, 4, 8)
-        assert best["stats_prefix"] in (0, 1) and best["data_envelope"] in (0, 1)
+        assert best["stats_prefix"] in (0, 1) and best["data_envelope"] in (0, 1) and best["rounds"] in (1, 2, 4)
         assert ctx.get_schedule() == best
         _check_batch(ctx.search_batch(dev(T), pq, rs), _cascade_refs(casc, T, qs, rs))
     finally:
