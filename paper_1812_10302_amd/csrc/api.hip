@@ -19,6 +19,22 @@ constexpr int64_t kMinBlock = 2048;   // smallest work-item block (sizes the ord
 constexpr int64_t kDefaultBlock = 4096;
 constexpr int kDefaultDiagMax = 16384;  // rounds with at most this many survivors: one wave per candidate
 
+// Decimation levels the proposals of a length-m query read (m a multiple of 64, step m/64 a power
+// of two from 2 to 32).
+uint32_t dec_level_of(int m) {
+    if (m % 64 != 0 || m < 128) return 0u;
+    const int ps = m / 64;
+    if ((ps & (ps - 1)) != 0 || ps > 32) return 0u;
+    return 1u << __builtin_ctz((unsigned)ps);
+}
+
+// entries of all decimated levels for a series of max_n points
+int64_t dec_total(int64_t max_n) {
+    int64_t t = 0;
+    for (int L = 1; L < kDecLevels; ++L) t += (max_n >> L) + 2;
+    return t;
+}
+
 int diag_max_of(const dtws_ctx *c) { return c->diag_max >= 0 ? c->diag_max : kDefaultDiagMax; }
 
 void set_err(dtws_ctx *c, hipError_t e, const char *what) {
@@ -238,6 +254,7 @@ struct BatchPlan {
     int max_m = 0, max_r = 0;
     int64_t max_nb = 0, cand = 0, block = 0;
     int64_t score_rows = 0;   // proposals of the learned order (kScoreSamples per block)
+    uint32_t dec_levels = 0;  // decimated prefix copies the proposals read
     bool bucket_used[kMaxChunks + 2] = {false};
 };
 
@@ -262,6 +279,7 @@ BatchPlan plan_batch(dtws_ctx *c, int64_t n, const int64_t *qoff, const int32_t 
         // replay reads it
         c->h_row_off[k] = p.score_rows;
         p.score_rows += (int64_t)b.nblocks * kScoreSamples;
+        p.dec_levels |= dec_level_of(b.m);
     }
     c->h_row_off[nq] = p.score_rows;
     // slots for distinct lengths and bands, in order of first appearance
@@ -376,6 +394,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     base.Lsorted = c->Lsorted;
     base.order = c->order;
 
+    const bool learned = (flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED;
     HIPCHK(c, hipMemcpyAsync(c->bq, c->h_bq, sizeof(BatchQ) * nq, hipMemcpyHostToDevice, s));
     {
         PROF(DTWS_K_OTHER);
@@ -399,20 +418,19 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         }
     } else {
         PROF(DTWS_K_STATS);
-        HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s));
+        HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s, &c->dec, learned ? p.dec_levels : 0u));
     }
     for (int t = 0; t < p.nr && c->data_envelope; ++t) {
         PROF(DTWS_K_ENV);
         const int64_t so = (int64_t)t * c->max_n;
         HIPCHK(c, launch_series_env(T, n, p.slot_r[t], c->envU + so, c->envL + so, s));
     }
-    const bool learned = (flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED;
     ScoreArgs sa{};
     if (learned) {
         // visiting order from the ordering network: blocks by ascending predicted distance of their
         // proposals (the blocked prefix gives every window's PAA)
         PROF(DTWS_K_SCORE);
-        if (same_m) HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s));
+        if (same_m) HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s, &c->dec, p.dec_levels));
         sa.K = kScoreSamples;
         sa.qpaa = c->qpaa;
         sa.score = c->score;
@@ -420,6 +438,8 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         sa.bstart = c->bstart;
         sa.row_off = c->row_off;
         sa.pre = Prefix{c->PP, c->anc, c->tot};
+        sa.dec = c->dec;
+        sa.dec_levels = p.dec_levels;
         sa.total_rows = p.score_rows;
         HIPCHK(c, hipMemcpyAsync(c->row_off, c->h_row_off, sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, s));
         HIPCHK(c, mlp_order_blocks(c->mlp, a, sa, s));
@@ -627,7 +647,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
     void *dev[] = {c->qpad, c->qhat64, c->qsorted, c->Usorted, c->Lsorted, c->order, c->keys, c->st_mu,
                    c->st_s, c->st_o, c->envU, c->envL, c->surv, c->surv_count, c->nb_d, c->nb_idx,
                    c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_idx, c->res_dist,
-                   c->res_status, c->counters, c->gen_rows, c->bq, c->PP, c->anc, c->tot,
+                   c->res_status, c->counters, c->gen_rows, c->bq, c->PP, c->PPd, c->anc, c->tot,
                    c->perm, c->heads, c->surv_q, c->surv_i, c->sorted, c->qcnt, c->fill, c->overflow,
                    c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q,
                    c->mlp.theta, c->mlp.grad, c->mlp.adam_m, c->mlp.adam_v, c->mlp.W1T, c->mlp.W2T, c->mlp.W2b,
@@ -707,7 +727,8 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
         c->bsurv_cap = cap;
         const int64_t nblk = max_n / 4096 + 2;
         ok = dalloc(&c->bq, Q) == hipSuccess && hipHostMalloc((void **)&c->h_bq, sizeof(BatchQ) * Q, 0) == hipSuccess &&
-             dalloc(&c->PP, max_n + 1) == hipSuccess && dalloc(&c->anc, nblk) == hipSuccess &&
+             dalloc(&c->PP, max_n + 1) == hipSuccess && dalloc(&c->PPd, dec_total(max_n)) == hipSuccess &&
+             dalloc(&c->anc, nblk) == hipSuccess &&
              dalloc(&c->tot, nblk) == hipSuccess && dalloc(&c->perm, Q * c->maxblocks) == hipSuccess &&
              dalloc(&c->heads, 8) == hipSuccess && dalloc(&c->surv_q, cap) == hipSuccess &&
              dalloc(&c->surv_i, cap) == hipSuccess && dalloc(&c->sorted, cap + 64 * Q) == hipSuccess &&
@@ -716,6 +737,13 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&c->wstart, Q + 1) == hipSuccess && dalloc(&c->bucket_w, 2 * (kMaxChunks + 2)) == hipSuccess &&
              dalloc(&c->bucket_j, 2 * (kMaxChunks + 2)) == hipSuccess && dalloc(&c->seg_off, Q) == hipSuccess &&
              dalloc(&c->nb_q, kNearBestCap) == hipSuccess && dalloc(&c->cert_q, kNearBestCap) == hipSuccess;
+        if (ok) {
+            int64_t off = 0;
+            for (int L = 1; L < kDecLevels; ++L) {
+                c->dec.lv[L] = c->PPd + off;
+                off += (max_n >> L) + 2;
+            }
+        }
     }
     if (ok) {
         MlpBufs &b = c->mlp;
@@ -902,7 +930,7 @@ DTWS_API int dtws_propose(dtws_ctx *c, const float *T, int64_t n, const float *Q
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, launch_query_prep(Q, m, 0, query_bufs(c, 0), s));
-    HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s));
+    HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s, &c->dec, dec_level_of(m)));
     BatchQ &bq = c->h_bq[0];
     bq = BatchQ{};
     bq.m = m;
@@ -927,6 +955,8 @@ DTWS_API int dtws_propose(dtws_ctx *c, const float *T, int64_t n, const float *Q
     sa.sstart = c->sstart;
     sa.row_off = c->row_off;
     sa.pre = Prefix{c->PP, c->anc, c->tot};
+    sa.dec = c->dec;
+    sa.dec_levels = dec_level_of(m);
     HIPCHK(c, launch_propose(a, sa, X, starts, s));
     // the staging entries are read by the copies above before the call returns
     HIPCHK(c, hipStreamSynchronize(s));

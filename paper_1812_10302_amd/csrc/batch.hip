@@ -33,7 +33,8 @@ __device__ inline uint64_t splitmix64_d(uint64_t x) {
 // workgroup scans the thread totals, and the results leave through LDS in two halves so that the
 // stores are coalesced.
 __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restrict__ T, int64_t n, double2 *PP,
-                                                           double *anc, double2 *tot) {
+                                                           double *anc, double2 *tot, Decimated dec,
+                                                           uint32_t levels) {
     constexpr int kHalf = kPB / 2, kPad = 16 + 1;           // 16 entries per thread, one spare
     __shared__ double2 stage[kPrefixThreads / 2 * kPad];
     __shared__ double ws1[kPrefixThreads / 64], ws2[kPrefixThreads / 64];
@@ -86,7 +87,12 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
         __syncthreads();
         for (int e = tid; e < kHalf; e += kPrefixThreads) {
             const int64_t x = (int64_t)h * kHalf + e;
-            if (x < lim) PP[x0 + x] = stage[(e >> 4) * kPad + (e & 15)];
+            if (x < lim) {
+                const double2 v = stage[(e >> 4) * kPad + (e & 15)];
+                PP[x0 + x] = v;
+                for (int L = 1; L < kDecLevels; ++L)
+                    if (((levels >> L) & 1u) && ((x0 + x) & ((1 << L) - 1)) == 0) dec.lv[L][(x0 + x) >> L] = v;
+            }
         }
         __syncthreads();
     }
@@ -97,7 +103,11 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
             // sentinels: the entry past the last block, and PP[n] when n ends a block
             anc[b + 1] = a;
             tot[b + 1] = make_double2(0.0, 0.0);
-            if (x0 + kPB == n) PP[n] = make_double2(0.0, 0.0);
+            if (x0 + kPB == n) {
+                PP[n] = make_double2(0.0, 0.0);
+                for (int L = 1; L < kDecLevels; ++L)
+                    if (((levels >> L) & 1u) && (n & ((1 << L) - 1)) == 0) dec.lv[L][n >> L] = make_double2(0.0, 0.0);
+            }
         }
     }
 }
@@ -613,9 +623,12 @@ __global__ __launch_bounds__(256) void k_cert_reduce_batch(BatchArgs a) {
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_prefix(const float *T, int64_t n, double2 *PP, double *anc, double2 *tot, hipStream_t s) {
+hipError_t launch_prefix(const float *T, int64_t n, double2 *PP, double *anc, double2 *tot, hipStream_t s,
+                         const Decimated *dec, uint32_t levels) {
+    const Decimated d = dec ? *dec : Decimated{};
+    if (!dec) levels = 0;
     const int64_t blocks = (n + kPB - 1) / kPB;
-    hipLaunchKernelGGL(k_prefix, dim3((unsigned)blocks), dim3(kPrefixThreads), 0, s, T, n, PP, anc, tot);
+    hipLaunchKernelGGL(k_prefix, dim3((unsigned)blocks), dim3(kPrefixThreads), 0, s, T, n, PP, anc, tot, d, levels);
     return hipGetLastError();
 }
 

@@ -54,6 +54,13 @@ struct Prefix {
     const double2 *tot;
 };
 
+// Decimated copies of the prefix for the proposals of the learned order: lv[L][k] = PP[k << L],
+// L = 1..5 (every 2nd .. 32nd entry), written by the prefix pass for the levels it is asked for.
+constexpr int kDecLevels = 6;
+struct Decimated {
+    double2 *lv[kDecLevels];
+};
+
 // Per-query parameters of a batch (device array, one entry per query).
 struct BatchQ {
     int64_t qoff;      // first element of the query in the packed query array
@@ -201,6 +208,8 @@ struct ScoreArgs {
     int32_t *bstart;           // start of the best-scored proposal of each block
     const int64_t *row_off;    // per query, nq + 1 entries
     Prefix pre;                // blocked prefix of the series
+    Decimated dec;             // its decimated copies
+    uint32_t dec_levels;       // bit L set: dec.lv[L] holds the current series
 };
 
 // ---------------------------------------------------------------- launchers (stream-ordered)
@@ -216,7 +225,8 @@ hipError_t launch_dtw(const DtwArgs &a, bool search, int64_t max_count, int num_
 hipError_t launch_bsf_update(uint64_t *keys, const float *d, const int64_t *idx, int64_t count, int num_cu,
                              hipStream_t s);
 hipError_t launch_certify(const CertArgs &c, hipStream_t s);
-hipError_t launch_prefix(const float *T, int64_t n, double2 *PP, double *anc, double2 *tot, hipStream_t s);
+hipError_t launch_prefix(const float *T, int64_t n, double2 *PP, double *anc, double2 *tot, hipStream_t s,
+                         const Decimated *dec = nullptr, uint32_t levels = 0);
 hipError_t launch_make_perm(const BatchArgs &a, int mode, uint64_t seed, int64_t max_nblocks, hipStream_t s);
 hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s);
 hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
@@ -286,6 +296,8 @@ struct dtws_ctx {
     // batched search
     dtws::BatchQ *bq = nullptr, *h_bq = nullptr;   // device / pinned host, max_q entries
     double2 *PP = nullptr;                   // blocked prefix, max_n + 1 entries
+    double2 *PPd = nullptr;                  // its decimated copies (see Decimated)
+    dtws::Decimated dec{};
     double *anc = nullptr;
     double2 *tot = nullptr;
     int32_t *perm = nullptr;

@@ -351,6 +351,11 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
         __shared__ double2 grid[4][128];
         double2 *gw = grid[threadIdx.x >> 6];
         const float inv_seg = 16.0f / (float)m;
+        // a decimated copy with step ps when the prefix pass wrote one (ps a power of two)
+        const int dl = __builtin_ctz((unsigned)ps);
+        const bool use_dec = (ps & (ps - 1)) == 0 && dl >= 1 && dl < kDecLevels && ((sa.dec_levels >> dl) & 1u);
+        const double2 *dsrc = use_dec ? sa.dec.lv[dl] : nullptr;
+        const int64_t nlast = use_dec ? ((a.n >> dl) << dl) : a.n;
         for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
             const int64_t b0 = g0 / kPB, e0 = (b0 + 1) * kPB;
             const double2 tb = sa.pre.tot[b0];
@@ -359,8 +364,8 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 int64_t x = g0 + ps * (lane + 64 * h);
-                x = x < a.n ? x : a.n;   // points past the series only serve idle lanes
-                const double2 p = sa.pre.PP[x];
+                x = x < nlast ? x : nlast;   // points past the series only serve idle lanes
+                const double2 p = use_dec ? dsrc[x >> dl] : sa.pre.PP[x];
                 const bool cross = x >= e0;
                 const double lx = (double)(x - e0);
                 double2 gv;
