@@ -36,25 +36,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    """SHA-256 over the library sources, to tell whether recorded counters still describe them."""
+# sources that define each kernel whose HBM traffic is recorded (profiles/hbm_traffic.md)
+KERNEL_SOURCES = {
+    "k_lb_batch<true>": ["batch.hip", "batch_stats.h", "device.h", "dtws_internal.h"],
+    "k_lb_batch": ["batch.hip", "batch_stats.h", "device.h", "dtws_internal.h"],
+    "k_prefix": ["batch.hip", "dtws_internal.h"],
+    "k_propose": ["mlp.hip", "device.h", "dtws_internal.h"],
+}
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """SHA-256 over the sources of `kernel`, to tell whether recorded counters still describe it."""
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_1812_10302_amd", "csrc")
-    for f in sorted(os.listdir(src)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(src, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(src, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()
 
 
 def traffic_of(kernel: str, launches: int, algorithmic: float):
-    """HBM bytes per launch of `kernel` recorded from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (see the
-    profiles folder), or None when none is recorded for the current sources."""
+    """HBM bytes per launch of `kernel` recorded from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    (profiles/hbm_traffic.md), or None when none is recorded for the kernel's current sources."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
         return None
-    cur = kernel_source_hash()
+    cur = kernel_source_hash(kernel)
     for line in open(path):
         if line.startswith("| `" + kernel + "`"):
             cols = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
