@@ -87,11 +87,15 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
         __syncthreads();
         for (int e = tid; e < kHalf; e += kPrefixThreads) {
             const int64_t x = (int64_t)h * kHalf + e;
-            if (x < lim) {
-                const double2 v = stage[(e >> 4) * kPad + (e & 15)];
-                PP[x0 + x] = v;
-                for (int L = 1; L < kDecLevels; ++L)
-                    if (((levels >> L) & 1u) && ((x0 + x) & ((1 << L) - 1)) == 0) dec.lv[L][(x0 + x) >> L] = v;
+            if (x < lim) PP[x0 + x] = stage[(e >> 4) * kPad + (e & 15)];
+        }
+        // decimated copies: consecutive threads write consecutive entries of each level
+        for (int L = 1; L < kDecLevels; ++L) {
+            if (!((levels >> L) & 1u)) continue;
+            for (int e = tid; e < (kHalf >> L); e += kPrefixThreads) {
+                const int el = e << L;   // block-local position within this half
+                const int64_t x = (int64_t)h * kHalf + el;
+                if (x < lim) dec.lv[L][(x0 + x) >> L] = stage[(el >> 4) * kPad + (el & 15)];
             }
         }
         __syncthreads();

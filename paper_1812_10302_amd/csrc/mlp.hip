@@ -356,16 +356,25 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
         const bool use_dec = (ps & (ps - 1)) == 0 && dl >= 1 && dl < kDecLevels && ((sa.dec_levels >> dl) & 1u);
         const double2 *dsrc = use_dec ? sa.dec.lv[dl] : nullptr;
         const int64_t nlast = use_dec ? ((a.n >> dl) << dl) : a.n;
+        // raw prefix at grid point k of the current group (points past the series only serve idle
+        // lanes); the upper half of one group's grid is the lower half of the next, and the
+        // next group's upper half is loaded one group ahead
+        auto grid_raw = [&](int64_t x) -> double2 {
+            x = x < nlast ? x : nlast;
+            return use_dec ? dsrc[x >> dl] : sa.pre.PP[x];
+        };
+        double2 rlo = grid_raw(first + ps * lane), rhi = grid_raw(first + ps * (lane + 64));
         for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
+            const double2 rnext = grid_raw(g0 + ps * (lane + 128));
             const int64_t b0 = g0 / kPB, e0 = (b0 + 1) * kPB;
             const double2 tb = sa.pre.tot[b0];
             const double a0 = sa.pre.anc[b0], delta = sa.pre.anc[b0 + 1] - a0;
             wave_sync();
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                int64_t x = g0 + ps * (lane + 64 * h);
-                x = x < nlast ? x : nlast;   // points past the series only serve idle lanes
-                const double2 p = use_dec ? dsrc[x >> dl] : sa.pre.PP[x];
+                // re-anchor to the group's first block (a window ends at most one block later)
+                const int64_t x = g0 + ps * (lane + 64 * h);
+                const double2 p = h == 0 ? rlo : rhi;
                 const bool cross = x >= e0;
                 const double lx = (double)(x - e0);
                 double2 gv;
@@ -373,6 +382,8 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
                 gv.y = cross ? tb.y + p.y + 2.0 * delta * p.x + lx * delta * delta : p.y;
                 gw[lane + 64 * h] = gv;
             }
+            rlo = rhi;
+            rhi = rnext;
             wave_sync();
             const int64_t i = g0 + lane * ps;
             if (i < last) {
