@@ -256,7 +256,7 @@ struct ItemSource {
     }
 };
 
-template <bool PREFIX>
+template <bool PREFIX, bool ENV>
 __global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int rank_lo, int rank_hi, int parts) {
     __shared__ WaveQueue queues[4][2];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -281,11 +281,11 @@ __global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int ra
             const float *eU = a.envU ? a.envU + bq.env_slot * a.slot_stride : nullptr;
             const float *eL = a.envU ? a.envL + bq.env_slot * a.slot_stride : nullptr;
             if (PREFIX) {
-                cascade(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, queues[wid][0], queues[wid][1],
+                cascade<ENV>(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, queues[wid][0], queues[wid][1],
                         StatsPrefix{a.T, a.pre, bq.m, 1.0 / bq.m}, emit, cnt);
             } else {
                 const int64_t so = bq.stat_slot * a.slot_stride;
-                cascade(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, queues[wid][0], queues[wid][1],
+                cascade<ENV>(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, queues[wid][0], queues[wid][1],
                         StatsArr{a.mu + so, a.s + so, a.o + so}, emit, cnt);
             }
         }
@@ -650,10 +650,15 @@ hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s) 
 
 hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
                            int blocks, hipStream_t s) {
-    if (prefix)
-        hipLaunchKernelGGL(k_lb_batch<true>, dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
+    const bool env = a.envU != nullptr;
+    if (prefix && env)
+        hipLaunchKernelGGL((k_lb_batch<true, true>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
+    else if (prefix)
+        hipLaunchKernelGGL((k_lb_batch<true, false>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
+    else if (env)
+        hipLaunchKernelGGL((k_lb_batch<false, true>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
     else
-        hipLaunchKernelGGL(k_lb_batch<false>, dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
+        hipLaunchKernelGGL((k_lb_batch<false, false>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
     return hipGetLastError();
 }
 

@@ -160,8 +160,9 @@ struct CascadeCounts {
 // full q2 batch first, then a full q1 batch, then new groups: q2 holds fewer than 64 entries when
 // level 1 pushes up to 64 into it, and q1 fewer than 64 when level 0 pushes up to two groups (128)
 // into it, which kQCap accommodates; at the end both queues are drained.
-//   stats(i, mu, s, o): normalisation parameters of candidate i.
-template <class Stats, class Emit, class Source>
+//   stats(i, mu, s, o): normalisation parameters of candidate i.  ENV = false compiles the
+//   data-envelope bound out (fewer registers when the caller never passes an envelope).
+template <bool ENV = true, class Stats, class Emit, class Source>
 __device__ __forceinline__ void cascade(const QView &v, const float *T, const float *envU, const float *envL,
                                         float thr, float q0, float ql, Source &src, WaveQueue &q1, WaveQueue &q2,
                                         const Stats &stats, const Emit &emit, CascadeCounts &cnt) {
@@ -193,7 +194,7 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
                     ++cnt.kq;
                 }
             }
-            if (alive && envU) {
+            if (ENV && alive && envU) {
                 const float kd = keogh_d(v, envU + i, envL + i, mu, s, o, thr);
                 if (kd > thr) {
                     alive = false;
@@ -238,42 +239,46 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
                     cg = cf;
                     cfresh = true;
                 }
-                // chains cj and cj + 1 (if it exists) at the same step t: groups cg and cg + 64
-                const bool two = cj + 1 < cJ;
-                int64_t ii[2];
-                bool valid[2];
-                double2 pe[2];
-                float c0v[2], clv[2];
+                // level-0 steps in a tight loop while q1 has room for two more groups (< 64 entries
+                // leaves 192 free slots); back to the scheduler when it fills or the item ends
+                do {
+                    // chains cj and cj + 1 (if it exists) at the same step t: groups cg and cg + 64
+                    const bool two = cj + 1 < cJ;
+                    int64_t ii[2];
+                    bool valid[2];
+                    double2 pe[2];
+                    float c0v[2], clv[2];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int64_t i = cg + 64 * h + lane;
-                    valid[h] = (h == 0 || two) && i < clast;
-                    ii[h] = valid[h] ? i : cf;
-                    pe[h] = stats.pre.PP[ii[h] + m];
-                    c0v[h] = T[ii[h]];
-                    clv[h] = T[ii[h] + m - 1];
-                }
+                    for (int h = 0; h < 2; ++h) {
+                        const int64_t i = cg + 64 * h + lane;
+                        valid[h] = (h == 0 || two) && i < clast;
+                        ii[h] = valid[h] ? i : cf;
+                        pe[h] = stats.pre.PP[ii[h] + m];
+                        c0v[h] = T[ii[h]];
+                        clv[h] = T[ii[h] + m - 1];
+                    }
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const double2 p0 = cfresh ? stats.pre.PP[ii[h]] : ccarry[h];
-                    ccarry[h] = pe[h];
-                    double a0, S1, S2;
-                    stats.sums_from(ii[h], p0, pe[h], a0, S1, S2);
-                    float mu = 0.0f, s = 0.0f, o = 0.0f;
-                    if (valid[h]) stats.finish(ii[h], a0, S1, S2, mu, s, o);
-                    const float d0 = q0 - fmaf(c0v[h] - mu, s, o), dl = ql - fmaf(clv[h] - mu, s, o);
-                    const bool alive = valid[h] && !(fmaf(d0, d0, dl * dl) > thr);
-                    if (valid[h] && !alive) ++cnt.kim;
-                    q_push(q1, t1, alive, (int32_t)ii[h], -1.0f, mu, s, o);
-                }
-                cfresh = false;
-                cg += m;
-                if (cg >= clast) {
-                    cj += two ? 2 : 1;
-                    cg = cf + 64 * cj;
-                    cfresh = true;
-                    if (cj >= cJ || cg >= clast) citem = false;
-                }
+                    for (int h = 0; h < 2; ++h) {
+                        const double2 p0 = cfresh ? stats.pre.PP[ii[h]] : ccarry[h];
+                        ccarry[h] = pe[h];
+                        double a0, S1, S2;
+                        stats.sums_from(ii[h], p0, pe[h], a0, S1, S2);
+                        float mu = 0.0f, s = 0.0f, o = 0.0f;
+                        if (valid[h]) stats.finish(ii[h], a0, S1, S2, mu, s, o);
+                        const float d0 = q0 - fmaf(c0v[h] - mu, s, o), dl = ql - fmaf(clv[h] - mu, s, o);
+                        const bool alive = valid[h] && !(fmaf(d0, d0, dl * dl) > thr);
+                        if (valid[h] && !alive) ++cnt.kim;
+                        q_push(q1, t1, alive, (int32_t)ii[h], -1.0f, mu, s, o);
+                    }
+                    cfresh = false;
+                    cg += m;
+                    if (cg >= clast) {
+                        cj += two ? 2 : 1;
+                        cg = cf + 64 * cj;
+                        cfresh = true;
+                        if (cj >= cJ || cg >= clast) citem = false;
+                    }
+                } while (citem && t1 - h1 < 64u);
                 continue;
             }
         }
