@@ -20,6 +20,23 @@ struct StatsPrefix {
     __device__ void sums(int64_t i, double &a0, double &S1, double &S2) const {
         sums_from(i, pre.PP[i], pre.PP[i + m], a0, S1, S2);
     }
+    // The same for a group of 64 consecutive windows that share the block b0 of their starts and
+    // whether they end past it (both wave-uniform: m and the group start are multiples of 64 and
+    // kPB is a multiple of 64); el = e - (b0 + 1) kPB for this lane's window end e.
+    __device__ void sums_group(int64_t b0, bool cross, int64_t el, double2 p0, double2 pe, double &a0,
+                               double &S1, double &S2) const {
+        a0 = pre.anc[b0];
+        if (cross) {
+            const double2 t = pre.tot[b0];
+            const double delta = pre.anc[b0 + 1] - a0;
+            const double c2 = (double)el;
+            S1 = (t.x - p0.x) + pe.x + c2 * delta;
+            S2 = (t.y - p0.y) + pe.y + 2.0 * delta * pe.x + c2 * delta * delta;
+        } else {
+            S1 = pe.x - p0.x;
+            S2 = pe.y - p0.y;
+        }
+    }
     // the same from the prefix entries p0 = PP[i] and pe = PP[i + m]
     __device__ void sums_from(int64_t i, double2 p0, double2 pe, double &a0, double &S1, double &S2) const {
         const int64_t e = i + m;

@@ -261,8 +261,13 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
                     for (int h = 0; h < 2; ++h) {
                         const double2 p0 = cfresh ? stats.pre.PP[ii[h]] : ccarry[h];
                         ccarry[h] = pe[h];
+                        // block of the group's starts and whether its windows end past it: the
+                        // same for all 64 lanes (scalar); idle lanes' values are never used
+                        const int64_t gs = cg + 64 * h;
+                        const int64_t b0 = gs / kPB, e0 = (b0 + 1) * kPB;
+                        const bool cross = gs + m >= e0;
                         double a0, S1, S2;
-                        stats.sums_from(ii[h], p0, pe[h], a0, S1, S2);
+                        stats.sums_group(b0, cross, gs + lane + m - e0, p0, pe[h], a0, S1, S2);
                         float mu = 0.0f, s = 0.0f, o = 0.0f;
                         if (valid[h]) stats.finish(ii[h], a0, S1, S2, mu, s, o);
                         const float d0 = q0 - fmaf(c0v[h] - mu, s, o), dl = ql - fmaf(clv[h] - mu, s, o);
