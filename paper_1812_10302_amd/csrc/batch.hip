@@ -258,7 +258,8 @@ struct ItemSource {
 
 template <bool PREFIX, bool ENV>
 __global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int rank_lo, int rank_hi, int parts) {
-    __shared__ WaveQueue queues[4][2];
+    __shared__ WaveQueue q1s[4];
+    __shared__ WaveQueue2 q2s[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     ItemSource src{&a, round, rank_lo, parts, (uint32_t)(rank_hi - rank_lo) * (uint32_t)parts, 0u, -1};
     src.total = src.per_q * (uint32_t)a.nq;
@@ -281,11 +282,11 @@ __global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int ra
             const float *eU = a.envU ? a.envU + bq.env_slot * a.slot_stride : nullptr;
             const float *eL = a.envU ? a.envL + bq.env_slot * a.slot_stride : nullptr;
             if (PREFIX) {
-                cascade<ENV>(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, queues[wid][0], queues[wid][1],
+                cascade<ENV>(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, q1s[wid], q2s[wid],
                         StatsPrefix{a.T, a.pre, bq.m, 1.0 / bq.m}, emit, cnt);
             } else {
                 const int64_t so = bq.stat_slot * a.slot_stride;
-                cascade<ENV>(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, queues[wid][0], queues[wid][1],
+                cascade<ENV>(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, q1s[wid], q2s[wid],
                         StatsArr{a.mu + so, a.s + so, a.o + so}, emit, cnt);
             }
         }
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int ra
     }
 finish:
     if (a.counters) {
-        const unsigned long long c_kim = wave_add_u64(cnt.kim), c_kq = wave_add_u64(cnt.kq),
+        const unsigned long long c_kim = cnt.wave_kim(), c_kq = wave_add_u64(cnt.kq),
                                  c_kd = wave_add_u64(cnt.kd);
         if (lane == 0) {
             atomicAdd(&a.counters[1], c_kim);

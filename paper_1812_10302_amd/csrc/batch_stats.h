@@ -23,12 +23,13 @@ struct StatsPrefix {
     // The same for a group of 64 consecutive windows that share the block b0 of their starts and
     // whether they end past it (both wave-uniform: m and the group start are multiples of 64 and
     // kPB is a multiple of 64); el = e - (b0 + 1) kPB for this lane's window end e.
-    __device__ void sums_group(int64_t b0, bool cross, int64_t el, double2 p0, double2 pe, double &a0,
+    __device__ void sums_group(int64_t b0, bool cross, int el, double2 p0, double2 pe, double &a0,
                                double &S1, double &S2) const {
-        a0 = pre.anc[b0];
+        a0 = ldc(pre.anc + b0);
         if (cross) {
-            const double2 t = pre.tot[b0];
-            const double delta = pre.anc[b0 + 1] - a0;
+            const double *tb = (const double *)(pre.tot + b0);
+            const double2 t = make_double2(ldc(tb), ldc(tb + 1));
+            const double delta = ldc(pre.anc + b0 + 1) - a0;
             const double c2 = (double)el;
             S1 = (t.x - p0.x) + pe.x + c2 * delta;
             S2 = (t.y - p0.y) + pe.y + 2.0 * delta * pe.x + c2 * delta * delta;
@@ -72,9 +73,10 @@ struct StatsPrefix {
             }
             var = q / m;
         }
-        if (!(var > 0.0)) var = 0.0;
         mu32 = (float)mu;
-        s = var <= kSigmaFlat * kSigmaFlat ? 0.0f : rsqrtf((float)var);
+        // var > kSigmaFlat^2 is a normal FP32 number: the hardware reciprocal square root needs no
+        // denormal scaling; anything else (flat, negative from rounding, NaN) gets scale 0
+        s = var > kSigmaFlat * kSigmaFlat ? __builtin_amdgcn_rsqf((float)var) : 0.0f;
         o = (float)(-(mu - (double)mu32)) * s;
     }
     __device__ void operator()(int64_t i, float &mu32, float &s, float &o) const {

@@ -15,6 +15,11 @@ __device__ inline unsigned long long wave_add_u64(unsigned long long v) {
 
 __device__ inline unsigned long long wave_add(unsigned long long v) { return wave_add_u64(v); }
 
+// Number of lanes below this one whose bit is set in mask (the hardware masked bit count).
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 __device__ inline uint64_t lanemask_lt() {
     const int lane = threadIdx.x & 63;
     return lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -32,6 +37,14 @@ __device__ inline void wave_sync() {
 template <class T>
 __device__ __forceinline__ T ldc(const T *p) {
     return *(const __attribute__((address_space(4))) T *)p;
+}
+
+// A value the caller knows to be the same in every lane, placed in scalar registers.
+__device__ __forceinline__ int64_t uniform(int64_t x) {
+    const uint64_t u = (uint64_t)x;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 __device__ inline float load_bsf(const uint64_t *key) {
@@ -97,19 +110,24 @@ __device__ inline float keogh_d(const QView &v, const float *Ui, const float *Li
 }
 
 // ---------------------------------------------------------------- wave-private queues
-constexpr int kQCap = 256;   // power of two, >= 3 * 64 (a level-0 step pushes two groups)
+constexpr int kQCap = 256;    // level-1 queue: power of two, >= 3 * 64 (a level-0 step pushes two groups)
+constexpr int kQCap2 = 128;   // level-2 queue: power of two, >= 2 * 64 (level 1 pushes one batch)
 constexpr int kK1 = 64;   // query-envelope terms of level 1
 
-struct WaveQueue {
-    int32_t idx[kQCap];
-    float kq[kQCap], mu[kQCap], s[kQCap], o[kQCap];
+template <int CAP>
+struct WaveQueueT {
+    static constexpr uint32_t kMask = CAP - 1;
+    int32_t idx[CAP];
+    float kq[CAP], mu[CAP], s[CAP], o[CAP];
 };
+using WaveQueue = WaveQueueT<kQCap>;
+using WaveQueue2 = WaveQueueT<kQCap2>;
 
-__device__ inline void q_push(WaveQueue &q, uint32_t &tail, bool pred, int32_t i, float kq, float mu, float s,
-                              float o) {
+template <class Q>
+__device__ inline void q_push(Q &q, uint32_t &tail, bool pred, int32_t i, float kq, float mu, float s, float o) {
     const uint64_t mask = __ballot(pred);
     if (pred) {
-        const uint32_t p = (tail + (uint32_t)__popcll(mask & lanemask_lt())) & (kQCap - 1);
+        const uint32_t p = (tail + rank_in(mask)) & Q::kMask;
         q.idx[p] = i;
         q.kq[p] = kq;
         q.mu[p] = mu;
@@ -121,13 +139,14 @@ __device__ inline void q_push(WaveQueue &q, uint32_t &tail, bool pred, int32_t i
 }
 
 // Pops up to 64 entries (one per lane); returns whether this lane got one.
-__device__ inline bool q_pop(WaveQueue &q, uint32_t &head, uint32_t tail, int32_t &i, float &kq, float &mu,
-                             float &s, float &o) {
+template <class Q>
+__device__ inline bool q_pop(Q &q, uint32_t &head, uint32_t tail, int32_t &i, float &kq, float &mu, float &s,
+                             float &o) {
     const int lane = threadIdx.x & 63;
     const uint32_t avail = tail - head;
     const uint32_t take = avail < 64u ? avail : 64u;
     const bool got = (uint32_t)lane < take;
-    const uint32_t p = (head + lane) & (kQCap - 1);
+    const uint32_t p = (head + lane) & Q::kMask;
     if (got) {
         i = q.idx[p];
         kq = q.kq[p];
@@ -142,7 +161,9 @@ __device__ inline bool q_pop(WaveQueue &q, uint32_t &head, uint32_t tail, int32_
 
 // ---------------------------------------------------------------- cascade over a candidate range
 struct CascadeCounts {
-    uint32_t kim = 0, kq = 0, kd = 0;
+    uint32_t kim = 0, kq = 0, kd = 0;   // per lane
+    uint32_t kim_w = 0;                 // LB_Kim prunes counted for the whole wave (same in every lane)
+    __device__ unsigned long long wave_kim() const { return wave_add_u64(kim) + kim_w; }
 };
 
 // Runs the bound cascade (one wave) on groups of 64 consecutive candidates handed out by
@@ -164,7 +185,7 @@ struct CascadeCounts {
 //   data-envelope bound out (fewer registers when the caller never passes an envelope).
 template <bool ENV = true, class Stats, class Emit, class Source>
 __device__ __forceinline__ void cascade(const QView &v, const float *T, const float *envU, const float *envL,
-                                        float thr, float q0, float ql, Source &src, WaveQueue &q1, WaveQueue &q2,
+                                        float thr, float q0, float ql, Source &src, WaveQueue &q1, WaveQueue2 &q2,
                                         const Stats &stats, const Emit &emit, CascadeCounts &cnt) {
     const int lane = threadIdx.x & 63;
     const int m = v.m, mpad = v.mpad;
@@ -234,6 +255,8 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
                         done = true;
                         continue;
                     }
+                    cf = uniform(cf);
+                    clast = uniform(clast);
                     citem = true;
                     cj = 0;
                     cg = cf;
@@ -243,37 +266,44 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
                 // leaves 192 free slots); back to the scheduler when it fills or the item ends
                 do {
                     // chains cj and cj + 1 (if it exists) at the same step t: groups cg and cg + 64
+                    cg = uniform(cg);
                     const bool two = cj + 1 < cJ;
-                    int64_t ii[2];
+                    // the two groups are addressed from scalar bases with 32-bit lane offsets; idle
+                    // lanes (past the item end, or no second chain) read the group's first start
+                    const int64_t span = clast - cg;
+                    const uint32_t lim = span < 128 ? (uint32_t)span : 128u;
+                    const double2 *P0 = stats.pre.PP + cg, *PE = P0 + m;
+                    const float *T0 = T + cg, *TL = T0 + (m - 1);
+                    uint32_t off[2];
                     bool valid[2];
                     double2 pe[2];
                     float c0v[2], clv[2];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const int64_t i = cg + 64 * h + lane;
-                        valid[h] = (h == 0 || two) && i < clast;
-                        ii[h] = valid[h] ? i : cf;
-                        pe[h] = stats.pre.PP[ii[h] + m];
-                        c0v[h] = T[ii[h]];
-                        clv[h] = T[ii[h] + m - 1];
+                        const uint32_t o = 64u * h + (uint32_t)lane;
+                        valid[h] = (h == 0 || two) && o < lim;
+                        off[h] = valid[h] ? o : 0u;
+                        pe[h] = PE[off[h]];
+                        c0v[h] = T0[off[h]];
+                        clv[h] = TL[off[h]];
                     }
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const double2 p0 = cfresh ? stats.pre.PP[ii[h]] : ccarry[h];
+                        const double2 p0 = cfresh ? P0[off[h]] : ccarry[h];
                         ccarry[h] = pe[h];
                         // block of the group's starts and whether its windows end past it: the
                         // same for all 64 lanes (scalar); idle lanes' values are never used
                         const int64_t gs = cg + 64 * h;
-                        const int64_t b0 = gs / kPB, e0 = (b0 + 1) * kPB;
+                        const int64_t b0 = gs >> kPBShift, e0 = (b0 + 1) << kPBShift;
                         const bool cross = gs + m >= e0;
                         double a0, S1, S2;
-                        stats.sums_group(b0, cross, gs + lane + m - e0, p0, pe[h], a0, S1, S2);
+                        stats.sums_group(b0, cross, (int)(gs + m - e0) + lane, p0, pe[h], a0, S1, S2);
                         float mu = 0.0f, s = 0.0f, o = 0.0f;
-                        if (valid[h]) stats.finish(ii[h], a0, S1, S2, mu, s, o);
+                        if (valid[h]) stats.finish(cg + off[h], a0, S1, S2, mu, s, o);
                         const float d0 = q0 - fmaf(c0v[h] - mu, s, o), dl = ql - fmaf(clv[h] - mu, s, o);
                         const bool alive = valid[h] && !(fmaf(d0, d0, dl * dl) > thr);
-                        if (valid[h] && !alive) ++cnt.kim;
-                        q_push(q1, t1, alive, (int32_t)ii[h], -1.0f, mu, s, o);
+                        cnt.kim_w += (uint32_t)(__popcll(__ballot(valid[h])) - __popcll(__ballot(alive)));
+                        q_push(q1, t1, alive, (int32_t)cg + (int32_t)off[h], -1.0f, mu, s, o);
                     }
                     cfresh = false;
                     cg += m;

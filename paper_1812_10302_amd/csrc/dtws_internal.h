@@ -188,7 +188,8 @@ constexpr int kScoreSamples = 4;         // proposals scored per block (one per 
 constexpr int kSeedCands = 64;           // best-scored proposals per query that seed the best-so-far (one wave)
 constexpr int kColsumGroups = 128;       // row groups of the bias-gradient reduction
 constexpr int64_t kMaxTrainRows = 1 << 16;  // rows per gradient / training step
-constexpr int kPB = 4096;                // blocked prefix: block length (points)
+constexpr int kPBShift = 12;
+constexpr int kPB = 1 << kPBShift;       // blocked prefix: block length (points)
 
 struct MlpBufs {
     float *theta, *grad, *adam_m, *adam_v;   // FP32 master parameters, gradient, Adam moments

@@ -71,17 +71,18 @@ __global__ __launch_bounds__(256) void k_lb_values(LbArgs a, QView v) {
 
 // Pruning: each wave owns groups of 64 consecutive candidates, grid-strided over [first, last).
 __global__ __launch_bounds__(256) void k_lb_prune(LbArgs a, QView v) {
-    __shared__ WaveQueue queues[4][2];
+    __shared__ WaveQueue q1s[4];
+    __shared__ WaveQueue2 q2s[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const float thr = a.key ? threshold_of(load_bsf(a.key)) : a.fixed_thr;
     CascadeCounts cnt;
     StrideSource src{a.first + wave * 64, nwaves * 64, a.last};
-    cascade(v, a.T, a.envU, a.envL, thr, a.qh[0], a.qh[a.m - 1], src, queues[wid][0], queues[wid][1],
+    cascade(v, a.T, a.envU, a.envL, thr, a.qh[0], a.qh[a.m - 1], src, q1s[wid], q2s[wid],
             StatsArrays{a.mu, a.s, a.o}, EmitList{a.surv, a.surv_count}, cnt);
     if (a.counters) {
-        const unsigned long long c_kim = wave_add_u64(cnt.kim), c_kq = wave_add_u64(cnt.kq),
+        const unsigned long long c_kim = cnt.wave_kim(), c_kq = wave_add_u64(cnt.kq),
                                  c_kd = wave_add_u64(cnt.kd);
         if (lane == 0) {
             atomicAdd(&a.counters[1], c_kim);
