@@ -303,6 +303,26 @@ struct PrefixView {
 #pragma unroll
         for (int k = 0; k < 16; ++k) out[k] = ((float)(g[k + 1] - g[k]) * inv_len[k] - mdf) * inv;
     }
+    // Term t of the same PAA alone (the four prefix lookups it needs).
+    __device__ float paa_term(int64_t i, int m, double inv_m, int t) const {
+        const int64_t b0 = i / kPB, e0 = (b0 + 1) * kPB;
+        const double delta = pre.anc[b0 + 1] - pre.anc[b0];
+        const double2 tt = pre.tot[b0];
+        const int64_t xs[4] = {i, i + ((t * m) >> 4), i + (((t + 1) * m) >> 4), i + m};
+        double gx[4], gy[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double2 p = pre.PP[xs[k]];
+            const double lx = (double)(xs[k] - e0);
+            const bool cross = xs[k] >= e0;
+            gx[k] = cross ? tt.x + p.x + lx * delta : p.x;
+            gy[k] = cross ? tt.y + p.y + 2.0 * delta * p.x + lx * delta * delta : p.y;
+        }
+        const double md = (gx[3] - gx[0]) * inv_m, var = (gy[3] - gy[0]) * inv_m - md * md;
+        const float inv = var > kSigmaFlat * kSigmaFlat ? rsqrtf((float)var) : 0.0f;
+        const float len = (float)((((t + 1) * m) >> 4) - ((t * m) >> 4));
+        return ((float)(gx[2] - gx[1]) / len - (float)md) * inv;
+    }
 };
 
 // Proposals: row (q, blk, j) covers the starts [blk * B + j * B / K, + B / K) of query q.  One wave
@@ -334,22 +354,22 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
         if (lane == 0) sa.sstart[k] = -1;
         return;
     }
-    float qp[16], inv_len[16];
+    float qp[16];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        qp[t] = sa.qpaa[q * 16 + t];
-        inv_len[t] = 1.0f / (float)((((t + 1) * m) >> 4) - ((t * m) >> 4));
-    }
+    for (int t = 0; t < 16; ++t) qp[t] = sa.qpaa[q * 16 + t];
     const double inv_m = 1.0 / m;
     const PrefixView pv{sa.pre};
     const int64_t ps = m >= 128 ? m >> 6 : 1;
     uint64_t best = ~0ull;
     if ((m & 63) == 0) {
         // m = 64 ps: the sampled starts and every segment boundary lie on the grid of step ps, so
-        // the 64 starts of a group need the prefix at 128 grid points only, staged once in LDS
-        // (re-anchored to the block of the group's first start)
-        __shared__ double2 grid[4][128];
-        double2 *gw = grid[threadIdx.x >> 6];
+        // the 64 starts of a group need the prefix at 128 grid points only (re-anchored to the
+        // block of the group's first start).  Lane l holds grid points l and l + 64, the start and
+        // end of its window; the segment sums (grid points 4 apart) go through LDS as FP32.
+        __shared__ double gsh[4][128];
+        __shared__ float dsh[4][128];
+        double *gw = gsh[threadIdx.x >> 6];
+        float *dw = dsh[threadIdx.x >> 6];
         const float inv_seg = 16.0f / (float)m;
         // a decimated copy with step ps when the prefix pass wrote one (ps a power of two)
         const int dl = __builtin_ctz((unsigned)ps);
@@ -369,7 +389,7 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
             const int64_t b0 = g0 / kPB, e0 = (b0 + 1) * kPB;
             const double2 tb = sa.pre.tot[b0];
             const double a0 = sa.pre.anc[b0], delta = sa.pre.anc[b0 + 1] - a0;
-            wave_sync();
+            double2 gv[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 // re-anchor to the group's first block (a window ends at most one block later)
@@ -377,34 +397,38 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
                 const double2 p = h == 0 ? rlo : rhi;
                 const bool cross = x >= e0;
                 const double lx = (double)(x - e0);
-                double2 gv;
-                gv.x = cross ? tb.x + p.x + lx * delta : p.x;
-                gv.y = cross ? tb.y + p.y + 2.0 * delta * p.x + lx * delta * delta : p.y;
-                gw[lane + 64 * h] = gv;
+                gv[h].x = cross ? tb.x + p.x + lx * delta : p.x;
+                gv[h].y = cross ? tb.y + p.y + 2.0 * delta * p.x + lx * delta * delta : p.y;
             }
             rlo = rhi;
             rhi = rnext;
+            gw[lane] = gv[0].x;
+            gw[lane + 64] = gv[1].x;
+            wave_sync();
+            // segment sums starting at grid points lane and lane + 64 (the last four are unused)
+            dw[lane] = (float)(gw[lane + 4] - gv[0].x);
+            dw[lane + 64] = (float)(gw[(lane + 68) & 127] - gv[1].x);
             wave_sync();
             const int64_t i = g0 + lane * ps;
             if (i < last) {
-                const double2 w0 = gw[lane], w1 = gw[lane + 64];
-                const double md = (w1.x - w0.x) * inv_m, var = (w1.y - w0.y) * inv_m - md * md;
+                const double md = (gv[1].x - gv[0].x) * inv_m, var = (gv[1].y - gv[0].y) * inv_m - md * md;
                 const float inv = var > kSigmaFlat * kSigmaFlat ? rsqrtf((float)var) : 0.0f;
-                const float mdf = (float)md;
-                double prev = w0.x;
+                // PAA term t: (segment sum / segment length - mean) / sigma - query term
+                const float A = inv_seg * inv, C = (float)md * inv;
                 float d = 0.0f;
 #pragma unroll
                 for (int t = 0; t < 16; ++t) {
-                    const double cur = gw[lane + 4 * (t + 1)].x;
-                    const float e = ((float)(cur - prev) * inv_seg - mdf) * inv - qp[t];
+                    const float e = fmaf(dw[lane + 4 * t], A, -(C + qp[t]));
                     d = fmaf(e, e, d);
-                    prev = cur;
                 }
                 const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)i;
                 best = key < best ? key : best;
             }
         }
     } else {
+        float inv_len[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) inv_len[t] = 1.0f / (float)((((t + 1) * m) >> 4) - ((t * m) >> 4));
         for (int64_t i = first + lane * ps; i < last; i += 64 * ps) {
             float f[16];
             pv.paa(i, m, inv_m, inv_len, f);
@@ -425,13 +449,7 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
     }
     const int64_t i = (int64_t)(uint32_t)best;
     if (lane < 16) {
-        float f[16];
-        pv.paa(i, m, inv_m, inv_len, f);
-        float v = f[0];
-#pragma unroll
-        for (int t = 1; t < 16; ++t)
-            if (lane == t) v = f[t];
-        x[16 + lane] = v;
+        x[16 + lane] = pv.paa_term(i, m, inv_m, lane);
     } else if (lane < 32) {
         x[lane - 16] = qp[lane - 16];
     }
