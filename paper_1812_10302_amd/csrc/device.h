@@ -47,8 +47,15 @@ __device__ __forceinline__ int64_t uniform(int64_t x) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__device__ inline float load_bsf(const uint64_t *key) {
-    return key_dist(__atomic_load_n(key, __ATOMIC_RELAXED));
+// Best-so-far keys change only through device-scope atomicMin, so a device-scope load sees them
+// (served by L2, no trip to memory).
+__device__ inline uint64_t load_key(const uint64_t *key) {
+    return __hip_atomic_load(key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline float load_bsf(const uint64_t *key) { return key_dist(load_key(key)); }
+// The distance half of the key alone (its upper 32 bits), as raw bits.
+__device__ inline uint32_t load_key_dist_bits(const uint64_t *key) {
+    return __hip_atomic_load((const uint32_t *)key + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------- bound terms
@@ -460,6 +467,8 @@ __device__ __forceinline__ void dtw_lanes(const float *T, int64_t start, float m
     for (int x = 0; x <= W; ++x) arr[x] = INFINITY;
     arr[R] = 0.0f;   // d(-1,-1) of the virtual column before column 0
     float thr = key ? fminf(thr0, threshold_of(load_bsf(key))) : thr0;
+    // the best-so-far is re-read every 16 columns; each read is issued 16 columns before its use
+    uint32_t kpend = key ? load_key_dist_bits(key) : ~0u;
     alive = live;
     jdead = m;
     const float *Tp = T + start;
@@ -483,7 +492,10 @@ __device__ __forceinline__ void dtw_lanes(const float *T, int64_t start, float m
             float mn = arr[0];
 #pragma unroll
             for (int x = 1; x < W; ++x) mn = fminf(mn, arr[x]);
-            if (key) thr = fminf(thr0, threshold_of(load_bsf(key)));
+            if (key) {
+                thr = fminf(thr0, threshold_of(__uint_as_float(kpend)));
+                kpend = load_key_dist_bits(key);
+            }
             if (alive && mn > thr) {
                 alive = false;
                 jdead = j + 1;

@@ -61,11 +61,11 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 __device__ __forceinline__ float cell_value(float diff, float mn) { return fmaf(diff, diff, mn); }
 __device__ __forceinline__ double cell_value(double diff, double mn) { return __dadd_rn(__dmul_rn(diff, diff), mn); }
 
-// One anti-diagonal: p1 = previous diagonal, p2 = the one before; qv / cv = the query and candidate
-// value of each slot's cell; pen = 0 for slots inside the band on this parity, infinity outside.
+// One anti-diagonal: p1 = previous diagonal, p2 = the one before; dd = the difference of query and
+// candidate value of each slot's cell, plus a huge value for slots outside the band on this parity
+// (its square overflows to infinity, so those slots stay infinite without a step on the chain).
 template <int CPL, bool ODD, typename F>
-__device__ __forceinline__ void diag_step(F (&p1)[CPL], F (&p2)[CPL], const F (&qv)[CPL], const F (&cv)[CPL],
-                                          const F (&pen)[CPL]) {
+__device__ __forceinline__ void diag_step(F (&p1)[CPL], F (&p2)[CPL], const F (&dd)[CPL]) {
     const F inf = (F)INFINITY;
     F nv[CPL];
 #pragma unroll
@@ -81,7 +81,7 @@ __device__ __forceinline__ void diag_step(F (&p1)[CPL], F (&p2)[CPL], const F (&
             left = wave_shl(fill, p1[c]);
         }
         const F mn = fmin(fmin(up, left), p2[c]);
-        nv[c] = cell_value(qv[c] - cv[c], mn) + pen[c];
+        nv[c] = cell_value(dd[c], mn);
     }
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
@@ -93,7 +93,8 @@ __device__ __forceinline__ void diag_step(F (&p1)[CPL], F (&p2)[CPL], const F (&
 // DTW of the wave's staged pair (qb[0..m), cb[0..m) with the paddings around them), band r <=
 // 64 CPL - 1.  With ABANDON the wave stops once every cell of two consecutive diagonals exceeds
 // the threshold (every warping path meets one of any two consecutive anti-diagonals, costs are
-// non-negative); the threshold is min(thr0, the query's best-so-far) re-read every 32 pairs.
+// non-negative); the threshold is min(thr0, the query's best-so-far), refreshed every 32 pairs from
+// a read issued 32 pairs earlier.
 // Returns the distance (wave-uniform); pairs = diagonal pairs computed.
 template <int CPL, bool ABANDON, typename F>
 __device__ F diag_dtw(const F *qb, const F *cb, int m, int r, const uint64_t *key, float thr0, bool &alive,
@@ -101,13 +102,14 @@ __device__ F diag_dtw(const F *qb, const F *cb, int m, int r, const uint64_t *ke
     const int lane = threadIdx.x & 63;
     const int s0 = r >> 1;   // slot of i == j on the diagonals of parity r & 1
     const F inf = (F)INFINITY;
+    const F big = DiagTraits<F>::big;
     F p1[CPL], p2[CPL], penE[CPL], penO[CPL], qv[CPL], cv[CPL];
     const F *qp[CPL], *cp[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int k = lane + 64 * c;
-        penE[c] = k <= r ? (F)0 : inf;
-        penO[c] = k <= r - 1 ? (F)0 : inf;
+        penE[c] = k <= r ? (F)0 : big;
+        penO[c] = k <= r - 1 ? (F)0 : big;
         // diagonal -2 holds only d(-1, -1) = 0; the loop starts at diagonal 0 (r even) or -1 (r odd)
         p1[c] = ((r & 1) && k == s0) ? (F)0 : inf;
         p2[c] = (!(r & 1) && k == s0) ? (F)0 : inf;
@@ -117,35 +119,53 @@ __device__ F diag_dtw(const F *qb, const F *cb, int m, int r, const uint64_t *ke
         cv[c] = cp[c][0];
     }
     float thr = thr0;
-    if (ABANDON && key) thr = fminf(thr0, threshold_of(load_bsf(key)));
+    uint32_t kpend = ~0u;   // best-so-far read 32 pairs before it tightens thr (latency hidden)
+    if (ABANDON && key) {
+        thr = fminf(thr0, threshold_of(load_bsf(key)));
+        kpend = load_key_dist_bits(key);
+    }
     alive = true;
-    int t = 0;
-    for (; t < m; ++t) {
-        F qn[CPL], cn[CPL];
+    // one (even, odd) pair of diagonals; the odd one and the next even one take the query at i + 1
+    // and the candidate at j + 1
+    auto pair = [&](int t) {
+        F qn[CPL], cn[CPL], de[CPL], dn[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            qn[c] = qp[c][t + 1];   // i + 1 on the odd diagonal
-            cn[c] = cp[c][t + 1];   // j + 1 on the next even diagonal
+            qn[c] = qp[c][t + 1];
+            cn[c] = cp[c][t + 1];
+            de[c] = (qv[c] - cv[c]) + penE[c];
+            dn[c] = (qn[c] - cv[c]) + penO[c];
         }
-        diag_step<CPL, false>(p1, p2, qv, cv, penE);
-        diag_step<CPL, true>(p1, p2, qn, cv, penO);
+        diag_step<CPL, false>(p1, p2, de);
+        diag_step<CPL, true>(p1, p2, dn);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             qv[c] = qn[c];
             cv[c] = cn[c];
         }
-        if (ABANDON && (t & 7) == 7) {
-            if (key && (t & 31) == 31) thr = fminf(thr0, threshold_of(load_bsf(key)));
+    };
+    // blocks of 8 pairs without a branch; with ABANDON a test after each block
+    int t = 0;
+    for (; t + 8 <= m; t += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pair(t + u);
+        if (ABANDON) {
+            if (key && (t & 31) == 24) {
+                thr = fminf(thr0, threshold_of(__uint_as_float(kpend)));
+                kpend = load_key_dist_bits(key);
+            }
             bool any = false;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) any |= (float)fmin(p1[c], p2[c]) <= thr;
             if (__ballot(any) == 0) {
                 alive = false;
-                ++t;
+                t += 8;
                 break;
             }
         }
     }
+    if (alive)
+        for (; t < m; ++t) pair(t);
     pairs = t;
     // the last diagonal 2m - 2 has parity r & 1: odd r ends on the odd step (p1), even r on the even
     // step, which the loop's last odd step moved to p2
