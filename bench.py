@@ -37,8 +37,8 @@ def log(*a):
 
 
 # sources that define each kernel whose HBM traffic is recorded (profiles/hbm_traffic.md)
+# (keyed by the kernel's name without template arguments)
 KERNEL_SOURCES = {
-    "k_lb_batch<true>": ["batch.hip", "batch_stats.h", "device.h", "dtws_internal.h"],
     "k_lb_batch": ["batch.hip", "batch_stats.h", "device.h", "dtws_internal.h"],
     "k_prefix": ["batch.hip", "dtws_internal.h"],
     "k_propose": ["mlp.hip", "device.h", "dtws_internal.h"],
@@ -50,7 +50,7 @@ def kernel_source_hash(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_1812_10302_amd", "csrc")
-    for f in KERNEL_SOURCES.get(kernel, []):
+    for f in KERNEL_SOURCES.get(kernel.split("<")[0], []):
         with open(os.path.join(src, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()
@@ -60,7 +60,7 @@ def traffic_of(kernel: str, launches: int, algorithmic: float):
     """HBM bytes per launch of `kernel` recorded from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
     (profiles/hbm_traffic.md), or None when none is recorded for the kernel's current sources."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
-    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
+    if not os.path.exists(path) or kernel.split("<")[0] not in KERNEL_SOURCES:
         return None
     cur = kernel_source_hash(kernel)
     for line in open(path):
@@ -83,7 +83,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=100_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="series points for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25, help="series points for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--train-n", type=int, default=10_000_000, help="training series length (ordering network)")
@@ -225,7 +225,8 @@ def main():
             # per candidate the cascade must read its series point (4 B) and its window statistics:
             # one (sum, sum of squares) prefix entry (16 B) or the three per-window values (12 B)
             per_cand = 20 if schedule["stats_prefix"] else 16
-            kernel = "k_lb_batch<true>" if schedule["stats_prefix"] else "k_lb_batch"
+            kernel = "k_lb_batch<%s, %s>" % ("true" if schedule["stats_prefix"] else "false",
+                                              "true" if schedule["data_envelope"] else "false")
             units = lb_candidates
         elif dominant == "stats":
             # blocked prefix: read 4 B, write 16 B per series point (one pass for the batch)
