@@ -493,7 +493,11 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
             const int64_t size = (rank_hi - rank_lo) * B;
             int parts = size <= k64 ? 16 : (size <= 2 * k1m ? 4 : 1);
             while (parts > 1 && B / parts < 256) parts /= 2;
-            HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)rank_lo, (int)rank_hi, parts, lb_blocks, s));
+            // series order, block-major, whenever the round's blocks are the same for every query:
+            // a round that holds them all, or any round of the series order
+            const bool natural = (rank_lo == 0 && rank_hi >= max_nb) ||
+                                 (flags & DTWS_ORDER_MASK) == DTWS_ORDER_NATURAL;
+            HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)rank_lo, (int)rank_hi, parts, natural, lb_blocks, s));
         }
         rc = dtw_round();
         if (rc != DTWS_OK) return rc;

@@ -177,8 +177,10 @@ struct EmitBatch {
 // Work-item source of one wave for one query: consumes the current item group by group, pops the
 // next item when it runs out, and stops (keeping the popped item) at the first item of another
 // query, so the caller can drain the queues before switching query.  Items of round r are
-// (query, rank k, part) in query-major order; part selects one of `parts` equal pieces of the
-// k-th block of the query's visiting order.
+// (query, rank k, part); part selects one of `parts` equal pieces of the k-th block of the
+// query's visiting order.  They go out query-major, or block-major in series order when the
+// round's blocks are the same for every query (then the waves on the queries of one block run at
+// about the same time and share its data through the caches).
 struct ItemSource {
     const BatchArgs *a;
     int round, rank_lo, parts;
@@ -188,6 +190,7 @@ struct ItemSource {
     bool pending = false;       // an item of another query was popped
     int pq = -1;
     int64_t pfirst = 0, plast = 0;
+    bool natural = false;       // the round holds every block: series order, block-major
 
     // pops items until one that exists; false when the round is exhausted
     __device__ bool pop(int &qq, int64_t &first, int64_t &last) {
@@ -197,13 +200,22 @@ struct ItemSource {
             if (lane == 0) idx = atomicAdd(&a->heads[round], 1u);
             idx = __builtin_amdgcn_readfirstlane(idx);   // wave-uniform: item state stays in SGPRs
             if (idx >= total) return false;
-            qq = (int)(idx / per_q);
-            const uint32_t rest = idx % per_q;
+            // a round that holds every block visits them in series order, the queries of one
+            // block one after another (their windows share the prefix and series data, which the
+            // caches then serve to all of them); otherwise query by query in visiting order
+            uint32_t rest;
+            if (natural) {
+                qq = (int)(idx % (uint32_t)a->nq);
+                rest = idx / (uint32_t)a->nq;
+            } else {
+                qq = (int)(idx / per_q);
+                rest = idx % per_q;
+            }
             const int k = rank_lo + (int)(rest / (uint32_t)parts);
             const int part = (int)(rest % (uint32_t)parts);
             const BatchQ bq = a->bq[qq];
             if (k >= bq.nblocks) continue;
-            const int64_t blk = a->perm[(int64_t)qq * a->maxblocks + k];
+            const int64_t blk = natural ? k : a->perm[(int64_t)qq * a->maxblocks + k];
             const int64_t piece = a->block / parts;
             first = blk * a->block + part * piece;
             if (first >= bq.N) continue;
@@ -257,12 +269,13 @@ struct ItemSource {
 };
 
 template <bool PREFIX, bool ENV>
-__global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int rank_lo, int rank_hi, int parts) {
+__global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int rank_lo, int rank_hi, int parts, int natural) {
     __shared__ WaveQueue q1s[4];
     __shared__ WaveQueue2 q2s[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     ItemSource src{&a, round, rank_lo, parts, (uint32_t)(rank_hi - rank_lo) * (uint32_t)parts, 0u, -1};
     src.total = src.per_q * (uint32_t)a.nq;
+    src.natural = natural != 0;
     CascadeCounts cnt;
     int q;
     int64_t f, l;
@@ -650,16 +663,20 @@ hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s) 
 }
 
 hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
-                           int blocks, hipStream_t s) {
+                           bool natural, int blocks, hipStream_t s) {
     const bool env = a.envU != nullptr;
     if (prefix && env)
-        hipLaunchKernelGGL((k_lb_batch<true, true>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
+        hipLaunchKernelGGL((k_lb_batch<true, true>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
+                           (int)natural);
     else if (prefix)
-        hipLaunchKernelGGL((k_lb_batch<true, false>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
+        hipLaunchKernelGGL((k_lb_batch<true, false>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
+                           (int)natural);
     else if (env)
-        hipLaunchKernelGGL((k_lb_batch<false, true>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
+        hipLaunchKernelGGL((k_lb_batch<false, true>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
+                           (int)natural);
     else
-        hipLaunchKernelGGL((k_lb_batch<false, false>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts);
+        hipLaunchKernelGGL((k_lb_batch<false, false>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
+                           (int)natural);
     return hipGetLastError();
 }
 

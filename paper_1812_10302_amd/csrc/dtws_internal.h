@@ -231,7 +231,7 @@ hipError_t launch_prefix(const float *T, int64_t n, double2 *PP, double *anc, do
 hipError_t launch_make_perm(const BatchArgs &a, int mode, uint64_t seed, int64_t max_nblocks, hipStream_t s);
 hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s);
 hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
-                           int blocks, hipStream_t s);
+                           bool natural, int blocks, hipStream_t s);
 hipError_t launch_segments(const BatchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_dtw_bucket(const BatchArgs &a, bool prefix, int nc, int blocks, hipStream_t s);
 hipError_t launch_cert_batch(const BatchArgs &a, int max_m, int max_r, hipStream_t s);
