@@ -751,6 +751,7 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
     }
     if (ok) {
         MlpBufs &b = c->mlp;
+        b.num_cu = c->num_cu;
         const int64_t R = kMlpChunk;
         ok = dalloc(&b.theta, kModelParams) == hipSuccess && dalloc(&b.grad, kModelParams) == hipSuccess &&
              dalloc(&b.adam_m, kModelParams) == hipSuccess && dalloc(&b.adam_v, kModelParams) == hipSuccess &&

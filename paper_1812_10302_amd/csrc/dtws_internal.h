@@ -197,6 +197,7 @@ struct MlpBufs {
     uint16_t *Xb, *XbT, *H1b, *H1T, *dA2b, *dA2T, *dA1T;
     float *C1, *C2, *y, *dy, *loss, *Xf;
     float *part;                             // kColsumGroups x 4 x 256 partial column sums
+    int num_cu;                              // compute units of the device (width of the fused forward)
 };
 
 // Scoring of a batch: row (q, blk, j) = row_off[q] + blk * K + j is the proposal of quarter j

@@ -60,6 +60,97 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ 
         for (int t = 0; t < 4; ++t) C[(tm * 16 + 4 * (lane >> 4) + t) * ldc + tn * 64 + 16 * c + r] = acc[c][t];
 }
 
+// ------------------------------------------------------------------ fused inference
+// Forward pass without the intermediate arrays, for scoring.  Both layers are computed transposed
+// (units x data rows, 16 data rows per wave and tile), so the layer-1 accumulators are already in
+// the lane layout of the layer-2 B operand: lane l holds data row l % 16 and units
+// 16 u + 4 (l / 16) .. + 3 of tile u.  Layer 2 takes its 32 hidden units of step s in the order
+// "units 32 s + 4 g .. + 3, then 32 s + 16 + 4 g .. + 3 for lane group g", the A operand (W2T rows)
+// follows the same order, and the head (ReLU, dot with w3, + b3) is folded into the layer-2
+// epilogue.  Rounding points are those of the unfused path: X, W1, W2 and the layer-1 activations
+// in bfloat16, FP32 accumulation.  W2T (rows padded to kInferW2Stride to spread the LDS banks),
+// W1T, b1, b2 and w3 are staged once per workgroup; workgroups loop over the row tiles.
+constexpr int kInferW2Stride = 264;   // bfloat16 per staged W2T row
+constexpr int kInferThreads = 512;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kInferThreads) void k_mlp_infer(const float *__restrict__ X, int64_t R,
+                                                             const uint16_t *__restrict__ W1T,
+                                                             const float *__restrict__ b1,
+                                                             const uint16_t *__restrict__ W2T,
+                                                             const float *__restrict__ b2,
+                                                             const float *__restrict__ w3,
+                                                             const float *__restrict__ b3, float *__restrict__ y) {
+    __shared__ uint16_t sW2[256 * kInferW2Stride];
+    __shared__ uint16_t sW1[256 * 32];
+    __shared__ float sB1[256], sB2[256], sW3[256];
+    for (int e = threadIdx.x; e < 256 * 256 / 8; e += blockDim.x) {
+        const int n = e / 32, h8 = e % 32;
+        *(uint4 *)(sW2 + n * kInferW2Stride + 8 * h8) = ((const uint4 *)W2T)[e];
+    }
+    for (int e = threadIdx.x; e < 256 * 32 / 8; e += blockDim.x) ((uint4 *)sW1)[e] = ((const uint4 *)W1T)[e];
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+        sB1[e] = b1[e];
+        sB2[e] = b2[e];
+        sW3[e] = w3[e];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t tiles = (R + 15) / 16;
+    const float bias3 = b3[0];
+    for (int64_t tile = wave; tile < tiles; tile += nwaves) {
+        const int64_t row = tile * 16 + r;
+        // layer-1 B operand: features 8 g .. + 7 of this lane's data row (zero past the last row)
+        u32x4 xw = u32x4{0u, 0u, 0u, 0u};
+        if (row < R) {
+            const float4 f0 = *(const float4 *)(X + row * 32 + 8 * g);
+            const float4 f1 = *(const float4 *)(X + row * 32 + 8 * g + 4);
+            xw = u32x4{(uint32_t)f2bf(f0.x) | ((uint32_t)f2bf(f0.y) << 16), (uint32_t)f2bf(f0.z) | ((uint32_t)f2bf(f0.w) << 16),
+                       (uint32_t)f2bf(f1.x) | ((uint32_t)f2bf(f1.y) << 16), (uint32_t)f2bf(f1.z) | ((uint32_t)f2bf(f1.w) << 16)};
+        }
+        const bf16x8 xb = __builtin_bit_cast(bf16x8, xw);
+        // layer 1 and its epilogue, packed as the layer-2 B operands of the 8 K steps
+        bf16x8 hb[8];
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+            uint32_t hw[4];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int u = 2 * s8 + h;
+                const bf16x8 a = *(const bf16x8 *)(sW1 + (16 * u + r) * 32 + 8 * g);
+                const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xb, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                const float4 bb = *(const float4 *)(sB1 + 16 * u + 4 * g);
+                hw[2 * h] = (uint32_t)f2bf(fmaxf(acc[0] + bb.x, 0.0f)) | ((uint32_t)f2bf(fmaxf(acc[1] + bb.y, 0.0f)) << 16);
+                hw[2 * h + 1] = (uint32_t)f2bf(fmaxf(acc[2] + bb.z, 0.0f)) | ((uint32_t)f2bf(fmaxf(acc[3] + bb.w, 0.0f)) << 16);
+            }
+            hb[s8] = __builtin_bit_cast(bf16x8, u32x4{hw[0], hw[1], hw[2], hw[3]});
+        }
+        // layer 2 by tiles of 16 output units, head folded in
+        float part = 0.0f;
+#pragma unroll 2
+        for (int v = 0; v < 16; ++v) {
+            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+            const uint16_t *wrow = sW2 + (16 * v + r) * kInferW2Stride + 4 * g;
+#pragma unroll
+            for (int s8 = 0; s8 < 8; ++s8) {
+                const uint2 lo = *(const uint2 *)(wrow + 32 * s8), hi = *(const uint2 *)(wrow + 32 * s8 + 16);
+                const bf16x8 a = __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[s8], acc, 0, 0, 0);
+            }
+            const float4 bb = *(const float4 *)(sB2 + 16 * v + 4 * g), ww = *(const float4 *)(sW3 + 16 * v + 4 * g);
+            part = fmaf(fmaxf(acc[0] + bb.x, 0.0f), ww.x, part);
+            part = fmaf(fmaxf(acc[1] + bb.y, 0.0f), ww.y, part);
+            part = fmaf(fmaxf(acc[2] + bb.z, 0.0f), ww.z, part);
+            part = fmaf(fmaxf(acc[3] + bb.w, 0.0f), ww.w, part);
+        }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (g == 0 && row < R) y[row] = part + bias3;
+    }
+}
+
 // ------------------------------------------------------------------ elementwise pieces
 // X (FP32 R x 32, rows >= R are zero padding) -> bfloat16 row-major and transposed (32 x Rp).
 __global__ void k_mlp_x(const float *X, int64_t R, int64_t Rp, uint16_t *Xb, uint16_t *XbT) {
@@ -576,6 +667,17 @@ hipError_t mlp_init(const MlpBufs &b, uint64_t seed, hipStream_t s) {
 
 // Forward pass on R rows (R <= kMlpChunk).  Training keeps the transposed operands and H2.
 hipError_t mlp_forward(const MlpBufs &b, const float *X, int64_t R, float *y, bool train, hipStream_t s) {
+    if (!train) {
+        // scoring: one fused pass, one workgroup per compute unit (its LDS holds the weights),
+        // none without a tile
+        const int64_t tiles = (R + 15) / 16, per_block = kInferThreads / 64;
+        int64_t blocks = (tiles + per_block - 1) / per_block;
+        if (blocks > b.num_cu) blocks = b.num_cu;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(kInferThreads), 0, s, X, R, b.W1T,
+                           b.theta + kOffb1, b.W2T, b.theta + kOffb2, b.theta + kOffw3, b.theta + kOffb3, y);
+        return hipGetLastError();
+    }
     const int64_t Rp = (R + 63) / 64 * 64;
     hipLaunchKernelGGL(k_mlp_x, dim3(nblk(Rp * 32)), dim3(256), 0, s, X, R, Rp, b.Xb, train ? b.XbT : nullptr);
     hipError_t e = mlp_gemm(b.Xb, 32, b.W1T, 32, b.C1, 256, (int)Rp, 256, 32, s);

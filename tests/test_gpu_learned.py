@@ -62,7 +62,7 @@ def test_paa_matches_oracle(ctx):
     assert np.isnan(bad).all()
 
 
-@pytest.mark.parametrize("rows", [1, 64, 200, 4096])
+@pytest.mark.parametrize("rows", [1, 64, 200, 4096, 70_001])
 def test_forward_matches_reference(ctx, rows):
     theta, X, _ = _random_problem(rows, rows)
     ctx.model_set(theta.astype(np.float32))
