@@ -416,16 +416,31 @@ struct PrefixView {
     }
 };
 
-// Proposals: row (q, blk, j) covers the starts [blk * B + j * B / K, + B / K) of query q.  One wave
-// per row evaluates every ps-th start, ps = max(1, m / 64), and keeps the one whose PAA is nearest
-// (squared Euclidean) to the query's PAA, lowest start on ties.  Its features (query PAA, then
-// candidate PAA) go to X and its start to sstart; an empty quarter gets start -1 and zero features.
+// Minimum of a 64-bit value over the wave (every lane gets it).
+__device__ inline uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Proposals: row (q, blk, j) covers the starts [blk * B + j * B / K, + B / K) of query q.  Every
+// ps-th start of a row, ps = max(1, m / 64), is compared with the query by the squared Euclidean
+// distance of the PAAs, and the nearest is kept (lowest start on ties).  Its features (query PAA,
+// then candidate PAA) go to X and its start to sstart; an empty quarter gets start -1 and zero
+// features.  One wave takes the K rows of a block: it walks the quarters in turn (the prefix grid
+// of the fast path carries over from one quarter to the next when a quarter is a whole number of
+// groups), keeps each quarter's winner in LDS, and computes the K feature rows together at the end.
 __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreArgs sa, int64_t row0, int64_t R,
                                                  float *X) {
-    const int lane = threadIdx.x & 63;
-    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (k >= R) return;
-    const int64_t row = row0 + k;
+    static_assert(kScoreSamples * 16 == 64, "one feature term per lane for all quarters of a block");
+    __shared__ uint64_t winners[4][kScoreSamples];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t k0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * kScoreSamples;
+    if (k0 >= R) return;
+    const int64_t row = row0 + k0;   // rows of a block are consecutive and belong to one query
     int lo = 0, hi = a.nq;   // row_off[lo] <= row < row_off[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -436,22 +451,14 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
     const int64_t local = row - sa.row_off[q];
     const BatchQ bq = a.bq[q];
     const int m = __builtin_amdgcn_readfirstlane(bq.m);
-    const int64_t quarter = a.block / sa.K;
-    const int64_t first = (local / sa.K) * a.block + (local % sa.K) * quarter;
-    const int64_t last = first + quarter < bq.N ? first + quarter : bq.N;
-    float *x = X + k * 32;
-    if (first >= last) {
-        if (lane < 32) x[lane] = 0.0f;
-        if (lane == 0) sa.sstart[k] = -1;
-        return;
-    }
+    const int64_t quarter = a.block / kScoreSamples;
+    const int64_t bfirst = (local / kScoreSamples) * a.block;
     float qp[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) qp[t] = sa.qpaa[q * 16 + t];
     const double inv_m = 1.0 / m;
     const PrefixView pv{sa.pre};
     const int64_t ps = m >= 128 ? m >> 6 : 1;
-    uint64_t best = ~0ull;
     if ((m & 63) == 0) {
         // m = 64 ps: the sampled starts and every segment boundary lie on the grid of step ps, so
         // the 64 starts of a group need the prefix at 128 grid points only (re-anchored to the
@@ -474,8 +481,18 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
             x = x < nlast ? x : nlast;
             return use_dec ? dsrc[x >> dl] : sa.pre.PP[x];
         };
-        double2 rlo = grid_raw(first + ps * lane), rhi = grid_raw(first + ps * (lane + 64));
-        for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
+        const bool carry = quarter % (64 * ps) == 0;   // quarters are whole groups: the grid carries over
+        double2 rlo = make_double2(0.0, 0.0), rhi = rlo;
+        for (int j = 0; j < kScoreSamples; ++j) {
+          const int64_t first = bfirst + j * quarter;
+          const int64_t last = first + quarter < bq.N ? first + quarter : bq.N;
+          uint64_t best = ~0ull;
+          if (first < last) {
+          if (j == 0 || !carry) {
+              rlo = grid_raw(first + ps * lane);
+              rhi = grid_raw(first + ps * (lane + 64));
+          }
+          for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
             const double2 rnext = grid_raw(g0 + ps * (lane + 128));
             const int64_t b0 = g0 / kPB, e0 = (b0 + 1) * kPB;
             const double2 tb = sa.pre.tot[b0];
@@ -515,36 +532,46 @@ __global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreA
                 const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)i;
                 best = key < best ? key : best;
             }
+          }
+          }
+          best = wave_min_u64(best);
+          if (lane == 0) winners[wid][j] = best;
         }
     } else {
         float inv_len[16];
 #pragma unroll
         for (int t = 0; t < 16; ++t) inv_len[t] = 1.0f / (float)((((t + 1) * m) >> 4) - ((t * m) >> 4));
-        for (int64_t i = first + lane * ps; i < last; i += 64 * ps) {
-            float f[16];
-            pv.paa(i, m, inv_m, inv_len, f);
-            float d = 0.0f;
+        for (int j = 0; j < kScoreSamples; ++j) {
+            const int64_t first = bfirst + j * quarter;
+            const int64_t last = first + quarter < bq.N ? first + quarter : bq.N;
+            uint64_t best = ~0ull;
+            for (int64_t i = first + lane * ps; i < last; i += 64 * ps) {
+                float f[16];
+                pv.paa(i, m, inv_m, inv_len, f);
+                float d = 0.0f;
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const float e = f[t] - qp[t];
-                d = fmaf(e, e, d);
+                for (int t = 0; t < 16; ++t) {
+                    const float e = f[t] - qp[t];
+                    d = fmaf(e, e, d);
+                }
+                const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)i;
+                best = key < best ? key : best;
             }
-            const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)i;
-            best = key < best ? key : best;
+            best = wave_min_u64(best);
+            if (lane == 0) winners[wid][j] = best;
         }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t o = __shfl_xor(best, off, 64);
-        best = o < best ? o : best;
-    }
-    const int64_t i = (int64_t)(uint32_t)best;
-    if (lane < 16) {
-        x[16 + lane] = pv.paa_term(i, m, inv_m, lane);
-    } else if (lane < 32) {
-        x[lane - 16] = qp[lane - 16];
-    }
-    if (lane == 0) sa.sstart[k] = (int32_t)i;
+    wave_sync();
+    // features: lanes 16 j .. 16 j + 15 fill row k0 + j (term t = lane % 16 of both PAAs)
+    const int j = lane >> 4, t = lane & 15;
+    const uint64_t w = winners[wid][j];
+    const bool empty = bfirst + j * quarter >= bq.N;
+    float *x = X + (k0 + j) * 32;
+    const int64_t i = empty ? bfirst : (int64_t)(uint32_t)w;   // a valid start either way
+    const float f = pv.paa_term(i, m, inv_m, t);
+    x[16 + t] = empty ? 0.0f : f;
+    x[t] = empty ? 0.0f : sa.qpaa[q * 16 + t];
+    if (t == 0) sa.sstart[k0 + j] = empty ? -1 : (int32_t)i;
 }
 
 // Score of a block = minimum predicted value over its proposals; bstart = that proposal's start.
@@ -731,7 +758,7 @@ hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArg
     const int64_t chunk = kMlpChunk / sa.K * sa.K;
     for (int64_t r0 = 0; r0 < sa.total_rows; r0 += chunk) {
         const int64_t R = sa.total_rows - r0 < chunk ? sa.total_rows - r0 : chunk;
-        hipLaunchKernelGGL(k_propose, dim3(nblk(R * 64)), dim3(256), 0, s, a, sa, r0, R, b.Xf);
+        hipLaunchKernelGGL(k_propose, dim3(nblk(R / kScoreSamples * 64)), dim3(256), 0, s, a, sa, r0, R, b.Xf);
         hipError_t e = mlp_forward(b, b.Xf, R, b.y, false, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_block_min, dim3(nblk(R / sa.K)), dim3(256), 0, s, b.y, sa.sstart, R, sa.K, r0, sa.score,
@@ -752,7 +779,7 @@ hipError_t launch_propose(const BatchArgs &a, const ScoreArgs &sa, float *X, int
     hipLaunchKernelGGL(k_query_paa, dim3(a.nq), dim3(64), 0, s, a, sa.qpaa);
     for (int64_t r0 = 0; r0 < sa.total_rows; r0 += kMlpChunk) {
         const int64_t R = sa.total_rows - r0 < kMlpChunk ? sa.total_rows - r0 : kMlpChunk;
-        hipLaunchKernelGGL(k_propose, dim3(nblk(R * 64)), dim3(256), 0, s, a, sa, r0, R, X + r0 * 32);
+        hipLaunchKernelGGL(k_propose, dim3(nblk(R / kScoreSamples * 64)), dim3(256), 0, s, a, sa, r0, R, X + r0 * 32);
         hipLaunchKernelGGL(k_widen_starts, dim3(nblk(R)), dim3(256), 0, s, sa.sstart, R, starts + r0);
     }
     return hipGetLastError();
