@@ -450,12 +450,17 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     }
     const int dtw_blocks = c->num_cu * (c->dtw_blocks_per_cu > 0 ? c->dtw_blocks_per_cu : 4);
     const int lb_blocks = c->num_cu * (c->lb_blocks_per_cu > 0 ? c->lb_blocks_per_cu : 8);
-    auto dtw_round = [&]() -> int {
-        { PROF(DTWS_K_OTHER); HIPCHK(c, launch_segments(a, c->num_cu, s)); }
-        for (int nc = 1; nc <= kMaxChunks + 1; ++nc) {
-            if (!p.bucket_used[nc]) continue;
-            PROF(DTWS_K_DTW);
-            HIPCHK(c, launch_dtw_bucket(a, !same_m, nc, dtw_blocks, s));
+    // known_count: the round's survivor count when the host knows it (-1 otherwise); a count the
+    // one-wave-per-candidate kernel takes whole needs neither the segments nor the lane kernels
+    auto dtw_round = [&](int64_t known_count) -> int {
+        const bool diag_only = known_count >= 0 && known_count <= (int64_t)a.diag_max;
+        if (!diag_only) {
+            { PROF(DTWS_K_OTHER); HIPCHK(c, launch_segments(a, c->num_cu, s)); }
+            for (int nc = 1; nc <= kMaxChunks + 1; ++nc) {
+                if (!p.bucket_used[nc]) continue;
+                PROF(DTWS_K_DTW);
+                HIPCHK(c, launch_dtw_bucket(a, !same_m, nc, dtw_blocks, s));
+            }
         }
         if (a.diag_max > 0 || a.diag_wide) {
             PROF(DTWS_K_DTW);
@@ -470,7 +475,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         if (learned) HIPCHK(c, launch_seed_learned(a, sa, s));
         else HIPCHK(c, launch_seed_random(a, seed, s));
     }
-    int rc = dtw_round();
+    int rc = dtw_round(learned ? (int64_t)nq * kSeedCands : (int64_t)nq);
     if (rc != DTWS_OK) return rc;
     // rounds over the work queue (candidates per query, cumulative): 64K, 1M, 16M, then the rest;
     // with fewer rounds (schedule) 1M then the rest, or everything at once
@@ -499,7 +504,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
                                  (flags & DTWS_ORDER_MASK) == DTWS_ORDER_NATURAL;
             HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)rank_lo, (int)rank_hi, parts, natural, lb_blocks, s));
         }
-        rc = dtw_round();
+        rc = dtw_round(-1);
         if (rc != DTWS_OK) return rc;
         rank_lo = rank_hi;
     }

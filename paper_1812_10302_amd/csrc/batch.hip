@@ -606,8 +606,8 @@ __global__ __launch_bounds__(256) void k_cert_dtw_batch(BatchArgs a) {
 
 // One block per query: minimum certified distance, lowest index on ties.
 __global__ __launch_bounds__(256) void k_cert_reduce_batch(BatchArgs a) {
-    __shared__ double sd[256];
-    __shared__ uint32_t si[256];
+    __shared__ double sd[4];
+    __shared__ uint32_t si[4];
     const int q = blockIdx.x;
     const uint32_t cnt0 = *a.cert_count;
     const uint32_t cnt = cnt0 < (uint32_t)kNearBestCap ? cnt0 : (uint32_t)kNearBestCap;
@@ -622,11 +622,24 @@ __global__ __launch_bounds__(256) void k_cert_reduce_batch(BatchArgs a) {
             bidx = idx;
         }
     }
-    sd[threadIdx.x] = best;
-    si[threadIdx.x] = bidx;
+    // (distance, index) minimum over the wave, then over the block's waves
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double od = __shfl_xor(best, off, 64);
+        const uint32_t oi = __shfl_xor(bidx, off, 64);
+        if (od < best || (od == best && oi < bidx)) {
+            best = od;
+            bidx = oi;
+        }
+    }
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sd[wid] = best;
+        si[wid] = bidx;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int t = 1; t < (int)blockDim.x; ++t)
+        for (int t = 1; t < (int)(blockDim.x >> 6); ++t)
             if (sd[t] < best || (sd[t] == best && si[t] < bidx)) {
                 best = sd[t];
                 bidx = si[t];
