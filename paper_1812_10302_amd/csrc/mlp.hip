@@ -596,16 +596,16 @@ __global__ void k_block_min(const float *y, const int32_t *sstart, int64_t R, in
 // Round -1 of the learned order: the best-so-far of every query starts from the proposals of its
 // kSeedCands best-scored blocks (repeating the last when a query has fewer blocks).
 __global__ void k_seed_learned(BatchArgs a, const int32_t *bstart, const int64_t *row_off, int K) {
-    for (int q = threadIdx.x; q < a.nq; q += blockDim.x) {
-        const int64_t nb = a.bq[q].nblocks;
-        for (int k = 0; k < kSeedCands; ++k) {
-            const int64_t blk = a.perm[(int64_t)q * a.maxblocks + (k < nb ? k : nb - 1)];
-            a.surv_q[q * kSeedCands + k] = q;
-            a.surv_i[q * kSeedCands + k] = bstart[row_off[q] / K + blk];
-        }
-        a.qcnt[q] = kSeedCands;
-    }
-    if (threadIdx.x == 0) *a.surv_count = (uint32_t)(a.nq * kSeedCands);
+    // one thread per (query, seed)
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)a.nq * kSeedCands) return;
+    const int q = (int)(e / kSeedCands), k = (int)(e % kSeedCands);
+    const int64_t nb = a.bq[q].nblocks;
+    const int64_t blk = a.perm[(int64_t)q * a.maxblocks + (k < nb ? k : nb - 1)];
+    a.surv_q[e] = q;
+    a.surv_i[e] = bstart[row_off[q] / K + blk];
+    if (k == 0) a.qcnt[q] = kSeedCands;
+    if (e == 0) *a.surv_count = (uint32_t)(a.nq * kSeedCands);
 }
 
 // Visiting order of a query's blocks by ascending score: counting sort into 2048 buckets between
@@ -651,12 +651,33 @@ __global__ __launch_bounds__(1024) void k_block_order(const BatchArgs a, const f
     };
     for (int64_t b = tid; b < nb; b += blockDim.x) atomicAdd(&hist[bucket(sc[b])], 1u);
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int k = 0; k < kOrderBuckets; ++k) {
-            const uint32_t c = hist[k];
-            hist[k] = run;
-            run += c;
+    // exclusive prefix of the histogram: each thread owns kOrderBuckets / blockDim.x consecutive
+    // buckets; a wave scan and a scan of the wave totals give every thread its offset
+    {
+        constexpr int kPer = kOrderBuckets / 1024;
+        static_assert(kOrderBuckets % 1024 == 0, "buckets per thread");
+        __shared__ uint32_t wsum[16];
+        uint32_t own[kPer], tsum = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            own[u] = hist[tid * kPer + u];
+            tsum += own[u];
+        }
+        uint32_t incl = tsum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(incl, off, 64);
+            if ((tid & 63) >= off) incl += o;
+        }
+        if ((tid & 63) == 63) wsum[tid >> 6] = incl;
+        __syncthreads();
+        uint32_t base = 0;
+        for (int w = 0; w < (tid >> 6); ++w) base += wsum[w];
+        uint32_t run = base + incl - tsum;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            hist[tid * kPer + u] = run;
+            run += own[u];
         }
     }
     __syncthreads();
@@ -786,7 +807,8 @@ hipError_t launch_propose(const BatchArgs &a, const ScoreArgs &sa, float *X, int
 }
 
 hipError_t launch_seed_learned(const BatchArgs &a, const ScoreArgs &sa, hipStream_t s) {
-    hipLaunchKernelGGL(k_seed_learned, dim3(1), dim3(256), 0, s, a, sa.bstart, sa.row_off, sa.K);
+    hipLaunchKernelGGL(k_seed_learned, dim3(nblk((int64_t)a.nq * kSeedCands)), dim3(256), 0, s, a, sa.bstart, sa.row_off,
+                       sa.K);
     return hipGetLastError();
 }
 
