@@ -83,7 +83,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=100_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 25, help="series points for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="series points for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--train-n", type=int, default=10_000_000, help="training series length (ordering network)")
