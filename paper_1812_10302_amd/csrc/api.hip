@@ -228,9 +228,9 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
     return DTWS_OK;
 }
 
+// Copies the result block (results and counters) to the host and parses the counters.
 int fetch_counters(dtws_ctx *c, int64_t candidates, hipStream_t s) {
-    HIPCHK(c, hipMemcpyAsync(c->h_counters, c->counters, sizeof(unsigned long long) * kNumCounters,
-                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_res_block, c->res_block, c->res_bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     const unsigned long long *h = c->h_counters;
     c->last.candidates = candidates;
@@ -398,12 +398,8 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     HIPCHK(c, hipMemcpyAsync(c->bq, c->h_bq, sizeof(BatchQ) * nq, hipMemcpyHostToDevice, s));
     {
         PROF(DTWS_K_OTHER);
-        HIPCHK(c, launch_fill_u64(c->keys, kEmptyKey, nq, s));
-        HIPCHK(c, launch_fill_u64((uint64_t *)c->counters, 0, kNumCounters, s));
-        HIPCHK(c, launch_fill_u32(c->heads, 0, 8, s));
-        HIPCHK(c, launch_fill_u32(c->nb_count, 0, 1, s));
-        HIPCHK(c, launch_fill_u32(c->cert_count, 0, 1, s));
-        HIPCHK(c, launch_fill_u32(c->overflow, 0, 1, s));
+        HIPCHK(c, launch_reset_batch(c->keys, nq, c->counters, kNumCounters, c->heads, 8, c->nb_count, c->cert_count,
+                                     c->overflow, s));
     }
     {
         PROF(DTWS_K_PREP);
@@ -509,11 +505,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         rank_lo = rank_hi;
     }
     { PROF(DTWS_K_CERT); HIPCHK(c, launch_cert_batch(a, max_m, max_r, s)); }
-    HIPCHK(c, hipMemcpyAsync(c->h_idx, c->res_idx, sizeof(int64_t) * nq, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_dist, c->res_dist, sizeof(double) * nq, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_status, c->res_status, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_counters, c->counters, sizeof(unsigned long long) * kNumCounters,
-                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_res_block, c->res_block, c->res_bytes, hipMemcpyDeviceToHost, s));
     return DTWS_OK;
 }
 
@@ -655,8 +647,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
     (void)hipSetDevice(c->device);
     void *dev[] = {c->qpad, c->qhat64, c->qsorted, c->Usorted, c->Lsorted, c->order, c->keys, c->st_mu,
                    c->st_s, c->st_o, c->envU, c->envL, c->surv, c->surv_count, c->nb_d, c->nb_idx,
-                   c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_idx, c->res_dist,
-                   c->res_status, c->counters, c->gen_rows, c->bq, c->PP, c->PPd, c->anc, c->tot,
+                   c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_block, c->gen_rows, c->bq, c->PP, c->PPd, c->anc, c->tot,
                    c->perm, c->heads, c->surv_q, c->surv_i, c->sorted, c->qcnt, c->fill, c->overflow,
                    c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q,
                    c->mlp.theta, c->mlp.grad, c->mlp.adam_m, c->mlp.adam_v, c->mlp.W1T, c->mlp.W2T, c->mlp.W2b,
@@ -674,7 +665,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
         delete[] c->ev;
     }
     delete[] c->ev_class;
-    void *host[] = {c->h_idx, c->h_dist, c->h_status, c->h_counters, c->h_bq, c->h_row_off};
+    void *host[] = {c->h_res_block, c->h_bq, c->h_row_off};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     delete c;
@@ -722,13 +713,24 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
               dalloc(&c->cert_rows, (size_t)256 * 3 * (max_m + 1)) == hipSuccess &&
               dalloc(&c->cert_idx, kNearBestCap) == hipSuccess && dalloc(&c->cert_count, 1) == hipSuccess &&
               dalloc(&c->cert_d, kNearBestCap) == hipSuccess &&
-              dalloc(&c->res_idx, Q) == hipSuccess && dalloc(&c->res_dist, Q) == hipSuccess &&
-              dalloc(&c->res_status, Q) == hipSuccess && dalloc(&c->counters, kNumCounters) == hipSuccess &&
-              dalloc(&c->gen_rows, (size_t)c->gen_lanes * 2 * (max_m + 1)) == hipSuccess &&
-              hipHostMalloc((void **)&c->h_idx, sizeof(int64_t) * Q, 0) == hipSuccess &&
-              hipHostMalloc((void **)&c->h_dist, sizeof(double) * Q, 0) == hipSuccess &&
-              hipHostMalloc((void **)&c->h_status, sizeof(int32_t) * Q, 0) == hipSuccess &&
-              hipHostMalloc((void **)&c->h_counters, sizeof(unsigned long long) * kNumCounters, 0) == hipSuccess;
+              dalloc(&c->gen_rows, (size_t)c->gen_lanes * 2 * (max_m + 1)) == hipSuccess;
+    if (ok) {
+        // results: index (Q x int64), distance (Q x double), status (Q x int32, padded to 8 B), counters
+        const size_t st_bytes = (sizeof(int32_t) * (size_t)Q + 7) & ~(size_t)7;
+        c->res_bytes = (sizeof(int64_t) + sizeof(double)) * (size_t)Q + st_bytes + sizeof(unsigned long long) * kNumCounters;
+        ok = hipMalloc((void **)&c->res_block, c->res_bytes) == hipSuccess &&
+             hipHostMalloc((void **)&c->h_res_block, c->res_bytes, 0) == hipSuccess;
+        if (ok) {
+            auto carve = [&](uint8_t *b, int64_t *&idx, double *&dist, int32_t *&st, unsigned long long *&cnt) {
+                idx = (int64_t *)b;
+                dist = (double *)(b + sizeof(int64_t) * (size_t)Q);
+                st = (int32_t *)(b + (sizeof(int64_t) + sizeof(double)) * (size_t)Q);
+                cnt = (unsigned long long *)(b + (sizeof(int64_t) + sizeof(double)) * (size_t)Q + st_bytes);
+            };
+            carve(c->res_block, c->res_idx, c->res_dist, c->res_status, c->counters);
+            carve(c->h_res_block, c->h_idx, c->h_dist, c->h_status, c->h_counters);
+        }
+    }
     if (ok) {
         c->maxblocks = (max_n + kMinBlock - 1) / kMinBlock + 1;
         int64_t cap = Q * max_n < (int64_t(1) << 25) ? Q * max_n : (int64_t(1) << 25);
@@ -822,9 +824,6 @@ DTWS_API int dtws_search(dtws_ctx *c, const float *T, int64_t n, const float *Q,
     }
     int rc = run_query(c, T, n, Q, m, r, flags, seed, 0, s);
     if (rc != DTWS_OK) return rc;
-    HIPCHK(c, hipMemcpyAsync(c->h_idx, c->res_idx, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_dist, c->res_dist, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_status, c->res_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     rc = fetch_counters(c, n - m + 1, s);
     if (rc != DTWS_OK) return rc;
     prof_end(c);

@@ -208,6 +208,27 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s
     return hipGetLastError();
 }
 
+// Start of a batched search in one launch: empty best-so-far keys, zero counters, work-queue heads,
+// near-best and certification counts and the overflow flag.
+__global__ void k_reset_batch(uint64_t *keys, int nq, unsigned long long *counters, int ncounters, uint32_t *heads,
+                              int nheads, uint32_t *nb_count, uint32_t *cert_count, uint32_t *overflow) {
+    for (int i = threadIdx.x; i < nq; i += blockDim.x) keys[i] = kEmptyKey;
+    for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0ull;
+    for (int i = threadIdx.x; i < nheads; i += blockDim.x) heads[i] = 0u;
+    if (threadIdx.x == 0) {
+        *nb_count = 0u;
+        *cert_count = 0u;
+        *overflow = 0u;
+    }
+}
+
+hipError_t launch_reset_batch(uint64_t *keys, int nq, unsigned long long *counters, int ncounters, uint32_t *heads,
+                              int nheads, uint32_t *nb_count, uint32_t *cert_count, uint32_t *overflow, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_batch, dim3(1), dim3(256), 0, s, keys, nq, counters, ncounters, heads, nheads, nb_count,
+                       cert_count, overflow);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ best-so-far update
 __global__ __launch_bounds__(256) void k_bsf_update(uint64_t *keys, const float *d, const int64_t *idx,
                                                     int64_t count) {

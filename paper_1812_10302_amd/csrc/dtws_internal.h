@@ -254,6 +254,8 @@ hipError_t launch_paa(const float *T, int64_t n, int m, const int64_t *starts, i
                       hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
+hipError_t launch_reset_batch(uint64_t *keys, int nq, unsigned long long *counters, int ncounters, uint32_t *heads,
+                              int nheads, uint32_t *nb_count, uint32_t *cert_count, uint32_t *overflow, hipStream_t s);
 // key of an empty best-so-far: distance +inf, index 0xFFFFFFFF
 constexpr uint64_t kEmptyKey = (uint64_t(0x7F800000u) << 32) | 0xFFFFFFFFull;
 
@@ -336,6 +338,9 @@ struct dtws_ctx {
     int64_t *h_idx = nullptr;
     double *h_dist = nullptr;
     int32_t *h_status = nullptr;
+    // the result arrays and the counters in one device and one pinned host block, fetched by one copy
+    uint8_t *res_block = nullptr, *h_res_block = nullptr;
+    size_t res_bytes = 0;
     unsigned long long *h_counters = nullptr;
     dtws_counters last{};
     // profiling (DTWS_PROFILE): event pairs around launches, class per pair
