@@ -433,7 +433,8 @@ __device__ inline uint64_t wave_min_u64(uint64_t v) {
 // features.  One wave takes the K rows of a block: it walks the quarters in turn (the prefix grid
 // of the fast path carries over from one quarter to the next when a quarter is a whole number of
 // groups), keeps each quarter's winner in LDS, and computes the K feature rows together at the end.
-__global__ __launch_bounds__(256) void k_propose(const BatchArgs a, const ScoreArgs sa, int64_t row0, int64_t R,
+// (five waves per SIMD: the grid loads and LDS round trips of a group are latency-bound)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_propose(const BatchArgs a, const ScoreArgs sa, int64_t row0, int64_t R,
                                                  float *X) {
     static_assert(kScoreSamples * 16 == 64, "one feature term per lane for all quarters of a block");
     __shared__ uint64_t winners[4][kScoreSamples];
