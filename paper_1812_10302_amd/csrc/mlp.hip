@@ -496,18 +496,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
           for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
             const double2 rnext = grid_raw(g0 + ps * (lane + 128));
             const int64_t b0 = g0 / kPB, e0 = (b0 + 1) * kPB;
-            const double2 tb = sa.pre.tot[b0];
-            const double a0 = sa.pre.anc[b0], delta = sa.pre.anc[b0 + 1] - a0;
-            double2 gv[2];
+            double2 gv[2] = {rlo, rhi};
+            if (g0 + 127 * ps >= e0) {   // (wave-uniform) some grid point lies past the block
+                const double2 tb = sa.pre.tot[b0];
+                const double delta = sa.pre.anc[b0 + 1] - sa.pre.anc[b0];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                // re-anchor to the group's first block (a window ends at most one block later)
-                const int64_t x = g0 + ps * (lane + 64 * h);
-                const double2 p = h == 0 ? rlo : rhi;
-                const bool cross = x >= e0;
-                const double lx = (double)(x - e0);
-                gv[h].x = cross ? tb.x + p.x + lx * delta : p.x;
-                gv[h].y = cross ? tb.y + p.y + 2.0 * delta * p.x + lx * delta * delta : p.y;
+                for (int h = 0; h < 2; ++h) {
+                    // re-anchor to the group's first block (a window ends at most one block later)
+                    const int64_t x = g0 + ps * (lane + 64 * h);
+                    const double2 p = h == 0 ? rlo : rhi;
+                    const bool cross = x >= e0;
+                    const double lx = (double)(x - e0);
+                    gv[h].x = cross ? tb.x + p.x + lx * delta : p.x;
+                    gv[h].y = cross ? tb.y + p.y + 2.0 * delta * p.x + lx * delta * delta : p.y;
+                }
             }
             rlo = rhi;
             rhi = rnext;
