@@ -251,9 +251,10 @@ __global__ __launch_bounds__(kStatThreads) void k_znorm_stats(const float *__res
     }
     __syncthreads();
     const int64_t cnt = N - c0 < kStatTile ? N - c0 : kStatTile;
+    const double inv_m = 1.0 / m;
     for (int t = tid; t < cnt; t += kStatThreads) {
         const double S1 = Pb1[t] - Pa1[t], S2 = Pb2[t] - Pa2[t];
-        const double md = S1 / m, msq = S2 / m;
+        const double md = EXPORT ? S1 / m : S1 * inv_m, msq = EXPORT ? S2 / m : S2 * inv_m;
         double var = msq - md * md;
         double mu = a + md;
         // The prefix difference carries an absolute error of about (t + m) * 2^-53 * msq, i.e. a
@@ -271,17 +272,18 @@ __global__ __launch_bounds__(kStatThreads) void k_znorm_stats(const float *__res
             }
             var = q / m;
         }
-        const double sigma = sqrt(var > 0.0 ? var : 0.0);
         const int64_t i = c0 + t;
         if (EXPORT) {
             mu_out[i] = mu;
-            sg_out[i] = sigma;
+            sg_out[i] = sqrt(var > 0.0 ? var : 0.0);
         } else {
+            // the scale is stored in FP32: the FP32 reciprocal square root of the FP64 variance
+            // (relative error ~2^-23; var > kSigmaFlat^2 is a normal FP32 number), 0 when flat
             const float m32 = (float)mu;
-            const double inv = sigma <= kSigmaFlat ? 0.0 : 1.0 / sigma;
+            const float inv = var > kSigmaFlat * kSigmaFlat ? __builtin_amdgcn_rsqf((float)var) : 0.0f;
             mu32[i] = m32;
-            s32[i] = (float)inv;
-            o32[i] = (float)(-(mu - (double)m32) * inv);
+            s32[i] = inv;
+            o32[i] = (float)(-(mu - (double)m32)) * inv;
         }
     }
 }
