@@ -262,7 +262,8 @@ DTWS_API int dtws_model_init(dtws_ctx *ctx, uint64_t seed);
 DTWS_API int dtws_model_get(dtws_ctx *ctx, float *params_host, int64_t count);
 DTWS_API int dtws_model_set(dtws_ctx *ctx, const float *params_host, int64_t count);
 
-/* Predictions y_dev[rows] for feature rows X_dev[rows][32] (FP32). */
+/* Predictions y_dev[rows] for feature rows X_dev[rows][32] (FP32, row-major; X_dev
+ * 16-byte aligned, as every torch or hipMalloc allocation is: DTWS_EINVAL otherwise). */
 DTWS_API int dtws_model_forward(dtws_ctx *ctx, const float *X_dev, int64_t rows, float *y_dev, void *stream);
 
 /* Gradient of the mean squared error against targets t_dev[rows] (rows <=

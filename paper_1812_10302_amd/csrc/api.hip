@@ -879,7 +879,7 @@ DTWS_API int dtws_model_set(dtws_ctx *c, const float *params, int64_t count) {
 }
 
 DTWS_API int dtws_model_forward(dtws_ctx *c, const float *X, int64_t rows, float *y, void *stream) {
-    if (!c || !X || !y || rows < 0) return DTWS_EINVAL;
+    if (!c || !X || !y || rows < 0 || ((uintptr_t)X & 15u) != 0) return DTWS_EINVAL;   // rows are read as float4
     if (!c->has_model) return DTWS_ENOMODEL;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;

@@ -71,6 +71,19 @@ def test_forward_matches_reference(ctx, rows):
     np.testing.assert_allclose(y, want, rtol=2e-3, atol=2e-3 * np.abs(want).max())
 
 
+def test_forward_rejects_misaligned_rows(ctx):
+    """Feature rows are read as 16-byte vectors: a pointer off that alignment is refused."""
+    theta, X, _ = _random_problem(5, 64)
+    ctx.model_set(theta.astype(np.float32))
+    flat = torch.zeros(64 * 32 + 1, dtype=torch.float32, device=DEV)
+    flat[1:] = dev(X).reshape(-1)
+    with pytest.raises(dtws.DtwsError):
+        ctx.model_forward(flat[1:].view(64, 32))
+    y = ctx.model_forward(flat[1:].clone().view(64, 32)).cpu().numpy()   # an aligned copy is fine
+    want, _ = M.forward(theta, X.astype(np.float64), bf16_ops=True)
+    np.testing.assert_allclose(y, want, rtol=2e-3, atol=2e-3 * np.abs(want).max())
+
+
 @pytest.mark.parametrize("rows", [64, 333, 4096])
 def test_gradients_match_reference(ctx, rows):
     theta, X, t = _random_problem(100 + rows, rows)
