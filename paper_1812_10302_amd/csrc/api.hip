@@ -20,9 +20,9 @@ constexpr int64_t kDefaultBlock = 4096;
 constexpr int kDefaultDiagMax = 16384;  // rounds with at most this many survivors: one wave per candidate
 
 // Decimation levels the proposals of a length-m query read (m a multiple of 64, step m/64 a power
-// of two from 2 to 32).
+// of two from 8 to 32; shorter steps take their grid from the series).
 uint32_t dec_level_of(int m) {
-    if (m % 64 != 0 || m < 128) return 0u;
+    if (m % 64 != 0 || m < 512) return 0u;
     const int ps = m / 64;
     if ((ps & (ps - 1)) != 0 || ps > 32) return 0u;
     return 1u << __builtin_ctz((unsigned)ps);
@@ -31,7 +31,7 @@ uint32_t dec_level_of(int m) {
 // entries of all decimated levels for a series of max_n points
 int64_t dec_total(int64_t max_n) {
     int64_t t = 0;
-    for (int L = 1; L < kDecLevels; ++L) t += (max_n >> L) + 2;
+    for (int L = kDecFirst; L < kDecLevels; ++L) t += (max_n >> L) + 2;
     return t;
 }
 
@@ -750,7 +750,7 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&c->nb_q, kNearBestCap) == hipSuccess && dalloc(&c->cert_q, kNearBestCap) == hipSuccess;
         if (ok) {
             int64_t off = 0;
-            for (int L = 1; L < kDecLevels; ++L) {
+            for (int L = kDecFirst; L < kDecLevels; ++L) {
                 c->dec.lv[L] = c->PPd + off;
                 off += (max_n >> L) + 2;
             }

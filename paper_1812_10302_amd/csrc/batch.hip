@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
             if (x < lim) PP[x0 + x] = stage[(e >> 4) * kPad + (e & 15)];
         }
         // decimated copies: consecutive threads write consecutive entries of each level
-        for (int L = 1; L < kDecLevels; ++L) {
+        for (int L = kDecFirst; L < kDecLevels; ++L) {
             if (!((levels >> L) & 1u)) continue;
             for (int e = tid; e < (kHalf >> L); e += kPrefixThreads) {
                 const int el = e << L;   // block-local position within this half
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
             tot[b + 1] = make_double2(0.0, 0.0);
             if (x0 + kPB == n) {
                 PP[n] = make_double2(0.0, 0.0);
-                for (int L = 1; L < kDecLevels; ++L)
+                for (int L = kDecFirst; L < kDecLevels; ++L)
                     if (((levels >> L) & 1u) && (n & ((1 << L) - 1)) == 0) dec.lv[L][n >> L] = make_double2(0.0, 0.0);
             }
         }

@@ -55,8 +55,9 @@ struct Prefix {
 };
 
 // Decimated copies of the prefix for the proposals of the learned order: lv[L][k] = PP[k << L],
-// L = 1..5 (every 2nd .. 32nd entry), written by the prefix pass for the levels it is asked for.
-constexpr int kDecLevels = 6;
+// L = 3..5 (every 8th .. 32nd entry; shorter steps read the series), written by the prefix pass
+// for the levels it is asked for.
+constexpr int kDecFirst = 3, kDecLevels = 6;
 struct Decimated {
     double2 *lv[kDecLevels];
 };

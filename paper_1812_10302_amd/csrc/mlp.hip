@@ -426,6 +426,24 @@ __device__ inline uint64_t wave_min_u64(uint64_t v) {
     return v;
 }
 
+// DPP move of an FP32 value; lanes without a source, and lanes of rows outside ROWS, read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_or_zero(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (row shifts within each 16-lane row, then the
+// row broadcasts of lanes 15 and 31 into the rows above them).
+__device__ __forceinline__ float wave_scan_incl(float x) {
+    x += dpp_or_zero<0x111, 0xF>(x);   // row_shr:1
+    x += dpp_or_zero<0x112, 0xF>(x);   // row_shr:2
+    x += dpp_or_zero<0x114, 0xF>(x);   // row_shr:4
+    x += dpp_or_zero<0x118, 0xF>(x);   // row_shr:8
+    x += dpp_or_zero<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    x += dpp_or_zero<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
 // Proposals: row (q, blk, j) covers the starts [blk * B + j * B / K, + B / K) of query q.  Every
 // ps-th start of a row, ps = max(1, m / 64), is compared with the query by the squared Euclidean
 // distance of the PAAs, and the nearest is kept (lowest start on ties).  Its features (query PAA,
@@ -472,7 +490,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         const float inv_seg = 16.0f / (float)m;
         // a decimated copy with step ps when the prefix pass wrote one (ps a power of two)
         const int dl = __builtin_ctz((unsigned)ps);
-        const bool use_dec = (ps & (ps - 1)) == 0 && dl >= 1 && dl < kDecLevels && ((sa.dec_levels >> dl) & 1u);
+        const bool use_dec = (ps & (ps - 1)) == 0 && dl >= kDecFirst && dl < kDecLevels && ((sa.dec_levels >> dl) & 1u);
         const double2 *dsrc = use_dec ? sa.dec.lv[dl] : nullptr;
         const int64_t nlast = use_dec ? ((a.n >> dl) << dl) : a.n;
         // raw prefix at grid point k of the current group (points past the series only serve idle
@@ -482,6 +500,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             x = x < nlast ? x : nlast;
             return use_dec ? dsrc[x >> dl] : sa.pre.PP[x];
         };
+        // Short steps (ps <= 4) take the grid from the series itself, 4 bytes per point read
+        // instead of a 16-byte prefix entry per grid point written and read again.  A group of 64
+        // grid intervals is summed relative to its own first point a_g in FP32 (a wave scan of
+        // small values), then shifted to the walk's anchor a (its first point) in FP64:
+        // sum (t - a) = sum (t - a_g) + c delta and sum (t - a)^2 = sum (t - a_g)^2
+        // + 2 delta sum (t - a_g) + c delta^2 over c points, delta = a_g - a.
+        const bool from_series = ps <= 4;
+        const float *T = a.T;
+        const int64_t n = a.n;
+        double anc = 0.0, run1 = 0.0, run2 = 0.0;
+        int64_t xnext = 0;
+        // prefix at grid points xnext + ps lane, then xnext moves to the next 64 grid points
+        auto grid_series = [&]() -> double2 {
+            const int64_t x0 = xnext + ps * lane;
+            float t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t x = x0 + u < n ? x0 + u : n - 1;   // points past the series serve idle lanes
+                t[u] = u < ps ? T[x] : 0.0f;
+            }
+            const float ag = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t[0])));   // a_g, lane 0's first point
+            float v1 = 0.0f, v2 = 0.0f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (u < ps) {
+                    const float d = t[u] - ag;
+                    v1 += d;
+                    v2 = fmaf(d, d, v2);
+                }
+            }
+            const float i1 = wave_scan_incl(v1), i2 = wave_scan_incl(v2);
+            const double e1 = (double)dpp_or_zero<0x138, 0xF>(i1), e2 = (double)dpp_or_zero<0x138, 0xF>(i2);
+            const double delta = (double)ag - anc, c = (double)(ps * lane);
+            const double2 r = make_double2(run1 + fma(c, delta, e1), run2 + fma(c * delta, delta, fma(2.0 * delta, e1, e2)));
+            const double s1 = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(i1), 63));
+            const double s2 = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(i2), 63));
+            const double cg = (double)(64 * ps);
+            run1 += fma(cg, delta, s1);
+            run2 += fma(cg * delta, delta, fma(2.0 * delta, s1, s2));
+            xnext += 64 * ps;
+            return r;
+        };
         const bool carry = quarter % (64 * ps) == 0;   // quarters are whole groups: the grid carries over
         double2 rlo = make_double2(0.0, 0.0), rhi = rlo;
         for (int j = 0; j < kScoreSamples; ++j) {
@@ -490,14 +550,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
           uint64_t best = ~0ull;
           if (first < last) {
           if (j == 0 || !carry) {
-              rlo = grid_raw(first + ps * lane);
-              rhi = grid_raw(first + ps * (lane + 64));
+              if (from_series) {
+                  anc = (double)T[first];
+                  run1 = run2 = 0.0;
+                  xnext = first;
+                  rlo = grid_series();
+                  rhi = grid_series();
+              } else {
+                  rlo = grid_raw(first + ps * lane);
+                  rhi = grid_raw(first + ps * (lane + 64));
+              }
           }
           for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
-            const double2 rnext = grid_raw(g0 + ps * (lane + 128));
+            const double2 rnext = from_series ? grid_series() : grid_raw(g0 + ps * (lane + 128));
             const int64_t b0 = g0 / kPB, e0 = (b0 + 1) * kPB;
             double2 gv[2] = {rlo, rhi};
-            if (g0 + 127 * ps >= e0) {   // (wave-uniform) some grid point lies past the block
+            if (!from_series && g0 + 127 * ps >= e0) {   // (wave-uniform) some grid point lies past the block
                 const double2 tb = sa.pre.tot[b0];
                 const double delta = sa.pre.anc[b0 + 1] - sa.pre.anc[b0];
 #pragma unroll
