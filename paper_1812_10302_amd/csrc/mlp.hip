@@ -457,7 +457,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     static_assert(kScoreSamples * 16 == 64, "one feature term per lane for all quarters of a block");
     __shared__ uint64_t winners[4][kScoreSamples];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t k0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * kScoreSamples;
+    // wave-uniform values are placed in scalar registers explicitly, so the walk below keeps its
+    // positions and loop control on the scalar unit
+    const int64_t k0 = uniform((((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * kScoreSamples);
     if (k0 >= R) return;
     const int64_t row = row0 + k0;   // rows of a block are consecutive and belong to one query
     int lo = 0, hi = a.nq;   // row_off[lo] <= row < row_off[hi]
@@ -467,9 +469,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         else hi = mid;
     }
     const int q = __builtin_amdgcn_readfirstlane(lo);
-    const int64_t local = row - sa.row_off[q];
+    const int64_t local = uniform(row - sa.row_off[q]);
     const BatchQ bq = a.bq[q];
     const int m = __builtin_amdgcn_readfirstlane(bq.m);
+    const int64_t qN = uniform(bq.N);
     const int64_t quarter = a.block / kScoreSamples;
     const int64_t bfirst = (local / kScoreSamples) * a.block;
     float qp[16];
@@ -511,24 +514,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         const int64_t n = a.n;
         double anc = 0.0, run1 = 0.0, run2 = 0.0;
         int64_t xnext = 0;
-        // prefix at grid points xnext + ps lane, then xnext moves to the next 64 grid points
-        auto grid_series = [&]() -> double2 {
-            const int64_t x0 = xnext + ps * lane;
-            float t[4];
+        // the series points of the 64 grid intervals from x (lane l: points x + ps l + u, u < ps),
+        // four loads per lane at 32-bit offsets from a uniform base, clamped to the last point of
+        // the series (clamped points only reach grid points past it, which serve idle lanes)
+        auto load_pts = [&](int64_t x, float (&t)[4]) {
+            const float *base = T + x;
+            const int64_t room = n - 1 - x;
+            const int lim = room < 0x7fffffff ? (int)room : 0x7fffffff;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int64_t x = x0 + u < n ? x0 + u : n - 1;   // points past the series serve idle lanes
-                t[u] = u < ps ? T[x] : 0.0f;
+                const int o = (int)ps * lane + u;
+                t[u] = base[o < lim ? o : lim];
             }
-            const float ag = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t[0])));   // a_g, lane 0's first point
+        };
+        // prefix at grid points xnext + ps lane from those points, then xnext moves on 64 points
+        auto grid_from = [&](const float (&t)[4]) -> double2 {
+            const float ag = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t[0])));   // a_g
             float v1 = 0.0f, v2 = 0.0f;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                if (u < ps) {
-                    const float d = t[u] - ag;
-                    v1 += d;
-                    v2 = fmaf(d, d, v2);
-                }
+                const float d = u < ps ? t[u] - ag : 0.0f;
+                v1 += d;
+                v2 = fmaf(d, d, v2);
             }
             const float i1 = wave_scan_incl(v1), i2 = wave_scan_incl(v2);
             const double e1 = (double)dpp_or_zero<0x138, 0xF>(i1), e2 = (double)dpp_or_zero<0x138, 0xF>(i2);
@@ -542,55 +549,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             xnext += 64 * ps;
             return r;
         };
+        float tp[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // points of the next grid group, loaded a group ahead
         const bool carry = quarter % (64 * ps) == 0;   // quarters are whole groups: the grid carries over
         double2 rlo = make_double2(0.0, 0.0), rhi = rlo;
         for (int j = 0; j < kScoreSamples; ++j) {
           const int64_t first = bfirst + j * quarter;
-          const int64_t last = first + quarter < bq.N ? first + quarter : bq.N;
+          const int64_t last = first + quarter < qN ? first + quarter : qN;
           uint64_t best = ~0ull;
           if (first < last) {
           if (j == 0 || !carry) {
               if (from_series) {
-                  anc = (double)T[first];
-                  run1 = run2 = 0.0;
                   xnext = first;
-                  rlo = grid_series();
-                  rhi = grid_series();
+                  float t0[4];
+                  load_pts(xnext, t0);
+                  anc = (double)__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t0[0])));
+                  run1 = run2 = 0.0;
+                  rlo = grid_from(t0);
+                  load_pts(xnext, t0);
+                  rhi = grid_from(t0);
+                  load_pts(xnext, tp);
               } else {
                   rlo = grid_raw(first + ps * lane);
                   rhi = grid_raw(first + ps * (lane + 64));
               }
           }
-          for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
-            const double2 rnext = from_series ? grid_series() : grid_raw(g0 + ps * (lane + 128));
-            const int64_t b0 = g0 / kPB, e0 = (b0 + 1) * kPB;
-            double2 gv[2] = {rlo, rhi};
-            if (!from_series && g0 + 127 * ps >= e0) {   // (wave-uniform) some grid point lies past the block
-                const double2 tb = sa.pre.tot[b0];
-                const double delta = sa.pre.anc[b0 + 1] - sa.pre.anc[b0];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    // re-anchor to the group's first block (a window ends at most one block later)
-                    const int64_t x = g0 + ps * (lane + 64 * h);
-                    const double2 p = h == 0 ? rlo : rhi;
-                    const bool cross = x >= e0;
-                    const double lx = (double)(x - e0);
-                    gv[h].x = cross ? tb.x + p.x + lx * delta : p.x;
-                    gv[h].y = cross ? tb.y + p.y + 2.0 * delta * p.x + lx * delta * delta : p.y;
-                }
-            }
-            rlo = rhi;
-            rhi = rnext;
-            gw[lane] = gv[0].x;
-            gw[lane + 64] = gv[1].x;
+          // PAA distance of the 64 sampled starts g0 + ps lane from the grid prefix at their
+          // window starts (g0v) and ends (g1v), both relative to one anchor
+          auto score_group = [&](int64_t g0, double2 g0v, double2 g1v) {
+            gw[lane] = g0v.x;
+            gw[lane + 64] = g1v.x;
             wave_sync();
             // segment sums starting at grid points lane and lane + 64 (the last four are unused)
-            dw[lane] = (float)(gw[lane + 4] - gv[0].x);
-            dw[lane + 64] = (float)(gw[(lane + 68) & 127] - gv[1].x);
+            dw[lane] = (float)(gw[lane + 4] - g0v.x);
+            dw[lane + 64] = (float)(gw[(lane + 68) & 127] - g1v.x);
             wave_sync();
             const int64_t i = g0 + lane * ps;
             if (i < last) {
-                const double md = (gv[1].x - gv[0].x) * inv_m, var = (gv[1].y - gv[0].y) * inv_m - md * md;
+                const double md = (g1v.x - g0v.x) * inv_m, var = (g1v.y - g0v.y) * inv_m - md * md;
                 const float inv = var > kSigmaFlat * kSigmaFlat ? rsqrtf((float)var) : 0.0f;
                 // PAA term t: (segment sum / segment length - mean) / sigma - query term
                 const float A = inv_seg * inv, C = (float)md * inv;
@@ -603,6 +598,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)i;
                 best = key < best ? key : best;
             }
+          };
+          if (from_series) {
+            for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
+              // take this group's points (loaded an iteration ago), then load the next group's
+              // into the carried registers
+              float tc[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) tc[u] = tp[u];
+              load_pts(xnext + 64 * ps, tp);
+              const double2 rnext = grid_from(tc);
+              const double2 g0v = rlo, g1v = rhi;
+              rlo = rhi;
+              rhi = rnext;
+              score_group(g0, g0v, g1v);
+            }
+          } else {
+            for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
+              const double2 rnext = grid_raw(g0 + ps * (lane + 128));
+              const int64_t b0 = g0 / kPB, e0 = (b0 + 1) * kPB;
+              double2 gv[2] = {rlo, rhi};
+              if (g0 + 127 * ps >= e0) {   // (wave-uniform) some grid point lies past the block
+                  const double2 tb = sa.pre.tot[b0];
+                  const double delta = sa.pre.anc[b0 + 1] - sa.pre.anc[b0];
+#pragma unroll
+                  for (int h = 0; h < 2; ++h) {
+                      // re-anchor to the group's first block (a window ends at most one block later)
+                      const int64_t x = g0 + ps * (lane + 64 * h);
+                      const double2 p = h == 0 ? rlo : rhi;
+                      const bool cross = x >= e0;
+                      const double lx = (double)(x - e0);
+                      gv[h].x = cross ? tb.x + p.x + lx * delta : p.x;
+                      gv[h].y = cross ? tb.y + p.y + 2.0 * delta * p.x + lx * delta * delta : p.y;
+                  }
+              }
+              rlo = rhi;
+              rhi = rnext;
+              score_group(g0, gv[0], gv[1]);
+            }
           }
           }
           best = wave_min_u64(best);
@@ -614,7 +647,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         for (int t = 0; t < 16; ++t) inv_len[t] = 1.0f / (float)((((t + 1) * m) >> 4) - ((t * m) >> 4));
         for (int j = 0; j < kScoreSamples; ++j) {
             const int64_t first = bfirst + j * quarter;
-            const int64_t last = first + quarter < bq.N ? first + quarter : bq.N;
+            const int64_t last = first + quarter < qN ? first + quarter : qN;
             uint64_t best = ~0ull;
             for (int64_t i = first + lane * ps; i < last; i += 64 * ps) {
                 float f[16];
@@ -636,7 +669,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     // features: lanes 16 j .. 16 j + 15 fill row k0 + j (term t = lane % 16 of both PAAs)
     const int j = lane >> 4, t = lane & 15;
     const uint64_t w = winners[wid][j];
-    const bool empty = bfirst + j * quarter >= bq.N;
+    const bool empty = bfirst + j * quarter >= qN;
     float *x = X + (k0 + j) * 32;
     const int64_t i = empty ? bfirst : (int64_t)(uint32_t)w;   // a valid start either way
     const float f = pv.paa_term(i, m, inv_m, t);
