@@ -3,8 +3,8 @@
 One step = the whole search path (window statistics, data envelope, bound cascade, banded DTW
 with the device best-so-far, FP64 certification) for every query of the workload, with the
 series already resident in HBM.  The timed path is the batched search with the learned block
-order (one graph replay per step), with two batches in flight by default: two library contexts,
-each replaying its graph on its own stream from its own host thread, so that one batch's
+order (one graph replay per step), with three batches in flight by default: three library
+contexts, each replaying its graph on its own stream from its own host thread, so that one batch's
 latency-bound phases overlap the other's streaming kernels (every step still runs the whole path
 on its batch; the rate with one batch in flight is reported beside it).  The plain per-query
 search and the batched search in series order are timed beside it.  The ordering network is trained before timing (seeded).  Default workload: float32 random walk of n = 1e8 points and
@@ -96,7 +96,7 @@ def main():
                     help="time only the batched search in learned order (profiling runs)")
     ap.add_argument("--schedule", default="",
                     help="comma-separated schedule fields (k=v) to use instead of the autotuner")
-    ap.add_argument("--inflight", type=int, default=2,
+    ap.add_argument("--inflight", type=int, default=3,
                     help="learned batches in flight: one library context, stream and host thread each")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, copy this many MiB on the device (HBM counter calibration)")
