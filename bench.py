@@ -265,14 +265,17 @@ def main():
         t_ms, nl = prof_total[dominant]
         if dominant == "lb":
             # per candidate the cascade must read its series point (4 B) and its window statistics:
-            # one (sum, sum of squares) prefix entry (16 B) or the three per-window values (12 B)
-            per_cand = 20 if schedule["stats_prefix"] else 16
+            # half a stored (sum, sum of squares) prefix entry (8 B: even entries only, an odd lane
+            # completes the even one before it with a point it reads anyway) or the three
+            # per-window values (12 B)
+            per_cand = 12 if schedule["stats_prefix"] else 16
             kernel = "k_lb_batch<%s, %s>" % ("true" if schedule["stats_prefix"] else "false",
                                               "true" if schedule["data_envelope"] else "false")
             units = lb_candidates
         elif dominant == "stats":
-            # blocked prefix: read 4 B, write 16 B per series point (one pass for the batch)
-            per_cand, kernel, units = 20, "k_prefix", wl.T.size
+            # blocked prefix: read 4 B, write 8 B per series point (a 16-byte entry at every
+            # second point; one pass for the batch)
+            per_cand, kernel, units = 12, "k_prefix", wl.T.size
         else:
             per_cand, kernel, units = None, f"class {dominant}", None
         if per_cand is not None:

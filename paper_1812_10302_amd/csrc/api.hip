@@ -348,7 +348,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         a.s = c->st_s;
         a.o = c->st_o;
     } else {
-        a.pre = Prefix{c->PP, c->anc, c->tot};
+        a.pre = Prefix{c->PP, c->anc, c->tot, T};
     }
     a.envU = c->data_envelope ? c->envU : nullptr;
     a.envL = c->data_envelope ? c->envL : nullptr;
@@ -433,9 +433,11 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         sa.sstart = c->sstart;
         sa.bstart = c->bstart;
         sa.row_off = c->row_off;
-        sa.pre = Prefix{c->PP, c->anc, c->tot};
+        sa.pre = Prefix{c->PP, c->anc, c->tot, T};
         sa.dec = c->dec;
         sa.dec_levels = p.dec_levels;
+        sa.kinds = 0;
+        for (int k = 0; k < nq; ++k) sa.kinds |= c->h_bq[k].m % 64 == 0 ? 1u : 2u;
         sa.total_rows = p.score_rows;
         HIPCHK(c, hipMemcpyAsync(c->row_off, c->h_row_off, sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, s));
         HIPCHK(c, mlp_order_blocks(c->mlp, a, sa, s));
@@ -963,9 +965,10 @@ DTWS_API int dtws_propose(dtws_ctx *c, const float *T, int64_t n, const float *Q
     sa.qpaa = c->qpaa;
     sa.sstart = c->sstart;
     sa.row_off = c->row_off;
-    sa.pre = Prefix{c->PP, c->anc, c->tot};
+    sa.pre = Prefix{c->PP, c->anc, c->tot, T};
     sa.dec = c->dec;
     sa.dec_levels = dec_level_of(m);
+    sa.kinds = m % 64 == 0 ? 1u : 2u;
     HIPCHK(c, launch_propose(a, sa, X, starts, s));
     // the staging entries are read by the copies above before the call returns
     HIPCHK(c, hipStreamSynchronize(s));

@@ -32,7 +32,7 @@ __device__ inline uint64_t splitmix64_d(uint64_t x) {
 // One workgroup per block of kPB points: each thread scans 16 consecutive points in FP64, the
 // workgroup scans the thread totals, and the results leave through LDS in two halves so that the
 // stores are coalesced.
-__global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restrict__ T, int64_t n, double2 *PP,
+__global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restrict__ T, int64_t n, double2 *PPe,
                                                            double *anc, double2 *tot, Decimated dec,
                                                            uint32_t levels) {
     constexpr int kHalf = kPB / 2, kPad = 16 + 1;           // 16 entries per thread, one spare
@@ -85,9 +85,11 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
             for (int u = 0; u < 16; ++u) stage[owner * kPad + u] = make_double2(b1 + v1[u], b2 + v2[u]);
         }
         __syncthreads();
-        for (int e = tid; e < kHalf; e += kPrefixThreads) {
+        // even entries only (consecutive threads write consecutive entries)
+        for (int e2 = tid; e2 < kHalf / 2; e2 += kPrefixThreads) {
+            const int e = 2 * e2;
             const int64_t x = (int64_t)h * kHalf + e;
-            if (x < lim) PP[x0 + x] = stage[(e >> 4) * kPad + (e & 15)];
+            if (x < lim) PPe[(x0 + x) >> 1] = stage[(e >> 4) * kPad + (e & 15)];
         }
         // decimated copies: consecutive threads write consecutive entries of each level
         for (int L = kDecFirst; L < kDecLevels; ++L) {
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
             anc[b + 1] = a;
             tot[b + 1] = make_double2(0.0, 0.0);
             if (x0 + kPB == n) {
-                PP[n] = make_double2(0.0, 0.0);
+                PPe[n >> 1] = make_double2(0.0, 0.0);   // n is even here
                 for (int L = kDecFirst; L < kDecLevels; ++L)
                     if (((levels >> L) & 1u) && (n & ((1 << L) - 1)) == 0) dec.lv[L][n >> L] = make_double2(0.0, 0.0);
             }
@@ -269,7 +271,9 @@ struct ItemSource {
 };
 
 template <bool PREFIX, bool ENV>
-__global__ __launch_bounds__(256) void k_lb_batch(BatchArgs a, int round, int rank_lo, int rank_hi, int parts, int natural) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_lb_batch(BatchArgs a, int round,
+                                                                                     int rank_lo, int rank_hi, int parts,
+                                                                                     int natural) {
     __shared__ WaveQueue q1s[4];
     __shared__ WaveQueue2 q2s[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;

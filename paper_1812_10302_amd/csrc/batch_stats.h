@@ -18,7 +18,7 @@ struct StatsPrefix {
     // (m <= 2048 < kPB: the window ends in its first block or the next; branch free, the lookups
     // past the last block hit sentinels).
     __device__ void sums(int64_t i, double &a0, double &S1, double &S2) const {
-        sums_from(i, pre.PP[i], pre.PP[i + m], a0, S1, S2);
+        sums_from(i, pre.at(i), pre.at(i + m), a0, S1, S2);
     }
     // The same for a group of 64 consecutive windows that share the block b0 of their starts and
     // whether they end past it (both wave-uniform: m and the group start are multiples of 64 and

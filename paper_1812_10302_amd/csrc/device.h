@@ -209,6 +209,12 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
     bool citem = false, cfresh = true;
     double2 ccarry[2];
     ccarry[0] = ccarry[1] = make_double2(0.0, 0.0);
+    // loads of the chain walk's next step, issued one step ahead (valid while cnext is set)
+    bool cnext = false;
+    double2 npe[2];
+    float nc0[2], ncl[2];
+    npe[0] = npe[1] = make_double2(0.0, 0.0);
+    nc0[0] = nc0[1] = ncl[0] = ncl[1] = 0.0f;
     for (;;) {
         if (t2 - h2 >= 64u || (done && t2 != h2)) {
             int32_t i = 0;
@@ -277,34 +283,92 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
                     const bool two = cj + 1 < cJ;
                     // the two groups are addressed from scalar bases with 32-bit lane offsets; idle
                     // lanes (past the item end, or no second chain) read the group's first start
-                    const int64_t span = clast - cg;
-                    const uint32_t lim = span < 128 ? (uint32_t)span : 128u;
-                    const double2 *P0 = stats.pre.PP + cg, *PE = P0 + m;
-                    const float *T0 = T + cg, *TL = T0 + (m - 1);
+                    auto lane_offsets = [&](int64_t g, bool tw, uint32_t (&off)[2], bool (&valid)[2]) {
+                        const int64_t span = clast - g;
+                        const uint32_t lim = span < 128 ? (uint32_t)span : 128u;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const uint32_t o = 64u * h + (uint32_t)lane;
+                            valid[h] = (h == 0 || tw) && o < lim;
+                            off[h] = valid[h] ? o : 0u;
+                        }
+                    };
+                    // stored (even) prefix entries of the window ends and the series points at
+                    // the window starts and ends of the step at g (g and m are even), into the
+                    // registers of the step loaded ahead
+                    auto load_step = [&](int64_t g, bool tw) {
+                        uint32_t o[2];
+                        bool v[2];
+                        lane_offsets(g, tw, o, v);
+                        const double2 *PE = stats.pre.PPe + ((g + m) >> 1);
+                        const float *Tg = T + g, *TLg = Tg + (m - 1);
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            npe[h] = PE[o[h] >> 1];
+                            nc0[h] = Tg[o[h]];
+                            ncl[h] = TLg[o[h]];
+                        }
+                    };
                     uint32_t off[2];
                     bool valid[2];
+                    lane_offsets(cg, two, off, valid);
+                    if (!cnext) load_step(cg, two);   // an item's first step: nothing was loaded ahead
                     double2 pe[2];
                     float c0v[2], clv[2];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const uint32_t o = 64u * h + (uint32_t)lane;
-                        valid[h] = (h == 0 || two) && o < lim;
-                        off[h] = valid[h] ? o : 0u;
-                        pe[h] = PE[off[h]];
-                        c0v[h] = T0[off[h]];
-                        clv[h] = TL[off[h]];
+                        pe[h] = npe[h];
+                        c0v[h] = nc0[h];
+                        clv[h] = ncl[h];
                     }
+                    // the next step's loads go out before this step's work, unconditionally (a
+                    // load under a branch makes every later wait count it): the chain pair's next
+                    // step, else the next pair's first step, else (the item ends) this step again
+                    {
+                        int64_t gn = cg + m;
+                        bool twn = two;
+                        cnext = gn < clast;
+                        if (!cnext) {
+                            const int cjn = cj + (two ? 2 : 1);
+                            gn = cf + 64 * cjn;
+                            twn = cjn + 1 < cJ;
+                            cnext = cjn < cJ && gn < clast;
+                            if (!cnext) {
+                                gn = cg;
+                                twn = two;
+                            }
+                        }
+                        load_step(uniform(gn), twn);
+                    }
+                    const double2 *P0 = stats.pre.PPe + (cg >> 1);
+                    const float *T0 = T + cg;
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const double2 p0 = cfresh ? P0[off[h]] : ccarry[h];
-                        ccarry[h] = pe[h];
                         // block of the group's starts and whether its windows end past it: the
                         // same for all 64 lanes (scalar); idle lanes' values are never used
                         const int64_t gs = cg + 64 * h;
                         const int64_t b0 = gs >> kPBShift, e0 = (b0 + 1) << kPBShift;
                         const bool cross = gs + m >= e0;
+                        // odd lanes (odd starts and ends) complete their prefix entries with the
+                        // point before: the window's last point at the end (already loaded), the
+                        // point before the start at a chain start
+                        const bool odd = (off[h] & 1u) != 0;
+                        double2 pev = pe[h];
+                        {
+                            const double d = odd ? (double)clv[h] - ldc(stats.pre.anc + (cross ? b0 + 1 : b0)) : 0.0;
+                            pev.x += d;
+                            pev.y = fma(d, d, pev.y);
+                        }
+                        double2 p0 = ccarry[h];
+                        if (cfresh) {
+                            p0 = P0[off[h] >> 1];
+                            const double d = odd ? (double)T0[off[h] & ~1u] - ldc(stats.pre.anc + b0) : 0.0;
+                            p0.x += d;
+                            p0.y = fma(d, d, p0.y);
+                        }
+                        ccarry[h] = pev;
                         double a0, S1, S2;
-                        stats.sums_group(b0, cross, (int)(gs + m - e0) + lane, p0, pe[h], a0, S1, S2);
+                        stats.sums_group(b0, cross, (int)(gs + m - e0) + lane, p0, pev, a0, S1, S2);
                         float mu = 0.0f, s = 0.0f, o = 0.0f;
                         if (valid[h]) stats.finish(cg + off[h], a0, S1, S2, mu, s, o);
                         const float d0 = q0 - fmaf(c0v[h] - mu, s, o), dl = ql - fmaf(clv[h] - mu, s, o);

@@ -44,14 +44,29 @@ struct QueryBufs {
 };
 
 
+constexpr int kPBShift = 12;
+constexpr int kPB = 1 << kPBShift;       // blocked prefix: block length (points)
+
 // Blocked prefix of the series: blocks of kPB points, anchor anc[b] = T[b * kPB]; for x in block b,
 // PP[x] = (sum, sum of squares) of (T[y] - anc[b]) over [b * kPB, x) and tot[b] the same over the
-// whole block.  One entry past the last block (anchor repeated, zero sums) and PP[n] exist, so
+// whole block.  Only the even entries are stored, PPe[k] = PP[2 k]: an odd entry is the even one
+// before it plus the single point between them (an odd x never starts a block, so that point has
+// x's anchor).  One entry past the last block (anchor repeated, zero sums) and PP[n] exist, so
 // readers may touch them without a test.
 struct Prefix {
-    const double2 *PP;
+    const double2 *PPe;
     const double *anc;
     const double2 *tot;
+    const float *T;   // the series the prefix was built from
+    __device__ double2 at(int64_t x) const {
+        double2 e = PPe[x >> 1];
+        if (x & 1) {
+            const double d = (double)T[x - 1] - anc[x >> kPBShift];
+            e.x += d;
+            e.y = fma(d, d, e.y);
+        }
+        return e;
+    }
 };
 
 // Decimated copies of the prefix for the proposals of the learned order: lv[L][k] = PP[k << L],
@@ -189,8 +204,6 @@ constexpr int kScoreSamples = 4;         // proposals scored per block (one per 
 constexpr int kSeedCands = 64;           // best-scored proposals per query that seed the best-so-far (one wave)
 constexpr int kColsumGroups = 128;       // row groups of the bias-gradient reduction
 constexpr int64_t kMaxTrainRows = 1 << 16;  // rows per gradient / training step
-constexpr int kPBShift = 12;
-constexpr int kPB = 1 << kPBShift;       // blocked prefix: block length (points)
 
 struct MlpBufs {
     float *theta, *grad, *adam_m, *adam_v;   // FP32 master parameters, gradient, Adam moments
@@ -213,6 +226,7 @@ struct ScoreArgs {
     Prefix pre;                // blocked prefix of the series
     Decimated dec;             // its decimated copies
     uint32_t dec_levels;       // bit L set: dec.lv[L] holds the current series
+    uint32_t kinds;            // bit 0: some query length is a multiple of 64, bit 1: some is not
 };
 
 // ---------------------------------------------------------------- launchers (stream-ordered)

@@ -374,7 +374,7 @@ struct PrefixView {
         const double2 t = pre.tot[b0];
         double2 p[17];
 #pragma unroll
-        for (int k = 0; k <= 16; ++k) p[k] = pre.PP[i + ((k * m) >> 4)];
+        for (int k = 0; k <= 16; ++k) p[k] = pre.at(i + ((k * m) >> 4));
         // sums relative to anc[b0] from the block start to x: P(x) in block b0, else the whole
         // block b0 plus P(x) re-anchored
         double g[17];
@@ -403,7 +403,7 @@ struct PrefixView {
         double gx[4], gy[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double2 p = pre.PP[xs[k]];
+            const double2 p = pre.at(xs[k]);
             const double lx = (double)(xs[k] - e0);
             const bool cross = xs[k] >= e0;
             gx[k] = cross ? tt.x + p.x + lx * delta : p.x;
@@ -451,9 +451,13 @@ __device__ __forceinline__ float wave_scan_incl(float x) {
 // features.  One wave takes the K rows of a block: it walks the quarters in turn (the prefix grid
 // of the fast path carries over from one quarter to the next when a quarter is a whole number of
 // groups), keeps each quarter's winner in LDS, and computes the K feature rows together at the end.
-// (five waves per SIMD: the grid loads and LDS round trips of a group are latency-bound)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_propose(const BatchArgs a, const ScoreArgs sa, int64_t row0, int64_t R,
-                                                 float *X) {
+// GRID selects the rows this instance serves: those of queries whose length is a multiple of 64
+// (the grid path) or the others (general path); the two are separate instances so that each gets
+// its own register allocation: five waves per SIMD for the grid path (the grid loads and LDS round
+// trips of a group are latency-bound), no cap for the general path (17 prefix lookups per start).
+template <bool GRID>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 5 : 1))) void k_propose(const BatchArgs a, const ScoreArgs sa,
+                                                                                       int64_t row0, int64_t R, float *X) {
     static_assert(kScoreSamples * 16 == 64, "one feature term per lane for all quarters of a block");
     __shared__ uint64_t winners[4][kScoreSamples];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -481,7 +485,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const double inv_m = 1.0 / m;
     const PrefixView pv{sa.pre};
     const int64_t ps = m >= 128 ? m >> 6 : 1;
-    if ((m & 63) == 0) {
+    if (((m & 63) == 0) != GRID) return;   // (wave-uniform) rows of the other instance
+    if constexpr (GRID) {
         // m = 64 ps: the sampled starts and every segment boundary lie on the grid of step ps, so
         // the 64 starts of a group need the prefix at 128 grid points only (re-anchored to the
         // block of the group's first start).  Lane l holds grid points l and l + 64, the start and
@@ -501,7 +506,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         // next group's upper half is loaded one group ahead
         auto grid_raw = [&](int64_t x) -> double2 {
             x = x < nlast ? x : nlast;
-            return use_dec ? dsrc[x >> dl] : sa.pre.PP[x];
+            return use_dec ? dsrc[x >> dl] : sa.pre.at(x);
         };
         // Short steps (ps <= 4) take the grid from the series itself, 4 bytes per point read
         // instead of a 16-byte prefix entry per grid point written and read again.  A group of 64
@@ -614,8 +619,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
               score_group(g0, g0v, g1v);
             }
           } else {
-            for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
-              const double2 rnext = grid_raw(g0 + ps * (lane + 128));
+            // grid from the prefix: re-anchor the grid points past the block of the group's first
+            // start (a window ends at most one block later), then score
+            auto prefix_group = [&](int64_t g0, double2 rnext) {
               const int64_t b0 = g0 / kPB, e0 = (b0 + 1) * kPB;
               double2 gv[2] = {rlo, rhi};
               if (g0 + 127 * ps >= e0) {   // (wave-uniform) some grid point lies past the block
@@ -623,7 +629,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                   const double delta = sa.pre.anc[b0 + 1] - sa.pre.anc[b0];
 #pragma unroll
                   for (int h = 0; h < 2; ++h) {
-                      // re-anchor to the group's first block (a window ends at most one block later)
                       const int64_t x = g0 + ps * (lane + 64 * h);
                       const double2 p = h == 0 ? rlo : rhi;
                       const bool cross = x >= e0;
@@ -635,6 +640,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
               rlo = rhi;
               rhi = rnext;
               score_group(g0, gv[0], gv[1]);
+            };
+            // (separate loops: the decimated copy is a plain load, the full prefix may need the
+            // point before an odd grid position)
+            if (use_dec) {
+              for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
+                int64_t x = g0 + ps * (lane + 128);
+                x = x < nlast ? x : nlast;
+                prefix_group(g0, dsrc[x >> dl]);
+              }
+            } else {
+              for (int64_t g0 = first; g0 < last; g0 += 64 * ps) {
+                int64_t x = g0 + ps * (lane + 128);
+                x = x < nlast ? x : nlast;
+                prefix_group(g0, sa.pre.at(x));
+              }
             }
           }
           }
@@ -883,7 +903,10 @@ hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArg
     const int64_t chunk = kMlpChunk / sa.K * sa.K;
     for (int64_t r0 = 0; r0 < sa.total_rows; r0 += chunk) {
         const int64_t R = sa.total_rows - r0 < chunk ? sa.total_rows - r0 : chunk;
-        hipLaunchKernelGGL(k_propose, dim3(nblk(R / kScoreSamples * 64)), dim3(256), 0, s, a, sa, r0, R, b.Xf);
+        if (sa.kinds & 1u)
+            hipLaunchKernelGGL(k_propose<true>, dim3(nblk(R / kScoreSamples * 64)), dim3(256), 0, s, a, sa, r0, R, b.Xf);
+        if (sa.kinds & 2u)
+            hipLaunchKernelGGL(k_propose<false>, dim3(nblk(R / kScoreSamples * 64)), dim3(256), 0, s, a, sa, r0, R, b.Xf);
         hipError_t e = mlp_forward(b, b.Xf, R, b.y, false, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_block_min, dim3(nblk(R / sa.K)), dim3(256), 0, s, b.y, sa.sstart, R, sa.K, r0, sa.score,
@@ -904,7 +927,12 @@ hipError_t launch_propose(const BatchArgs &a, const ScoreArgs &sa, float *X, int
     hipLaunchKernelGGL(k_query_paa, dim3(a.nq), dim3(64), 0, s, a, sa.qpaa);
     for (int64_t r0 = 0; r0 < sa.total_rows; r0 += kMlpChunk) {
         const int64_t R = sa.total_rows - r0 < kMlpChunk ? sa.total_rows - r0 : kMlpChunk;
-        hipLaunchKernelGGL(k_propose, dim3(nblk(R / kScoreSamples * 64)), dim3(256), 0, s, a, sa, r0, R, X + r0 * 32);
+        if (sa.kinds & 1u)
+            hipLaunchKernelGGL(k_propose<true>, dim3(nblk(R / kScoreSamples * 64)), dim3(256), 0, s, a, sa, r0, R,
+                               X + r0 * 32);
+        if (sa.kinds & 2u)
+            hipLaunchKernelGGL(k_propose<false>, dim3(nblk(R / kScoreSamples * 64)), dim3(256), 0, s, a, sa, r0, R,
+                               X + r0 * 32);
         hipLaunchKernelGGL(k_widen_starts, dim3(nblk(R)), dim3(256), 0, s, sa.sstart, R, starts + r0);
     }
     return hipGetLastError();
