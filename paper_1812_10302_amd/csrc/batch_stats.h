@@ -22,14 +22,13 @@ struct StatsPrefix {
     }
     // The same for a group of 64 consecutive windows that share the block b0 of their starts and
     // whether they end past it (both wave-uniform: m and the group start are multiples of 64 and
-    // kPB is a multiple of 64); el = e - (b0 + 1) kPB for this lane's window end e.
-    __device__ void sums_group(int64_t b0, bool cross, int el, double2 p0, double2 pe, double &a0,
+    // kPB is a multiple of 64); el = e - (b0 + 1) kPB for this lane's window end e.  The block's
+    // anchor a_lo = anc[b0], the next one a_hi = anc[b0 + 1] and the block totals t = tot[b0] are
+    // passed in (the caller loads them for both groups of a step together).
+    __device__ void sums_group(bool cross, int el, double2 p0, double2 pe, double a_lo, double a_hi, double2 t,
                                double &S1, double &S2) const {
-        a0 = ldc(pre.anc + b0);
         if (cross) {
-            const double *tb = (const double *)(pre.tot + b0);
-            const double2 t = make_double2(ldc(tb), ldc(tb + 1));
-            const double delta = ldc(pre.anc + b0 + 1) - a0;
+            const double delta = a_hi - a_lo;
             const double c2 = (double)el;
             S1 = (t.x - p0.x) + pe.x + c2 * delta;
             S2 = (t.y - p0.y) + pe.y + 2.0 * delta * pe.x + c2 * delta * delta;

@@ -342,6 +342,18 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
                     }
                     const double2 *P0 = stats.pre.PPe + (cg >> 1);
                     const float *T0 = T + cg;
+                    // anchors and totals of the blocks of both groups' starts (scalar loads, issued
+                    // together; the entry past the last block exists)
+                    double alo[2], ahi[2];
+                    double2 tbk[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int64_t b0 = (cg + 64 * h) >> kPBShift;
+                        const double *tb = (const double *)(stats.pre.tot + b0);
+                        alo[h] = ldc(stats.pre.anc + b0);
+                        ahi[h] = ldc(stats.pre.anc + b0 + 1);
+                        tbk[h] = make_double2(ldc(tb), ldc(tb + 1));
+                    }
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         // block of the group's starts and whether its windows end past it: the
@@ -353,22 +365,24 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
                         // point before: the window's last point at the end (already loaded), the
                         // point before the start at a chain start
                         const bool odd = (off[h] & 1u) != 0;
+                        const double aend = cross ? ahi[h] : alo[h];
                         double2 pev = pe[h];
                         {
-                            const double d = odd ? (double)clv[h] - ldc(stats.pre.anc + (cross ? b0 + 1 : b0)) : 0.0;
+                            const double d = odd ? (double)clv[h] - aend : 0.0;
                             pev.x += d;
                             pev.y = fma(d, d, pev.y);
                         }
                         double2 p0 = ccarry[h];
                         if (cfresh) {
                             p0 = P0[off[h] >> 1];
-                            const double d = odd ? (double)T0[off[h] & ~1u] - ldc(stats.pre.anc + b0) : 0.0;
+                            const double d = odd ? (double)T0[off[h] & ~1u] - alo[h] : 0.0;
                             p0.x += d;
                             p0.y = fma(d, d, p0.y);
                         }
                         ccarry[h] = pev;
-                        double a0, S1, S2;
-                        stats.sums_group(b0, cross, (int)(gs + m - e0) + lane, p0, pev, a0, S1, S2);
+                        const double a0 = alo[h];
+                        double S1, S2;
+                        stats.sums_group(cross, (int)(gs + m - e0) + lane, p0, pev, alo[h], ahi[h], tbk[h], S1, S2);
                         float mu = 0.0f, s = 0.0f, o = 0.0f;
                         if (valid[h]) stats.finish(cg + off[h], a0, S1, S2, mu, s, o);
                         const float d0 = q0 - fmaf(c0v[h] - mu, s, o), dl = ql - fmaf(clv[h] - mu, s, o);

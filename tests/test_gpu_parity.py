@@ -246,6 +246,20 @@ def test_batch_mixed_lengths_and_bands(ctx, casc):
     _check_batch(got, _cascade_refs(casc, T, qs, rs))
 
 
+@pytest.mark.parametrize("n", [1 << 18, (1 << 18) + 1])
+def test_batch_prefix_matches_at_series_end(ctx, casc, n):
+    """Different m per query, each cut from the very end of the series, so the best window ends at
+    n: the prefix entry at n (the sentinel after the last block when n is a whole number of blocks,
+    an odd entry completed from the last point otherwise) decides the statistics of the match."""
+    T = W.random_walk(n, 37)
+    specs = [(64, 3), (128, 6), (130, 7), (200, 10), (512, 25), (1024, 51)]
+    qs = [W.noisy_cut(T, n - m, m, 0.02, 1_000 + k) for k, (m, _) in enumerate(specs)]
+    rs = [r for _, r in specs]
+    got = ctx.search_batch(dev(T), [dev(q) for q in qs], rs)
+    _check_batch(got, _cascade_refs(casc, T, qs, rs))
+    assert [i for i, _ in got] == [n - m for m, _ in specs]
+
+
 def test_batch_shared_length(ctx, casc):
     """All queries of one length: per-window statistics arrays shared by the batch."""
     T = W.random_walk(300_000, 32)
