@@ -260,6 +260,44 @@ def test_batch_prefix_matches_at_series_end(ctx, casc, n):
     assert [i for i, _ in got] == [n - m for m, _ in specs]
 
 
+def test_batch_contexts_in_flight_from_threads(casc):
+    """Several batches in flight: two contexts, each searched repeatedly from its own host thread
+    (each replays its own graph on its own stream), agree with the oracle on every call."""
+    import threading
+    T = W.random_walk(300_001, 38)
+    specs = [(64, 3), (128, 6), (200, 10), (512, 25)]
+    qs = [W.noisy_cut(T, 17_000 + 61_000 * k, m, 0.1, 1_100 + k) for k, (m, _) in enumerate(specs)]
+    rs = [r for _, r in specs]
+    ref = _cascade_refs(casc, T, qs, rs)
+    Td = dev(T)
+    pq = dtws.PackedQueries([dev(q) for q in qs])
+    ctxs = [dtws.Context(0, max_n=T.size, max_m=512, max_queries=len(qs)) for _ in range(2)]
+    outs = [[] for _ in ctxs]
+    errors = []
+
+    def work(k):
+        try:
+            for _ in range(4):
+                outs[k].append(ctxs[k].search_batch(Td, pq, rs, flags=dtws.ORDER_NATURAL, seed=7))
+        except Exception as e:   # reported below; the thread itself must not raise
+            errors.append(e)
+
+    try:
+        threads = [threading.Thread(target=work, args=(k,)) for k in range(len(ctxs))]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        assert not errors, errors
+        for got_list in outs:
+            assert len(got_list) == 4
+            for got in got_list:
+                _check_batch(got, ref)
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def test_batch_shared_length(ctx, casc):
     """All queries of one length: per-window statistics arrays shared by the batch."""
     T = W.random_walk(300_000, 32)
