@@ -206,12 +206,14 @@ typedef struct {
                                   unit, 1..64 (4) */
     int32_t diag_max;          /* a DTW round with at most this many candidates runs one
                                   wave per candidate along anti-diagonals instead of one
-                                  lane per candidate (bands r <= 255; 0 = never; 16384).
-                                  Bands 112 <= r <= 255 always run one wave per candidate */
+                                  lane per candidate (bands r <= 1023; 0 = never; 16384).
+                                  Bands 112 <= r <= 1023 always run one wave per candidate;
+                                  wider bands run one lane per candidate with its rows in
+                                  global memory */
     int32_t band_lanes;        /* dtws_dtw_band: 0 = automatic (default: one wave per
-                                  candidate for r <= 255 when count <= diag_max or r >= 112,
+                                  candidate for r <= 1023 when count <= diag_max or r >= 112,
                                   else one lane), 1 = one lane per candidate, 64 = one wave
-                                  per candidate (r <= 255) */
+                                  per candidate (r <= 1023) */
     int32_t stats_prefix;      /* batched search, window statistics: 0 = per-length arrays
                                   when the batch has few distinct lengths (default), 1 =
                                   always from the blocked prefix of the series */

@@ -462,7 +462,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         }
         if (a.diag_max > 0 || a.diag_wide) {
             PROF(DTWS_K_DTW);
-            HIPCHK(c, launch_dtw_diag(a, !same_m, c->num_cu * 4, s));
+            HIPCHK(c, launch_dtw_diag(a, !same_m, p.max_r, c->num_cu * 4, s));
         }
         return DTWS_OK;
     };

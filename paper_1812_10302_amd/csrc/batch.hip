@@ -730,7 +730,7 @@ hipError_t launch_dtw_bucket(const BatchArgs &a, bool prefix, int nc, int blocks
 hipError_t launch_cert_batch(const BatchArgs &a, int max_m, int max_r, hipStream_t s) {
     hipLaunchKernelGGL(k_cert_select_batch, dim3(16), dim3(256), 0, s, a);
     if (max_r <= kDiagMaxBand) {
-        hipError_t e = launch_cert_diag(a, 256, s);
+        hipError_t e = launch_cert_diag(a, max_r, 256, s);
         if (e != hipSuccess) return e;
     } else {
         const size_t shm = sizeof(double) * (2 * (size_t)max_m + 3 * (size_t)(max_r + 4));

@@ -17,10 +17,16 @@
 
 namespace dtws {
 
-constexpr int kDiagMaxCpl = 4;            // bands up to r = 255
-constexpr int kDiagPadQLo = 129, kDiagPadQHi = 64 * kDiagMaxCpl + 2;
-constexpr int kDiagPadCLo = 64 * kDiagMaxCpl, kDiagPadCHi = 130;
-constexpr int kDiagPad = kDiagPadQLo + kDiagPadQHi + kDiagPadCLo + kDiagPadCHi;
+// Kernel instances by the most slot registers per lane they serve (MAXCPL): 4 for bands up to
+// r = 255, 16 for bands up to r = 1023.  Pads around the staged arrays, for r < 64 MAXCPL: the
+// first diagonals read the query down to index -(r + 1) / 2 and the candidate down to -64 MAXCPL;
+// the last ones read the query up to m + 64 MAXCPL and the candidate up to m + r / 2 + 1.
+template <int MAXCPL>
+struct DiagPads {
+    static constexpr int QLo = 32 * MAXCPL + 1, QHi = 64 * MAXCPL + 2;
+    static constexpr int CLo = 64 * MAXCPL, CHi = 32 * MAXCPL + 2;
+    static constexpr int All = QLo + QHi + CLo + CHi;
+};
 
 template <typename F> struct DiagTraits;
 template <> struct DiagTraits<float> {
@@ -191,9 +197,17 @@ __device__ inline unsigned long long band_cells_upto(int m, int r, long long dl)
     return wave_add_u64(n);
 }
 
-template <int CPL, bool ABANDON, typename F>
+// The diagonal loop for the band's slot registers per lane, cpl = r / 64 + 1, rounded up to an
+// instantiated count (extra slots lie outside the band and stay infinite).
+template <int MAXCPL, bool ABANDON, typename F>
 __device__ F diag_dispatch(int cpl, const F *qb, const F *cb, int m, int r, const uint64_t *key, float thr0,
                            bool &alive, int &pairs) {
+    if constexpr (MAXCPL > 4) {
+        if (cpl > 12) return diag_dtw<16, ABANDON>(qb, cb, m, r, key, thr0, alive, pairs);
+        if (cpl > 8) return diag_dtw<12, ABANDON>(qb, cb, m, r, key, thr0, alive, pairs);
+        if (cpl > 6) return diag_dtw<8, ABANDON>(qb, cb, m, r, key, thr0, alive, pairs);
+        if (cpl > 4) return diag_dtw<6, ABANDON>(qb, cb, m, r, key, thr0, alive, pairs);
+    }
     switch (cpl) {
     case 1: return diag_dtw<1, ABANDON>(qb, cb, m, r, key, thr0, alive, pairs);
     case 2: return diag_dtw<2, ABANDON>(qb, cb, m, r, key, thr0, alive, pairs);
@@ -203,24 +217,26 @@ __device__ F diag_dispatch(int cpl, const F *qb, const F *cb, int m, int r, cons
 }
 
 // Pads around the staged arrays: query +big, candidate -big.
-template <typename F>
+template <int MAXCPL, typename F>
 __device__ inline void stage_pads(F *qb, F *cb, int m) {
+    using P = DiagPads<MAXCPL>;
     const int lane = threadIdx.x & 63;
     const F big = DiagTraits<F>::big;
-    for (int x = lane; x < kDiagPadQLo; x += 64) qb[x - kDiagPadQLo] = big;
-    for (int x = lane; x < kDiagPadQHi; x += 64) qb[m + x] = big;
-    for (int x = lane; x < kDiagPadCLo; x += 64) cb[x - kDiagPadCLo] = -big;
-    for (int x = lane; x < kDiagPadCHi; x += 64) cb[m + x] = -big;
+    for (int x = lane; x < P::QLo; x += 64) qb[x - P::QLo] = big;
+    for (int x = lane; x < P::QHi; x += 64) qb[m + x] = big;
+    for (int x = lane; x < P::CLo; x += 64) cb[x - P::CLo] = -big;
+    for (int x = lane; x < P::CHi; x += 64) cb[m + x] = -big;
 }
 
 // Batched search, latency schedule: one wave per survivor of the round's list, used when the round
 // has at most a.diag_max survivors (the lane-per-candidate kernels exit in that case).
-template <bool PREFIX>
+template <bool PREFIX, int MAXCPL>
 __global__ __launch_bounds__(128) void k_dtw_diag(BatchArgs a) {
+    using P = DiagPads<MAXCPL>;
     extern __shared__ float lds_f[];
     if (*a.overflow) return;
     const uint32_t count = *a.surv_count;
-    // small rounds: every survivor here; large rounds: only the wide-band bucket (112 <= r <= 255),
+    // small rounds: every survivor here; large rounds: only the wide-band bucket (112 <= r <= 1023),
     // read from its sorted segments, the other buckets go to the lane-per-candidate kernels
     const bool all = count <= a.diag_max;
     if (!all && !a.diag_wide) return;
@@ -230,8 +246,8 @@ __global__ __launch_bounds__(128) void k_dtw_diag(BatchArgs a) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    float *qb = lds_f + (int64_t)wid * (2 * a.max_m + kDiagPad) + kDiagPadQLo;
-    float *cb = qb + a.max_m + kDiagPadQHi + kDiagPadCLo;
+    float *qb = lds_f + (int64_t)wid * (2 * a.max_m + P::All) + P::QLo;
+    float *cb = qb + a.max_m + P::QHi + P::CLo;
     unsigned long long n_started = 0, n_aband = 0, n_cells = 0, n_lane_cells = 0;
     for (int64_t g = glo + wave; g < ghi; g += nwaves) {
         // wave-uniform values in scalar registers keep the diagonal loop uniform
@@ -262,12 +278,12 @@ __global__ __launch_bounds__(128) void k_dtw_diag(BatchArgs a) {
             qb[x] = qh[x];
             cb[x] = fmaf(Tp[x] - mu, s, o);
         }
-        stage_pads(qb, cb, m);
+        stage_pads<MAXCPL>(qb, cb, m);
         wave_sync();
         const int cpl = (r >> 6) + 1;
         bool alive;
         int pairs;
-        const float D = diag_dispatch<kDiagMaxCpl, true>(cpl, qb, cb, m, r, a.keys + q, INFINITY, alive, pairs);
+        const float D = diag_dispatch<MAXCPL, true>(cpl, qb, cb, m, r, a.keys + q, INFINITY, alive, pairs);
         ++n_started;
         n_lane_cells += (unsigned long long)pairs * 2 * 64 * cpl;
         if (!alive) ++n_aband;
@@ -292,13 +308,15 @@ __global__ __launch_bounds__(128) void k_dtw_diag(BatchArgs a) {
 
 // FP64 certification, one wave per selected near-best candidate: two-pass FP64 normalisation of the
 // window, then the exact (non-abandoning) recurrence in FP64.
+template <int MAXCPL>
 __global__ __launch_bounds__(64) void k_cert_diag(BatchArgs a) {
+    using P = DiagPads<MAXCPL>;
     extern __shared__ double lds_d[];
     const uint32_t cnt0 = *a.cert_count;
     const uint32_t cnt = cnt0 < (uint32_t)kNearBestCap ? cnt0 : (uint32_t)kNearBestCap;
     const int lane = threadIdx.x & 63;
-    double *qb = lds_d + kDiagPadQLo;
-    double *cb = qb + a.max_m + kDiagPadQHi + kDiagPadCLo;
+    double *qb = lds_d + P::QLo;
+    double *cb = qb + a.max_m + P::QHi + P::CLo;
     for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
         const int q = __builtin_amdgcn_readfirstlane(a.cert_q[e]);
         const BatchQ bq = a.bq[q];
@@ -324,11 +342,11 @@ __global__ __launch_bounds__(64) void k_cert_diag(BatchArgs a) {
             qb[x] = qsrc[x];
             cb[x] = flat ? 0.0 : ((double)wv[x] - mu) / sigma;
         }
-        stage_pads(qb, cb, m);
+        stage_pads<MAXCPL>(qb, cb, m);
         wave_sync();
         bool alive;
         int pairs;
-        const double D = diag_dispatch<kDiagMaxCpl, false>((r >> 6) + 1, qb, cb, m, r, nullptr, INFINITY, alive,
+        const double D = diag_dispatch<MAXCPL, false>((r >> 6) + 1, qb, cb, m, r, nullptr, INFINITY, alive,
                                                            pairs);
         if (lane == 0) a.cert_d[e] = D;
     }
@@ -356,8 +374,9 @@ __device__ inline void wave_norm(const float *w, int m, float &mu, float &s, flo
 // Plain search and the stage entry point: one wave per start of a DtwArgs list (explicit starts,
 // device-side survivors, a range or a single start).  In search mode with a device-side count,
 // rounds of more than a.diag_max survivors are left to the lane-per-candidate kernels.
-template <bool SEARCH>
+template <bool SEARCH, int MAXCPL>
 __global__ __launch_bounds__(128) void k_dtw_diag_list(DtwArgs a) {
+    using P = DiagPads<MAXCPL>;
     extern __shared__ float lds_f[];
     int64_t count = a.single >= 0 ? 1 : (a.count_dev ? (int64_t)*a.count_dev : a.count);
     if (a.count_dev && count > a.count) count = a.count;
@@ -366,8 +385,8 @@ __global__ __launch_bounds__(128) void k_dtw_diag_list(DtwArgs a) {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int m = a.m, r = a.r;
-    float *qb = lds_f + (int64_t)wid * (2 * m + kDiagPad) + kDiagPadQLo;
-    float *cb = qb + m + kDiagPadQHi + kDiagPadCLo;
+    float *qb = lds_f + (int64_t)wid * (2 * m + P::All) + P::QLo;
+    float *cb = qb + m + P::QHi + P::CLo;
     const float *qh = a.qpad + kQPad;
     unsigned long long n_started = 0, n_aband = 0, n_cells = 0, n_lane_cells = 0;
     for (int64_t k = wave; k < count; k += nwaves) {
@@ -393,11 +412,11 @@ __global__ __launch_bounds__(128) void k_dtw_diag_list(DtwArgs a) {
             qb[x] = qh[x];
             cb[x] = fmaf(Tp[x] - mu, s, o);
         }
-        stage_pads(qb, cb, m);
+        stage_pads<MAXCPL>(qb, cb, m);
         wave_sync();
         bool alive;
         int pairs;
-        const float D = diag_dispatch<kDiagMaxCpl, true>((r >> 6) + 1, qb, cb, m, r, SEARCH ? a.key : nullptr,
+        const float D = diag_dispatch<MAXCPL, true>((r >> 6) + 1, qb, cb, m, r, SEARCH ? a.key : nullptr,
                                                          SEARCH ? INFINITY : a.abandon_at, alive, pairs);
         if (SEARCH) {
             ++n_started;
@@ -425,14 +444,16 @@ __global__ __launch_bounds__(128) void k_dtw_diag_list(DtwArgs a) {
 }
 
 // FP64 certification of the plain path, one wave per selected candidate.
+template <int MAXCPL>
 __global__ __launch_bounds__(64) void k_cert_diag_list(CertArgs c) {
+    using P = DiagPads<MAXCPL>;
     extern __shared__ double lds_d[];
     const uint32_t cnt0 = *c.cert_count;
     const uint32_t cnt = cnt0 < (uint32_t)kNearBestCap ? cnt0 : (uint32_t)kNearBestCap;
     const int lane = threadIdx.x & 63;
     const int m = c.m, r = c.r;
-    double *qb = lds_d + kDiagPadQLo;
-    double *cb = qb + m + kDiagPadQHi + kDiagPadCLo;
+    double *qb = lds_d + P::QLo;
+    double *cb = qb + m + P::QHi + P::CLo;
     for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
         const float *wv = c.T + __builtin_amdgcn_readfirstlane((int)c.cert_idx[e]);
         double sum = 0.0;
@@ -454,45 +475,71 @@ __global__ __launch_bounds__(64) void k_cert_diag_list(CertArgs c) {
             qb[x] = c.qhat64[x];
             cb[x] = flat ? 0.0 : ((double)wv[x] - mu) / sigma;
         }
-        stage_pads(qb, cb, m);
+        stage_pads<MAXCPL>(qb, cb, m);
         wave_sync();
         bool alive;
         int pairs;
-        const double D = diag_dispatch<kDiagMaxCpl, false>((r >> 6) + 1, qb, cb, m, r, nullptr, INFINITY, alive,
+        const double D = diag_dispatch<MAXCPL, false>((r >> 6) + 1, qb, cb, m, r, nullptr, INFINITY, alive,
                                                            pairs);
         if (lane == 0) c.cert_d[e] = D;
     }
 }
 
+// the instance for a launch's widest band
+static bool diag_wide_of(int max_r) { return max_r > kDiagMaxBandNarrow; }
+
 hipError_t launch_dtw_diag_list(const DtwArgs &a, bool search, int blocks, hipStream_t s) {
-    const size_t shm = 2 * diag_lds_bytes(a.m, false);
-    if (search)
-        hipLaunchKernelGGL(k_dtw_diag_list<true>, dim3(blocks), dim3(128), shm, s, a);
-    else
-        hipLaunchKernelGGL(k_dtw_diag_list<false>, dim3(blocks), dim3(128), shm, s, a);
+    const size_t shm = 2 * diag_lds_bytes(a.m, false, a.r);
+    if (diag_wide_of(a.r)) {
+        if (search)
+            hipLaunchKernelGGL((k_dtw_diag_list<true, 16>), dim3(blocks), dim3(128), shm, s, a);
+        else
+            hipLaunchKernelGGL((k_dtw_diag_list<false, 16>), dim3(blocks), dim3(128), shm, s, a);
+    } else {
+        if (search)
+            hipLaunchKernelGGL((k_dtw_diag_list<true, 4>), dim3(blocks), dim3(128), shm, s, a);
+        else
+            hipLaunchKernelGGL((k_dtw_diag_list<false, 4>), dim3(blocks), dim3(128), shm, s, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_cert_diag_list(const CertArgs &c, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_cert_diag_list, dim3(blocks), dim3(64), diag_lds_bytes(c.m, true), s, c);
-    return hipGetLastError();
-}
-
-size_t diag_lds_bytes(int max_m, bool fp64) {
-    return (size_t)(2 * max_m + kDiagPad) * (fp64 ? sizeof(double) : sizeof(float));
-}
-
-hipError_t launch_dtw_diag(const BatchArgs &a, bool prefix, int blocks, hipStream_t s) {
-    const size_t shm = 2 * diag_lds_bytes(a.max_m, false);
-    if (prefix)
-        hipLaunchKernelGGL(k_dtw_diag<true>, dim3(blocks), dim3(128), shm, s, a);
+    const size_t shm = diag_lds_bytes(c.m, true, c.r);
+    if (diag_wide_of(c.r))
+        hipLaunchKernelGGL(k_cert_diag_list<16>, dim3(blocks), dim3(64), shm, s, c);
     else
-        hipLaunchKernelGGL(k_dtw_diag<false>, dim3(blocks), dim3(128), shm, s, a);
+        hipLaunchKernelGGL(k_cert_diag_list<4>, dim3(blocks), dim3(64), shm, s, c);
     return hipGetLastError();
 }
 
-hipError_t launch_cert_diag(const BatchArgs &a, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_cert_diag, dim3(blocks), dim3(64), diag_lds_bytes(a.max_m, true), s, a);
+size_t diag_lds_bytes(int max_m, bool fp64, int max_r) {
+    const int pads = diag_wide_of(max_r) ? DiagPads<16>::All : DiagPads<4>::All;
+    return (size_t)(2 * max_m + pads) * (fp64 ? sizeof(double) : sizeof(float));
+}
+
+hipError_t launch_dtw_diag(const BatchArgs &a, bool prefix, int max_r, int blocks, hipStream_t s) {
+    const size_t shm = 2 * diag_lds_bytes(a.max_m, false, max_r);
+    if (diag_wide_of(max_r)) {
+        if (prefix)
+            hipLaunchKernelGGL((k_dtw_diag<true, 16>), dim3(blocks), dim3(128), shm, s, a);
+        else
+            hipLaunchKernelGGL((k_dtw_diag<false, 16>), dim3(blocks), dim3(128), shm, s, a);
+    } else {
+        if (prefix)
+            hipLaunchKernelGGL((k_dtw_diag<true, 4>), dim3(blocks), dim3(128), shm, s, a);
+        else
+            hipLaunchKernelGGL((k_dtw_diag<false, 4>), dim3(blocks), dim3(128), shm, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cert_diag(const BatchArgs &a, int max_r, int blocks, hipStream_t s) {
+    const size_t shm = diag_lds_bytes(a.max_m, true, max_r);
+    if (diag_wide_of(max_r))
+        hipLaunchKernelGGL(k_cert_diag<16>, dim3(blocks), dim3(64), shm, s, a);
+    else
+        hipLaunchKernelGGL(k_cert_diag<4>, dim3(blocks), dim3(64), shm, s, a);
     return hipGetLastError();
 }
 

@@ -259,10 +259,11 @@ hipError_t mlp_adam(const MlpBufs &b, int step, float lr, hipStream_t s);
 hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArgs &sa, hipStream_t s);
 hipError_t launch_seed_learned(const BatchArgs &a, const ScoreArgs &sa, hipStream_t s);
 hipError_t launch_propose(const BatchArgs &a, const ScoreArgs &sa, float *X, int64_t *starts, hipStream_t s);
-constexpr int kDiagMaxBand = 255;        // widest band of the one-wave-per-candidate kernels
-size_t diag_lds_bytes(int max_m, bool fp64);
-hipError_t launch_dtw_diag(const BatchArgs &a, bool prefix, int blocks, hipStream_t s);
-hipError_t launch_cert_diag(const BatchArgs &a, int blocks, hipStream_t s);
+constexpr int kDiagMaxBand = 1023;       // widest band of the one-wave-per-candidate kernels
+constexpr int kDiagMaxBandNarrow = 255;  // widest band of their narrow instances (smaller pads)
+size_t diag_lds_bytes(int max_m, bool fp64, int max_r);
+hipError_t launch_dtw_diag(const BatchArgs &a, bool prefix, int max_r, int blocks, hipStream_t s);
+hipError_t launch_cert_diag(const BatchArgs &a, int max_r, int blocks, hipStream_t s);
 hipError_t launch_dtw_diag_list(const DtwArgs &a, bool search, int blocks, hipStream_t s);
 hipError_t launch_cert_diag_list(const CertArgs &c, int blocks, hipStream_t s);
 hipError_t launch_paa(const float *T, int64_t n, int m, const int64_t *starts, int64_t count, float *out,

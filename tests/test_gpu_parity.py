@@ -298,6 +298,21 @@ def test_batch_contexts_in_flight_from_threads(casc):
             c.close()
 
 
+def test_wide_bands_plain_and_batched(ctx, casc):
+    """Bands from 256 up to unconstrained DTW (r = m - 1) and r = 1023: the wide one-wave
+    instances in the plain search (DTW and FP64 certification) and in the batched search."""
+    T = W.random_walk(12_001, 39)
+    specs = [(400, 256), (600, 599), (1024, 819), (128, 6)]
+    qs = [W.noisy_cut(T, 900 + 2_500 * k, m, 0.1, 1_200 + k) if k % 2 == 0 else W.random_walk(m, 1_300 + k)
+          for k, (m, _) in enumerate(specs)]
+    rs = [r for _, r in specs]
+    ref = _cascade_refs(casc, T, qs, rs)
+    for q, r, (ri, rd) in zip(qs, rs, ref):
+        gi, gd = ctx.search(dev(T), dev(q), r, seed=7)
+        assert gi == ri and abs(gd - rd) <= 1e-9 * rd + 1e-12, (len(q), r, gi, ri, gd, rd)
+    _check_batch(ctx.search_batch(dev(T), [dev(q) for q in qs], rs), ref)
+
+
 def test_batch_shared_length(ctx, casc):
     """All queries of one length: per-window statistics arrays shared by the batch."""
     T = W.random_walk(300_000, 32)
@@ -338,10 +353,13 @@ def test_batch_graph_replays_match_eager(ctx, casc):
 # --------------------------------------------------------------------- schedules
 @pytest.mark.parametrize("n,m,r", [(400, 2, 0), (400, 2, 1), (900, 3, 2), (2500, 17, 4), (2000, 100, 0),
                                    (3000, 130, 63), (3000, 130, 64), (2000, 300, 127), (2100, 300, 128),
-                                   (1500, 400, 255), (4200, 2048, 102), (2048, 2048, 255), (1200, 256, 255)])
+                                   (1500, 400, 255), (4200, 2048, 102), (2048, 2048, 255), (1200, 256, 255),
+                                   (1500, 400, 256), (2200, 700, 399), (1800, 600, 599), (2000, 1024, 819),
+                                   (2200, 2048, 1023)])
 def test_dtw_band_wave_schedule(ctx, n, m, r):
     """One wave per candidate along anti-diagonals (odd / even bands, one to four slot registers,
-    r = 0, r = m - 1 clamped, n = m) against the oracle, and against the lane schedule."""
+    and the wide instance's six to sixteen up to r = 1023; r = 0, r = m - 1 clamped, unconstrained
+    DTW, n = m) against the oracle, and against the lane schedule."""
     T, Q = W.tiny_random(n, m, 7 * n + m + r)
     N = n - m + 1
     starts = np.arange(0, N, max(1, N // 600), dtype=np.int64)
