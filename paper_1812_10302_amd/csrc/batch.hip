@@ -41,12 +41,32 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t b = blockIdx.x, x0 = b * kPB;
     const double a = (double)T[x0];
+    // this thread's 16 points: four 16-byte loads when the block is whole and the series is
+    // 16-byte aligned (x0 is a multiple of 4096), else point by point with a bounds test
+    float t[16];
+    if (x0 + kPB <= n && ((uintptr_t)T & 15u) == 0) {
+        const float4 *T4 = (const float4 *)(T + x0) + 4 * tid;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const float4 f = T4[w];
+            t[4 * w] = f.x;
+            t[4 * w + 1] = f.y;
+            t[4 * w + 2] = f.z;
+            t[4 * w + 3] = f.w;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int64_t y = x0 + 16 * tid + u;
+            t[u] = y < n ? T[y] : 0.0f;
+        }
+    }
     double v1[16], v2[16];
     double r1 = 0.0, r2 = 0.0;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         const int64_t y = x0 + 16 * tid + u;
-        const double d = y < n ? (double)T[y] - a : 0.0;
+        const double d = y < n ? (double)t[u] - a : 0.0;
         v1[u] = r1;
         v2[u] = r2;
         r1 += d;
