@@ -26,6 +26,13 @@
  *     share the best-so-far value for pruning through an atomic; each keeps
  *     its own best (distance, index) and the results are reduced by minimum
  *     distance, then lowest index.
+ *   - a window is normalised point by point as the bounds need it: LB_Kim
+ *     takes its moments and its first and last points, LB_Keogh against the
+ *     query envelope normalises each point as it adds its term, and only a
+ *     survivor of both is normalised in full (the values are the same either
+ *     way).  oc_search_many runs several queries of one length in one
+ *     scan, sharing each window's moments; every query keeps its own
+ *     best-so-far and cascade, so each result is oc_search's.
  *   - pruning compares with a relative slack of 1e-12 (prune only when
  *     bound > bsf * (1 + 1e-12)), so FP64 rounding in a bound can never drop
  *     a candidate whose distance ties the best.  Slack only weakens pruning.
@@ -39,15 +46,35 @@
 #define SIGMA_FLAT 1e-8
 #define SLACK (1.0 + 1e-12)
 
+/* Mean and population sigma of x[0..m) (eq. (Normalization1)), two passes in FP64: the mean first,
+ * then the mean squared deviation.  Each pass keeps eight partial sums (elements j = k mod 8), added
+ * in a fixed order at the end; that is only another rounding order of the same sums. */
+__attribute__((target_clones("avx2", "default")))
+static void window_moments(const float *x, int m, double *mu_out, double *sigma_out) {
+    double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int j = 0;
+    for (; j + 8 <= m; j += 8)
+        for (int k = 0; k < 8; ++k) p[k] += (double)x[j + k];
+    for (; j < m; ++j) p[j & 7] += (double)x[j];
+    double mu = (((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]))) / m;
+    for (int k = 0; k < 8; ++k) p[k] = 0.0;
+    for (j = 0; j + 8 <= m; j += 8)
+        for (int k = 0; k < 8; ++k) { double d = (double)x[j + k] - mu; p[k] += d * d; }
+    for (; j < m; ++j) { double d = (double)x[j] - mu; p[j & 7] += d * d; }
+    double v = (((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]))) / m;
+    *mu_out = mu;
+    *sigma_out = sqrt(v);
+}
+
+/* normalised value of one point: (t - mu) / sigma, or 0 for a flat window (sigma <= 1e-8) */
+static inline double znorm_point(float t, double mu, double sigma) {
+    return sigma <= SIGMA_FLAT ? 0.0 : ((double)t - mu) / sigma;
+}
+
 static void znorm_window(const float *x, int m, double *out) {
-    double s = 0.0;
-    for (int j = 0; j < m; ++j) s += (double)x[j];
-    double mu = s / m;
-    double v = 0.0;
-    for (int j = 0; j < m; ++j) { double d = (double)x[j] - mu; v += d * d; }
-    double sigma = sqrt(v / m);
-    if (sigma <= SIGMA_FLAT) { for (int j = 0; j < m; ++j) out[j] = 0.0; return; }
-    for (int j = 0; j < m; ++j) out[j] = ((double)x[j] - mu) / sigma;
+    double mu, sigma;
+    window_moments(x, m, &mu, &sigma);
+    for (int j = 0; j < m; ++j) out[j] = znorm_point(x[j], mu, sigma);
 }
 
 static void envelope(const double *x, int m, int r, double *U, double *L) {
@@ -57,6 +84,20 @@ static void envelope(const double *x, int m, int r, double *U, double *L) {
         for (int k = a + 1; k <= b; ++k) { if (x[k] > u) u = x[k]; if (x[k] < l) l = x[k]; }
         U[i] = u; L[i] = l;
     }
+}
+
+/* eq. (LBKeoghEC) for the window x[0..m) normalised with (mu, sigma) point by point as it goes,
+ * with early abandon once the partial sum exceeds thr (the values are znorm_point's). */
+static double lb_keogh_window(const float *x, double mu, double sigma, const double *U, const double *L, int m,
+                              double thr) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double c = znorm_point(x[i], mu, sigma);
+        if (c > U[i]) { double d = c - U[i]; s += d * d; }
+        else if (c < L[i]) { double d = c - L[i]; s += d * d; }
+        if (s > thr) return s;
+    }
+    return s;
 }
 
 /* eq. (LBKeoghEC) with early abandon once the partial sum exceeds thr. */
@@ -136,11 +177,16 @@ int oc_search(const float *T, int64_t n, const float *Q, int32_t m, int32_t r, i
             double bsf = bitsd(__atomic_load_n(&gbsf, __ATOMIC_RELAXED));
             if (best < bsf) bsf = best;
             double thr = bsf * SLACK;
-            znorm_window(T + i, m, ch);
-            double lk = (m == 1) ? (qh[0] - ch[0]) * (qh[0] - ch[0])
-                                 : (qh[0] - ch[0]) * (qh[0] - ch[0]) + (qh[m - 1] - ch[m - 1]) * (qh[m - 1] - ch[m - 1]);
+            /* LB_Kim needs only the window's moments and its first and last points; the whole
+             * window is normalised once the candidate survives it */
+            double mu, sigma;
+            window_moments(T + i, m, &mu, &sigma);
+            double c0 = znorm_point(T[i], mu, sigma), cl = znorm_point(T[i + m - 1], mu, sigma);
+            double lk = (m == 1) ? (qh[0] - c0) * (qh[0] - c0)
+                                 : (qh[0] - c0) * (qh[0] - c0) + (qh[m - 1] - cl) * (qh[m - 1] - cl);
             if (lk > thr) { c[1]++; continue; }
-            if (lb_keogh(ch, U, Lq, m, thr) > thr) { c[2]++; continue; }
+            if (lb_keogh_window(T + i, mu, sigma, U, Lq, m, thr) > thr) { c[2]++; continue; }
+            for (int j = 0; j < m; ++j) ch[j] = znorm_point(T[i + j], mu, sigma);
             envelope(ch, m, r, Uc, Lc);
             if (lb_keogh(qh, Uc, Lc, m, thr) > thr) { c[3]++; continue; }
             double d = dtw_band(qh, ch, m, r, thr, prev, cur);
@@ -159,6 +205,87 @@ int oc_search(const float *T, int64_t n, const float *Q, int32_t m, int32_t r, i
     *best_idx = gidx;
     *best_dist = gbest;
     if (counters) for (int k = 0; k < 6; ++k) counters[k] = cnt[k];
+    return 0;
+}
+
+/* The same search for nq queries of one length m against one series (queries back to back in Q,
+ * band r[k] for query k): every window's moments are computed once and serve all the queries; each
+ * query keeps its own best-so-far and its own cascade, exactly as oc_search.  best_idx[k] and
+ * best_dist[k] receive query k's result; counters as oc_search, summed over the queries. */
+int oc_search_many(const float *T, int64_t n, const float *Q, int32_t m, const int32_t *r_in, int32_t nq,
+                   int32_t nthreads, int64_t *best_idx, double *best_dist, int64_t *counters) {
+    if (!T || !Q || !r_in || nq < 1 || m < 1 || n < m) return -1;
+    for (int k = 0; k < nq; ++k) if (r_in[k] < 0) return -1;
+    int64_t N = n - m + 1;
+    int *r = (int *)malloc(sizeof(int) * nq);
+    double *qh = (double *)malloc(sizeof(double) * (size_t)m * 3 * nq);
+    uint64_t *gbsf = (uint64_t *)malloc(sizeof(uint64_t) * nq);
+    double *gbest = (double *)malloc(sizeof(double) * nq);
+    int64_t *gidx = (int64_t *)malloc(sizeof(int64_t) * nq);
+    for (int k = 0; k < nq; ++k) {
+        r[k] = r_in[k] > m - 1 ? m - 1 : r_in[k];
+        double *q = qh + (size_t)3 * m * k;
+        znorm_window(Q + (size_t)m * k, m, q);
+        envelope(q, m, r[k], q + m, q + 2 * m);
+        gbsf[k] = dbits(INFINITY);
+        gbest[k] = INFINITY;
+        gidx[k] = -1;
+    }
+    int64_t cnt[6] = {0, 0, 0, 0, 0, 0};
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+    {
+        int p = omp_get_num_threads(), t = omp_get_thread_num();
+        int64_t a = N * t / p, b = N * (t + 1) / p;
+        double *buf = (double *)malloc(sizeof(double) * (size_t)m * 6 + 16);
+        double *best = (double *)malloc(sizeof(double) * nq);
+        int64_t *bidx = (int64_t *)malloc(sizeof(int64_t) * nq);
+        double *ch = buf, *Uc = buf + m, *Lc = buf + 2 * m, *prev = buf + 3 * m, *cur = buf + 4 * m + 2;
+        int64_t c[6] = {0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < nq; ++k) { best[k] = INFINITY; bidx[k] = -1; }
+        for (int64_t i = a; i < b; ++i) {
+            double mu, sigma;
+            window_moments(T + i, m, &mu, &sigma);
+            double c0 = znorm_point(T[i], mu, sigma), cl = znorm_point(T[i + m - 1], mu, sigma);
+            int full = 0;   /* ch holds the normalised window */
+            for (int k = 0; k < nq; ++k) {
+                const double *q = qh + (size_t)3 * m * k, *U = q + m, *Lq = q + 2 * m;
+                c[0]++;
+                double bsf = bitsd(__atomic_load_n(&gbsf[k], __ATOMIC_RELAXED));
+                if (best[k] < bsf) bsf = best[k];
+                double thr = bsf * SLACK;
+                double lk = (m == 1) ? (q[0] - c0) * (q[0] - c0)
+                                     : (q[0] - c0) * (q[0] - c0) + (q[m - 1] - cl) * (q[m - 1] - cl);
+                if (lk > thr) { c[1]++; continue; }
+                if (lb_keogh_window(T + i, mu, sigma, U, Lq, m, thr) > thr) { c[2]++; continue; }
+                if (!full) {
+                    for (int j = 0; j < m; ++j) ch[j] = znorm_point(T[i + j], mu, sigma);
+                    full = 1;
+                }
+                envelope(ch, m, r[k], Uc, Lc);
+                if (lb_keogh(q, Uc, Lc, m, thr) > thr) { c[3]++; continue; }
+                double d = dtw_band(q, ch, m, r[k], thr, prev, cur);
+                if (d == INFINITY) { c[4]++; continue; }
+                c[5]++;
+                if (d < best[k]) { best[k] = d; bidx[k] = i; publish_bsf(&gbsf[k], d); }
+            }
+        }
+#pragma omp critical
+        {
+            for (int k = 0; k < nq; ++k)
+                if (bidx[k] >= 0 && (best[k] < gbest[k] || (best[k] == gbest[k] && bidx[k] < gidx[k]))) {
+                    gbest[k] = best[k];
+                    gidx[k] = bidx[k];
+                }
+            for (int k = 0; k < 6; ++k) cnt[k] += c[k];
+        }
+        free(buf);
+        free(best);
+        free(bidx);
+    }
+    for (int k = 0; k < nq; ++k) { best_idx[k] = gidx[k]; best_dist[k] = gbest[k]; }
+    if (counters) for (int k = 0; k < 6; ++k) counters[k] = cnt[k];
+    free(r); free(qh); free(gbsf); free(gbest); free(gidx);
     return 0;
 }
 

@@ -22,7 +22,7 @@ def build_cascade() -> str:
     """Compile cascade.c with gcc (-O2, OpenMP).  Always recompiles."""
     out = cascade_path()
     tmp = out + ".tmp"
-    subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC, "-lm"],
+    subprocess.run(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC, "-lm"],
                    check=True)
     os.replace(tmp, out)
     return out
@@ -43,6 +43,9 @@ class Cascade:
         lib.oc_dtw_starts.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32, P,
                                       ctypes.c_int64, ctypes.c_int32, P]
         lib.oc_dtw_starts.restype = ctypes.c_int
+        lib.oc_search_many.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32,
+                                       P, P, P]
+        lib.oc_search_many.restype = ctypes.c_int
         lib.oc_num_threads.restype = ctypes.c_int
         self.lib = lib
 
@@ -62,6 +65,25 @@ class Cascade:
         if rc != 0:
             raise ValueError("oc_search rejected its arguments")
         return int(idx.value), float(dist.value), cnt
+
+    def search_many(self, T, queries, rs, nthreads: int = 0):
+        """The searches of several queries of one length in one scan of the series (each window's
+        moments shared); returns [(index, distance)] in query order and the summed counters."""
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        m = int(np.asarray(queries[0]).size)
+        if any(np.asarray(q).size != m for q in queries):
+            raise ValueError("search_many needs queries of one length")
+        Q = np.ascontiguousarray(np.concatenate([np.asarray(q, np.float32) for q in queries]))
+        r = np.ascontiguousarray(np.asarray(rs, dtype=np.int32))
+        nq = len(queries)
+        idx = np.empty(nq, dtype=np.int64)
+        dist = np.empty(nq, dtype=np.float64)
+        cnt = np.zeros(6, dtype=np.int64)
+        rc = self.lib.oc_search_many(T.ctypes.data, T.size, Q.ctypes.data, m, r.ctypes.data, nq, int(nthreads),
+                                     idx.ctypes.data, dist.ctypes.data, cnt.ctypes.data)
+        if rc != 0:
+            raise ValueError("oc_search_many rejected its arguments")
+        return [(int(i), float(d)) for i, d in zip(idx, dist)], cnt
 
     def dtw_starts(self, T, Q, r: int, starts, nthreads: int = 0) -> np.ndarray:
         T = np.ascontiguousarray(T, dtype=np.float32)

@@ -57,6 +57,20 @@ def test_hand_envelope_and_bounds():
     assert R.lb_kim_fl(e["q"], e["c"]) == e["lb_kim_fl"]
 
 
+def test_hand_lb_kim_fl():
+    k = GOLD["lb_kim_fl"]
+    assert R.lb_kim_fl(k["q"], k["c"]) == k["lb_kim_fl"]
+    assert R.dtw(k["q"], k["c"], 1) == k["dtw_r1"]
+
+
+def test_hand_series_envelope_lb():
+    e = GOLD["series_envelope_lb"]
+    T = np.array(e["T"], np.float32)
+    for case in e["cases"]:
+        got = R.lb_keogh_d_series(T, case["i"], e["m"], e["r"], case["qhat"])
+        assert got == pytest.approx(case["lb"], rel=1e-14)
+
+
 def test_hand_fragments():
     f = GOLD["fragments"]
     assert [list(x) for x in R.fragments(f["N"], f["F"], f["m"])] == f["start_len"]
@@ -121,6 +135,7 @@ def test_bounds_below_dtw_and_tight_at_r0():
         if r == 0:
             assert lbs[1] == pytest.approx(d, rel=1e-12, abs=1e-12)
             assert lbs[2] == pytest.approx(d, rel=1e-12, abs=1e-12)
+            assert lbs[3] == pytest.approx(d, rel=1e-12, abs=1e-12)
             assert lbs[0] <= lbs[1] + 1e-12
     assert viol == 0
 
@@ -187,6 +202,20 @@ def test_cascade_equals_bruteforce_small(casc, seed, n, m, r):
         j, e, cnt = casc.search(T, Q, r, threads)
         assert j == i and e == pytest.approx(d, rel=1e-12)
         assert cnt[0] == n - m + 1
+
+
+@pytest.mark.parametrize("seed,n,m", [(41, 600, 16), (42, 900, 33), (43, 300, 64)])
+def test_cascade_many_equals_bruteforce_small(casc, seed, n, m):
+    T, _ = W.tiny_random(n, m, seed)
+    rng = np.random.default_rng(seed)
+    qs = [np.cumsum(rng.standard_normal(m)).astype(np.float32) for _ in range(4)]
+    qs.append(W.noisy_cut(T, 17, m, 0.1, seed))          # a near copy: a tight best-so-far early
+    rs = [0, 1, m // 4, m - 1, 3]
+    got, cnt = casc.search_many(T, qs, rs, 3)
+    assert cnt[0] == len(qs) * (n - m + 1)
+    for (j, e), q, r in zip(got, qs, rs):
+        i, d = R.best_match(T, q, r)
+        assert j == i and e == pytest.approx(d, rel=1e-12)
 
 
 def test_cascade_dtw_starts_equals_numpy(casc):
@@ -256,3 +285,71 @@ def _pins_pass(fn) -> bool:
 def test_pins_catch_planted_mistakes(mode):
     assert _pins_pass(R.dtw)
     assert not _pins_pass(lambda x, y, r: _mut_dtw(x, y, r, mode))
+
+
+# The bounds get the same treatment: a mistaken LB_KimFL or series envelope fails the pins above.
+def _mut_kim(q, c, mode):
+    q = np.asarray(q, float)
+    c = np.asarray(c, float)
+    if mode == "first_pair_only":
+        return float((q[0] - c[0]) ** 2)
+    if mode == "unsquared":
+        return float(abs(q[0] - c[0]) + abs(q[-1] - c[-1]))
+    raise ValueError(mode)
+
+
+def _kim_pins_pass(fn) -> bool:
+    k = GOLD["lb_kim_fl"]
+    if abs(fn(k["q"], k["c"]) - k["lb_kim_fl"]) > 1e-12:
+        return False
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        m = int(rng.integers(2, 12))
+        x, y = R.znorm(rng.standard_normal(m)), R.znorm(rng.standard_normal(m))
+        if fn(x, y) > R.dtw(x, y, int(rng.integers(0, m))) + 1e-12:
+            return False
+    return True
+
+
+def _mut_series_lb(T, i, m, r, qhat, mode):
+    """lb_keogh_d_series with a planted mistake in its envelope."""
+    if mode == "band_plus_two":
+        return R.lb_keogh_d_series(T, i, m, r + 2, qhat)
+    if mode == "own_window_only":
+        # envelope of the series cut to the candidate's window (a tighter, different bound)
+        return R.lb_keogh_d(qhat, R.znorm(np.asarray(T, float)[i:i + m]), r)
+    raise ValueError(mode)
+
+
+def _series_pins_pass(fn) -> bool:
+    e = GOLD["series_envelope_lb"]
+    T = np.array(e["T"], np.float32)
+    for case in e["cases"]:
+        if abs(fn(T, case["i"], e["m"], e["r"], case["qhat"]) - case["lb"]) > 1e-12:
+            return False
+    rng = np.random.default_rng(32)
+    Ts, _ = W.tiny_random(300, 8, 32)
+    for _ in range(100):
+        m = int(rng.integers(2, 20))
+        r = int(rng.integers(0, m))
+        i = int(rng.integers(0, Ts.size - m + 1))
+        qh = R.znorm(rng.standard_normal(m))
+        d = R.dtw(qh, R.znorm(Ts[i:i + m]), r)
+        lb = fn(Ts, i, m, r, qh)
+        if lb > d * (1 + 1e-12) + 1e-12:
+            return False
+        if r == 0 and abs(lb - d) > 1e-9 * max(d, 1.0):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("mode", ["first_pair_only", "unsquared"])
+def test_kim_pins_catch_planted_mistakes(mode):
+    assert _kim_pins_pass(R.lb_kim_fl)
+    assert not _kim_pins_pass(lambda q, c: _mut_kim(q, c, mode))
+
+
+@pytest.mark.parametrize("mode", ["band_plus_two", "own_window_only"])
+def test_series_envelope_pins_catch_planted_mistakes(mode):
+    assert _series_pins_pass(R.lb_keogh_d_series)
+    assert not _series_pins_pass(lambda T, i, m, r, q: _mut_series_lb(T, i, m, r, q, mode))
