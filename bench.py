@@ -1,24 +1,31 @@
 """Benchmark: exact best-match DTW search on one MI355X.
 
-One step = the whole search path (window statistics, data envelope, bound cascade, banded DTW
-with the device best-so-far, FP64 certification) for every query of the workload, with the
-series already resident in HBM.  The timed path is the batched search with the learned block
-order (one graph replay per step), with three batches in flight by default: three library
-contexts, each replaying its graph on its own stream from its own host thread, so that one batch's
-latency-bound phases overlap the other's streaming kernels (every step still runs the whole path
-on its batch; the rate with one batch in flight is reported beside it).  The plain per-query
-search and the batched search in series order are timed beside it.  The ordering network is trained before timing (seeded).  Default workload: float32 random walk of n = 1e8 points and
-three queries (m = 128, 512, 1024, cut from the series plus N(0, 0.1) noise, band 5%).
+One step = the whole search path for every query of the workload, with the series resident in HBM:
+query preparation, window statistics, the learned ordering (proposals, network, block order, the
+seeded best-so-far), the bound cascade, banded DTW with the device best-so-far, FP64 certification,
+results on the host.  The timed path is the batched search in learned order, one graph replay per
+step and one batch in flight.
 
-Prints one JSON line.  value = seconds per query (lower is better).  The roofline object is
-for the kernel class with the largest total time, timed with HIP events recorded on the
-launch stream inside the library (DTWS_PROFILE) over a separate profiled pass.
+Default workload (the largest): a float32 random walk of n = 1e9 points with 1000 planted copies of
+10 motif shapes, 128 queries of m = 1024 with a 10% band (r = 102).  The plain per-query search is
+timed beside it on a seeded subset of the queries, and the same batch in series order and in PAA
+order (the learned order's control) once each.  The ordering network is trained in the library
+(dtws_model_train) on a separate series before timing.  Unless --main-only is given, the smaller
+workloads (one query on n = 262,144; three queries on a 1e8 random walk; 256 mixed queries on it;
+64 queries on a 1e8 sinusoid mixture) are measured the same way with fewer steps and reported under
+"other_configs".
+
+Prints one JSON line.  value = seconds per query of the timed path (lower is better).  The roofline
+object is for the kernel class with the largest total time in a profiled pass (HIP events recorded
+on the launch stream inside the library).
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -33,46 +40,13 @@ METRIC = "search s/query and DTW GCUPS (frac. VALU peak), batched+learned vs pla
 HBM_PEAK_GBS = 8000.0
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 DTW_PEAK_GCUPS = VALU_LANE_OPS / 3 / 1e9
+# algorithmic VALU lane-operations of the bound cascade: LB_KimFL per (query, candidate) pair
+# (sub, sub, mul, fma, compare) and per LB_Keogh term (sub, fma, two max, fma, plus its load)
+KIM_OPS, KEOGH_TERM_OPS = 5, 6
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-# sources that define each kernel whose HBM traffic is recorded (profiles/hbm_traffic.md)
-# (keyed by the kernel's name without template arguments)
-KERNEL_SOURCES = {
-    "k_lb_batch": ["batch.hip", "batch_stats.h", "device.h", "dtws_internal.h"],
-    "k_prefix": ["batch.hip", "dtws_internal.h"],
-    "k_propose": ["mlp.hip", "device.h", "dtws_internal.h"],
-}
-
-
-def kernel_source_hash(kernel: str) -> str:
-    """SHA-256 over the sources of `kernel`, to tell whether recorded counters still describe it."""
-    import hashlib
-    h = hashlib.sha256()
-    src = os.path.join(ROOT, "paper_1812_10302_amd", "csrc")
-    for f in KERNEL_SOURCES.get(kernel.split("<")[0], []):
-        with open(os.path.join(src, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
-    return h.hexdigest()
-
-
-def traffic_of(kernel: str, launches: int, algorithmic: float):
-    """HBM bytes per launch of `kernel` recorded from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-    (profiles/hbm_traffic.md), or None when none is recorded for the kernel's current sources."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
-    if not os.path.exists(path) or kernel.split("<")[0] not in KERNEL_SOURCES:
-        return None
-    cur = kernel_source_hash(kernel)
-    for line in open(path):
-        if line.startswith("| `" + kernel + "`"):
-            cols = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
-            # | kernel | sources sha256 | bytes per launch (calibrated) | ...
-            if cols[1] == cur:
-                return float(cols[2])
-    return None
 
 
 def cells(m: int, r: int) -> int:
@@ -80,26 +54,208 @@ def cells(m: int, r: int) -> int:
     return m * (2 * r + 1) - r * (r + 1)
 
 
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return platform.processor() or "unknown"
+
+
+# ------------------------------------------------------------------------------ workloads
+def workload(name: str):
+    """(Workload, training recipe) of a named workload; the recipe is (series generator, shapes,
+    queries per shape, epochs, block)."""
+    from paper_1812_10302_amd import workloads as W
+    if name == "motifs1e9":
+        wl = W.planted_motifs(1_000_000_000)
+        train = (lambda: W.sinusoid_mix(10_000_000, 8), [(1024, 102)], 48, 10, 16384)
+    elif name == "rw1e8_3q":
+        wl = W.three_queries_large(100_000_000)
+        train = (lambda: W.random_walk(10_000_000, 8), [(128, 6), (512, 25), (1024, 51)], 32, 20, 16384)
+    elif name == "rw1e8_256q":
+        base = W.three_queries_large(100_000_000)
+        wl = W.batched_queries(base.T, 256, seed=6)
+        wl.name = "rw100000000_256q_m64-2048_r0-10pct"
+        train = (lambda: W.random_walk(10_000_000, 8), [(128, 6), (512, 25), (1024, 51), (2048, 102)], 12, 8, 16384)
+    elif name == "mix1e8_64q":
+        T = W.sinusoid_mix(100_000_000, 7)
+        wl = W.mixed_queries(T, 64, 256, seed=9000)
+        train = (lambda: W.sinusoid_mix(10_000_000, 8), [(256, 12)], 96, 12, 16384)
+    elif name == "rw262144_1q":
+        wl = W.single_query_small()
+        train = None
+    else:
+        raise ValueError(name)
+    return wl, train
+
+
+def measure(wl, train, steps: int, warmup: int, plain_queries: int, profile: bool, log_prefix: str = ""):
+    """Times the batched learned search (or the batched natural one when there is no training
+    recipe), the plain search on a seeded subset, and the ablation orders.  Returns a dict."""
+    import torch
+    import paper_1812_10302_amd as dtws
+
+    dev = torch.device("cuda:0")
+    T = torch.from_numpy(wl.T).to(dev)
+    Qs = [torch.from_numpy(q).to(dev) for q in wl.queries]
+    ms = [int(q.size) for q in wl.queries]
+    rs = [int(r) for r in wl.bands]
+    nq = len(Qs)
+    ctx = dtws.Context(0, max_n=wl.T.size, max_m=max(ms), max_queries=nq)
+    pq = dtws.PackedQueries(Qs)
+    out = {"workload": wl.name, "n": int(wl.T.size), "queries": nq, "m": sorted(set(ms)),
+           "r": [min(rs), max(rs)]}
+
+    # ordering network, trained in the library on its own series (untimed)
+    order = dtws.ORDER_NATURAL
+    if train is not None:
+        gen, shapes, qps, epochs, block = train
+        ctx.set_schedule(block=block)
+        t0 = time.time()
+        Ttr = torch.from_numpy(gen()).to(dev)
+        curve, pairs = ctx.model_train(Ttr, shapes, qps, epochs, seed=9)
+        del Ttr
+        out["ordering_network"] = {"pairs": pairs, "epochs": epochs, "block": block,
+                                   "loss_first_last": [round(curve[0], 5), round(curve[-1], 5)],
+                                   "train_s": round(time.time() - t0, 2)}
+        log(f"{log_prefix}ordering network: {pairs} pairs, loss {curve[0]:.4f} -> {curve[-1]:.4f} "
+            f"({time.time() - t0:.1f}s)")
+        order = dtws.ORDER_LEARNED
+    # launch schedule picked by the library's autotuner (untimed; the learned order keeps its block)
+    t0 = time.time()
+    schedule, tune_ms = ctx.autotune_batch(T, pq, rs, flags=order, seed=7, reps=1)
+    log(f"{log_prefix}autotuned {schedule} ({tune_ms:.2f} ms per batch, {time.time() - t0:.1f}s)")
+    out["schedule"] = schedule
+
+    def step(flags=0):
+        return ctx.search_batch(T, pq, rs, flags=order | flags, seed=7)
+
+    for _ in range(max(1, warmup)):
+        results = step()                 # the first call captures the graph
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t1) / steps
+    assert res == results
+    out["step_ms"] = round(step_s * 1e3, 3)
+    out["batched_s_per_query"] = round(step_s / nq, 7)
+    out["mode"] = "batched+learned" if train is not None else "batched"
+
+    # plain search, one query at a time, on a seeded subset (the results must agree)
+    rng = np.random.default_rng(11)
+    sub = sorted(rng.choice(nq, size=min(plain_queries, nq), replace=False).tolist())
+    for k in sub[:1]:
+        ctx.search(T, Qs[k], rs[k], seed=7)
+    torch.cuda.synchronize()
+    per = []
+    for k in sub:
+        a = time.perf_counter()
+        got = ctx.search(T, Qs[k], rs[k], seed=7)
+        per.append(time.perf_counter() - a)
+        assert got == results[k], (k, got, results[k])
+    out["plain_s_per_query"] = round(float(np.mean(per)), 6)
+    out["plain_queries"] = sub
+    out["batched_over_plain"] = round(out["batched_s_per_query"] / out["plain_s_per_query"], 4)
+
+    # ablations, one call each: series order and (with a model) the PAA order of the same proposals
+    abl = {}
+    for name, flag in (("natural", dtws.ORDER_NATURAL), ("paa", dtws.ORDER_PAA)):
+        if flag == order or (flag == dtws.ORDER_PAA and train is None):
+            continue
+        ctx.search_batch(T, pq, rs, flags=flag, seed=7)      # capture
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        got = ctx.search_batch(T, pq, rs, flags=flag, seed=7)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - a
+        assert got == results, f"{name} order disagrees"
+        c = ctx.counters()
+        abl[name] = {"s_per_query": round(dt / nq, 7), "dtw_cells": c["dtw_cells"], "dtw_started": c["dtw_started"],
+                     "pruned_kim": c["pruned_kim"]}
+    out["ablations"] = abl
+
+    # profiled pass of the timed path: kernel classes and counters
+    if profile:
+        step(dtws.PROFILE)
+        p = ctx.profile()
+        out["kernel_ms"] = {k: [round(v[0], 4), v[1]] for k, v in p.items()}
+        out["counters"] = ctx.counters()
+    out["results"] = [[int(i), float(d)] for i, d in results]
+    out["_ctx"], out["_T"], out["_Qs"] = ctx, T, Qs
+    return out
+
+
+def roofline_of(meas):
+    """Roofline object for the dominant kernel class of the profiled pass."""
+    prof, cnt = meas["kernel_ms"], meas["counters"]
+    dominant = max(prof, key=lambda k: prof[k][0])
+    t_ms, nl = prof[dominant]
+    sched = meas["schedule"]
+    if dominant == "lb" and sched.get("lb_tile", 1):
+        # tiled cascade: VALU-bound; algorithmic lane-operations = LB_KimFL per (query, candidate)
+        # pair plus every LB_Keogh term evaluated
+        ops = KIM_OPS * cnt["candidates"] + KEOGH_TERM_OPS * cnt["lb_terms"]
+        ach = ops / (t_ms * 1e-3) / 1e12
+        peak = VALU_LANE_OPS / 1e12
+        # the bytes the method streams per query pass (each query reads the series once, plus the
+        # window halo per tile), as a separate figure: the tile serves every query from one read
+        n, m = meas["n"], max(meas["m"])
+        qpass = meas["queries"] * (4 * n + 4 * (m - 1) * (n // 2048))
+        return {"bound": "alu", "kernel": "k_lb_tile", "achieved": round(ach, 3), "peak": round(peak, 3),
+                "unit": "Tlane-op/s", "frac": round(ach / peak, 4), "traffic": None,
+                "algorithmic_lane_ops_per_launch": int(ops / max(nl, 1)), "avg_launch_ms": round(t_ms / max(nl, 1), 4),
+                "launches": nl, "per_query_pass_bytes": int(qpass),
+                "per_query_pass_GBps": round(qpass / (t_ms * 1e-3) / 1e9, 1)}
+    if dominant == "dtw":
+        c = cnt["dtw_cells"]
+        g = c / (t_ms * 1e-3) / 1e9
+        return {"bound": "alu", "kernel": "DTW kernels", "achieved": round(g, 1), "peak": round(DTW_PEAK_GCUPS, 1),
+                "unit": "GCUPS", "frac": round(g / DTW_PEAK_GCUPS, 4), "traffic": None,
+                "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
+    return {"bound": "latency", "kernel": f"class {dominant}", "achieved": None, "peak": None, "unit": None,
+            "frac": None, "traffic": None, "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
+
+
+def dtw_rates(ctx, T, shapes, n):
+    """Exact banded DTW (no abandoning) of many random candidates per query shape through
+    dtws_dtw_band: the DTW kernel's own rate."""
+    import torch
+    rng = np.random.default_rng(11)
+    out = []
+    for q, m, r in shapes:
+        count = (1 << 20) if m <= 256 else ((1 << 18) if r <= 111 else (1 << 16))
+        st = torch.from_numpy(rng.integers(0, n - m + 1, count)).to(T.device)
+        ctx.dtw_band(T, q, r, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            ctx.dtw_band(T, q, r, st)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 3
+        g = count * cells(m, r) / dt / 1e9
+        out.append({"m": m, "r": r, "candidates": count, "ms": round(dt * 1e3, 3), "gcups": round(g, 1),
+                    "frac_valu_peak": round(g / DTW_PEAK_GCUPS, 4)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=100_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="series points for the CPU baseline")
+    ap.add_argument("--workload", default="motifs1e9",
+                    choices=["motifs1e9", "rw1e8_3q", "rw1e8_256q", "mix1e8_64q", "rw262144_1q"])
+    ap.add_argument("--plain-queries", type=int, default=8, help="queries of the plain-search subset")
+    ap.add_argument("--main-only", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--train-n", type=int, default=10_000_000, help="training series length (ordering network)")
-    ap.add_argument("--train-pairs", type=int, default=999_000)
-    ap.add_argument("--train-epochs", type=int, default=20)
-    ap.add_argument("--only-learned", action="store_true",
-                    help="time only the batched search in learned order (profiling runs)")
-    ap.add_argument("--schedule", default="",
-                    help="comma-separated schedule fields (k=v) to use instead of the autotuner")
-    ap.add_argument("--inflight", type=int, default=3,
-                    help="learned batches in flight: one library context, stream and host thread each")
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="after timing, copy this many MiB on the device (HBM counter calibration)")
+    ap.add_argument("--cpu-sample", type=int, default=250_000_000, help="series points of the CPU baseline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search shards by "
@@ -107,264 +263,91 @@ def main():
         sys.exit(2)
 
     import torch
-    import paper_1812_10302_amd as dtws
-    from paper_1812_10302_amd import workloads as W
 
     t0 = time.time()
-    wl = W.three_queries_large(args.n)
+    wl, train = workload(args.workload)
     log(f"workload {wl.name}: generated in {time.time() - t0:.1f}s")
-    dev = torch.device("cuda:0")
-    T = torch.from_numpy(wl.T).to(dev)
-    Qs = [torch.from_numpy(q).to(dev) for q in wl.queries]
-    ms = [q.size for q in wl.queries]
-    rs = list(wl.bands)
-    nq = len(Qs)
-    ctx = dtws.Context(0, max_n=wl.T.size, max_m=max(ms), max_queries=nq)
-    torch.cuda.synchronize()
+    meas = measure(wl, train, args.steps, args.warmup, args.plain_queries, not args.no_profile)
+    ctx, T, Qs = meas.pop("_ctx"), meas.pop("_T"), meas.pop("_Qs")
+    log(f"{wl.name}: {meas['step_ms']} ms per step, {meas['batched_s_per_query']} s/query batched, "
+        f"{meas['plain_s_per_query']} s/query plain")
 
-    # ---------------------------------------------------------------- plain: one query at a time
-    def plain_step(flags=0):
-        return [ctx.search(T, q, r, flags=flags, seed=7) for q, r in zip(Qs, rs)]
-
-    per_query = []
-    plain_s, plain_results = None, None
-    if not args.only_learned:
-        for _ in range(args.warmup):
-            plain_step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            for q, r in zip(Qs, rs):
-                a = time.perf_counter()
-                ctx.search(T, q, r, seed=7)
-                per_query.append(time.perf_counter() - a)
-        torch.cuda.synchronize()
-        plain_s = (time.perf_counter() - t1) / args.steps / nq
-        plain_results = plain_step()
-
-    # ---------------------------------------------------------------- ordering network (untimed)
-    from paper_1812_10302_amd import proposal
-    t0 = time.time()
-    train_T = W.random_walk(args.train_n, 8)
-    Xs, Ys = [], []
-    for k, (m, r) in enumerate(zip(ms, rs)):
-        rows_per_query = args.train_n // 1024 + 320
-        X, Y = proposal.make_pairs(ctx, train_T, m, r, max(1, args.train_pairs // (rows_per_query * nq)),
-                                   seed=80 + k)
-        Xs.append(X)
-        Ys.append(Y)
-    curve = proposal.train(ctx, torch.cat(Xs).contiguous(), torch.cat(Ys).contiguous(), epochs=args.train_epochs,
-                           seed=9, log=log)
-    train_s = time.time() - t0
-    log(f"ordering network trained in {train_s:.1f}s, loss {curve[0]:.4f} -> {curve[-1]:.4f}")
-
-    # ---------------------------------------------------------------- batched: all queries, graph replay
-    pq = dtws.PackedQueries(Qs)
-
-    def batch_step(order, flags=0):
-        return ctx.search_batch(T, pq, rs, flags=order | flags, seed=7)
-
-    def time_batched(order):
-        for _ in range(max(1, args.warmup)):
-            batch_step(order)        # the first call captures the graph
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            res = batch_step(order)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t1) / args.steps, res
-
-    natural_step_s, natural_results = (None, None) if args.only_learned else time_batched(dtws.ORDER_NATURAL)
-    if args.schedule:
-        ctx.set_schedule(**{k: int(v) for k, v in (kv.split("=") for kv in args.schedule.split(","))})
-        schedule = ctx.get_schedule()
-        log(f"schedule {schedule} (given)")
-    else:
-        # launch schedule for the learned batch picked by the library's autotuner (untimed)
-        t0 = time.time()
-        schedule, tune_ms = ctx.autotune_batch(T, pq, rs, flags=dtws.ORDER_LEARNED, seed=7, reps=3)
-        log(f"autotuned schedule {schedule} ({tune_ms:.2f} ms per batch, tuning took {time.time() - t0:.1f}s)")
-    single_step_s, results = time_batched(dtws.ORDER_LEARNED)
-    elapsed_step = single_step_s
-    if args.inflight > 1:
-        # several batches in flight: each context runs whole steps on its own stream from its own
-        # host thread, so one batch's latency-bound phases (DTW, certification, host round trips)
-        # overlap another's streaming kernels; every step still runs the whole path on its batch
-        import threading
-        params = ctx.model_get()
-        ctxs = [ctx]
-        for _ in range(args.inflight - 1):
-            c2 = dtws.Context(0, max_n=wl.T.size, max_m=max(ms), max_queries=nq)
-            c2.model_set(params)
-            c2.set_schedule(**schedule)
-            ctxs.append(c2)
-        for c in ctxs:
-            for _ in range(max(1, args.warmup)):
-                assert c.search_batch(T, pq, rs, flags=dtws.ORDER_LEARNED, seed=7) == results
-        torch.cuda.synchronize()
-        share = [args.steps // len(ctxs) + (1 if k < args.steps % len(ctxs) else 0) for k in range(len(ctxs))]
-        outs = [None] * len(ctxs)
-        start = threading.Barrier(len(ctxs) + 1)
-
-        def worker(k):
-            start.wait()
-            for _ in range(share[k]):
-                outs[k] = ctxs[k].search_batch(T, pq, rs, flags=dtws.ORDER_LEARNED, seed=7)
-
-        threads = [threading.Thread(target=worker, args=(k,)) for k in range(len(ctxs))]
-        for th in threads:
-            th.start()
-        torch.cuda.synchronize()
-        start.wait()
-        t1 = time.perf_counter()
-        for th in threads:
-            th.join()
-        torch.cuda.synchronize()
-        elapsed_step = (time.perf_counter() - t1) / args.steps
-        assert all(o == results for o, k in zip(outs, share) if k > 0), "batches in flight disagree"
-    ms_per_step = elapsed_step * 1e3
-    s_per_query = elapsed_step / nq
-    log("plain:", plain_results)
-    log("batched natural:", natural_results)
-    log("batched learned:", results)
-    if not args.only_learned:
-        assert results == natural_results, "learned and natural orders disagree"
-        assert [i for i, _ in results] == [i for i, _ in plain_results], "batched and plain disagree"
-    if args.copy_calibration_mib > 0:
-        # a plain device copy of known size: its HBM counters calibrate the traffic of the others
-        nb = args.copy_calibration_mib << 20
-        src_buf = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst_buf = torch.empty_like(src_buf)
-        torch.cuda.synchronize()
-        dst_buf.copy_(src_buf)
-        torch.cuda.synchronize()
-        del src_buf, dst_buf
-
-    def batch_step_learned(flags=0):
-        return batch_step(dtws.ORDER_LEARNED, flags)
-
-    # ---------------------------------------------------------------- profiled passes
-    def profiled(run):
-        run()
-        p = ctx.profile()
-        return {k: [v[0], v[1]] for k, v in p.items()}, ctx.counters()
-
-    prof_total, cnt_total = {k: [0.0, 0] for k in dtws.KERNEL_CLASSES}, {}
-    per_query_prof = []
+    roofline, dtw_rate = None, []
     if not args.no_profile:
-        prof_total, cnt_total = profiled(lambda: batch_step_learned(dtws.PROFILE))
-        for q, r in ([] if args.only_learned else zip(Qs, rs)):
-            kp, c = profiled(lambda: ctx.search(T, q, r, flags=dtws.PROFILE, seed=7))
-            per_query_prof.append({"m": int(q.numel()), "r": int(r),
-                                   "plain_kernel_ms": {k: round(v[0], 4) for k, v in kp.items()}, "counters": c})
-    dtw_cells = cnt_total.get("dtw_cells", 0)
-    lb_candidates = cnt_total.get("candidates", 0)
-    roofline = None
-    if not args.no_profile:
-        dominant = max(prof_total, key=lambda k: prof_total[k][0])
-        t_ms, nl = prof_total[dominant]
-        if dominant == "lb":
-            # per candidate the cascade must read its series point (4 B) and its window statistics:
-            # half a stored (sum, sum of squares) prefix entry (8 B: even entries only, an odd lane
-            # completes the even one before it with a point it reads anyway) or the three
-            # per-window values (12 B)
-            per_cand = 12 if schedule["stats_prefix"] else 16
-            kernel = "k_lb_batch<%s, %s>" % ("true" if schedule["stats_prefix"] else "false",
-                                              "true" if schedule["data_envelope"] else "false")
-            units = lb_candidates
-        elif dominant == "stats":
-            # blocked prefix: read 4 B, write 8 B per series point (a 16-byte entry at every
-            # second point; one pass for the batch)
-            per_cand, kernel, units = 12, "k_prefix", wl.T.size
-        else:
-            per_cand, kernel, units = None, f"class {dominant}", None
-        if per_cand is not None:
-            ach = units * per_cand / (t_ms * 1e-3) / 1e9
-            roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                        "traffic": traffic_of(kernel, nl, units * per_cand / max(nl, 1)),
-                        "algorithmic_bytes_per_launch": round(units * per_cand / max(nl, 1)),
-                        "bytes_per_unit": per_cand, "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
-        else:
-            roofline = {"bound": "latency", "kernel": kernel, "achieved": None, "peak": None, "unit": None,
-                        "frac": None, "traffic": None, "avg_launch_ms": round(t_ms / max(nl, 1), 4),
-                        "launches": nl}
+        roofline = roofline_of(meas)
+        shapes = []
+        seen = set()
+        for q, m, r in zip(Qs, [int(q.numel()) for q in Qs], wl.bands):
+            if (m, int(r)) not in seen and len(shapes) < 3:
+                seen.add((m, int(r)))
+                shapes.append((q, m, int(r)))
+        dtw_rate = dtw_rates(ctx, T, shapes, wl.T.size)
+    ctx.close()
+    del T, Qs
+    torch.cuda.empty_cache()
 
-    # ---------------------------------------------------------------- DTW kernel throughput
-    # exact banded DTW (no abandoning) of many random candidates per query shape, default schedule:
-    # the rate of the DTW kernel itself, which the pruned search above hardly exercises
-    dtw_rate = []
-    if not args.no_profile:
-        rng = np.random.default_rng(11)
-        # the bench queries' bands, plus the longest query with a band of 0.8 m (the wide-band
-        # regime: one wave per candidate, 13 slot registers per lane)
-        shapes = list(zip(Qs, ms, rs)) + [(Qs[-1], ms[-1], int(0.8 * ms[-1]))]
-        for q, m, r in shapes:
-            count = (1 << 20) if m <= 256 else ((1 << 18) if r <= 111 else (1 << 14))
-            st = torch.from_numpy(rng.integers(0, wl.T.size - m + 1, count)).to(dev)
-            ctx.dtw_band(T, q, r, st)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(3):
-                ctx.dtw_band(T, q, r, st)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / 3
-            g = count * cells(m, r) / dt / 1e9
-            dtw_rate.append({"m": m, "r": r, "candidates": count, "ms": round(dt * 1e3, 3), "gcups": round(g, 1),
-                             "frac_valu_peak": round(g / DTW_PEAK_GCUPS, 4)})
-
-    # ---------------------------------------------------------------- CPU baseline (oracle)
+    # CPU baseline: the oracle (C FP64 cascade, all host threads) as it stands, one query, on the
+    # first cpu_sample points of the series, scaled to the whole series
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import Cascade
         casc = Cascade()
         ns = min(args.cpu_sample, wl.T.size)
-        Ts = wl.T[:ns]
+        q, r = wl.queries[0], int(wl.bands[0])
         t = time.perf_counter()
-        for q, r in zip(wl.queries, rs):
-            casc.search(Ts, q, r)
+        idx, dist, _ = casc.search(wl.T[:ns], q, r)
         dt = time.perf_counter() - t
-        scale = (wl.T.size - np.mean(ms) + 1) / (ns - np.mean(ms) + 1)
-        cpu = {"value": round(dt / nq * scale, 4), "unit": "s/query", "cores": casc.num_threads(), "kind": "oracle",
-               "sample": f"C FP64 cascade oracle on the first {ns} points for each of the {nq} queries "
-                         f"({dt:.2f}s), scaled linearly to n={wl.T.size}"}
+        scale = (wl.T.size - q.size + 1) / (ns - q.size + 1)
+        cpu = {"value": round(dt * scale, 4), "unit": "s/query", "cores": casc.num_threads(), "kind": "oracle",
+               "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+               "sample": f"C FP64 cascade oracle, query 0 (m={q.size}, r={r}) over the first {ns} points "
+                         f"({dt:.2f}s, best {idx} at {dist:.6g}), scaled linearly to n={wl.T.size}"}
+        log(f"cpu baseline: {cpu}")
+
+    others = {}
+    if not args.main_only:
+        for name in ("rw262144_1q", "rw1e8_3q", "mix1e8_64q", "rw1e8_256q"):
+            if name == args.workload:
+                continue
+            t0 = time.time()
+            w2, tr2 = workload(name)
+            m2 = measure(w2, tr2, 3, 1, 3, False, log_prefix=f"[{name}] ")
+            c2 = m2.pop("_ctx")
+            c2.close()
+            m2.pop("_T"), m2.pop("_Qs"), m2.pop("results")
+            torch.cuda.empty_cache()
+            others[name] = m2
+            log(f"[{name}] {m2['step_ms']} ms per step ({time.time() - t0:.1f}s)")
 
     out = {
         "metric": METRIC,
-        "value": round(s_per_query, 6),
+        "value": meas["batched_s_per_query"],
         "unit": "s/query",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": meas["step_ms"],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": int(wl.T.size), "m": ms, "r": rs, "mode": "batched+learned",
-                   "note": wl.note},
-        "batches_in_flight": args.inflight,
-        "learned_one_in_flight_s_per_query": round(single_step_s / nq, 6),
-        "batched_natural_s_per_query": round(natural_step_s / nq, 6) if natural_step_s else None,
-        "ordering_network": {"train_series": f"random walk n={args.train_n} seed 8", "pairs": int(sum(x.shape[0] for x in Xs)),
-                             "epochs": args.train_epochs, "loss_curve": [round(v, 5) for v in curve],
-                             "train_s": round(train_s, 2)},
-        "schedule": schedule,
-        "plain_s_per_query": round(plain_s, 6) if plain_s else None,
-        "batched_over_plain": round(s_per_query / plain_s, 4) if plain_s else None,
+        "config": {"workload": wl.name, "n": meas["n"], "queries": meas["queries"], "m": meas["m"],
+                   "r": meas["r"], "mode": meas["mode"], "batches_in_flight": 1},
+        "plain_s_per_query": meas["plain_s_per_query"],
+        "plain_queries": meas["plain_queries"],
+        "batched_over_plain": meas["batched_over_plain"],
+        "ablations": meas["ablations"],
+        "ordering_network": meas.get("ordering_network"),
+        "schedule": meas["schedule"],
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "plain_per_query_s": [round(float(np.median(per_query[i::nq])), 6) for i in range(nq)] if per_query else None,
-        "batched_kernel_ms": {k: [round(v[0], 4), v[1]] for k, v in prof_total.items()},
+        "kernel_ms": meas.get("kernel_ms"),
+        "counters": meas.get("counters"),
         "dtw_throughput": dtw_rate,
-        "dtw_gcups": max((d["gcups"] for d in dtw_rate), default=None),
         "dtw_frac_valu_peak": max((d["frac_valu_peak"] for d in dtw_rate), default=None),
-        "search_dtw_gcups": round(dtw_cells / (prof_total["dtw"][0] * 1e-3) / 1e9, 2)
-        if prof_total["dtw"][0] > 0 else None,
-        "counters": cnt_total,
-        "plain_profile": per_query_prof,
-        "results": [[int(i), float(d)] for i, d in results],
+        "other_configs": others,
+        "results": meas["results"][:8],
     }
     print(json.dumps(out), flush=True)
 

@@ -59,12 +59,23 @@ enum dtws_status {
 #define DTWS_ORDER_NATURAL 0u        /* blocks in series order (plain search)                     */
 #define DTWS_ORDER_RANDOM 1u         /* blocks in a seeded random permutation                     */
 #define DTWS_ORDER_LEARNED 2u        /* blocks by ascending score of the learned model            */
+#define DTWS_ORDER_PAA 3u            /* blocks by ascending PAA distance of the same proposals the
+                                        learned model scores (no network): the learned order's
+                                        control, batched calls only                                */
 #define DTWS_ORDER_MASK 3u
 #define DTWS_NO_LOWER_BOUNDS 4u      /* skip the bound cascade: DTW (with abandoning) on all      */
 #define DTWS_PROFILE 8u              /* time every kernel with HIP events on the call's stream
                                         (adds an event pair per launch); see dtws_get_profile     */
 
 #define DTWS_NO_GRAPH 16u            /* batched calls: enqueue eagerly instead of replaying a graph */
+#define DTWS_LB_SORTED 32u           /* the Prepare / Improve scheme of Section 3.3 (Algorithm 1):
+                                        every candidate's three bounds computed once, independent of
+                                        the best-so-far (eq. (lbMatrix)), their maximum sorted, and
+                                        the candidates visited in ascending order of it, in segments
+                                        that each run DTW on the candidates whose bound is still
+                                        within the best-so-far (eqs. (bitmapMatrix), (candidateMatrix)).
+                                        A non-learned ordering; same results.  Batched calls run it
+                                        query by query.  Allocates 16 B per point of max_n on first use */
 
 /* Kernel classes reported by dtws_get_profile. */
 enum dtws_kernel_class {
@@ -100,6 +111,10 @@ typedef struct {
     int64_t certified;         /* near-best candidates re-evaluated in FP64             */
     int64_t dtw_lane_cells;    /* lane-cells issued by the DTW kernels: band bucket x
                                   columns x 64 lanes per wave step, idle lanes included */
+    int64_t lb_terms;          /* query-envelope LB_Keogh terms evaluated by the tiled
+                                  batched cascade (0 for the other cascade kernels)     */
+    int64_t fallbacks;         /* batched queries redone by the plain search after a
+                                  list overflowed (their work is not in the counters)   */
 } dtws_counters;
 
 /* ---------------------------------------------------------------- context */
@@ -140,6 +155,11 @@ DTWS_API int dtws_get_profile(dtws_ctx *ctx, double *ms_host, int64_t *launches_
  *   flags: DTWS_ORDER_* and DTWS_NO_LOWER_BOUNDS, seed: picks the random
  *   candidate whose DTW initialises the best-so-far (Algorithm 1, the random
  *   subsequence) and the random order.  The result never depends on it.
+ * Every candidate whose FP32 distance lies within the pruning slack of the
+ * final best-so-far is certified in FP64.  When they outnumber the near-best
+ * list (for example many exact ties: a flat query against a long flat stretch)
+ * the series is scanned again in list-sized chunks under the final
+ * best-so-far, so the result stays the lowest-index FP64 minimum.
  * Blocking: the result is written to *out_host when the call returns. */
 DTWS_API int dtws_search(dtws_ctx *ctx, const float *T_dev, int64_t n, const float *Q_dev, int32_t m,
                          int32_t r, uint32_t flags, uint64_t seed, void *stream, dtws_match *out_host);
@@ -222,6 +242,14 @@ typedef struct {
     int32_t rounds;            /* batched search: bound-cascade / DTW rounds over the work
                                   queue, per query 64K, 1M, 16M candidates then the rest (4,
                                   default), 1M then the rest (2), or all at once (1) */
+    int32_t list_cap;          /* capacity of the near-best list and of the batched survivor
+                                  list: 0 = full size (default), else 64 .. 2^20 entries.  A list
+                                  that overflows is recovered (see dtws_search), so this only
+                                  changes speed; small values exist to exercise that path */
+    int32_t lb_tile;           /* batched search: 1 = the rounds in which every query visits the
+                                  same candidates (series order, or a single round) run the tiled
+                                  cascade, one LDS-staged series tile shared by all queries
+                                  (default); 0 = per-query work items */
     int32_t reserved;          /* 0 */
 } dtws_schedule;
 
@@ -248,7 +276,8 @@ DTWS_API int dtws_autotune_batch(dtws_ctx *ctx, const float *T_dev, int64_t n, c
  * Model: y = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3, x = (16-segment PAA of
  * the normalised query, 16-segment PAA of the normalised candidate), segment t
  * of a length-m window = positions [floor(t m / 16), floor((t+1) m / 16)),
- * trained on y* = log(DTW / m + 1e-4) (the training recipe is the caller's).  Products in bfloat16 on the matrix cores
+ * trained on y* = log(DTW / m + 1e-4) (dtws_model_train below, or the caller's own recipe through
+ * dtws_model_train_step).  Products in bfloat16 on the matrix cores
  * with FP32 accumulation; FP32 master parameters; Adam (beta 0.9 / 0.999,
  * eps 1e-8).  Parameters: one flat FP32 vector of DTWS_MODEL_PARAMS values in
  * the order W1 (32 x 256, row = input), b1 (256), W2 (256 x 256, row = layer-1
@@ -278,14 +307,62 @@ DTWS_API int dtws_model_grad(dtws_ctx *ctx, const float *X_dev, const float *t_d
 DTWS_API int dtws_model_train_step(dtws_ctx *ctx, const float *X_dev, const float *t_dev, int64_t rows, float lr,
                                    float *loss_host, void *stream);
 
+/* Training recipe of dtws_model_train.  Queries are drawn from the training series, shape by shape
+ * (query length m[k], band r[k] of the labels, k < shapes): of every four queries three are cuts of
+ * the series at a seeded start plus Gaussian noise of standard deviation noise_std x (0.5, 1, 2) in
+ * turn, one an independent random walk.  A query's candidates are its proposals over the whole
+ * series (the rows the learned order scores, for the context's current block), random_per_query
+ * uniform starts, and for a cut query near_per_query starts within +-m/4 of its source and
+ * near_per_query within +-2 proposal strides of it.  Each pair's label is its exact banded DTW
+ * distance d from this library's DTW kernels; the target is log(d / m + 1e-4).  Every epoch visits
+ * the pairs in a seeded order, batch rows per Adam step (a last partial batch is skipped), with the
+ * learning rate falling linearly from lr to lr_final over the epochs. */
+#define DTWS_TRAIN_MAX_SHAPES 8
+typedef struct {
+    int32_t shapes;                      /* 1 .. DTWS_TRAIN_MAX_SHAPES                         */
+    int32_t m[DTWS_TRAIN_MAX_SHAPES];    /* query lengths (2 .. max_m, < n)                    */
+    int32_t r[DTWS_TRAIN_MAX_SHAPES];    /* bands (>= 0; clamped to m - 1)                     */
+    int32_t queries_per_shape;           /* >= 1                                               */
+    int32_t random_per_query;            /* >= 0                                               */
+    int32_t near_per_query;              /* >= 0                                               */
+    int32_t epochs;                      /* >= 0 (0: build the pairs only)                     */
+    int32_t batch;                       /* rows per Adam step, 64 .. DTWS_MODEL_MAX_ROWS      */
+    int32_t init;                        /* 1: fresh initialisation from seed; 0: continue     */
+    float lr, lr_final;                  /* > 0                                                */
+    float noise_std;                     /* >= 0                                               */
+    int32_t reserved;                    /* 0                                                  */
+    uint64_t seed;
+} dtws_train_cfg;
+
+/* Trains the ordering network on pairs drawn from the training series Ttrain_dev[n] (device,
+ * n <= max_n) as described above; everything runs on the device in this library's kernels.  The
+ * model records the context's current work-item block: the learned order then uses that block,
+ * whatever the schedule says, so training and search see the same proposals (set the block with
+ * dtws_set_schedule before training).  loss_curve_host[epochs] (may be NULL) receives each epoch's
+ * mean batch loss, *pairs_host (may be NULL) the number of pairs.  Allocates its pair buffers
+ * (about 132 bytes per pair) for the duration of the call.  Blocking.  DTWS_EINVAL for a recipe
+ * outside the ranges above or fewer pairs than one batch; DTWS_ENOMODEL for init = 0 without a
+ * model. */
+DTWS_API int dtws_model_train(dtws_ctx *ctx, const float *Ttrain_dev, int64_t n, const dtws_train_cfg *cfg,
+                              void *stream, float *loss_curve_host, int64_t *pairs_host);
+
+/* Serialised model: a 64-byte header (magic "DTWSMLP1", the parameter count, the work-item block it
+ * was trained with, the FNV-1a 64-bit hash of the parameters) followed by the FP32 parameters.
+ * dtws_model_save with buf_host NULL writes the size needed to *bytes_inout; otherwise *bytes_inout
+ * must be at least that size and receives it.  dtws_model_load checks size, magic, count and hash
+ * (DTWS_EINVAL on any mismatch, nothing changed) and resets the Adam state. */
+DTWS_API int dtws_model_save(dtws_ctx *ctx, void *buf_host, size_t *bytes_inout);
+DTWS_API int dtws_model_load(dtws_ctx *ctx, const void *buf_host, size_t bytes);
+
 /* Proposals that the learned order scores (DTWS_ORDER_LEARNED).  The candidates
- * 0 .. n-m are cut into quarter blocks of block/4 starts (block: 4096); the
+ * 0 .. n-m are cut into quarter blocks of block/4 starts (block: the one the model
+ * was trained with, else the schedule's); the
  * proposal of a quarter is its start whose 16-segment PAA is nearest (squared
  * Euclidean, FP32, lowest start on ties) to the query's, among every ps-th start
  * of the quarter, ps = max(1, m/64) for m >= 128 and 1 below.  Row k (quarter k)
  * gets starts_dev[k] (-1 for a quarter past the last candidate) and X_dev[k][32] =
  * (query PAA, candidate PAA), the network's input.  rows = 4 * ceil((n-m+1) /
- * 4096) is written to *rows_out; with starts_dev and X_dev both NULL nothing else
+ * block) is written to *rows_out; with starts_dev and X_dev both NULL nothing else
  * happens, else max_rows must be >= rows (DTWS_EINVAL otherwise).  Uses the
  * context's workspace (calls on one context must not overlap); blocking. */
 DTWS_API int dtws_propose(dtws_ctx *ctx, const float *T_dev, int64_t n, const float *Q_dev, int32_t m,

@@ -21,17 +21,19 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdtws.so")
 
 OK, EINVAL, ENOMEM, ENODEV, EHIP, EOVERFLOW, ENOMODEL = 0, -1, -2, -3, -4, -5, -6
-ORDER_NATURAL, ORDER_RANDOM, ORDER_LEARNED = 0, 1, 2
+ORDER_NATURAL, ORDER_RANDOM, ORDER_LEARNED, ORDER_PAA = 0, 1, 2, 3
 NO_LOWER_BOUNDS = 4
 PROFILE = 8
 NO_GRAPH = 16
+LB_SORTED = 32
 KERNEL_CLASSES = ("prep", "stats", "env", "lb", "dtw", "cert", "other", "score")
 MODEL_PARAMS = 74497
+TRAIN_MAX_SHAPES = 8
 MODEL_MAX_ROWS = 65536
 MAX_M = 2048
 
 COUNTER_FIELDS = ("candidates", "pruned_kim", "pruned_keogh_q", "pruned_keogh_d", "dtw_started",
-                  "dtw_abandoned", "dtw_cells", "certified", "dtw_lane_cells")
+                  "dtw_abandoned", "dtw_cells", "certified", "dtw_lane_cells", "lb_terms", "fallbacks")
 
 
 class Match(ctypes.Structure):
@@ -47,10 +49,18 @@ class Schedule(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int64), ("lb_blocks_per_cu", ctypes.c_int32),
                 ("dtw_blocks_per_cu", ctypes.c_int32), ("diag_max", ctypes.c_int32), ("band_lanes", ctypes.c_int32),
                 ("stats_prefix", ctypes.c_int32), ("data_envelope", ctypes.c_int32), ("rounds", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("list_cap", ctypes.c_int32), ("lb_tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("shapes", ctypes.c_int32), ("m", ctypes.c_int32 * 8), ("r", ctypes.c_int32 * 8),
+                ("queries_per_shape", ctypes.c_int32), ("random_per_query", ctypes.c_int32),
+                ("near_per_query", ctypes.c_int32), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("init", ctypes.c_int32), ("lr", ctypes.c_float), ("lr_final", ctypes.c_float),
+                ("noise_std", ctypes.c_float), ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class DtwsError(RuntimeError):
@@ -99,6 +109,9 @@ def _load():
         "dtws_model_forward": ([P, P, I64, P, P], ctypes.c_int),
         "dtws_model_grad": ([P, P, P, I64, P, P, P], ctypes.c_int),
         "dtws_model_train_step": ([P, P, P, I64, F32, P, P], ctypes.c_int),
+        "dtws_model_train": ([P, P, I64, ctypes.POINTER(TrainCfg), P, P, ctypes.POINTER(I64)], ctypes.c_int),
+        "dtws_model_save": ([P, P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "dtws_model_load": ([P, P, ctypes.c_size_t], ctypes.c_int),
         "dtws_paa": ([P, P, I64, I32, P, I64, P, P], ctypes.c_int),
         "dtws_propose": ([P, P, I64, P, I32, P, P, I64, ctypes.POINTER(I64), P], ctypes.c_int),
         "dtws_get_schedule": ([P, ctypes.POINTER(Schedule)], ctypes.c_int),
@@ -335,6 +348,45 @@ class Context:
                                                   ctypes.byref(loss) if want_loss else None, _stream(X)),
                     "dtws_model_train_step")
         return float(loss.value) if want_loss else None
+
+    def model_train(self, T, shapes, queries_per_shape: int, epochs: int, seed: int = 0, random_per_query: int = 256,
+                    near_per_query: int = 32, batch: int = 4096, lr: float = 1e-3, lr_final: float | None = None,
+                    noise_std: float = 0.1, init: bool = True):
+        """Train the ordering network in the library (dtws_model_train) on pairs drawn from the
+        training series T (float32 CUDA tensor) for the (m, r) shapes; returns (per-epoch mean
+        loss, number of pairs)."""
+        _dev_f32(T, "T")
+        shapes = list(shapes)
+        if not 1 <= len(shapes) <= TRAIN_MAX_SHAPES:
+            raise ValueError(f"1 to {TRAIN_MAX_SHAPES} (m, r) shapes")
+        cfg = TrainCfg()
+        cfg.shapes = len(shapes)
+        for k, (m, r) in enumerate(shapes):
+            cfg.m[k], cfg.r[k] = int(m), int(r)
+        cfg.queries_per_shape, cfg.random_per_query, cfg.near_per_query = int(queries_per_shape), int(
+            random_per_query), int(near_per_query)
+        cfg.epochs, cfg.batch, cfg.init = int(epochs), int(batch), 1 if init else 0
+        cfg.lr, cfg.lr_final = float(lr), float(lr / 10 if lr_final is None else lr_final)
+        cfg.noise_std, cfg.seed = float(noise_std), int(seed)
+        curve = np.zeros(max(int(epochs), 1), np.float32)
+        pairs = ctypes.c_int64(0)
+        self._check(_load().dtws_model_train(self._h, T.data_ptr(), T.numel(), ctypes.byref(cfg), _stream(T),
+                                             curve.ctypes.data, ctypes.byref(pairs)), "dtws_model_train")
+        return [float(v) for v in curve[:int(epochs)]], int(pairs.value)
+
+    def model_save(self) -> bytes:
+        """The trained model as bytes (header with a content hash, then the FP32 parameters)."""
+        size = ctypes.c_size_t(0)
+        lib = _load()
+        self._check(lib.dtws_model_save(self._h, None, ctypes.byref(size)), "dtws_model_save")
+        buf = ctypes.create_string_buffer(size.value)
+        self._check(lib.dtws_model_save(self._h, ctypes.cast(buf, ctypes.c_void_p), ctypes.byref(size)),
+                    "dtws_model_save")
+        return buf.raw[:size.value]
+
+    def model_load(self, blob: bytes):
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        self._check(_load().dtws_model_load(self._h, ctypes.cast(buf, ctypes.c_void_p), len(blob)), "dtws_model_load")
 
     def paa(self, T, m: int, starts):
         """16-segment PAA of the normalised windows T[s:s+m] (rows x 16 float32 CUDA tensor)."""

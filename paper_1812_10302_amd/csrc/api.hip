@@ -5,6 +5,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -36,6 +37,11 @@ int64_t dec_total(int64_t max_n) {
 }
 
 int diag_max_of(const dtws_ctx *c) { return c->diag_max >= 0 ? c->diag_max : kDefaultDiagMax; }
+
+// capacity of the near-best list in effect (the schedule may lower it)
+uint32_t nb_cap_of(const dtws_ctx *c) {
+    return c->list_cap > 0 && c->list_cap < kNearBestCap ? (uint32_t)c->list_cap : (uint32_t)kNearBestCap;
+}
 
 void set_err(dtws_ctx *c, hipError_t e, const char *what) {
     if (!c) return;
@@ -120,18 +126,18 @@ int check_series(dtws_ctx *c, const float *T, int64_t n, int32_t m) {
     return DTWS_OK;
 }
 
-// One query through the plain pipeline, results into the device result slot `slot`.
-// Window statistics for m and the data envelope for r must already be in the context.
-int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int r, uint32_t flags, uint64_t seed,
-              int slot, hipStream_t s) {
-    const int64_t N = n - m + 1;
+// Kernel arguments of the plain pipeline for one query in result slot `slot`.
+struct PlainArgs {
+    LbArgs l;
+    DtwArgs d;
+    CertArgs ce;
+};
+
+PlainArgs plain_args(dtws_ctx *c, const float *T, int64_t n, int m, int r, int slot) {
     const QueryBufs b = query_bufs(c, slot);
     uint64_t *key = c->keys + slot;
-    { PROF(DTWS_K_PREP); HIPCHK(c, launch_query_prep(Q, m, r, b, s)); }
-    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u64(key, kEmptyKey, 1, s)); }
-    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u32(c->nb_count, 0, 1, s)); }
-
-    DtwArgs d{};
+    PlainArgs p{};
+    DtwArgs &d = p.d;
     d.T = T;
     d.m = m;
     d.r = r;
@@ -146,22 +152,14 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
     d.nb_d = c->nb_d;
     d.nb_idx = c->nb_idx;
     d.nb_count = c->nb_count;
+    d.nb_cap = nb_cap_of(c);
     d.counters = c->counters;
     d.abandon_at = INFINITY;
     // one wave per candidate for small rounds, and always for bands wider than the register kernel
     const bool diag = r <= kDiagMaxBand;
     d.diag_max = !diag ? 0u : (2 * r + 1 > 16 * kMaxChunks ? 0xFFFFFFFFu : (uint32_t)diag_max_of(c));
 
-    // best-so-far from one seeded random candidate (Algorithm 1, before the main loop)
-    {
-        DtwArgs d0 = d;
-        d0.single = (int64_t)(splitmix64(seed) % (uint64_t)N);
-        PROF(DTWS_K_DTW);
-        if (diag) HIPCHK(c, launch_dtw_diag_list(d0, true, 1, s));
-        else HIPCHK(c, launch_dtw(d0, true, 1, c->num_cu, c->gen_rows, c->gen_lanes, s));
-    }
-
-    LbArgs l{};
+    LbArgs &l = p.l;
     l.T = T;
     l.m = m;
     l.qh = b.qpad + kQPad;
@@ -179,35 +177,7 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
     l.surv_count = c->surv_count;
     l.counters = c->counters;
 
-    // chunks grow geometrically so that the best-so-far tightens before the bulk of the series
-    int64_t size = 1 << 16;
-    for (int64_t a0 = 0; a0 < N;) {
-        const int64_t a1 = (N - a0 < size) ? N : a0 + size;
-        if (flags & DTWS_NO_LOWER_BOUNDS) {
-            DtwArgs dr = d;
-            dr.range_first = a0;
-            dr.count = a1 - a0;
-            PROF(DTWS_K_DTW);
-            HIPCHK(c, launch_dtw(dr, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
-        } else {
-            { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u32(c->surv_count, 0, 1, s)); }
-            l.first = a0;
-            l.last = a1;
-            { PROF(DTWS_K_LB); HIPCHK(c, launch_lb(l, 1, c->num_cu, s)); }
-            DtwArgs ds = d;
-            ds.starts32 = c->surv;
-            ds.count_dev = c->surv_count;
-            ds.count = a1 - a0;
-            PROF(DTWS_K_DTW);
-            // both schedules are enqueued; the device-side survivor count picks the one that runs
-            HIPCHK(c, launch_dtw(ds, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
-            if (ds.diag_max > 0) HIPCHK(c, launch_dtw_diag_list(ds, true, c->num_cu * 4, s));
-        }
-        a0 = a1;
-        size *= 16;   // 64K, 1M, then the rest: few launches once the best-so-far is tight
-    }
-
-    CertArgs ce{};
+    CertArgs &ce = p.ce;
     ce.T = T;
     ce.m = m;
     ce.r = r;
@@ -216,6 +186,7 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
     ce.nb_d = c->nb_d;
     ce.nb_idx = c->nb_idx;
     ce.nb_count = c->nb_count;
+    ce.nb_cap = d.nb_cap;
     ce.scratch = c->cert_rows;
     ce.cert_idx = c->cert_idx;
     ce.cert_count = c->cert_count;
@@ -224,7 +195,162 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
     ce.res_dist = c->res_dist + slot;
     ce.res_status = c->res_status + slot;
     ce.counters = c->counters;
-    { PROF(DTWS_K_CERT); HIPCHK(c, launch_certify(ce, s)); }
+    return p;
+}
+
+// Candidates [a0, a1) of the plain search: the bound cascade against the query's best-so-far, then
+// DTW of its survivors (or DTW of every candidate without the bounds).
+int plain_chunk(dtws_ctx *c, const PlainArgs &p, int64_t a0, int64_t a1, uint32_t flags, hipStream_t s) {
+    if (flags & DTWS_NO_LOWER_BOUNDS) {
+        DtwArgs dr = p.d;
+        dr.range_first = a0;
+        dr.count = a1 - a0;
+        PROF(DTWS_K_DTW);
+        HIPCHK(c, launch_dtw(dr, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
+        return DTWS_OK;
+    }
+    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u32(c->surv_count, 0, 1, s)); }
+    LbArgs l = p.l;
+    l.first = a0;
+    l.last = a1;
+    { PROF(DTWS_K_LB); HIPCHK(c, launch_lb(l, 1, c->num_cu, s)); }
+    DtwArgs ds = p.d;
+    ds.starts32 = c->surv;
+    ds.count_dev = c->surv_count;
+    ds.count = a1 - a0;
+    PROF(DTWS_K_DTW);
+    // both schedules are enqueued; the device-side survivor count picks the one that runs
+    HIPCHK(c, launch_dtw(ds, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
+    if (ds.diag_max > 0) HIPCHK(c, launch_dtw_diag_list(ds, true, c->num_cu * 4, s));
+    return DTWS_OK;
+}
+
+// The Prepare / Improve scheme of Section 3.3 (Algorithm 1) with the candidates visited in ascending
+// order of their bound.  Prepare: every candidate's three bounds in full, independent of the
+// best-so-far (eq. (lbMatrix)); a candidate survives the similarity map of eq. (bitmapMatrix) exactly
+// when the largest of them lies within the threshold, so only that maximum is kept, fused with the
+// start into a 64-bit key, and the keys are sorted.  Improve: segments of the sorted list, growing
+// geometrically (64K, 1M, 16M, then the rest), each running DTW on its candidates whose bound is
+// still within the best-so-far (the candidate matrix of eq. (candidateMatrix)); once a segment ends
+// beyond the threshold every later one is empty.  The sort buffers (16 B per candidate of max_n and
+// the sort's temporary storage) are allocated on the first call.
+int lb_sorted_improve(dtws_ctx *c, const PlainArgs &p, int64_t N, hipStream_t s) {
+    if (!c->lbs_keys) {
+        size_t bytes = 0;
+        HIPCHK(c, sort_keys_u64(nullptr, bytes, nullptr, nullptr, c->max_n, s));
+        if (hipMalloc((void **)&c->lbs_keys, sizeof(uint64_t) * 2 * (size_t)c->max_n) != hipSuccess ||
+            hipMalloc(&c->lbs_temp, bytes ? bytes : 1) != hipSuccess) {
+            (void)hipGetLastError();
+            if (c->lbs_keys) (void)hipFree(c->lbs_keys);
+            c->lbs_keys = nullptr;
+            c->lbs_temp = nullptr;
+            return DTWS_ENOMEM;
+        }
+        c->lbs_temp_bytes = bytes;
+    }
+    uint64_t *keys = c->lbs_keys, *sorted = c->lbs_keys + c->max_n;
+    {
+        PROF(DTWS_K_LB);
+        LbArgs l = p.l;
+        l.first = 0;
+        l.last = N;
+        l.out_key = keys;
+        HIPCHK(c, launch_lb(l, 0, c->num_cu, s));
+        size_t bytes = c->lbs_temp_bytes;
+        HIPCHK(c, sort_keys_u64(c->lbs_temp, bytes, keys, sorted, N, s));
+    }
+    int64_t size = 1 << 16;
+    for (int64_t a0 = 0; a0 < N;) {
+        const int64_t a1 = (N - a0 < size) ? N : a0 + size;
+        { PROF(DTWS_K_LB); HIPCHK(c, launch_lb_sorted_segment(sorted, a0, a1, p.d.key, c->surv, c->surv_count, c->num_cu, s)); }
+        DtwArgs ds = p.d;
+        ds.starts32 = c->surv;
+        ds.count_dev = c->surv_count;
+        ds.count = a1 - a0;
+        PROF(DTWS_K_DTW);
+        HIPCHK(c, launch_dtw(ds, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
+        if (ds.diag_max > 0) HIPCHK(c, launch_dtw_diag_list(ds, true, c->num_cu * 4, s));
+        a0 = a1;
+        size *= 16;
+    }
+    return DTWS_OK;
+}
+
+// One query through the plain pipeline, results into the device result slot `slot`.
+// Window statistics for m and the data envelope for r must already be in the context.
+int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int r, uint32_t flags, uint64_t seed,
+              int slot, hipStream_t s) {
+    const int64_t N = n - m + 1;
+    const QueryBufs b = query_bufs(c, slot);
+    const PlainArgs p = plain_args(c, T, n, m, r, slot);
+    { PROF(DTWS_K_PREP); HIPCHK(c, launch_query_prep(Q, m, r, b, s)); }
+    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u64(p.d.key, kEmptyKey, 1, s)); }
+    { PROF(DTWS_K_OTHER); HIPCHK(c, launch_fill_u32(c->nb_count, 0, 1, s)); }
+
+    // best-so-far from one seeded random candidate (Algorithm 1, before the main loop)
+    {
+        DtwArgs d0 = p.d;
+        d0.single = (int64_t)(splitmix64(seed) % (uint64_t)N);
+        PROF(DTWS_K_DTW);
+        if (r <= kDiagMaxBand) HIPCHK(c, launch_dtw_diag_list(d0, true, 1, s));
+        else HIPCHK(c, launch_dtw(d0, true, 1, c->num_cu, c->gen_rows, c->gen_lanes, s));
+    }
+
+    if (flags & DTWS_LB_SORTED) {
+        const int rc = lb_sorted_improve(c, p, N, s);
+        if (rc != DTWS_OK) return rc;
+    } else {
+        // chunks grow geometrically so that the best-so-far tightens before the bulk of the series
+        int64_t size = 1 << 16;
+        for (int64_t a0 = 0; a0 < N;) {
+            const int64_t a1 = (N - a0 < size) ? N : a0 + size;
+            const int rc = plain_chunk(c, p, a0, a1, flags, s);
+            if (rc != DTWS_OK) return rc;
+            a0 = a1;
+            size *= 16;   // 64K, 1M, then the rest: few launches once the best-so-far is tight
+        }
+    }
+    { PROF(DTWS_K_CERT); HIPCHK(c, launch_certify(p.ce, s)); }
+    return DTWS_OK;
+}
+
+// The near-best list of a plain search overflowed: more candidates lie within the FP32 slack of
+// the final best-so-far than it holds (for example a flat query against a long flat stretch of the
+// series, where every window of the stretch is an exact tie).  The key on the device is final, so
+// the candidates the certification must see are exactly those with an FP32 distance within the
+// slack of it.  The series is searched again in chunks of at most nb_cap candidates under that
+// fixed key (a chunk cannot overflow the list), each chunk's near-best list is certified in FP64,
+// and the chunk results are reduced in series order, lowest index on ties.  Blocking; the result
+// replaces the slot's entry in the host staging arrays.
+int recertify_chunked(dtws_ctx *c, const float *T, int64_t n, int m, int r, uint32_t flags, int slot,
+                      hipStream_t s) {
+    const int64_t N = n - m + 1;
+    const PlainArgs p = plain_args(c, T, n, m, r, slot);
+    const int64_t S = p.d.nb_cap;
+    double best = INFINITY;
+    int64_t bidx = -1;
+    for (int64_t a0 = 0; a0 < N; a0 += S) {
+        const int64_t a1 = N - a0 < S ? N : a0 + S;
+        HIPCHK(c, launch_fill_u32(c->nb_count, 0, 1, s));
+        const int rc = plain_chunk(c, p, a0, a1, flags, s);
+        if (rc != DTWS_OK) return rc;
+        HIPCHK(c, launch_certify(p.ce, s));
+        int64_t idx = -1;
+        double dist = 0.0;
+        int32_t st = 0;
+        HIPCHK(c, hipMemcpyAsync(&idx, c->res_idx + slot, sizeof(idx), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(&dist, c->res_dist + slot, sizeof(dist), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(&st, c->res_status + slot, sizeof(st), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (st == DTWS_EOVERFLOW) return DTWS_EOVERFLOW;   // cannot happen: a chunk holds <= nb_cap
+        if (idx >= 0 && dist < best) {   // chunks in series order: strict < keeps the lowest index
+            best = dist;
+            bidx = idx;
+        }
+    }
+    c->h_idx[slot] = bidx;
+    c->h_dist[slot] = best;
+    c->h_status[slot] = bidx >= 0 ? DTWS_OK : DTWS_EHIP;
     return DTWS_OK;
 }
 
@@ -242,9 +368,31 @@ int fetch_counters(dtws_ctx *c, int64_t candidates, hipStream_t s) {
     c->last.dtw_cells = (int64_t)h[6];
     c->last.certified = (int64_t)h[7];
     c->last.dtw_lane_cells = (int64_t)h[8];
+    c->last.lb_terms = (int64_t)h[9];
+    c->last.fallbacks = 0;
     return DTWS_OK;
 }
 
+
+// Copies only the counters to the host and parses them (the result staging is left alone).
+int fetch_counters_only(dtws_ctx *c, int64_t candidates, hipStream_t s) {
+    HIPCHK(c, hipMemcpyAsync(c->h_counters, c->counters, sizeof(unsigned long long) * kNumCounters,
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const unsigned long long *h = c->h_counters;
+    c->last.candidates = candidates;
+    c->last.pruned_kim = (int64_t)h[1];
+    c->last.pruned_keogh_q = (int64_t)h[2];
+    c->last.pruned_keogh_d = (int64_t)h[3];
+    c->last.dtw_started = (int64_t)h[4];
+    c->last.dtw_abandoned = (int64_t)h[5];
+    c->last.dtw_cells = (int64_t)h[6];
+    c->last.certified = (int64_t)h[7];
+    c->last.dtw_lane_cells = (int64_t)h[8];
+    c->last.lb_terms = (int64_t)h[9];
+    c->last.fallbacks = 0;
+    return DTWS_OK;
+}
 
 // Batched pipeline (see batch.hip): all queries in rounds over a device work queue.
 struct BatchPlan {
@@ -256,11 +404,15 @@ struct BatchPlan {
     int64_t score_rows = 0;   // proposals of the learned order (kScoreSamples per block)
     uint32_t dec_levels = 0;  // decimated prefix copies the proposals read
     bool bucket_used[kMaxChunks + 2] = {false};
+    int ngroups = 0;          // distinct lengths (tiled cascade: queries grouped by length)
+    int64_t max_N = 0;        // largest candidate count of a query
 };
 
-BatchPlan plan_batch(dtws_ctx *c, int64_t n, const int64_t *qoff, const int32_t *mh, const int32_t *rh, int nq) {
+BatchPlan plan_batch(dtws_ctx *c, int64_t n, const int64_t *qoff, const int32_t *mh, const int32_t *rh, int nq,
+                     bool learned) {
     BatchPlan p;
-    p.block = c->block > 0 ? c->block : kDefaultBlock;
+    // the learned order scores the blocks the model was trained on
+    p.block = learned ? learned_block(c) : (c->block > 0 ? c->block : kDefaultBlock);
     for (int k = 0; k < nq; ++k) {
         BatchQ &b = c->h_bq[k];
         b.qoff = qoff[k];
@@ -282,6 +434,18 @@ BatchPlan plan_batch(dtws_ctx *c, int64_t n, const int64_t *qoff, const int32_t 
         p.dec_levels |= dec_level_of(b.m);
     }
     c->h_row_off[nq] = p.score_rows;
+    // queries grouped by length for the tiled cascade: h_tile_q[0 .. ngroups] = first position of
+    // each group in the list, the list (sorted by length, then index) from h_tile_q[max_q + 1]
+    {
+        int32_t *gfirst = c->h_tile_q, *qlist = c->h_tile_q + c->max_q + 1;
+        for (int k = 0; k < nq; ++k) qlist[k] = k;
+        std::stable_sort(qlist, qlist + nq, [&](int32_t x, int32_t y) { return c->h_bq[x].m < c->h_bq[y].m; });
+        p.ngroups = 0;
+        for (int k = 0; k < nq; ++k)
+            if (k == 0 || c->h_bq[qlist[k]].m != c->h_bq[qlist[k - 1]].m) gfirst[p.ngroups++] = k;
+        gfirst[p.ngroups] = nq;
+        for (int k = 0; k < nq; ++k) p.max_N = c->h_bq[k].N > p.max_N ? c->h_bq[k].N : p.max_N;
+    }
     // slots for distinct lengths and bands, in order of first appearance
     bool m_fit = true, r_fit = true;
     for (int k = 0; k < nq; ++k) {
@@ -361,7 +525,8 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     a.surv_count = c->surv_count;
     a.qcnt = c->qcnt;
     a.overflow = c->overflow;
-    a.surv_cap = c->bsurv_cap;
+    a.surv_cap = c->list_cap > 0 && c->list_cap < c->bsurv_cap ? c->list_cap : c->bsurv_cap;
+    a.nb_cap = nb_cap_of(c);
     a.sorted = c->sorted;
     a.qorder = c->qorder;
     a.wstart = c->wstart;
@@ -394,8 +559,11 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     base.Lsorted = c->Lsorted;
     base.order = c->order;
 
-    const bool learned = (flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED;
+    // the learned order and its PAA control score the same proposals; only the scorer differs
+    const bool paa_only = (flags & DTWS_ORDER_MASK) == DTWS_ORDER_PAA;
+    const bool learned = (flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED || paa_only;
     HIPCHK(c, hipMemcpyAsync(c->bq, c->h_bq, sizeof(BatchQ) * nq, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->tile_q, c->h_tile_q, sizeof(int32_t) * (c->max_q + 1 + nq), hipMemcpyHostToDevice, s));
     {
         PROF(DTWS_K_OTHER);
         HIPCHK(c, launch_reset_batch(c->keys, nq, c->counters, kNumCounters, c->heads, 8, c->nb_count, c->cert_count,
@@ -440,7 +608,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         for (int k = 0; k < nq; ++k) sa.kinds |= c->h_bq[k].m % 64 == 0 ? 1u : 2u;
         sa.total_rows = p.score_rows;
         HIPCHK(c, hipMemcpyAsync(c->row_off, c->h_row_off, sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, s));
-        HIPCHK(c, mlp_order_blocks(c->mlp, a, sa, s));
+        HIPCHK(c, mlp_order_blocks(c->mlp, a, sa, paa_only, s));
     } else {
         PROF(DTWS_K_OTHER);
         HIPCHK(c, launch_make_perm(a, (flags & DTWS_ORDER_MASK) == DTWS_ORDER_RANDOM ? 1 : 0, seed ^ 0xA5A5ull,
@@ -500,7 +668,19 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
             // a round that holds them all, or any round of the series order
             const bool natural = (rank_lo == 0 && rank_hi >= max_nb) ||
                                  (flags & DTWS_ORDER_MASK) == DTWS_ORDER_NATURAL;
-            HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)rank_lo, (int)rank_hi, parts, natural, lb_blocks, s));
+            if (natural && c->lb_tile) {
+                // every query visits the same candidates: series tiles shared by all queries
+                TileArgs t{};
+                t.gfirst = c->tile_q;
+                t.qlist = c->tile_q + c->max_q + 1;
+                t.ngroups = p.ngroups;
+                t.c_lo = rank_lo * B;
+                t.c_hi = rank_hi * B;
+                t.halo = max_m - 1;
+                HIPCHK(c, launch_lb_tile(a, t, !same_m, p.max_N, s));
+            } else {
+                HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)rank_lo, (int)rank_hi, parts, natural, lb_blocks, s));
+            }
         }
         rc = dtw_round(-1);
         if (rc != DTWS_OK) return rc;
@@ -522,13 +702,15 @@ void parse_counters(dtws_ctx *c, int64_t candidates) {
     c->last.dtw_cells = (int64_t)h[6];
     c->last.certified = (int64_t)h[7];
     c->last.dtw_lane_cells = (int64_t)h[8];
+    c->last.lb_terms = (int64_t)h[9];
+    c->last.fallbacks = 0;
 }
 
 int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int64_t *qoff, const int32_t *mh,
               const int32_t *rh, int nq, uint32_t flags, uint64_t seed, hipStream_t s, dtws_match *out) {
-    const BatchPlan p = plan_batch(c, n, qoff, mh, rh, nq);
+    const BatchPlan p = plan_batch(c, n, qoff, mh, rh, nq, (flags & DTWS_ORDER_MASK) >= DTWS_ORDER_LEARNED);
     const size_t cert_shm = sizeof(double) * (2 * (size_t)p.max_m + 3 * (size_t)(p.max_r + 4));
-    if ((flags & DTWS_NO_LOWER_BOUNDS) || cert_shm > 60 * 1024) {
+    if ((flags & (DTWS_NO_LOWER_BOUNDS | DTWS_LB_SORTED)) || cert_shm > 60 * 1024) {
         // outside the batched pipeline's envelope: every query through the plain path
         dtws_counters sum{};
         int worst = DTWS_OK;
@@ -556,7 +738,7 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
         // per-query parameters and the tuning knobs.
         std::vector<int64_t> sig = {(int64_t)(uintptr_t)T, n, (int64_t)(uintptr_t)Qp, nq, (int64_t)flags,
                                     (int64_t)seed, p.block, c->lb_blocks_per_cu, c->dtw_blocks_per_cu, c->diag_max,
-                                    c->stats_prefix, c->data_envelope, c->rounds};
+                                    c->stats_prefix, c->data_envelope, c->rounds, c->lb_tile, c->list_cap};
         for (int k = 0; k < nq; ++k) {
             sig.push_back(qoff[k]);
             sig.push_back(mh[k]);
@@ -606,10 +788,24 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
     }
     for (int k = 0; k < nq; ++k) {
         if (out[k].status == DTWS_EOVERFLOW) {
-            // survivor or near-best list overflowed: redo this query through the plain path
+            // survivor or near-best list overflowed: redo this query through the plain path (its
+            // kernels add to the profile of the batch; the counters keep the batch's and count the
+            // fallback in `fallbacks`)
             dtws_counters keep = c->last;
-            const int r2 = dtws_search(c, T, n, Qp + qoff[k], mh[k], rh[k], 0, seed + k, s, &out[k]);
+            double keep_ms[DTWS_K_COUNT];
+            int64_t keep_n[DTWS_K_COUNT];
+            for (int j = 0; j < DTWS_K_COUNT; ++j) {
+                keep_ms[j] = c->prof_ms[j];
+                keep_n[j] = c->prof_n[j];
+            }
+            const int r2 = dtws_search(c, T, n, Qp + qoff[k], mh[k], rh[k], flags & DTWS_PROFILE, seed + k, s,
+                                       &out[k]);
+            for (int j = 0; j < DTWS_K_COUNT; ++j) {
+                c->prof_ms[j] += keep_ms[j];
+                c->prof_n[j] += keep_n[j];
+            }
             c->last = keep;
+            c->last.fallbacks += 1;
             if (r2 != DTWS_OK) worst = r2;
         } else if (out[k].status != DTWS_OK) {
             worst = out[k].status;
@@ -619,6 +815,64 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
 }
 
 }  // namespace
+
+namespace dtws {
+
+QueryBufs query_bufs_of(dtws_ctx *c, int slot) { return query_bufs(c, slot); }
+
+void set_hip_error(dtws_ctx *c, hipError_t e, const char *what) { set_err(c, e, what); }
+
+// Work-item block of the learned order: the block the model was trained with, else the schedule's.
+int64_t learned_block(const dtws_ctx *c) {
+    if (c->model_block > 0) return c->model_block;
+    return c->block > 0 ? c->block : kDefaultBlock;
+}
+
+int64_t propose_rows(const dtws_ctx *c, int64_t n, int m) {
+    const int64_t B = learned_block(c);
+    const int64_t N = n - m + 1, nb = (N + B - 1) / B;
+    return nb * kScoreSamples;
+}
+
+// Proposals of the normalised query in slot 0 (query preparation already enqueued) over T: starts
+// and feature rows.  Uses the context's prefix and staging entries h_bq[0] / h_row_off[0..1]: the
+// caller synchronises before those change.
+int enqueue_propose(dtws_ctx *c, const float *T, int64_t n, int m, int64_t *starts, float *X, hipStream_t s) {
+    const int64_t B = learned_block(c);
+    const int64_t N = n - m + 1, nb = (N + B - 1) / B, rows = nb * kScoreSamples;
+    HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s, &c->dec, dec_level_of(m)));
+    BatchQ &bq = c->h_bq[0];
+    bq = BatchQ{};
+    bq.m = m;
+    bq.N = N;
+    bq.nblocks = (int32_t)nb;
+    c->h_row_off[0] = 0;
+    c->h_row_off[1] = rows;
+    HIPCHK(c, hipMemcpyAsync(c->bq, c->h_bq, sizeof(BatchQ), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->row_off, c->h_row_off, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
+    BatchArgs a{};
+    a.T = T;
+    a.n = n;
+    a.nq = 1;
+    a.block = B;
+    a.max_m = c->max_m;
+    a.bq = c->bq;
+    a.qhat64 = c->qhat64;
+    ScoreArgs sa{};
+    sa.K = kScoreSamples;
+    sa.total_rows = rows;
+    sa.qpaa = c->qpaa;
+    sa.sstart = c->sstart;
+    sa.row_off = c->row_off;
+    sa.pre = Prefix{c->PP, c->anc, c->tot, T};
+    sa.dec = c->dec;
+    sa.dec_levels = dec_level_of(m);
+    sa.kinds = m % 64 == 0 ? 1u : 2u;
+    HIPCHK(c, launch_propose(a, sa, X, starts, s));
+    return DTWS_OK;
+}
+
+}  // namespace dtws
 
 // ============================================================================ C ABI
 extern "C" {
@@ -655,7 +909,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
                    c->mlp.theta, c->mlp.grad, c->mlp.adam_m, c->mlp.adam_v, c->mlp.W1T, c->mlp.W2T, c->mlp.W2b,
                    c->mlp.Xb, c->mlp.XbT, c->mlp.H1b, c->mlp.H1T, c->mlp.dA2b, c->mlp.dA2T, c->mlp.dA1T,
                    c->mlp.C1, c->mlp.C2, c->mlp.y, c->mlp.dy, c->mlp.loss, c->mlp.Xf, c->mlp.part, c->qpaa,
-                   c->score, c->sstart, c->bstart, c->row_off};
+                   c->score, c->sstart, c->bstart, c->row_off, c->tile_q, c->lbs_keys, c->lbs_temp};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -667,7 +921,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
         delete[] c->ev;
     }
     delete[] c->ev_class;
-    void *host[] = {c->h_res_block, c->h_bq, c->h_row_off};
+    void *host[] = {c->h_res_block, c->h_bq, c->h_row_off, c->h_tile_q};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     delete c;
@@ -735,7 +989,8 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
     }
     if (ok) {
         c->maxblocks = (max_n + kMinBlock - 1) / kMinBlock + 1;
-        int64_t cap = Q * max_n < (int64_t(1) << 25) ? Q * max_n : (int64_t(1) << 25);
+        // batched survivor list: up to 2^28 entries (12 B each with the sorted copy)
+        int64_t cap = Q * max_n < (int64_t(1) << 28) ? Q * max_n : (int64_t(1) << 28);
         if (cap < Q * kSeedCands) cap = Q * kSeedCands;   // round -1 of the learned order
         c->bsurv_cap = cap;
         const int64_t nblk = max_n / 4096 + 2;
@@ -749,7 +1004,9 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&c->overflow, 1) == hipSuccess && dalloc(&c->qorder, Q + 1) == hipSuccess &&
              dalloc(&c->wstart, Q + 1) == hipSuccess && dalloc(&c->bucket_w, 2 * (kMaxChunks + 2)) == hipSuccess &&
              dalloc(&c->bucket_j, 2 * (kMaxChunks + 2)) == hipSuccess && dalloc(&c->seg_off, Q) == hipSuccess &&
-             dalloc(&c->nb_q, kNearBestCap) == hipSuccess && dalloc(&c->cert_q, kNearBestCap) == hipSuccess;
+             dalloc(&c->nb_q, kNearBestCap) == hipSuccess && dalloc(&c->cert_q, kNearBestCap) == hipSuccess &&
+             dalloc(&c->tile_q, 2 * Q + 2) == hipSuccess &&
+             hipHostMalloc((void **)&c->h_tile_q, sizeof(int32_t) * (2 * Q + 2), 0) == hipSuccess;
         if (ok) {
             int64_t off = 0;
             for (int L = kDecFirst; L < kDecLevels; ++L) {
@@ -812,8 +1069,11 @@ DTWS_API int dtws_get_counters(dtws_ctx *c, dtws_counters *out) {
 DTWS_API int dtws_search(dtws_ctx *c, const float *T, int64_t n, const float *Q, int32_t m, int32_t r,
                          uint32_t flags, uint64_t seed, void *stream, dtws_match *out) {
     if (check_series(c, T, n, m) != DTWS_OK || !Q || !out || r < 0) return DTWS_EINVAL;
-    if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE | DTWS_NO_GRAPH)) return DTWS_EINVAL;
+    if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE | DTWS_NO_GRAPH | DTWS_LB_SORTED))
+        return DTWS_EINVAL;
+    if ((flags & DTWS_LB_SORTED) && (flags & DTWS_NO_LOWER_BOUNDS)) return DTWS_EINVAL;
     if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED) return DTWS_ENOMODEL;
+    if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_PAA) return DTWS_EINVAL;   // batched calls only
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     if (r > m - 1) r = m - 1;
@@ -829,6 +1089,12 @@ DTWS_API int dtws_search(dtws_ctx *c, const float *T, int64_t n, const float *Q,
     rc = fetch_counters(c, n - m + 1, s);
     if (rc != DTWS_OK) return rc;
     prof_end(c);
+    if (c->h_status[0] == DTWS_EOVERFLOW) {
+        rc = recertify_chunked(c, T, n, m, r, flags, 0, s);
+        if (rc != DTWS_OK) return rc;
+        rc = fetch_counters_only(c, n - m + 1, s);   // the counters include the second scan
+        if (rc != DTWS_OK) return rc;
+    }
     out->index = c->h_idx[0];
     out->distance = c->h_dist[0];
     out->status = c->h_status[0];
@@ -840,7 +1106,8 @@ DTWS_API int dtws_search_batch(dtws_ctx *c, const float *T, int64_t n, const flo
                                const int32_t *mh, const int32_t *rh, int32_t nq, uint32_t flags, uint64_t seed,
                                void *stream, dtws_match *out) {
     if (!c || !T || !Qp || !qoff || !mh || !rh || !out || nq < 1 || nq > c->max_q) return DTWS_EINVAL;
-    if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE | DTWS_NO_GRAPH)) return DTWS_EINVAL;
+    if (flags & ~(DTWS_ORDER_MASK | DTWS_NO_LOWER_BOUNDS | DTWS_PROFILE | DTWS_NO_GRAPH | DTWS_LB_SORTED))
+        return DTWS_EINVAL;
     if ((flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED && !c->has_model) return DTWS_ENOMODEL;
     for (int k = 0; k < nq; ++k)
         if (check_series(c, T, n, mh[k]) != DTWS_OK || rh[k] < 0 || qoff[k] < 0) return DTWS_EINVAL;
@@ -856,6 +1123,7 @@ DTWS_API int dtws_model_init(dtws_ctx *c, uint64_t seed) {
     HIPCHK(c, hipStreamSynchronize(nullptr));
     c->has_model = true;
     c->model_step = 0;
+    c->model_block = 0;
     return DTWS_OK;
 }
 
@@ -877,6 +1145,7 @@ DTWS_API int dtws_model_set(dtws_ctx *c, const float *params, int64_t count) {
     HIPCHK(c, hipStreamSynchronize(nullptr));
     c->has_model = true;
     c->model_step = 0;
+    c->model_block = 0;
     return DTWS_OK;
 }
 
@@ -933,43 +1202,15 @@ DTWS_API int dtws_paa(dtws_ctx *c, const float *T, int64_t n, int32_t m, const i
 DTWS_API int dtws_propose(dtws_ctx *c, const float *T, int64_t n, const float *Q, int32_t m, int64_t *starts,
                          float *X, int64_t max_rows, int64_t *rows_out, void *stream) {
     if (check_series(c, T, n, m) != DTWS_OK || !rows_out) return DTWS_EINVAL;
-    const int64_t B = c->block > 0 ? c->block : kDefaultBlock;
-    const int64_t N = n - m + 1, nb = (N + B - 1) / B, rows = nb * kScoreSamples;
+    const int64_t rows = propose_rows(c, n, m);
     *rows_out = rows;
     if (!starts && !X) return DTWS_OK;
     if (!Q || !starts || !X || max_rows < rows) return DTWS_EINVAL;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, launch_query_prep(Q, m, 0, query_bufs(c, 0), s));
-    HIPCHK(c, launch_prefix(T, n, c->PP, c->anc, c->tot, s, &c->dec, dec_level_of(m)));
-    BatchQ &bq = c->h_bq[0];
-    bq = BatchQ{};
-    bq.m = m;
-    bq.N = N;
-    bq.nblocks = (int32_t)nb;
-    c->h_row_off[0] = 0;
-    c->h_row_off[1] = rows;
-    HIPCHK(c, hipMemcpyAsync(c->bq, c->h_bq, sizeof(BatchQ), hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->row_off, c->h_row_off, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
-    BatchArgs a{};
-    a.T = T;
-    a.n = n;
-    a.nq = 1;
-    a.block = B;
-    a.max_m = c->max_m;
-    a.bq = c->bq;
-    a.qhat64 = c->qhat64;
-    ScoreArgs sa{};
-    sa.K = kScoreSamples;
-    sa.total_rows = rows;
-    sa.qpaa = c->qpaa;
-    sa.sstart = c->sstart;
-    sa.row_off = c->row_off;
-    sa.pre = Prefix{c->PP, c->anc, c->tot, T};
-    sa.dec = c->dec;
-    sa.dec_levels = dec_level_of(m);
-    sa.kinds = m % 64 == 0 ? 1u : 2u;
-    HIPCHK(c, launch_propose(a, sa, X, starts, s));
+    const int rc = enqueue_propose(c, T, n, m, starts, X, s);
+    if (rc != DTWS_OK) return rc;
     // the staging entries are read by the copies above before the call returns
     HIPCHK(c, hipStreamSynchronize(s));
     return DTWS_OK;
@@ -1049,6 +1290,7 @@ DTWS_API int dtws_dtw_band(dtws_ctx *c, const float *T, int64_t n, const float *
     d.n = n;
     d.single = -1;
     d.abandon_at = abandon_at;
+    d.nb_cap = nb_cap_of(c);
     d.dist_out = dist;
     const bool wave = r <= kDiagMaxBand &&
                       (c->band_lanes == 64 ||

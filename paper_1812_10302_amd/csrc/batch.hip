@@ -139,18 +139,29 @@ __global__ __launch_bounds__(kPrefixThreads) void k_prefix(const float *__restri
 }
 
 // ------------------------------------------------------------------ work order
-// Primes above any block count (series < 2^31 points, blocks >= 2048 points): A = p mod nb is
-// then coprime to nb, so k -> (A k + C) mod nb is a permutation.
-__constant__ uint64_t kPrimes[8] = {1000003ull, 1000033ull, 1000037ull, 1000039ull,
-                                    1000081ull, 1000099ull, 1000117ull, 1000121ull};
+__device__ inline uint64_t gcd_u64(uint64_t a, uint64_t b) {
+    while (b) {
+        const uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
 
-// mode 0: series order; 1: seeded permutation k -> (A k + C) mod nb with A coprime to nb.
+// mode 0: series order; 1: seeded permutation k -> (A k + C) mod nb.  A starts at a seeded value in
+// [1, nb - 1] and steps up to the first value coprime to nb (nb - 1 always is), so the map is a
+// bijection of [0, nb) for every block count.
 __global__ void k_make_perm(BatchArgs a, int mode, uint64_t seed) {
     const int q = blockIdx.y;
     const BatchQ bq = a.bq[q];
     const int64_t nb = bq.nblocks;
     const uint64_t h = splitmix64_d(seed ^ (0x51ED2701ull * (uint64_t)(q + 1)));
-    const uint64_t A = kPrimes[h & 7] % (uint64_t)nb, C = (h >> 8) % (uint64_t)nb;
+    uint64_t A = 1, C = 0;
+    if (mode == 1 && nb > 1) {
+        A = 1 + h % (uint64_t)(nb - 1);
+        while (gcd_u64(A, (uint64_t)nb) != 1) A = A + 1 < (uint64_t)nb ? A + 1 : 1;
+        C = (h >> 8) % (uint64_t)nb;
+    }
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += (int64_t)gridDim.x * blockDim.x) {
         int64_t v = k;
         if (mode == 1 && nb > 1) v = (int64_t)((A * (uint64_t)k + C) % (uint64_t)nb);
@@ -170,32 +181,6 @@ __global__ void k_seed_random(BatchArgs a, uint64_t seed) {
 }
 
 // ------------------------------------------------------------------ batched bound cascade
-struct EmitBatch {
-    int32_t *surv_q, *surv_i;
-    uint32_t *count, *qcnt, *overflow;
-    int64_t cap;
-    int q;
-    __device__ void operator()(bool alive, int64_t i) const {
-        const uint64_t mask = __ballot(alive);
-        if (!mask) return;
-        const int lane = threadIdx.x & 63;
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        const uint32_t pc = (uint32_t)__popcll(mask);
-        uint32_t base = 0;
-        if (lane == leader) {
-            base = atomicAdd(count, pc);
-            if ((int64_t)base + pc > cap) atomicOr(overflow, 1u);
-            else atomicAdd(&qcnt[q], pc);
-        }
-        base = __shfl(base, leader, 64);
-        const int64_t pos = (int64_t)base + __popcll(mask & lanemask_lt());
-        if (alive && (int64_t)base + pc <= cap) {
-            surv_q[pos] = q;
-            surv_i[pos] = (int32_t)i;
-        }
-    }
-};
-
 // Work-item source of one wave for one query: consumes the current item group by group, pops the
 // next item when it runs out, and stops (keeping the popped item) at the first item of another
 // query, so the caller can drain the queues before switching query.  Items of round r are
@@ -439,7 +424,7 @@ __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
             if (alive) {
                 atomicMin((unsigned long long *)(a.keys + q), (unsigned long long)pack_key(D, (uint32_t)start));
                 const uint32_t pos = atomicAdd(a.nb_count, 1u);
-                if (pos < (uint32_t)kNearBestCap) {
+                if (pos < a.nb_cap) {
                     a.nb_d[pos] = D;
                     a.nb_idx[pos] = (uint32_t)start;
                     a.nb_q[pos] = q;
@@ -527,7 +512,7 @@ __global__ __launch_bounds__(64) void k_dtw_batch_wide(BatchArgs a) {
         if (alive && D <= thr) {
             atomicMin((unsigned long long *)(a.keys + q), (unsigned long long)pack_key(D, (uint32_t)start));
             const uint32_t pos = atomicAdd(a.nb_count, 1u);
-            if (pos < (uint32_t)kNearBestCap) {
+            if (pos < a.nb_cap) {
                 a.nb_d[pos] = D;
                 a.nb_idx[pos] = (uint32_t)start;
                 a.nb_q[pos] = q;
@@ -545,12 +530,12 @@ __global__ __launch_bounds__(64) void k_dtw_batch_wide(BatchArgs a) {
 // ------------------------------------------------------------------ batched certification
 __global__ __launch_bounds__(256) void k_cert_select_batch(BatchArgs a) {
     const uint32_t total = *a.nb_count;
-    const uint32_t cnt = total < (uint32_t)kNearBestCap ? total : (uint32_t)kNearBestCap;
+    const uint32_t cnt = total < a.nb_cap ? total : a.nb_cap;
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
         const int q = a.nb_q[e];
         if (a.nb_d[e] <= threshold_of(load_bsf(a.keys + q))) {
             const uint32_t pos = atomicAdd(a.cert_count, 1u);
-            if (pos < (uint32_t)kNearBestCap) {
+            if (pos < a.nb_cap) {
                 a.cert_idx[pos] = a.nb_idx[e];
                 a.cert_q[pos] = q;
             }
@@ -575,7 +560,7 @@ __global__ __launch_bounds__(256) void k_cert_dtw_batch(BatchArgs a) {
     extern __shared__ double sm[];
     __shared__ double red[4];
     const uint32_t cnt0 = *a.cert_count;
-    const uint32_t cnt = cnt0 < (uint32_t)kNearBestCap ? cnt0 : (uint32_t)kNearBestCap;
+    const uint32_t cnt = cnt0 < a.nb_cap ? cnt0 : a.nb_cap;
     const int tid = threadIdx.x, nt = blockDim.x;
     for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
         const int q = a.cert_q[e];
@@ -634,7 +619,7 @@ __global__ __launch_bounds__(256) void k_cert_reduce_batch(BatchArgs a) {
     __shared__ uint32_t si[4];
     const int q = blockIdx.x;
     const uint32_t cnt0 = *a.cert_count;
-    const uint32_t cnt = cnt0 < (uint32_t)kNearBestCap ? cnt0 : (uint32_t)kNearBestCap;
+    const uint32_t cnt = cnt0 < a.nb_cap ? cnt0 : a.nb_cap;
     double best = INFINITY;
     uint32_t bidx = 0xffffffffu;
     for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
@@ -670,8 +655,8 @@ __global__ __launch_bounds__(256) void k_cert_reduce_batch(BatchArgs a) {
             }
         a.res_idx[q] = bidx == 0xffffffffu ? -1 : (int64_t)bidx;
         a.res_dist[q] = best;
-        const bool overflow = *a.overflow || *a.nb_count > (uint32_t)kNearBestCap ||
-                              *a.cert_count > (uint32_t)kNearBestCap;
+        const bool overflow = *a.overflow || *a.nb_count > a.nb_cap ||
+                              *a.cert_count > a.nb_cap;
         a.res_status[q] = overflow ? DTWS_EOVERFLOW : (bidx == 0xffffffffu ? DTWS_EHIP : DTWS_OK);
         if (a.counters && q == 0) atomicAdd(&a.counters[7], (unsigned long long)cnt);
     }

@@ -95,6 +95,34 @@ struct StatsArr {
     }
 };
 
+// Appends the survivors of one wave (alive lanes, start i, query q) to the batch's survivor list;
+// an append past the capacity raises the overflow flag instead (the batch then falls back).
+struct EmitBatch {
+    int32_t *surv_q, *surv_i;
+    uint32_t *count, *qcnt, *overflow;
+    int64_t cap;
+    int q;
+    __device__ void operator()(bool alive, int64_t i) const {
+        const uint64_t mask = __ballot(alive);
+        if (!mask) return;
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        const uint32_t pc = (uint32_t)__popcll(mask);
+        uint32_t base = 0;
+        if (lane == leader) {
+            base = atomicAdd(count, pc);
+            if ((int64_t)base + pc > cap) atomicOr(overflow, 1u);
+            else atomicAdd(&qcnt[q], pc);
+        }
+        base = __shfl(base, leader, 64);
+        const int64_t pos = (int64_t)base + __popcll(mask & lanemask_lt());
+        if (alive && (int64_t)base + pc <= cap) {
+            surv_q[pos] = q;
+            surv_i[pos] = (int32_t)i;
+        }
+    }
+};
+
 // Query of wave w of DTW bucket c in the survivor segments (segments are query-major).
 __device__ inline int wave_query(const BatchArgs &a, int c, int64_t w, int32_t &wq0) {
     int lo = a.bucket_j[2 * c], hi = a.bucket_j[2 * c + 1];   // wstart[lo] <= w < wstart[hi]

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(128) void k_dtw_diag(BatchArgs a) {
         if (alive && D <= threshold_of(load_bsf(a.keys + q)) && lane == 0) {
             atomicMin((unsigned long long *)(a.keys + q), (unsigned long long)pack_key(D, (uint32_t)start));
             const uint32_t pos = atomicAdd(a.nb_count, 1u);
-            if (pos < (uint32_t)kNearBestCap) {
+            if (pos < a.nb_cap) {
                 a.nb_d[pos] = D;
                 a.nb_idx[pos] = (uint32_t)start;
                 a.nb_q[pos] = q;
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(64) void k_cert_diag(BatchArgs a) {
     using P = DiagPads<MAXCPL>;
     extern __shared__ double lds_d[];
     const uint32_t cnt0 = *a.cert_count;
-    const uint32_t cnt = cnt0 < (uint32_t)kNearBestCap ? cnt0 : (uint32_t)kNearBestCap;
+    const uint32_t cnt = cnt0 < a.nb_cap ? cnt0 : a.nb_cap;
     const int lane = threadIdx.x & 63;
     double *qb = lds_d + P::QLo;
     double *cb = qb + a.max_m + P::QHi + P::CLo;
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(128) void k_dtw_diag_list(DtwArgs a) {
             if (alive && D <= threshold_of(load_bsf(a.key)) && lane == 0) {
                 atomicMin((unsigned long long *)a.key, (unsigned long long)pack_key(D, (uint32_t)start));
                 const uint32_t pos = atomicAdd(a.nb_count, 1u);
-                if (pos < (uint32_t)kNearBestCap) {
+                if (pos < a.nb_cap) {
                     a.nb_d[pos] = D;
                     a.nb_idx[pos] = (uint32_t)start;
                 }
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(64) void k_cert_diag_list(CertArgs c) {
     using P = DiagPads<MAXCPL>;
     extern __shared__ double lds_d[];
     const uint32_t cnt0 = *c.cert_count;
-    const uint32_t cnt = cnt0 < (uint32_t)kNearBestCap ? cnt0 : (uint32_t)kNearBestCap;
+    const uint32_t cnt = cnt0 < c.nb_cap ? cnt0 : c.nb_cap;
     const int lane = threadIdx.x & 63;
     const int m = c.m, r = c.r;
     double *qb = lds_d + P::QLo;

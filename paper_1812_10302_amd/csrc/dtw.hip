@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_dtw(DtwArgs a) {
             if (valid && !bad && alive) {
                 atomicMin((unsigned long long *)a.key, (unsigned long long)pack_key(D, (uint32_t)start));
                 const uint32_t pos = atomicAdd(a.nb_count, 1u);
-                if (pos < (uint32_t)kNearBestCap) {
+                if (pos < a.nb_cap) {
                     a.nb_d[pos] = D;
                     a.nb_idx[pos] = (uint32_t)start;
                 }
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(64) void k_dtw_wide(DtwArgs a, float *rows, int64_t
             if (alive && D <= thr) {
                 atomicMin((unsigned long long *)a.key, (unsigned long long)pack_key(D, (uint32_t)start));
                 const uint32_t pos = atomicAdd(a.nb_count, 1u);
-                if (pos < (uint32_t)kNearBestCap) {
+                if (pos < a.nb_cap) {
                     a.nb_d[pos] = D;
                     a.nb_idx[pos] = (uint32_t)start;
                 }
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void k_certify(CertArgs c) {
     __syncthreads();
     const float thr = threshold_of(key_dist(*c.key));
     const uint32_t total = *c.nb_count;
-    const uint32_t cnt = total < (uint32_t)kNearBestCap ? total : (uint32_t)kNearBestCap;
+    const uint32_t cnt = total < c.nb_cap ? total : c.nb_cap;
     const int m = c.m, r = c.r;
     double *ch = c.scratch + (int64_t)tid * 3 * (m + 1);
     double *prev = ch + m, *cur = prev + (m + 1);
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_certify(CertArgs c) {
         }
         *c.res_idx = bi == 0xffffffffu ? -1 : (int64_t)bi;
         *c.res_dist = bd;
-        *c.res_status = total > (uint32_t)kNearBestCap ? DTWS_EOVERFLOW : (bi == 0xffffffffu ? DTWS_EHIP : DTWS_OK);
+        *c.res_status = total > c.nb_cap ? DTWS_EOVERFLOW : (bi == 0xffffffffu ? DTWS_EHIP : DTWS_OK);
         if (c.counters) atomicAdd(&c.counters[7], (unsigned long long)s_cert);
     }
 }
@@ -334,18 +334,17 @@ __global__ __launch_bounds__(256) void k_certify(CertArgs c) {
 // each anti-diagonal and synchronise between anti-diagonals.  Anti-diagonals are kept in a ring
 // of three row-indexed buffers of length L = r + 4 in LDS, next to the normalised query and
 // candidate (FP64, two-pass statistics as in eq. (Normalization1)).
-constexpr int kCertCap = kNearBestCap;
 constexpr int kCertBlocks = 64;
 constexpr int kCertThreads = 256;
 
 __global__ __launch_bounds__(256) void k_cert_select(CertArgs c) {
     const float thr = threshold_of(key_dist(*c.key));
     const uint32_t total = *c.nb_count;
-    const uint32_t cnt = total < (uint32_t)kNearBestCap ? total : (uint32_t)kNearBestCap;
+    const uint32_t cnt = total < c.nb_cap ? total : c.nb_cap;
     for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
         if (c.nb_d[e] <= thr) {
             const uint32_t pos = atomicAdd(c.cert_count, 1u);
-            if (pos < (uint32_t)kCertCap) c.cert_idx[pos] = c.nb_idx[e];
+            if (pos < c.nb_cap) c.cert_idx[pos] = c.nb_idx[e];
         }
     }
 }
@@ -367,7 +366,7 @@ __global__ __launch_bounds__(kCertThreads) void k_cert_dtw(CertArgs c) {
     const int m = c.m, r = c.r, L = r + 4;
     double *qh = sm, *ch = sm + m, *ring = sm + 2 * m;   // ring: 3 x L
     const uint32_t cnt0 = *c.cert_count;
-    const uint32_t cnt = cnt0 < (uint32_t)kCertCap ? cnt0 : (uint32_t)kCertCap;
+    const uint32_t cnt = cnt0 < c.nb_cap ? cnt0 : c.nb_cap;
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int j = tid; j < m; j += nt) qh[j] = c.qhat64[j];
     for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
@@ -424,7 +423,7 @@ __global__ __launch_bounds__(256) void k_cert_reduce(CertArgs c) {
     __shared__ double sd[256];
     __shared__ uint32_t si[256];
     const uint32_t cnt0 = *c.cert_count;
-    const uint32_t cnt = cnt0 < (uint32_t)kCertCap ? cnt0 : (uint32_t)kCertCap;
+    const uint32_t cnt = cnt0 < c.nb_cap ? cnt0 : c.nb_cap;
     double best = INFINITY;
     uint32_t bidx = 0xffffffffu;
     for (uint32_t e = threadIdx.x; e < cnt; e += blockDim.x) {
@@ -446,7 +445,7 @@ __global__ __launch_bounds__(256) void k_cert_reduce(CertArgs c) {
             }
         *c.res_idx = bidx == 0xffffffffu ? -1 : (int64_t)bidx;
         *c.res_dist = best;
-        const bool overflow = *c.nb_count > (uint32_t)kNearBestCap || cnt0 > (uint32_t)kCertCap;
+        const bool overflow = *c.nb_count > c.nb_cap || cnt0 > c.nb_cap;
         *c.res_status = overflow ? DTWS_EOVERFLOW : (bidx == 0xffffffffu ? DTWS_EHIP : DTWS_OK);
         if (c.counters) atomicAdd(&c.counters[7], (unsigned long long)cnt);
     }

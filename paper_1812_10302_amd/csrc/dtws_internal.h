@@ -101,6 +101,7 @@ struct LbArgs {
     const uint64_t *key;   // best-so-far key (threshold source) or null
     float fixed_thr;       // threshold when key is null
     float *out_kim, *out_kq, *out_kd;
+    uint64_t *out_key;     // stage values: (bits(max of the three bounds) << 32) | start, or null
     int32_t *surv;
     uint32_t *surv_count;
     unsigned long long *counters;
@@ -120,6 +121,8 @@ struct DtwArgs {
     const float *mu, *s, *o;     // per-window normalisation, or null to compute per lane
     float abandon_at;            // threshold of the stage entry point
     uint32_t diag_max;           // search rounds of at most this many survivors: one wave per candidate
+    uint32_t nb_cap;             // capacity of the near-best list (entries beyond it are dropped and
+                                 // the certification reports an overflow)
     float *dist_out;             // stage entry point output
     uint64_t *key;               // search mode: best-so-far key
     float *nb_d;
@@ -138,6 +141,7 @@ struct CertArgs {
     uint32_t *cert_idx; // [1024] compacted qualifying candidates
     uint32_t *cert_count;
     double *cert_d;     // [1024] their FP64 distances
+    uint32_t nb_cap;    // capacity of the near-best and certification lists
     int64_t *res_idx;
     double *res_dist;
     int32_t *res_status;
@@ -192,7 +196,17 @@ struct BatchArgs {
     float *wide_rows;
     int64_t wide_lanes;
     uint32_t diag_max;         // rounds with at most this many survivors use one wave per candidate
+    uint32_t nb_cap;           // capacity of the near-best and certification lists
     bool diag_wide;            // bands 112..255 always use one wave per candidate
+};
+
+// Tiled bound cascade (tile.hip): the queries of a batch grouped by length.
+struct TileArgs {
+    const int32_t *gfirst;   // [ngroups + 1]: group g's queries are qlist[gfirst[g] .. gfirst[g + 1])
+    const int32_t *qlist;    // query indices sorted by length
+    int ngroups;
+    int64_t c_lo, c_hi;      // candidate starts of the round, the same for every query
+    int halo;                // largest query length of the batch - 1
 };
 
 // ---------------------------------------------------------------- ordering network
@@ -237,6 +251,10 @@ hipError_t launch_znorm_stats(const float *T, int64_t n, int m, double *mu, doub
                               float *o32, hipStream_t s);
 hipError_t launch_series_env(const float *T, int64_t n, int r, float *U, float *L, hipStream_t s);
 hipError_t launch_lb(const LbArgs &a, int mode, int num_cu, hipStream_t s);
+hipError_t launch_lb_sorted_segment(const uint64_t *keys, int64_t a0, int64_t a1, const uint64_t *bsf_key,
+                                    int32_t *surv, uint32_t *count, int num_cu, hipStream_t s);
+hipError_t sort_keys_u64(void *temp, size_t &temp_bytes, const uint64_t *in, uint64_t *out, int64_t count,
+                         hipStream_t s);
 hipError_t launch_dtw(const DtwArgs &a, bool search, int64_t max_count, int num_cu, float *wide_rows,
                       int64_t wide_lanes, hipStream_t s);
 hipError_t launch_bsf_update(uint64_t *keys, const float *d, const int64_t *idx, int64_t count, int num_cu,
@@ -249,6 +267,8 @@ hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s);
 hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
                            bool natural, int blocks, hipStream_t s);
 hipError_t launch_segments(const BatchArgs &a, int num_cu, hipStream_t s);
+hipError_t launch_lb_tile(const BatchArgs &a, const TileArgs &t, bool prefix, int64_t max_N, hipStream_t s);
+size_t tile_lds_bytes(int max_m);
 hipError_t launch_dtw_bucket(const BatchArgs &a, bool prefix, int nc, int blocks, hipStream_t s);
 hipError_t launch_cert_batch(const BatchArgs &a, int max_m, int max_r, hipStream_t s);
 hipError_t mlp_init(const MlpBufs &b, uint64_t seed, hipStream_t s);
@@ -256,7 +276,7 @@ hipError_t mlp_refresh(const MlpBufs &b, hipStream_t s);
 hipError_t mlp_forward(const MlpBufs &b, const float *X, int64_t R, float *y, bool train, hipStream_t s);
 hipError_t mlp_backward(const MlpBufs &b, const float *X, const float *t, int64_t R, hipStream_t s);
 hipError_t mlp_adam(const MlpBufs &b, int step, float lr, hipStream_t s);
-hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArgs &sa, hipStream_t s);
+hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArgs &sa, bool paa_only, hipStream_t s);
 hipError_t launch_seed_learned(const BatchArgs &a, const ScoreArgs &sa, hipStream_t s);
 hipError_t launch_propose(const BatchArgs &a, const ScoreArgs &sa, float *X, int64_t *starts, hipStream_t s);
 constexpr int kDiagMaxBand = 1023;       // widest band of the one-wave-per-candidate kernels
@@ -275,6 +295,15 @@ hipError_t launch_reset_batch(uint64_t *keys, int nq, unsigned long long *counte
 // key of an empty best-so-far: distance +inf, index 0xFFFFFFFF
 constexpr uint64_t kEmptyKey = (uint64_t(0x7F800000u) << 32) | 0xFFFFFFFFull;
 
+}  // namespace dtws
+
+// Host helpers shared by the C ABI's translation units (defined in api.hip).
+namespace dtws {
+int64_t learned_block(const dtws_ctx *c);
+int64_t propose_rows(const dtws_ctx *c, int64_t n, int m);
+int enqueue_propose(dtws_ctx *c, const float *T, int64_t n, int m, int64_t *starts, float *X, hipStream_t s);
+QueryBufs query_bufs_of(dtws_ctx *c, int slot);
+void set_hip_error(dtws_ctx *c, hipError_t e, const char *what);
 }  // namespace dtws
 
 // Opaque context (declared in dtws.h).
@@ -343,10 +372,17 @@ struct dtws_ctx {
     int stats_prefix = 0;   // batched: 1 = window statistics always from the blocked prefix
     int data_envelope = 1;  // batched: 0 = skip the data-envelope bound
     int rounds = 4;         // batched: rounds over the work queue (4, 2 or 1)
+    int list_cap = 0;       // capacity of the near-best and batched survivor lists (0 = full size)
+    int lb_tile = 1;        // batched: tiled multi-query cascade for rounds over the same candidates
+    uint64_t *lbs_keys = nullptr;   // LB-sorted order: 2 x max_n keys and the sort's temporary storage,
+    void *lbs_temp = nullptr;       // allocated on first use
+    size_t lbs_temp_bytes = 0;
+    int32_t *tile_q = nullptr, *h_tile_q = nullptr;   // device / pinned: groups by length, then queries
     // ordering network
     dtws::MlpBufs mlp{};
     bool has_model = false;
     int model_step = 0;
+    int64_t model_block = 0;   // work-item block the model was trained with (0: none recorded)
     float *qpaa = nullptr, *score = nullptr;
     int32_t *sstart = nullptr, *bstart = nullptr;
     int64_t *row_off = nullptr, *h_row_off = nullptr;

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(256) void k_lb_values(LbArgs a, QView v) {
         if (a.out_kim) a.out_kim[i] = kim;
         if (a.out_kq) a.out_kq[i] = kq;
         if (a.out_kd) a.out_kd[i] = kd;
+        if (a.out_key) a.out_key[i] = ((uint64_t)__float_as_uint(fmaxf(fmaxf(kim, kq), kd)) << 32) | (uint64_t)i;
     }
 }
 
@@ -90,6 +91,35 @@ __global__ __launch_bounds__(256) void k_lb_prune(LbArgs a, QView v) {
             atomicAdd(&a.counters[3], c_kd);
         }
     }
+}
+
+// One segment [a0, a1) of the LB-sorted candidate list (keys ascending: (bits(LB) << 32) | start,
+// LB >= 0 so its bits order like its value): the leading candidates whose bound lies within the
+// pruning slack of the current best-so-far go to surv, their number to *count; the rest of the
+// segment (and every later one) is pruned.
+__global__ __launch_bounds__(256) void k_lbs_segment(const uint64_t *keys, int64_t a0, int64_t a1,
+                                                     const uint64_t *bsf_key, int32_t *surv, uint32_t *count) {
+    const float thr = threshold_of(key_dist(*bsf_key));
+    const uint64_t lim = ((uint64_t)__float_as_uint(thr) << 32) | 0xFFFFFFFFull;   // keys with LB <= thr
+    int64_t lo = a0, hi = a1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] > lim) hi = mid;
+        else lo = mid + 1;
+    }
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = a0 + gtid; k < lo; k += stride) surv[k - a0] = (int32_t)(keys[k] & 0xFFFFFFFFull);
+    if (gtid == 0) *count = (uint32_t)(lo - a0);
+}
+
+hipError_t launch_lb_sorted_segment(const uint64_t *keys, int64_t a0, int64_t a1, const uint64_t *bsf_key,
+                                    int32_t *surv, uint32_t *count, int num_cu, hipStream_t s) {
+    int64_t blocks = (a1 - a0 + 255) / 256;
+    if (blocks > num_cu * 4) blocks = num_cu * 4;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_lbs_segment, dim3((unsigned)blocks), dim3(256), 0, s, keys, a0, a1, bsf_key, surv, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_lb(const LbArgs &a, int mode, int num_cu, hipStream_t s) {

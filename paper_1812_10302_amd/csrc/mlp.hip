@@ -897,8 +897,28 @@ hipError_t mlp_adam(const MlpBufs &b, int step, float lr, hipStream_t s) {
     return e;
 }
 
-// Scores every block of every query of the batch and writes the visiting order into a.perm.
-hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArgs &sa, hipStream_t s) {
+// PAA score of a feature row (the learned order's control): the squared Euclidean distance of its
+// query half to its candidate half, as log(d + 1e-4) (a monotone map that spreads the small
+// distances over the order's buckets the way the network's log target does).
+__global__ void k_paa_score(const float *X, int64_t R, float *y) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= R) return;
+    const float4 *x = (const float4 *)(X + k * 32);
+    float d = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float4 a = x[t], c = x[t + 4];
+        d = fmaf(a.x - c.x, a.x - c.x, d);
+        d = fmaf(a.y - c.y, a.y - c.y, d);
+        d = fmaf(a.z - c.z, a.z - c.z, d);
+        d = fmaf(a.w - c.w, a.w - c.w, d);
+    }
+    y[k] = logf(d + 1e-4f);
+}
+
+// Scores every block of every query of the batch and writes the visiting order into a.perm: by the
+// network's prediction, or (paa_only) by the proposals' PAA distance.
+hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArgs &sa, bool paa_only, hipStream_t s) {
     hipLaunchKernelGGL(k_query_paa, dim3(a.nq), dim3(64), 0, s, a, sa.qpaa);
     const int64_t chunk = kMlpChunk / sa.K * sa.K;
     for (int64_t r0 = 0; r0 < sa.total_rows; r0 += chunk) {
@@ -907,8 +927,12 @@ hipError_t mlp_order_blocks(const MlpBufs &b, const BatchArgs &a, const ScoreArg
             hipLaunchKernelGGL(k_propose<true>, dim3(nblk(R / kScoreSamples * 64)), dim3(256), 0, s, a, sa, r0, R, b.Xf);
         if (sa.kinds & 2u)
             hipLaunchKernelGGL(k_propose<false>, dim3(nblk(R / kScoreSamples * 64)), dim3(256), 0, s, a, sa, r0, R, b.Xf);
-        hipError_t e = mlp_forward(b, b.Xf, R, b.y, false, s);
-        if (e != hipSuccess) return e;
+        if (paa_only) {
+            hipLaunchKernelGGL(k_paa_score, dim3(nblk(R)), dim3(256), 0, s, b.Xf, R, b.y);
+        } else {
+            hipError_t e = mlp_forward(b, b.Xf, R, b.y, false, s);
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(k_block_min, dim3(nblk(R / sa.K)), dim3(256), 0, s, b.y, sa.sstart, R, sa.K, r0, sa.score,
                            sa.bstart);
     }

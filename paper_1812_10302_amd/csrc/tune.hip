@@ -17,8 +17,8 @@ constexpr int32_t kDiagMaxes[] = {0, 2048, 16384, 65536};
 constexpr int32_t kLbWidths[] = {4, 8, 16, 32};
 constexpr int32_t kDtwWidths[] = {2, 4, 8};
 constexpr int32_t kRounds[] = {4, 2, 1};
-constexpr int kKnobs = 7;
-constexpr int kKnobValues[kKnobs] = {4, 4, 4, 3, 2, 2, 3};
+constexpr int kKnobs = 8;
+constexpr int kKnobValues[kKnobs] = {4, 4, 4, 3, 2, 2, 3, 2};
 
 bool valid_block(int64_t b) {
     if (b == 0) return true;
@@ -47,6 +47,8 @@ DTWS_API int dtws_get_schedule(dtws_ctx *c, dtws_schedule *out) {
     out->stats_prefix = c->stats_prefix;
     out->data_envelope = c->data_envelope;
     out->rounds = c->rounds;
+    out->list_cap = c->list_cap;
+    out->lb_tile = c->lb_tile;
     out->reserved = 0;
     return DTWS_OK;
 }
@@ -56,7 +58,8 @@ DTWS_API int dtws_set_schedule(dtws_ctx *c, const dtws_schedule *s) {
     if (!valid_block(s->block) || s->lb_blocks_per_cu < 0 || s->lb_blocks_per_cu > 64 || s->dtw_blocks_per_cu < 0 ||
         s->dtw_blocks_per_cu > 64 || s->diag_max < -1 || s->diag_max > (1 << 24) ||
         (s->band_lanes != 0 && s->band_lanes != 1 && s->band_lanes != 64) || (s->stats_prefix != 0 && s->stats_prefix != 1) ||
-        (s->data_envelope != 0 && s->data_envelope != 1) || (s->rounds != 1 && s->rounds != 2 && s->rounds != 4))
+        (s->data_envelope != 0 && s->data_envelope != 1) || (s->rounds != 1 && s->rounds != 2 && s->rounds != 4) ||
+        (s->list_cap != 0 && (s->list_cap < 64 || s->list_cap > (1 << 20))) || (s->lb_tile != 0 && s->lb_tile != 1))
         return DTWS_EINVAL;
     c->block = s->block;
     c->lb_blocks_per_cu = s->lb_blocks_per_cu;
@@ -66,6 +69,13 @@ DTWS_API int dtws_set_schedule(dtws_ctx *c, const dtws_schedule *s) {
     c->stats_prefix = s->stats_prefix;
     c->data_envelope = s->data_envelope;
     c->rounds = s->rounds;
+    if (s->list_cap != c->list_cap && c->graph_exec) {
+        // the capacity is baked into the captured graph's kernel arguments
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+    }
+    c->list_cap = s->list_cap;
+    c->lb_tile = s->lb_tile;
     return DTWS_OK;
 }
 
@@ -108,9 +118,12 @@ DTWS_API int dtws_autotune_batch(dtws_ctx *c, const float *T, int64_t n, const f
             case 3: t.dtw_blocks_per_cu = kDtwWidths[v]; break;
             case 4: t.stats_prefix = v; break;
             case 5: t.data_envelope = 1 - v; break;
-            default: t.rounds = kRounds[v]; break;
+            case 6: t.rounds = kRounds[v]; break;
+            default: t.lb_tile = 1 - v; break;
             }
             if (memcmp(&t, &base, sizeof(t)) == 0) continue;
+            // the learned order keeps the block its model was trained with
+            if (knob == 1 && (flags & DTWS_ORDER_MASK) == DTWS_ORDER_LEARNED && c->model_block > 0) continue;
             double ms = 0.0;
             rc = run(t, got, ms);
             if (rc != DTWS_OK) break;

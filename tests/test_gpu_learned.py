@@ -3,7 +3,7 @@
 Tolerances: the reference rounds to bfloat16 at the same points as the kernels, so the remaining
 differences are FP32-vs-FP64 accumulation and the occasional bfloat16 rounding of an activation
 that falls on the other side of a rounding boundary; forward values agree to ~1e-3 relative and
-gradients to ~1e-2 in relative L2 norm per parameter block.
+gradients element by element to 1e-2 of each parameter block's largest entry plus 2e-2 relative.
 """
 import numpy as np
 import pytest
@@ -93,8 +93,16 @@ def test_gradients_match_reference(ctx, rows):
     assert loss == pytest.approx(want_loss, rel=2e-3)
     got_b, want_b = _blocks(g.cpu().numpy().astype(np.float64)), _blocks(want)
     for name, _ in M.SHAPES:
-        err = np.linalg.norm(got_b[name] - want_b[name]) / max(np.linalg.norm(want_b[name]), 1e-12)
-        assert err < 2e-2, (name, err)
+        gb, wb = got_b[name], want_b[name]
+        # element by element: an absolute floor of 1e-2 of the block's largest reference entry
+        # (bfloat16 rounding of an activation flips at a few rows) plus 2e-2 relative
+        tol = 1e-2 * np.abs(wb).max() + 2e-2 * np.abs(wb)
+        err = np.abs(gb - wb)
+        worst = int(np.argmax(err - tol))
+        print(f"{name}: worst element {worst}: gpu {gb[worst]:.6g} ref {wb[worst]:.6g} "
+              f"(|diff| {err[worst]:.3g}, tolerance {tol[worst]:.3g}); max |diff| / max|ref| "
+              f"{err.max() / max(np.abs(wb).max(), 1e-300):.3g}")
+        assert np.all(err <= tol), (name, worst, gb[worst], wb[worst])
 
 
 def test_adam_step_matches_reference(ctx):
@@ -140,27 +148,75 @@ def test_proposals_match_oracle(ctx):
 
 
 def test_training_reduces_loss(ctx):
-    T = W.sinusoid_mix(1_000_000, 51)
-    X, Y = proposal.make_pairs(ctx, T, 128, 6, 40, seed=52)
-    curve = proposal.train(ctx, X, Y, epochs=6, batch=2048, lr=2e-3, seed=53)
+    """Training through the C ABI (pairs, labels, targets, shuffling and Adam in the library): the
+    loss falls, the pair count is the recipe's, and the same seed gives the same curve."""
+    T = dev(W.sinusoid_mix(1_000_000, 51))
+    ctx.set_schedule(block=4096)
+    curve, pairs = ctx.model_train(T, [(128, 6)], 40, epochs=6, seed=53, batch=2048, lr=2e-3)
+    print("loss curve:", [round(v, 4) for v in curve], "pairs", pairs)
     assert curve[-1] < 0.5 * curve[0], curve
+    # 40 queries: 977 blocks x 4 proposals (the last block's empty quarters dropped) + 256 random,
+    # + 64 near-source starts for the 30 cut queries
+    props = (1_000_000 - 128 + 1 + 1023) // 1024
+    assert pairs == 40 * (props + 256) + 30 * 64
+    again, pairs2 = ctx.model_train(T, [(128, 6)], 40, epochs=6, seed=53, batch=2048, lr=2e-3)
+    assert pairs2 == pairs
+    np.testing.assert_allclose(again, curve, rtol=1e-5)
+
+
+def test_training_labels_are_exact_dtw(ctx):
+    """Training labels a pair with the library's non-abandoning banded DTW of the query against the
+    candidate (the same kernels dtws_dtw_band runs): on the proposals of a query those distances
+    are the oracle's."""
+    T = W.random_walk(200_000, 54)
+    Q = W.noisy_cut(T, 77_777, 256, 0.1, 55)
+    Td, Qd = dev(T), dev(Q)
+    st, _ = ctx.propose(Td, Qd)
+    st = st[st >= 0]
+    d = ctx.dtw_band(Td, Qd, 12, st).cpu().numpy()
+    want = R.distances_at(T, Q, 12, st.cpu().numpy())
+    np.testing.assert_allclose(d, want, rtol=1e-4, atol=1e-5)
+
+
+def test_model_save_load_roundtrip(ctx):
+    T = dev(W.random_walk(300_000, 56))
+    ctx.set_schedule(block=8192)
+    ctx.model_train(T, [(128, 6)], 8, epochs=1, seed=57, batch=1024)
+    blob = ctx.model_save()
+    params = ctx.model_get()
+    assert len(blob) == 64 + 4 * dtws.MODEL_PARAMS and blob[:8] == b"DTWSMLP1"
+    ctx.model_init(1)
+    assert not np.array_equal(ctx.model_get(), params)
+    ctx.model_load(blob)
+    np.testing.assert_array_equal(ctx.model_get(), params)
+    bad = bytearray(blob)
+    bad[100] ^= 1                      # one flipped bit in the parameters: the hash rejects it
+    with pytest.raises(dtws.DtwsError):
+        ctx.model_load(bytes(bad))
+    with pytest.raises(dtws.DtwsError):
+        ctx.model_load(blob[:-4])
+    np.testing.assert_array_equal(ctx.model_get(), params)
+    ctx.set_schedule(block=4096)
 
 
 def test_learned_order_identical_results_and_gain(ctx):
-    """Same best matches under natural, random and learned block orders; the trained ordering
-    reaches a tight best-so-far earlier and starts fewer DTW cells than the natural order."""
-    train_T = W.sinusoid_mix(2_000_000, 61)
-    X, Y = proposal.make_pairs(ctx, train_T, 256, 12, 120, seed=62)
-    proposal.train(ctx, X, Y, epochs=10, batch=4096, lr=1e-3, seed=63)
+    """Same best matches under natural, random, PAA and learned block orders.  The trained ordering
+    starts fewer DTW cells than the natural order; against its own input ordering (the same
+    proposals ranked by PAA distance, no network) the cells of both are reported and the learned
+    order must not start more."""
+    ctx.set_schedule(block=4096)
+    train_T = dev(W.sinusoid_mix(2_000_000, 61))
+    ctx.model_train(train_T, [(256, 12)], 120, epochs=10, seed=63)
     T = W.sinusoid_mix(2_500_000, 64)
     wl = W.mixed_queries(T, nq=12, m=256, seed=65)
     Td = dev(T)
     pq = dtws.PackedQueries([dev(q) for q in wl.queries])
     res, cells = {}, {}
     for name, flag in (("natural", dtws.ORDER_NATURAL), ("random", dtws.ORDER_RANDOM),
-                       ("learned", dtws.ORDER_LEARNED)):
+                       ("paa", dtws.ORDER_PAA), ("learned", dtws.ORDER_LEARNED)):
         res[name] = ctx.search_batch(Td, pq, wl.bands, flags=flag | dtws.NO_GRAPH, seed=5)
         cells[name] = ctx.counters()["dtw_cells"]
-    assert res["learned"] == res["natural"] == res["random"]
+    assert res["learned"] == res["natural"] == res["random"] == res["paa"]
     print("DTW cells by order:", cells)
     assert cells["learned"] < cells["natural"]
+    assert cells["learned"] <= cells["paa"]

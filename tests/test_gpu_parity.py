@@ -417,10 +417,72 @@ def test_schedules_give_identical_results(ctx, casc):
         ctx.set_schedule(**default)
 
 
+def test_tiled_cascade_equals_per_query_items(ctx, casc):
+    """The tiled cascade (one LDS-staged series tile shared by every query of a length) against the
+    per-query work items and the oracle: seven queries in four length groups (the longest, m = 2048,
+    with a 2047-point halo), a series that ends inside a tile, statistics from the per-length arrays
+    and from the prefix, the data envelope on and off, four rounds and one, series and random order."""
+    n = 7 * 2048 * 9 + 1_234
+    T = W.random_walk(n, 38)
+    specs = [(64, 3), (64, 0), (64, 12), (200, 20), (200, 5), (2048, 102), (1000, 255)]
+    qs = [W.noisy_cut(T, (13_331 * (k + 1)) % (n - m), m, 0.1, 980 + k) if k % 3 else W.random_walk(m, 990 + k)
+          for k, (m, _) in enumerate(specs)]
+    qs.append(W.noisy_cut(T, n - 64, 64, 0.01, 999))            # a match at the very end of the series
+    specs.append((64, 3))
+    rs = [r for _, r in specs]
+    ref = _cascade_refs(casc, T, qs, rs)
+    Td = dev(T)
+    Qd = [dev(q) for q in qs]
+    default = ctx.get_schedule()
+    try:
+        for sched in ({"lb_tile": 1}, {"lb_tile": 0}, {"lb_tile": 1, "stats_prefix": 1},
+                      {"lb_tile": 1, "data_envelope": 0}, {"lb_tile": 1, "rounds": 1, "block": 2048},
+                      {"lb_tile": 1, "rounds": 2, "block": 16384, "stats_prefix": 1, "data_envelope": 0}):
+            ctx.set_schedule(**sched)
+            print("tiled cascade schedule", sched, flush=True)
+            for order in (dtws.ORDER_NATURAL, dtws.ORDER_RANDOM):
+                _check_batch(ctx.search_batch(Td, Qd, rs, flags=order, seed=9), ref)
+            assert ctx.counters()["fallbacks"] == 0
+    finally:
+        ctx.set_schedule(**default)
+    ctx.search_batch(Td, Qd, rs)
+    c = ctx.counters()
+    assert c["lb_terms"] > 0 and c["pruned_kim"] + c["pruned_keogh_q"] + c["pruned_keogh_d"] > 0
+
+
+@pytest.mark.parametrize("n,m,r,seed", [(3000, 40, 4, 41), (5000, 128, 0, 42), (4000, 200, 199, 43),
+                                        (20_000, 512, 25, 44), (64, 64, 3, 45)])
+def test_lb_sorted_order_matches_oracle(ctx, n, m, r, seed):
+    """The Prepare / Improve scheme with the candidates in ascending order of their bound returns the
+    oracle's match (plain, and batched query by query)."""
+    T, Q = W.tiny_random(n, m, seed)
+    i_ref, d_ref = R.best_match(T, Q, r)
+    idx, dist = ctx.search(dev(T), dev(Q), r, flags=dtws.LB_SORTED, seed=seed)
+    assert idx == i_ref, (idx, i_ref, dist, d_ref)
+    assert abs(dist - d_ref) <= 1e-9 * d_ref + 1e-12
+    got = ctx.search_batch(dev(T), [dev(Q), dev(Q)], [r, 0], flags=dtws.LB_SORTED)
+    assert got[0] == (idx, dist)
+    i0, d0 = R.best_match(T, Q, 0)
+    assert got[1][0] == i0 and abs(got[1][1] - d0) <= 1e-9 * d0 + 1e-12
+
+
+def test_lb_sorted_order_single_query_workload(ctx, small_wl):
+    """n = 262,144, m = 128, r = 6: the LB-sorted order against the brute-force oracle, with the
+    DTW count it needs (the bound's order reaches the best match among the first candidates)."""
+    wl, D = small_wl
+    i_ref = int(np.argmin(D))
+    idx, dist = ctx.search(dev(wl.T), dev(wl.queries[0]), wl.bands[0], flags=dtws.LB_SORTED, seed=4)
+    assert idx == i_ref and abs(dist - D[i_ref]) <= 1e-9 * D[i_ref]
+    sorted_dtw = ctx.counters()["dtw_started"]
+    ctx.search(dev(wl.T), dev(wl.queries[0]), wl.bands[0], seed=4)
+    print(f"DTW started: LB-sorted {sorted_dtw}, series order {ctx.counters()['dtw_started']}")
+    assert sorted_dtw <= ctx.counters()["dtw_started"]
+
+
 def test_set_schedule_rejects_bad_fields(ctx):
     default = ctx.get_schedule()
     for bad in ({"block": 3000}, {"diag_max": -2}, {"band_lanes": 2}, {"lb_blocks_per_cu": 65},
-                {"stats_prefix": 2}, {"data_envelope": -1}, {"rounds": 3}):
+                {"stats_prefix": 2}, {"data_envelope": -1}, {"rounds": 3}, {"list_cap": 63}, {"lb_tile": 2}):
         with pytest.raises(dtws.DtwsError):
             ctx.set_schedule(**bad)
         assert ctx.get_schedule() == default
