@@ -93,7 +93,8 @@ def workload(name: str):
     return wl, train
 
 
-def measure(wl, train, steps: int, warmup: int, plain_queries: int, profile: bool, log_prefix: str = ""):
+def measure(wl, train, steps: int, warmup: int, plain_queries: int, profile: bool, log_prefix: str = "",
+            fixed_schedule: dict | None = None):
     """Times the batched learned search (or the batched natural one when there is no training
     recipe), the plain search on a seeded subset, and the ablation orders.  Returns a dict."""
     import torch
@@ -105,7 +106,9 @@ def measure(wl, train, steps: int, warmup: int, plain_queries: int, profile: boo
     ms = [int(q.size) for q in wl.queries]
     rs = [int(r) for r in wl.bands]
     nq = len(Qs)
-    ctx = dtws.Context(0, max_n=wl.T.size, max_m=max(ms), max_queries=nq)
+    # the context holds the longest query of the workload and of the training recipe
+    max_m = max(ms + ([m for m, _ in train[1]] if train is not None else []))
+    ctx = dtws.Context(0, max_n=wl.T.size, max_m=max_m, max_queries=nq)
     pq = dtws.PackedQueries(Qs)
     out = {"workload": wl.name, "n": int(wl.T.size), "queries": nq, "m": sorted(set(ms)),
            "r": [min(rs), max(rs)]}
@@ -125,10 +128,16 @@ def measure(wl, train, steps: int, warmup: int, plain_queries: int, profile: boo
         log(f"{log_prefix}ordering network: {pairs} pairs, loss {curve[0]:.4f} -> {curve[-1]:.4f} "
             f"({time.time() - t0:.1f}s)")
         order = dtws.ORDER_LEARNED
-    # launch schedule picked by the library's autotuner (untimed; the learned order keeps its block)
+    # launch schedule picked by the library's autotuner (untimed; the learned order keeps its block),
+    # or the one given on the command line
     t0 = time.time()
-    schedule, tune_ms = ctx.autotune_batch(T, pq, rs, flags=order, seed=7, reps=1)
-    log(f"{log_prefix}autotuned {schedule} ({tune_ms:.2f} ms per batch, {time.time() - t0:.1f}s)")
+    if fixed_schedule:
+        ctx.set_schedule(**fixed_schedule)
+        schedule = ctx.get_schedule()
+        log(f"{log_prefix}schedule {schedule} (given)")
+    else:
+        schedule, tune_ms = ctx.autotune_batch(T, pq, rs, flags=order, seed=7, reps=1)
+        log(f"{log_prefix}autotuned {schedule} ({tune_ms:.2f} ms per batch, {time.time() - t0:.1f}s)")
     out["schedule"] = schedule
 
     def step(flags=0):
@@ -189,6 +198,10 @@ def measure(wl, train, steps: int, warmup: int, plain_queries: int, profile: boo
     out["results"] = [[int(i), float(d)] for i, d in results]
     out["_ctx"], out["_T"], out["_Qs"] = ctx, T, Qs
     return out
+
+
+# seeded query subsets the oracle runs on at full n for the smaller workloads (m <= 1024)
+ORACLE_SUBSET = {"rw262144_1q": [0], "rw1e8_3q": [0, 1, 2], "mix1e8_64q": [0, 40], "rw1e8_256q": [7, 25, 198]}
 
 
 def roofline_of(meas):
@@ -256,6 +269,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=250_000_000, help="series points of the CPU baseline")
+    ap.add_argument("--schedule", default=None,
+                    help="JSON object of schedule fields for the main workload instead of the autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search shards by "
@@ -267,7 +282,8 @@ def main():
     t0 = time.time()
     wl, train = workload(args.workload)
     log(f"workload {wl.name}: generated in {time.time() - t0:.1f}s")
-    meas = measure(wl, train, args.steps, args.warmup, args.plain_queries, not args.no_profile)
+    meas = measure(wl, train, args.steps, args.warmup, args.plain_queries, not args.no_profile,
+                   fixed_schedule=json.loads(args.schedule) if args.schedule else None)
     ctx, T, Qs = meas.pop("_ctx"), meas.pop("_T"), meas.pop("_Qs")
     log(f"{wl.name}: {meas['step_ms']} ms per step, {meas['batched_s_per_query']} s/query batched, "
         f"{meas['plain_s_per_query']} s/query plain")
@@ -314,10 +330,25 @@ def main():
             m2 = measure(w2, tr2, 3, 1, 3, False, log_prefix=f"[{name}] ")
             c2 = m2.pop("_ctx")
             c2.close()
-            m2.pop("_T"), m2.pop("_Qs"), m2.pop("results")
+            m2.pop("_T"), m2.pop("_Qs")
+            res2 = m2.pop("results")
             torch.cuda.empty_cache()
+            if not args.no_cpu_baseline:
+                # the oracle at full n on a seeded subset of the queries (the same answers required)
+                from oracle import Cascade
+                casc = Cascade()
+                nq2 = len(w2.queries)
+                sub = ORACLE_SUBSET.get(name, list(range(nq2)))
+                t1 = time.perf_counter()
+                for k in sub:
+                    got = casc.search(w2.T, w2.queries[k], int(w2.bands[k]))[:2]
+                    assert got[0] == res2[k][0] and abs(got[1] - res2[k][1]) <= 1e-9 * got[1] + 1e-12, (name, k)
+                m2["oracle_s_per_query"] = round((time.perf_counter() - t1) / len(sub), 3)
+                m2["oracle_queries"] = sub
+                m2["oracle_cores"] = casc.num_threads()
             others[name] = m2
-            log(f"[{name}] {m2['step_ms']} ms per step ({time.time() - t0:.1f}s)")
+            log(f"[{name}] {m2['step_ms']} ms per step, oracle {m2.get('oracle_s_per_query')} s/query "
+                f"({time.time() - t0:.1f}s)")
 
     out = {
         "metric": METRIC,

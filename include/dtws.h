@@ -273,9 +273,11 @@ DTWS_API int dtws_autotune_batch(dtws_ctx *ctx, const float *T_dev, int64_t n, c
  * Not part of the paper's method: a network scores blocks of candidates so that
  * DTWS_ORDER_LEARNED visits the most promising blocks first; the bounds and the
  * exact DTW still decide, so results equal those of the natural order.
- * Model: y = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3, x = (16-segment PAA of
- * the normalised query, 16-segment PAA of the normalised candidate), segment t
- * of a length-m window = positions [floor(t m / 16), floor((t+1) m / 16)),
+ * Model: y = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3 + log(d(x) / 16 + 1e-4),
+ * x = (16-segment PAA of the normalised query, 16-segment PAA of the normalised
+ * candidate), segment t of a length-m window = positions [floor(t m / 16),
+ * floor((t+1) m / 16)), d(x) = sum_t (x_t - x_{t+16})^2 (FP32) the squared PAA
+ * distance: the network learns a correction to the logarithm of the PAA distance,
  * trained on y* = log(DTW / m + 1e-4) (dtws_model_train below, or the caller's own recipe through
  * dtws_model_train_step).  Products in bfloat16 on the matrix cores
  * with FP32 accumulation; FP32 master parameters; Adam (beta 0.9 / 0.999,
@@ -285,7 +287,9 @@ DTWS_API int dtws_autotune_batch(dtws_ctx *ctx, const float *T_dev, int64_t n, c
 #define DTWS_MODEL_PARAMS 74497
 #define DTWS_MODEL_MAX_ROWS 65536   /* rows per dtws_model_grad / dtws_model_train_step */
 
-/* He-normal initialisation from a seed (counter-based; deterministic). */
+/* He-normal initialisation of the hidden layers from a seed (counter-based; deterministic), zero
+ * biases and a zero output layer (w3, b3): the initial model orders exactly by its PAA-distance
+ * term. */
 DTWS_API int dtws_model_init(dtws_ctx *ctx, uint64_t seed);
 
 /* Copy the FP32 parameters out of / into the context (count = DTWS_MODEL_PARAMS).

@@ -22,7 +22,9 @@
  *     row of the band whose every cell exceeds it proves DTW > bsf, because
  *     every warping path crosses every row and costs are non-negative.
  *   - threads: the candidates are split into contiguous segments, one per
- *     thread (the paper's static OpenMP partition, Section 3.3).  Threads
+ *     thread (the paper's static OpenMP partition, Section 3.3).  A thread
+ *     scans its segment in two passes, every 64th start first, then the rest,
+ *     so that it meets a close match early.  Threads
  *     share the best-so-far value for pruning through an atomic; each keeps
  *     its own best (distance, index) and the results are reduced by minimum
  *     distance, then lowest index.
@@ -66,15 +68,17 @@ static void window_moments(const float *x, int m, double *mu_out, double *sigma_
     *sigma_out = sqrt(v);
 }
 
-/* normalised value of one point: (t - mu) / sigma, or 0 for a flat window (sigma <= 1e-8) */
-static inline double znorm_point(float t, double mu, double sigma) {
-    return sigma <= SIGMA_FLAT ? 0.0 : ((double)t - mu) / sigma;
-}
+/* 1 / sigma, or 0 for a flat window (sigma <= 1e-8): a flat window normalises to zeros */
+static inline double inv_sigma(double sigma) { return sigma <= SIGMA_FLAT ? 0.0 : 1.0 / sigma; }
+
+/* normalised value of one point, (t - mu) / sigma as (t - mu) * (1 / sigma) */
+static inline double znorm_point(float t, double mu, double inv) { return ((double)t - mu) * inv; }
 
 static void znorm_window(const float *x, int m, double *out) {
     double mu, sigma;
     window_moments(x, m, &mu, &sigma);
-    for (int j = 0; j < m; ++j) out[j] = znorm_point(x[j], mu, sigma);
+    const double inv = inv_sigma(sigma);
+    for (int j = 0; j < m; ++j) out[j] = znorm_point(x[j], mu, inv);
 }
 
 static void envelope(const double *x, int m, int r, double *U, double *L) {
@@ -88,11 +92,11 @@ static void envelope(const double *x, int m, int r, double *U, double *L) {
 
 /* eq. (LBKeoghEC) for the window x[0..m) normalised with (mu, sigma) point by point as it goes,
  * with early abandon once the partial sum exceeds thr (the values are znorm_point's). */
-static double lb_keogh_window(const float *x, double mu, double sigma, const double *U, const double *L, int m,
+static double lb_keogh_window(const float *x, double mu, double inv, const double *U, const double *L, int m,
                               double thr) {
     double s = 0.0;
     for (int i = 0; i < m; ++i) {
-        double c = znorm_point(x[i], mu, sigma);
+        double c = znorm_point(x[i], mu, inv);
         if (c > U[i]) { double d = c - U[i]; s += d * d; }
         else if (c < L[i]) { double d = c - L[i]; s += d * d; }
         if (s > thr) return s;
@@ -142,6 +146,18 @@ static double dtw_band(const double *x, const double *y, int m, int r, double th
 static inline uint64_t dbits(double d) { uint64_t u; memcpy(&u, &d, 8); return u; }
 static inline double bitsd(uint64_t u) { double d; memcpy(&d, &u, 8); return d; }
 
+/* Position number `it` of a thread's scan of its segment [a, b): first every SCAN_STRIDE-th start
+ * (a, a + SCAN_STRIDE, ...), then the others in order.  Any order gives the same exact result
+ * (ties are resolved by index); sampling the whole segment first finds a close match, and with it
+ * a tight best-so-far, early. */
+#define SCAN_STRIDE 64
+static inline int64_t scan_position(int64_t a, int64_t b, int64_t it) {
+    const int64_t len = b - a, first = (len + SCAN_STRIDE - 1) / SCAN_STRIDE;
+    if (it < first) return a + it * SCAN_STRIDE;
+    it -= first;   /* the it-th start that is not a multiple of the stride past a */
+    return a + (it / (SCAN_STRIDE - 1)) * SCAN_STRIDE + 1 + it % (SCAN_STRIDE - 1);
+}
+
 /* Shared best-so-far (a non-negative double: its bit pattern orders like the value). */
 static void publish_bsf(uint64_t *g, double d) {
     uint64_t nb = dbits(d), cur = __atomic_load_n(g, __ATOMIC_RELAXED);
@@ -172,7 +188,8 @@ int oc_search(const float *T, int64_t n, const float *Q, int32_t m, int32_t r, i
         double *ch = buf, *Uc = buf + m, *Lc = buf + 2 * m, *prev = buf + 3 * m, *cur = buf + 4 * m + 2;
         double best = INFINITY;
         int64_t bidx = -1, c[6] = {0, 0, 0, 0, 0, 0};
-        for (int64_t i = a; i < b; ++i) {
+        for (int64_t it = 0; it < b - a; ++it) {
+            const int64_t i = scan_position(a, b, it);
             c[0]++;
             double bsf = bitsd(__atomic_load_n(&gbsf, __ATOMIC_RELAXED));
             if (best < bsf) bsf = best;
@@ -181,18 +198,19 @@ int oc_search(const float *T, int64_t n, const float *Q, int32_t m, int32_t r, i
              * window is normalised once the candidate survives it */
             double mu, sigma;
             window_moments(T + i, m, &mu, &sigma);
-            double c0 = znorm_point(T[i], mu, sigma), cl = znorm_point(T[i + m - 1], mu, sigma);
+            const double inv = inv_sigma(sigma);
+            double c0 = znorm_point(T[i], mu, inv), cl = znorm_point(T[i + m - 1], mu, inv);
             double lk = (m == 1) ? (qh[0] - c0) * (qh[0] - c0)
                                  : (qh[0] - c0) * (qh[0] - c0) + (qh[m - 1] - cl) * (qh[m - 1] - cl);
             if (lk > thr) { c[1]++; continue; }
-            if (lb_keogh_window(T + i, mu, sigma, U, Lq, m, thr) > thr) { c[2]++; continue; }
-            for (int j = 0; j < m; ++j) ch[j] = znorm_point(T[i + j], mu, sigma);
+            if (lb_keogh_window(T + i, mu, inv, U, Lq, m, thr) > thr) { c[2]++; continue; }
+            for (int j = 0; j < m; ++j) ch[j] = znorm_point(T[i + j], mu, inv);
             envelope(ch, m, r, Uc, Lc);
             if (lb_keogh(qh, Uc, Lc, m, thr) > thr) { c[3]++; continue; }
             double d = dtw_band(qh, ch, m, r, thr, prev, cur);
             if (d == INFINITY) { c[4]++; continue; }
             c[5]++;
-            if (d < best) { best = d; bidx = i; publish_bsf(&gbsf, d); }
+            if (d < best || (d == best && i < bidx)) { best = d; bidx = i; publish_bsf(&gbsf, d); }
         }
 #pragma omp critical
         {
@@ -243,10 +261,12 @@ int oc_search_many(const float *T, int64_t n, const float *Q, int32_t m, const i
         double *ch = buf, *Uc = buf + m, *Lc = buf + 2 * m, *prev = buf + 3 * m, *cur = buf + 4 * m + 2;
         int64_t c[6] = {0, 0, 0, 0, 0, 0};
         for (int k = 0; k < nq; ++k) { best[k] = INFINITY; bidx[k] = -1; }
-        for (int64_t i = a; i < b; ++i) {
+        for (int64_t it = 0; it < b - a; ++it) {
+            const int64_t i = scan_position(a, b, it);
             double mu, sigma;
             window_moments(T + i, m, &mu, &sigma);
-            double c0 = znorm_point(T[i], mu, sigma), cl = znorm_point(T[i + m - 1], mu, sigma);
+            const double inv = inv_sigma(sigma);
+            double c0 = znorm_point(T[i], mu, inv), cl = znorm_point(T[i + m - 1], mu, inv);
             int full = 0;   /* ch holds the normalised window */
             for (int k = 0; k < nq; ++k) {
                 const double *q = qh + (size_t)3 * m * k, *U = q + m, *Lq = q + 2 * m;
@@ -257,9 +277,9 @@ int oc_search_many(const float *T, int64_t n, const float *Q, int32_t m, const i
                 double lk = (m == 1) ? (q[0] - c0) * (q[0] - c0)
                                      : (q[0] - c0) * (q[0] - c0) + (q[m - 1] - cl) * (q[m - 1] - cl);
                 if (lk > thr) { c[1]++; continue; }
-                if (lb_keogh_window(T + i, mu, sigma, U, Lq, m, thr) > thr) { c[2]++; continue; }
+                if (lb_keogh_window(T + i, mu, inv, U, Lq, m, thr) > thr) { c[2]++; continue; }
                 if (!full) {
-                    for (int j = 0; j < m; ++j) ch[j] = znorm_point(T[i + j], mu, sigma);
+                    for (int j = 0; j < m; ++j) ch[j] = znorm_point(T[i + j], mu, inv);
                     full = 1;
                 }
                 envelope(ch, m, r[k], Uc, Lc);
@@ -267,7 +287,7 @@ int oc_search_many(const float *T, int64_t n, const float *Q, int32_t m, const i
                 double d = dtw_band(q, ch, m, r[k], thr, prev, cur);
                 if (d == INFINITY) { c[4]++; continue; }
                 c[5]++;
-                if (d < best[k]) { best[k] = d; bidx[k] = i; publish_bsf(&gbsf[k], d); }
+                if (d < best[k] || (d == best[k] && i < bidx[k])) { best[k] = d; bidx[k] = i; publish_bsf(&gbsf[k], d); }
             }
         }
 #pragma omp critical

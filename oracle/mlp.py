@@ -7,8 +7,10 @@ bounds and exact DTW decide every result.  Its inputs are Piecewise Aggregate Ap
 (PAA): the means of 16 consecutive segments of the z-normalised query and of the z-normalised
 candidate, segment s covering positions [floor(s*m/16), floor((s+1)*m/16)).
 
-Network: y = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3 with x in R^32 (query PAA, then
-candidate PAA), hidden widths 256 and 256.  Loss: mean squared error against given targets (the
+Network: y = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3 + log(d(x) / 16 + 1e-4) with x in R^32
+(query PAA, then candidate PAA), hidden widths 256 and 256, and d(x) = sum_t (x_t - x_{t+16})^2 the
+squared distance of the two PAAs: the network learns a correction to the logarithm of the PAA
+distance (a model with a zero output layer orders exactly as the PAA distance does).  Loss: mean squared error against given targets (the
 training recipe uses log(DTW / m + 1e-4)).  Parameters are kept as one flat FP32 vector in the order
 W1 (32 x 256, row = input), b1 (256), W2 (256 x 256, row = layer-1 unit), b2 (256), w3 (256), b3 (1).
 
@@ -90,6 +92,13 @@ def proposals(T, Q, block: int = 4096, quarters: int = 4):
     return starts, dists
 
 
+def paa_skip(X) -> np.ndarray:
+    """log(d / 16 + 1e-4) per row, d = squared distance of the query half to the candidate half."""
+    X = np.asarray(X, dtype=np.float64)
+    d = ((X[:, :16] - X[:, 16:]) ** 2).sum(axis=1)
+    return np.log(d / 16.0 + 1e-4)
+
+
 def forward(theta, X, bf16_ops: bool = False):
     """Returns (y, cache) for inputs X of shape (R, 32)."""
     p = unflatten(theta)
@@ -99,7 +108,7 @@ def forward(theta, X, bf16_ops: bool = False):
     Hq = _q(Hl1, bf16_ops)
     A2 = Hq @ _q(p["W2"], bf16_ops) + p["b2"]
     Hl2 = np.maximum(A2, 0.0)
-    y = Hl2 @ p["w3"] + p["b3"][0]
+    y = Hl2 @ p["w3"] + p["b3"][0] + paa_skip(X)
     return y, (Xq, A1, Hq, A2, Hl2, p)
 
 

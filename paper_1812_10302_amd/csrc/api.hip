@@ -1298,8 +1298,24 @@ DTWS_API int dtws_dtw_band(dtws_ctx *c, const float *T, int64_t n, const float *
     if (wave) {
         const int64_t blocks = (count + 1) / 2;
         HIPCHK(c, launch_dtw_diag_list(d, false, (int)(blocks < c->num_cu * 8 ? blocks : c->num_cu * 8), s));
-    } else {
+    } else if (2 * r + 1 > 16 * kMaxChunks) {
         HIPCHK(c, launch_dtw(d, false, count, c->num_cu, c->gen_rows, c->gen_lanes, s));
+    } else {
+        // one lane per candidate, as in the search: the windows' normalisation first (one coalesced
+        // wave per start, into the context's statistics arrays), in pieces of at most max_n starts
+        for (int64_t k0 = 0; k0 < count; k0 += c->max_n) {
+            const int64_t cnt = count - k0 < c->max_n ? count - k0 : c->max_n;
+            HIPCHK(c, launch_start_stats(T, n, m, starts + k0, cnt, c->st_mu, c->st_s, c->st_o, c->num_cu, s));
+            DtwArgs dk = d;
+            dk.starts64 = starts + k0;
+            dk.count = cnt;
+            dk.dist_out = dist + k0;
+            dk.mu = c->st_mu;
+            dk.s = c->st_s;
+            dk.o = c->st_o;
+            dk.stats_by_k = true;
+            HIPCHK(c, launch_dtw(dk, false, cnt, c->num_cu, c->gen_rows, c->gen_lanes, s));
+        }
     }
     return DTWS_OK;
 }

@@ -550,10 +550,63 @@ __device__ __forceinline__ void dtw_lanes(const float *T, int64_t start, float m
     alive = live;
     jdead = m;
     const float *Tp = T + start;
-    float tcur = Tp[0];
     float qcur[NC];
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) qcur[cc] = qpad[qoff[cc]];
+    if constexpr (NC <= 3) {
+        // narrow bands: a column is little work (16 NC cells), so one column of work cannot cover
+        // the latency of the next column's series load; the series comes in blocks of 16 columns,
+        // the next block's loads issued before this block's columns (indices clamped to the window)
+        float tb[16], tn[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) tb[u] = Tp[u < m ? u : m - 1];
+        int j0 = 0;
+        for (; j0 < m; j0 += 16) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int jj = j0 + 16 + u;
+                tn[u] = Tp[jj < m ? jj : m - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int jc = j0 + u;
+                if (jc < m) {
+                    const int jn = jc + 1 < m ? jc + 1 : jc;
+                    float qnext[NC];
+#pragma unroll
+                    for (int cc = 0; cc < NC; ++cc) qnext[cc] = qpad[qoff[cc] + jn];
+                    column<NC>(arr, qcur, fmaf(tb[u] - mu, s, o));
+#pragma unroll
+                    for (int cc = 0; cc < NC; ++cc) qcur[cc] = qnext[cc];
+                }
+            }
+            if (j0 + 16 <= m) {
+                // the check after every 16 columns, as below
+                float mn = arr[0];
+#pragma unroll
+                for (int x = 1; x < W; ++x) mn = fminf(mn, arr[x]);
+                if (key) {
+                    thr = fminf(thr0, threshold_of(__uint_as_float(kpend)));
+                    kpend = load_key_dist_bits(key);
+                }
+                if (alive && mn > thr) {
+                    alive = false;
+                    jdead = j0 + 16;
+                }
+                if (__ballot(alive) == 0) {
+                    j0 += 16;
+                    break;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) tb[u] = tn[u];
+        }
+        jrun = j0 < m ? j0 : m;
+        D = arr[R];
+        if (alive && !(D <= thr)) alive = key ? false : alive;   // search mode keeps only improvements
+        return;
+    }
+    float tcur = Tp[0];
     int j = 0;
     for (; j < m; ++j) {
         const int jn = j + 1 < m ? j + 1 : j;

@@ -371,6 +371,35 @@ __device__ inline void wave_norm(const float *w, int m, float &mu, float &s, flo
     norm_params(mu64, sqrt(v / m), mu, s, o);
 }
 
+// Normalisation parameters of the windows at starts[k] (one wave per start, coalesced loads, FP64
+// two-pass), so that the one-lane-per-candidate DTW kernel reads them instead of normalising each
+// window in its own lane; starts outside [0, n-m] get zeros (the DTW kernel rejects them).
+__global__ __launch_bounds__(256) void k_start_stats(const float *T, int64_t n, int m, const int64_t *starts,
+                                                     int64_t count, float *mu, float *sg, float *off) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t k = wave; k < count; k += nwaves) {
+        const int64_t st = starts[k];
+        float a = 0.0f, b = 0.0f, c = 0.0f;
+        if (st >= 0 && st <= n - m) wave_norm(T + st, m, a, b, c);
+        if (lane == 0) {
+            mu[k] = a;
+            sg[k] = b;
+            off[k] = c;
+        }
+    }
+}
+
+hipError_t launch_start_stats(const float *T, int64_t n, int m, const int64_t *starts, int64_t count, float *mu,
+                              float *sg, float *off, int num_cu, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 3) / 4;
+    if (blocks > (int64_t)num_cu * 16) blocks = (int64_t)num_cu * 16;
+    hipLaunchKernelGGL(k_start_stats, dim3((unsigned)blocks), dim3(256), 0, s, T, n, m, starts, count, mu, sg, off);
+    return hipGetLastError();
+}
+
 // Plain search and the stage entry point: one wave per start of a DtwArgs list (explicit starts,
 // device-side survivors, a range or a single start).  In search mode with a device-side count,
 // rounds of more than a.diag_max survivors are left to the lane-per-candidate kernels.

@@ -53,9 +53,10 @@ __global__ __launch_bounds__(256) void k_dtw(DtwArgs a) {
         }
         float mu, s, o;
         if (a.mu) {
-            mu = a.mu[start];
-            s = a.s[start];
-            o = a.o[start];
+            const int64_t si = a.stats_by_k ? (valid ? k : 0) : start;
+            mu = a.mu[si];
+            s = a.s[si];
+            o = a.o[si];
         } else {
             lane_stats(a.T + start, m, mu, s, o);
         }

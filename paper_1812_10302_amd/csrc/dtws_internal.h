@@ -119,6 +119,7 @@ struct DtwArgs {
     int64_t count;               // host count, or capacity bound when count_dev is set
     int64_t single;              // >= 0: evaluate only this start
     const float *mu, *s, *o;     // per-window normalisation, or null to compute per lane
+    bool stats_by_k;             // mu/s/o are indexed by the list position k, not by the start
     float abandon_at;            // threshold of the stage entry point
     uint32_t diag_max;           // search rounds of at most this many survivors: one wave per candidate
     uint32_t nb_cap;             // capacity of the near-best list (entries beyond it are dropped and
@@ -215,7 +216,9 @@ constexpr int64_t kOffW1 = 0, kOffb1 = 32 * 256, kOffW2 = kOffb1 + 256, kOffb2 =
                   kOffw3 = kOffb2 + 256, kOffb3 = kOffw3 + 256;
 constexpr int64_t kMlpChunk = 1 << 18;   // rows per forward pass (workspace size)
 constexpr int kScoreSamples = 4;         // proposals scored per block (one per quarter block)
-constexpr int kSeedCands = 64;           // best-scored proposals per query that seed the best-so-far (one wave)
+constexpr int kSeedBlocks = 16;          // best-scored blocks per query whose proposals seed the best-so-far
+constexpr int kSeedOffsets = 16;         // starts evaluated around each of them: proposal - 8 .. proposal + 7
+constexpr int kSeedCands = kSeedBlocks * kSeedOffsets;
 constexpr int kColsumGroups = 128;       // row groups of the bias-gradient reduction
 constexpr int64_t kMaxTrainRows = 1 << 16;  // rows per gradient / training step
 
@@ -286,6 +289,8 @@ hipError_t launch_dtw_diag(const BatchArgs &a, bool prefix, int max_r, int block
 hipError_t launch_cert_diag(const BatchArgs &a, int max_r, int blocks, hipStream_t s);
 hipError_t launch_dtw_diag_list(const DtwArgs &a, bool search, int blocks, hipStream_t s);
 hipError_t launch_cert_diag_list(const CertArgs &c, int blocks, hipStream_t s);
+hipError_t launch_start_stats(const float *T, int64_t n, int m, const int64_t *starts, int64_t count, float *mu,
+                              float *sg, float *off, int num_cu, hipStream_t s);
 hipError_t launch_paa(const float *T, int64_t n, int m, const int64_t *starts, int64_t count, float *out,
                       hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);

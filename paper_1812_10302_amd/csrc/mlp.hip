@@ -103,14 +103,26 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_infer(const float *__rest
     for (int64_t tile = wave; tile < tiles; tile += nwaves) {
         const int64_t row = tile * 16 + r;
         // layer-1 B operand: features 8 g .. + 7 of this lane's data row (zero past the last row)
-        u32x4 xw = u32x4{0u, 0u, 0u, 0u};
+        float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0;
         if (row < R) {
-            const float4 f0 = *(const float4 *)(X + row * 32 + 8 * g);
-            const float4 f1 = *(const float4 *)(X + row * 32 + 8 * g + 4);
-            xw = u32x4{(uint32_t)f2bf(f0.x) | ((uint32_t)f2bf(f0.y) << 16), (uint32_t)f2bf(f0.z) | ((uint32_t)f2bf(f0.w) << 16),
-                       (uint32_t)f2bf(f1.x) | ((uint32_t)f2bf(f1.y) << 16), (uint32_t)f2bf(f1.z) | ((uint32_t)f2bf(f1.w) << 16)};
+            f0 = *(const float4 *)(X + row * 32 + 8 * g);
+            f1 = *(const float4 *)(X + row * 32 + 8 * g + 4);
         }
+        const u32x4 xw = u32x4{(uint32_t)f2bf(f0.x) | ((uint32_t)f2bf(f0.y) << 16), (uint32_t)f2bf(f0.z) | ((uint32_t)f2bf(f0.w) << 16),
+                               (uint32_t)f2bf(f1.x) | ((uint32_t)f2bf(f1.y) << 16), (uint32_t)f2bf(f1.z) | ((uint32_t)f2bf(f1.w) << 16)};
         const bf16x8 xb = __builtin_bit_cast(bf16x8, xw);
+        // the PAA-distance term (FP32 features): the lane of group g ^ 2 holds the other half of
+        // the same 8 segments; the two query-half groups together cover all 16
+        float dd = 0.0f;
+        {
+            const float p[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float e = p[k] - __shfl_xor(p[k], 32, 64);
+                dd = fmaf(e, e, dd);
+            }
+            dd += __shfl_xor(dd, 16, 64);
+        }
         // layer 1 and its epilogue, packed as the layer-2 B operands of the 8 K steps
         bf16x8 hb[8];
 #pragma unroll
@@ -147,7 +159,7 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_infer(const float *__rest
         }
         part += __shfl_xor(part, 16, 64);
         part += __shfl_xor(part, 32, 64);
-        if (g == 0 && row < R) y[row] = part + bias3;
+        if (g == 0 && row < R) y[row] = part + bias3 + logf(dd * (1.0f / 16.0f) + 1e-4f);
     }
 }
 
@@ -174,12 +186,21 @@ __global__ void k_mlp_act1(const float *C1, const float *b1, int64_t Rp, uint16_
 }
 
 // Layer 2 epilogue and head, one wave per row: H2 = relu(C2 + b2) (written back into C2 when
-// training), y = H2 . w3 + b3.
+// training), y = H2 . w3 + b3 + log(d / 16 + 1e-4), d the squared distance of the row's two PAA
+// halves (FP32 features X, rows >= Rx are padding without features).
 __global__ void k_mlp_head(float *C2, const float *b2, const float *w3, const float *b3, int64_t R, float *y,
-                           bool keep) {
+                           bool keep, const float *X, int64_t Rx) {
     const int lane = threadIdx.x & 63;
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (row >= R) return;
+    float dd = 0.0f;
+    if (lane < 16 && row < Rx) {
+        const float e = X[row * 32 + lane] - X[row * 32 + lane + 16];
+        dd = e * e;
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) dd += __shfl_xor(dd, off, 64);
+    dd = __shfl(dd, 0, 64);
     float acc = 0.0f;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -190,7 +211,7 @@ __global__ void k_mlp_head(float *C2, const float *b2, const float *w3, const fl
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) y[row] = acc + b3[0];
+    if (lane == 0) y[row] = acc + b3[0] + logf(dd * (1.0f / 16.0f) + 1e-4f);
 }
 
 // Loss and output gradient: dy = 2 (y - t) / R (zero for padding rows), loss = mean (y - t)^2;
@@ -289,7 +310,8 @@ __global__ void k_mlp_refresh(const float *W1, const float *W2, uint16_t *W1T, u
     }
 }
 
-// Counter-based He-normal initialisation (Box-Muller on splitmix64 draws); zero biases.
+// Counter-based He-normal initialisation of the hidden layers (Box-Muller on splitmix64 draws); zero
+// biases and a zero output layer.
 __device__ inline uint64_t mix64(uint64_t x) {
     x += 0x9E3779B97F4A7C15ull;
     x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -303,7 +325,7 @@ __global__ void k_mlp_init(float *theta, uint64_t seed) {
     float scale = 0.0f;
     if (i < ob1) scale = sqrtf(2.0f / 32.0f);
     else if (i >= oW2 && i < ob2) scale = sqrtf(2.0f / 256.0f);
-    else if (i >= ow3 && i < ob3) scale = sqrtf(1.0f / 256.0f);
+    // the output layer starts at zero: an untrained model orders by the PAA-distance term alone
     (void)oW1;
     const uint64_t h1 = mix64(seed ^ (uint64_t)(2 * i)), h2 = mix64(seed ^ (uint64_t)(2 * i + 1));
     const float u1 = ((h1 >> 40) + 1) * (1.0f / 16777217.0f), u2 = (h2 >> 40) * (1.0f / 16777216.0f);
@@ -718,16 +740,23 @@ __global__ void k_block_min(const float *y, const int32_t *sstart, int64_t R, in
 }
 
 // Round -1 of the learned order: the best-so-far of every query starts from the proposals of its
-// kSeedCands best-scored blocks (repeating the last when a query has fewer blocks).
+// kSeedBlocks best-scored blocks (repeating the last when a query has fewer blocks), each with the
+// kSeedOffsets starts around it (offsets -8 .. +7, clipped to the candidates): a proposal lies on the
+// sampling grid, so a near copy of the query is found at its own alignment, not only at the nearest
+// grid start.
 __global__ void k_seed_learned(BatchArgs a, const int32_t *bstart, const int64_t *row_off, int K) {
     // one thread per (query, seed)
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)a.nq * kSeedCands) return;
     const int q = (int)(e / kSeedCands), k = (int)(e % kSeedCands);
-    const int64_t nb = a.bq[q].nblocks;
-    const int64_t blk = a.perm[(int64_t)q * a.maxblocks + (k < nb ? k : nb - 1)];
+    const int kb = k / kSeedOffsets, off = k % kSeedOffsets - kSeedOffsets / 2;
+    const BatchQ bq = a.bq[q];
+    const int64_t nb = bq.nblocks;
+    const int64_t blk = a.perm[(int64_t)q * a.maxblocks + (kb < nb ? kb : nb - 1)];
+    int64_t st = (int64_t)bstart[row_off[q] / K + blk] + off;
+    st = st < 0 ? 0 : (st > bq.N - 1 ? bq.N - 1 : st);
     a.surv_q[e] = q;
-    a.surv_i[e] = bstart[row_off[q] / K + blk];
+    a.surv_i[e] = (int32_t)st;
     if (k == 0) a.qcnt[q] = kSeedCands;
     if (e == 0) *a.surv_count = (uint32_t)(a.nq * kSeedCands);
 }
@@ -859,7 +888,7 @@ hipError_t mlp_forward(const MlpBufs &b, const float *X, int64_t R, float *y, bo
     e = mlp_gemm(b.H1b, 256, b.W2T, 256, b.C2, 256, (int)Rp, 256, 256, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mlp_head, dim3(nblk(Rp * 64)), dim3(256), 0, s, b.C2, b.theta + kOffb2, b.theta + kOffw3,
-                       b.theta + kOffb3, Rp, y, train);
+                       b.theta + kOffb3, Rp, y, train, X, R);
     return hipGetLastError();
 }
 
@@ -898,8 +927,8 @@ hipError_t mlp_adam(const MlpBufs &b, int step, float lr, hipStream_t s) {
 }
 
 // PAA score of a feature row (the learned order's control): the squared Euclidean distance of its
-// query half to its candidate half, as log(d + 1e-4) (a monotone map that spreads the small
-// distances over the order's buckets the way the network's log target does).
+// query half to its candidate half, as log(d / 16 + 1e-4): the network's PAA-distance term, so the
+// control is the network with a zero output layer.
 __global__ void k_paa_score(const float *X, int64_t R, float *y) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= R) return;
@@ -913,7 +942,7 @@ __global__ void k_paa_score(const float *X, int64_t R, float *y) {
         d = fmaf(a.z - c.z, a.z - c.z, d);
         d = fmaf(a.w - c.w, a.w - c.w, d);
     }
-    y[k] = logf(d + 1e-4f);
+    y[k] = logf(d * (1.0f / 16.0f) + 1e-4f);
 }
 
 // Scores every block of every query of the batch and writes the visiting order into a.perm: by the

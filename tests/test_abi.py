@@ -51,6 +51,11 @@ def test_argument_errors_before_any_device_work():
     assert lib.dtws_dtw_band(None, None, 100, None, 8, 1, None, 4, 0.0, None, None) == dtws.EINVAL
     assert lib.dtws_bsf_update(None, None, None, None, 4, None) == dtws.EINVAL
     assert lib.dtws_get_counters(None, None) == dtws.EINVAL
+    cfg = dtws.TrainCfg()
+    assert lib.dtws_model_train(None, None, 100, ctypes.byref(cfg), None, None, None) == dtws.EINVAL
+    size = ctypes.c_size_t(0)
+    assert lib.dtws_model_save(None, None, ctypes.byref(size)) == dtws.EINVAL
+    assert lib.dtws_model_load(None, None, 0) == dtws.EINVAL
     lib.dtws_destroy(None)   # accepted
 
 

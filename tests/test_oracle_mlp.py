@@ -35,8 +35,23 @@ def test_forward_linear_region_closed_form():
          "w3": rng.normal(0, 0.1, 256), "b3": np.array([0.25])}
     X = np.abs(rng.normal(0, 1, (5, 32)))
     y, _ = M.forward(M.flatten(p), X)
-    want = ((X @ p["W1"] + p["b1"]) @ p["W2"] + p["b2"]) @ p["w3"] + 0.25
+    skip = np.log(((X[:, :16] - X[:, 16:]) ** 2).sum(axis=1) / 16 + 1e-4)
+    want = ((X @ p["W1"] + p["b1"]) @ p["W2"] + p["b2"]) @ p["w3"] + 0.25 + skip
     np.testing.assert_allclose(y, want, rtol=1e-12)
+
+
+def test_zero_output_layer_is_the_paa_distance():
+    """With w3 = 0 and b3 = 0 the model's value is log(d / 16 + 1e-4) of the PAA distance d:
+    identical halves give log(1e-4); halves that differ by 1 in one segment give log(1/16 + 1e-4);
+    by 2 in every segment, d = 64 and the value is log(4 + 1e-4)."""
+    theta = M.init_params(4)
+    p = M.unflatten(theta)
+    p["w3"] = np.zeros(256)
+    p["b3"] = np.zeros(1)
+    q = np.linspace(-1.5, 1.5, 16)
+    X = np.stack([np.concatenate([q, q]), np.concatenate([q, q + np.eye(16)[5]]), np.concatenate([q, q - 2.0])])
+    y, _ = M.forward(M.flatten(p), X)
+    np.testing.assert_allclose(y, [np.log(1e-4), np.log(1 / 16 + 1e-4), np.log(4 + 1e-4)], rtol=1e-14)
 
 
 def test_bf16_rounding_definition():
