@@ -94,7 +94,7 @@ def workload(name: str):
 
 
 def measure(wl, train, steps: int, warmup: int, plain_queries: int, profile: bool, log_prefix: str = "",
-            fixed_schedule: dict | None = None):
+            fixed_schedule: dict | None = None, no_ablations: bool = False):
     """Times the batched learned search (or the batched natural one when there is no training
     recipe), the plain search on a seeded subset, and the ablation orders.  Returns a dict."""
     import torch
@@ -174,7 +174,7 @@ def measure(wl, train, steps: int, warmup: int, plain_queries: int, profile: boo
 
     # ablations, one call each: series order and (with a model) the PAA order of the same proposals
     abl = {}
-    for name, flag in (("natural", dtws.ORDER_NATURAL), ("paa", dtws.ORDER_PAA)):
+    for name, flag in (() if no_ablations else (("natural", dtws.ORDER_NATURAL), ("paa", dtws.ORDER_PAA))):
         if flag == order or (flag == dtws.ORDER_PAA and train is None):
             continue
         ctx.search_batch(T, pq, rs, flags=flag, seed=7)      # capture
@@ -186,7 +186,7 @@ def measure(wl, train, steps: int, warmup: int, plain_queries: int, profile: boo
         assert got == results, f"{name} order disagrees"
         c = ctx.counters()
         abl[name] = {"s_per_query": round(dt / nq, 7), "dtw_cells": c["dtw_cells"], "dtw_started": c["dtw_started"],
-                     "pruned_kim": c["pruned_kim"]}
+                     "pruned_kim": c["pruned_kim"], "fallbacks": c["fallbacks"]}
     out["ablations"] = abl
 
     # profiled pass of the timed path: kernel classes and counters
@@ -225,11 +225,15 @@ def roofline_of(meas):
                 "algorithmic_lane_ops_per_launch": int(ops / max(nl, 1)), "avg_launch_ms": round(t_ms / max(nl, 1), 4),
                 "launches": nl, "per_query_pass_bytes": int(qpass),
                 "per_query_pass_GBps": round(qpass / (t_ms * 1e-3) / 1e9, 1)}
-    if dominant == "dtw":
-        c = cnt["dtw_cells"]
+    if dominant in ("dtw", "dtw_wave"):
+        # algorithmic unit: one band cell of the DTW recurrence (3 VALU lane-operations)
+        c = cnt["dtw_cells"] - cnt["dtw_wave_cells"] if dominant == "dtw" else cnt["dtw_wave_cells"]
         g = c / (t_ms * 1e-3) / 1e9
-        return {"bound": "alu", "kernel": "DTW kernels", "achieved": round(g, 1), "peak": round(DTW_PEAK_GCUPS, 1),
+        name = ("k_dtw_batch (one lane per candidate)" if dominant == "dtw"
+                else "k_dtw_diag (one wave per candidate)")
+        return {"bound": "alu", "kernel": name, "achieved": round(g, 1), "peak": round(DTW_PEAK_GCUPS, 1),
                 "unit": "GCUPS", "frac": round(g / DTW_PEAK_GCUPS, 4), "traffic": None,
+                "algorithmic_cells_per_launch": int(c / max(nl, 1)),
                 "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
     return {"bound": "latency", "kernel": f"class {dominant}", "achieved": None, "peak": None, "unit": None,
             "frac": None, "traffic": None, "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
@@ -269,6 +273,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=250_000_000, help="series points of the CPU baseline")
+    ap.add_argument("--no-ablations", action="store_true", help="skip the natural / PAA order ablations")
     ap.add_argument("--schedule", default=None,
                     help="JSON object of schedule fields for the main workload instead of the autotuner")
     args = ap.parse_args()
@@ -283,7 +288,8 @@ def main():
     wl, train = workload(args.workload)
     log(f"workload {wl.name}: generated in {time.time() - t0:.1f}s")
     meas = measure(wl, train, args.steps, args.warmup, args.plain_queries, not args.no_profile,
-                   fixed_schedule=json.loads(args.schedule) if args.schedule else None)
+                   fixed_schedule=json.loads(args.schedule) if args.schedule else None,
+                   no_ablations=args.no_ablations)
     ctx, T, Qs = meas.pop("_ctx"), meas.pop("_T"), meas.pop("_Qs")
     log(f"{wl.name}: {meas['step_ms']} ms per step, {meas['batched_s_per_query']} s/query batched, "
         f"{meas['plain_s_per_query']} s/query plain")

@@ -83,11 +83,13 @@ enum dtws_kernel_class {
     DTWS_K_STATS = 1,   /* per-window mean / sigma                               */
     DTWS_K_ENV = 2,     /* raw-series envelope                                   */
     DTWS_K_LB = 3,      /* lower-bound cascade                                   */
-    DTWS_K_DTW = 4,     /* banded DTW (including the best-so-far update)         */
+    DTWS_K_DTW = 4,     /* banded DTW, one lane per candidate (with the best-so-far
+                           update)                                               */
     DTWS_K_CERT = 5,    /* FP64 certification                                    */
     DTWS_K_OTHER = 6,   /* fills and bookkeeping                                 */
     DTWS_K_SCORE = 7,   /* learned ordering: features, network, block order      */
-    DTWS_K_COUNT = 8
+    DTWS_K_DTW_WAVE = 8,   /* banded DTW, one wave per candidate (with the update)  */
+    DTWS_K_COUNT = 9
 };
 
 /* Result of one search: 0-based start and its squared z-normalised DTW
@@ -115,6 +117,8 @@ typedef struct {
                                   batched cascade (0 for the other cascade kernels)     */
     int64_t fallbacks;         /* batched queries redone by the plain search after a
                                   list overflowed (their work is not in the counters)   */
+    int64_t dtw_wave_cells;    /* the part of dtw_cells evaluated by the one-wave-per-
+                                  candidate DTW kernels                                 */
 } dtws_counters;
 
 /* ---------------------------------------------------------------- context */
@@ -250,7 +254,11 @@ typedef struct {
                                   same candidates (series order, or a single round) run the tiled
                                   cascade, one LDS-staged series tile shared by all queries
                                   (default); 0 = per-query work items */
-    int32_t reserved;          /* 0 */
+    int32_t dtw_bound;         /* search DTW on one lane per candidate, bands of 97 to 223 cells:
+                                  1 = every 16 columns the abandoning test adds the LB_Keogh
+                                  terms of the columns still to come (query envelope, computed
+                                  per candidate before its DTW; default), 0 = the band minimum
+                                  alone */
 } dtws_schedule;
 
 DTWS_API int dtws_get_schedule(dtws_ctx *ctx, dtws_schedule *out_host);
@@ -260,7 +268,7 @@ DTWS_API int dtws_set_schedule(dtws_ctx *ctx, const dtws_schedule *s_host);
 /* Autotuner: runs dtws_search_batch on the given batch (arguments as there;
  * DTWS_PROFILE is ignored) under candidate schedules, by coordinate descent over
  * diag_max, block, lb_blocks_per_cu, dtw_blocks_per_cu, stats_prefix,
- * data_envelope and rounds starting from the current schedule; each candidate is called once untimed (graph capture) and then `reps`
+ * data_envelope, rounds, lb_tile and dtw_bound starting from the current schedule; each candidate is called once untimed (graph capture) and then `reps`
  * times (1..100) timed on the host clock.  All candidates must return identical
  * matches (DTWS_EHIP otherwise, schedule unchanged).  Installs the fastest, writes
  * it to *best_host and its mean time per call (ms) to *best_ms_host.  Blocking. */

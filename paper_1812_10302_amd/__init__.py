@@ -26,14 +26,15 @@ NO_LOWER_BOUNDS = 4
 PROFILE = 8
 NO_GRAPH = 16
 LB_SORTED = 32
-KERNEL_CLASSES = ("prep", "stats", "env", "lb", "dtw", "cert", "other", "score")
+KERNEL_CLASSES = ("prep", "stats", "env", "lb", "dtw", "cert", "other", "score", "dtw_wave")
 MODEL_PARAMS = 74497
 TRAIN_MAX_SHAPES = 8
 MODEL_MAX_ROWS = 65536
 MAX_M = 2048
 
 COUNTER_FIELDS = ("candidates", "pruned_kim", "pruned_keogh_q", "pruned_keogh_d", "dtw_started",
-                  "dtw_abandoned", "dtw_cells", "certified", "dtw_lane_cells", "lb_terms", "fallbacks")
+                  "dtw_abandoned", "dtw_cells", "certified", "dtw_lane_cells", "lb_terms", "fallbacks",
+                  "dtw_wave_cells")
 
 
 class Match(ctypes.Structure):
@@ -49,10 +50,10 @@ class Schedule(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int64), ("lb_blocks_per_cu", ctypes.c_int32),
                 ("dtw_blocks_per_cu", ctypes.c_int32), ("diag_max", ctypes.c_int32), ("band_lanes", ctypes.c_int32),
                 ("stats_prefix", ctypes.c_int32), ("data_envelope", ctypes.c_int32), ("rounds", ctypes.c_int32),
-                ("list_cap", ctypes.c_int32), ("lb_tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("list_cap", ctypes.c_int32), ("lb_tile", ctypes.c_int32), ("dtw_bound", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class TrainCfg(ctypes.Structure):

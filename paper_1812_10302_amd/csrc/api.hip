@@ -116,6 +116,8 @@ QueryBufs query_bufs(dtws_ctx *c, int slot) {
     b.qsorted = c->qsorted + (int64_t)slot * c->mstride;
     b.Usorted = c->Usorted + (int64_t)slot * c->mstride;
     b.Lsorted = c->Lsorted + (int64_t)slot * c->mstride;
+    b.Unat = c->Unat + (int64_t)slot * c->mstride;
+    b.Lnat = c->Lnat + (int64_t)slot * c->mstride;
     b.order = c->order + (int64_t)slot * c->mstride;
     return b;
 }
@@ -155,6 +157,10 @@ PlainArgs plain_args(dtws_ctx *c, const float *T, int64_t n, int m, int r, int s
     d.nb_cap = nb_cap_of(c);
     d.counters = c->counters;
     d.abandon_at = INFINITY;
+    if (c->dtw_bound) {
+        d.Un = b.Unat;
+        d.Ln = b.Lnat;
+    }
     // one wave per candidate for small rounds, and always for bands wider than the register kernel
     const bool diag = r <= kDiagMaxBand;
     d.diag_max = !diag ? 0u : (2 * r + 1 > 16 * kMaxChunks ? 0xFFFFFFFFu : (uint32_t)diag_max_of(c));
@@ -218,10 +224,12 @@ int plain_chunk(dtws_ctx *c, const PlainArgs &p, int64_t a0, int64_t a1, uint32_
     ds.starts32 = c->surv;
     ds.count_dev = c->surv_count;
     ds.count = a1 - a0;
-    PROF(DTWS_K_DTW);
     // both schedules are enqueued; the device-side survivor count picks the one that runs
-    HIPCHK(c, launch_dtw(ds, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
-    if (ds.diag_max > 0) HIPCHK(c, launch_dtw_diag_list(ds, true, c->num_cu * 4, s));
+    { PROF(DTWS_K_DTW); HIPCHK(c, launch_dtw(ds, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s)); }
+    if (ds.diag_max > 0) {
+        PROF(DTWS_K_DTW_WAVE);
+        HIPCHK(c, launch_dtw_diag_list(ds, true, c->num_cu * 4, s));
+    }
     return DTWS_OK;
 }
 
@@ -267,9 +275,11 @@ int lb_sorted_improve(dtws_ctx *c, const PlainArgs &p, int64_t N, hipStream_t s)
         ds.starts32 = c->surv;
         ds.count_dev = c->surv_count;
         ds.count = a1 - a0;
-        PROF(DTWS_K_DTW);
-        HIPCHK(c, launch_dtw(ds, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s));
-        if (ds.diag_max > 0) HIPCHK(c, launch_dtw_diag_list(ds, true, c->num_cu * 4, s));
+        { PROF(DTWS_K_DTW); HIPCHK(c, launch_dtw(ds, true, a1 - a0, c->num_cu, c->gen_rows, c->gen_lanes, s)); }
+        if (ds.diag_max > 0) {
+            PROF(DTWS_K_DTW_WAVE);
+            HIPCHK(c, launch_dtw_diag_list(ds, true, c->num_cu * 4, s));
+        }
         a0 = a1;
         size *= 16;
     }
@@ -291,7 +301,7 @@ int run_query(dtws_ctx *c, const float *T, int64_t n, const float *Q, int m, int
     {
         DtwArgs d0 = p.d;
         d0.single = (int64_t)(splitmix64(seed) % (uint64_t)N);
-        PROF(DTWS_K_DTW);
+        PROF(r <= kDiagMaxBand ? DTWS_K_DTW_WAVE : DTWS_K_DTW);
         if (r <= kDiagMaxBand) HIPCHK(c, launch_dtw_diag_list(d0, true, 1, s));
         else HIPCHK(c, launch_dtw(d0, true, 1, c->num_cu, c->gen_rows, c->gen_lanes, s));
     }
@@ -354,10 +364,8 @@ int recertify_chunked(dtws_ctx *c, const float *T, int64_t n, int m, int r, uint
     return DTWS_OK;
 }
 
-// Copies the result block (results and counters) to the host and parses the counters.
-int fetch_counters(dtws_ctx *c, int64_t candidates, hipStream_t s) {
-    HIPCHK(c, hipMemcpyAsync(c->h_res_block, c->res_block, c->res_bytes, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+// Fills the context's counters of the last call from the host copy of the device counters.
+void parse_counters(dtws_ctx *c, int64_t candidates) {
     const unsigned long long *h = c->h_counters;
     c->last.candidates = candidates;
     c->last.pruned_kim = (int64_t)h[1];
@@ -369,28 +377,24 @@ int fetch_counters(dtws_ctx *c, int64_t candidates, hipStream_t s) {
     c->last.certified = (int64_t)h[7];
     c->last.dtw_lane_cells = (int64_t)h[8];
     c->last.lb_terms = (int64_t)h[9];
+    c->last.dtw_wave_cells = (int64_t)h[10];
     c->last.fallbacks = 0;
-    return DTWS_OK;
 }
 
+// Copies the result block (results and counters) to the host and parses the counters.
+int fetch_counters(dtws_ctx *c, int64_t candidates, hipStream_t s) {
+    HIPCHK(c, hipMemcpyAsync(c->h_res_block, c->res_block, c->res_bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    parse_counters(c, candidates);
+    return DTWS_OK;
+}
 
 // Copies only the counters to the host and parses them (the result staging is left alone).
 int fetch_counters_only(dtws_ctx *c, int64_t candidates, hipStream_t s) {
     HIPCHK(c, hipMemcpyAsync(c->h_counters, c->counters, sizeof(unsigned long long) * kNumCounters,
                              hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    const unsigned long long *h = c->h_counters;
-    c->last.candidates = candidates;
-    c->last.pruned_kim = (int64_t)h[1];
-    c->last.pruned_keogh_q = (int64_t)h[2];
-    c->last.pruned_keogh_d = (int64_t)h[3];
-    c->last.dtw_started = (int64_t)h[4];
-    c->last.dtw_abandoned = (int64_t)h[5];
-    c->last.dtw_cells = (int64_t)h[6];
-    c->last.certified = (int64_t)h[7];
-    c->last.dtw_lane_cells = (int64_t)h[8];
-    c->last.lb_terms = (int64_t)h[9];
-    c->last.fallbacks = 0;
+    parse_counters(c, candidates);
     return DTWS_OK;
 }
 
@@ -504,6 +508,8 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     a.order = c->order;
     a.Us = c->Usorted;
     a.Ls = c->Lsorted;
+    a.Un = c->dtw_bound ? c->Unat : nullptr;
+    a.Ln = c->dtw_bound ? c->Lnat : nullptr;
     a.qs = c->qsorted;
     a.mstride = c->mstride;
     a.keys = c->keys;
@@ -557,6 +563,8 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     base.qsorted = c->qsorted;
     base.Usorted = c->Usorted;
     base.Lsorted = c->Lsorted;
+    base.Unat = c->Unat;
+    base.Lnat = c->Lnat;
     base.order = c->order;
 
     // the learned order and its PAA control score the same proposals; only the scorer differs
@@ -629,7 +637,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
             }
         }
         if (a.diag_max > 0 || a.diag_wide) {
-            PROF(DTWS_K_DTW);
+            PROF(DTWS_K_DTW_WAVE);
             HIPCHK(c, launch_dtw_diag(a, !same_m, p.max_r, c->num_cu * 4, s));
         }
         return DTWS_OK;
@@ -691,21 +699,6 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     return DTWS_OK;
 }
 
-void parse_counters(dtws_ctx *c, int64_t candidates) {
-    const unsigned long long *h = c->h_counters;
-    c->last.candidates = candidates;
-    c->last.pruned_kim = (int64_t)h[1];
-    c->last.pruned_keogh_q = (int64_t)h[2];
-    c->last.pruned_keogh_d = (int64_t)h[3];
-    c->last.dtw_started = (int64_t)h[4];
-    c->last.dtw_abandoned = (int64_t)h[5];
-    c->last.dtw_cells = (int64_t)h[6];
-    c->last.certified = (int64_t)h[7];
-    c->last.dtw_lane_cells = (int64_t)h[8];
-    c->last.lb_terms = (int64_t)h[9];
-    c->last.fallbacks = 0;
-}
-
 int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int64_t *qoff, const int32_t *mh,
               const int32_t *rh, int nq, uint32_t flags, uint64_t seed, hipStream_t s, dtws_match *out) {
     const BatchPlan p = plan_batch(c, n, qoff, mh, rh, nq, (flags & DTWS_ORDER_MASK) >= DTWS_ORDER_LEARNED);
@@ -738,7 +731,8 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
         // per-query parameters and the tuning knobs.
         std::vector<int64_t> sig = {(int64_t)(uintptr_t)T, n, (int64_t)(uintptr_t)Qp, nq, (int64_t)flags,
                                     (int64_t)seed, p.block, c->lb_blocks_per_cu, c->dtw_blocks_per_cu, c->diag_max,
-                                    c->stats_prefix, c->data_envelope, c->rounds, c->lb_tile, c->list_cap};
+                                    c->stats_prefix, c->data_envelope, c->rounds, c->lb_tile, c->list_cap,
+                                    c->dtw_bound};
         for (int k = 0; k < nq; ++k) {
             sig.push_back(qoff[k]);
             sig.push_back(mh[k]);
@@ -901,7 +895,7 @@ DTWS_API int dtws_device_count(void) {
 DTWS_API void dtws_destroy(dtws_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    void *dev[] = {c->qpad, c->qhat64, c->qsorted, c->Usorted, c->Lsorted, c->order, c->keys, c->st_mu,
+    void *dev[] = {c->qpad, c->qhat64, c->qsorted, c->Usorted, c->Lsorted, c->Unat, c->Lnat, c->order, c->keys, c->st_mu,
                    c->st_s, c->st_o, c->envU, c->envL, c->surv, c->surv_count, c->nb_d, c->nb_idx,
                    c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_block, c->gen_rows, c->bq, c->PP, c->PPd, c->anc, c->tot,
                    c->perm, c->heads, c->surv_q, c->surv_i, c->sorted, c->qcnt, c->fill, c->overflow,
@@ -960,6 +954,7 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
     bool ok = dalloc(&c->qpad, Q * c->qstride) == hipSuccess && dalloc(&c->qhat64, Q * max_m) == hipSuccess &&
               dalloc(&c->qsorted, Q * c->mstride) == hipSuccess && dalloc(&c->Usorted, Q * c->mstride) == hipSuccess &&
               dalloc(&c->Lsorted, Q * c->mstride) == hipSuccess && dalloc(&c->order, Q * c->mstride) == hipSuccess &&
+              dalloc(&c->Unat, Q * c->mstride) == hipSuccess && dalloc(&c->Lnat, Q * c->mstride) == hipSuccess &&
               dalloc(&c->keys, Q) == hipSuccess && dalloc(&c->st_mu, c->nslots * max_n) == hipSuccess &&
               dalloc(&c->st_s, c->nslots * max_n) == hipSuccess && dalloc(&c->st_o, c->nslots * max_n) == hipSuccess &&
               dalloc(&c->envU, c->nslots * max_n) == hipSuccess && dalloc(&c->envL, c->nslots * max_n) == hipSuccess &&

@@ -391,6 +391,7 @@ __device__ inline void stats_of(const Stats &st, int64_t i, float &mu, float &s,
 template <int NC, bool PREFIX>
 __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
     constexpr int W = 16 * NC;
+    extern __shared__ float bound_lds[];   // [kBoundBlocks][256] when the suffix bound is on
     if (*a.overflow || *a.surv_count <= a.diag_max) return;
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -411,11 +412,21 @@ __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
             const int64_t so = bq.stat_slot * a.slot_stride;
             StatsArr{a.mu + so, a.s + so, a.o + so}(start, mu, s, o);
         }
+        const float *sfx = nullptr;
+        int G = 16;
+        if constexpr (NC >= kBoundMinNC) {
+            if (a.Un) {
+                const int64_t qo = (int64_t)__builtin_amdgcn_readfirstlane(q) * a.mstride;
+                G = bound_block(bq.m);
+                bound_suffix(a.T + start, mu, s, o, a.Un + qo, a.Ln + qo, bq.m, G, bound_lds + threadIdx.x);
+                sfx = bound_lds + threadIdx.x;
+            }
+        }
         bool alive;
         float D;
         int jdead, jrun;
         dtw_lanes<NC>(a.T, start, mu, s, o, a.qpad + q * a.qstride, bq.m, bq.r, valid, a.keys + q, INFINITY,
-                          alive, D, jdead, jrun);
+                      alive, D, jdead, jrun, sfx, G);
         n_lane_cells += (unsigned long long)jrun * W;
         if (valid) {
             ++n_started;
@@ -713,7 +724,7 @@ static hipError_t launch_dtw_bucket_t(const BatchArgs &a, int nc, int blocks, hi
     const dim3 g(blocks), b(256);
     switch (nc) {
 #define DTWS_BCASE(N) \
-    case N: hipLaunchKernelGGL((k_dtw_batch<N, PREFIX>), g, b, 0, s, a); break;
+    case N: hipLaunchKernelGGL((k_dtw_batch<N, PREFIX>), g, b, N >= kBoundMinNC && a.Un ? kBoundLdsBytes : 0, s, a); break;
         DTWS_BCASE(1) DTWS_BCASE(2) DTWS_BCASE(3) DTWS_BCASE(4) DTWS_BCASE(5) DTWS_BCASE(6) DTWS_BCASE(7)
         DTWS_BCASE(8) DTWS_BCASE(9) DTWS_BCASE(10) DTWS_BCASE(11) DTWS_BCASE(12) DTWS_BCASE(13) DTWS_BCASE(14)
 #undef DTWS_BCASE

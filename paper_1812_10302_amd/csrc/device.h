@@ -521,14 +521,54 @@ __device__ inline void lane_stats(const float *w, int m, float &mu, float &s, fl
 
 
 
+// Lane DTW kernels with bands of at least kBoundMinNC chunks (97 cells and more) may add a bound of
+// the columns still to come to their abandoning test.  Every warping path visits every later column
+// j, in a cell of a row i with |i - j| <= r, whose cost (q_i - c_j)^2 is at least the LB_Keogh term
+// of c_j against the query envelope (eq. (LBKeoghEC)), because L_j <= q_i <= U_j.  So after column
+// j the distance is at least the band minimum plus the terms of the columns after j.
+constexpr int kBoundMinNC = 7;
+constexpr int kBoundBlocks = 64;                                    // suffix entries per lane
+constexpr size_t kBoundLdsBytes = sizeof(float) * kBoundBlocks * 256;   // per 256-lane workgroup
+
+// Columns per suffix block for a window of m points: a multiple of 16 (the abandoning test runs
+// after every 16th column) with at most kBoundBlocks blocks.
+__device__ __forceinline__ int bound_block(int m) { return 16 * ((m + 16 * kBoundBlocks - 1) / (16 * kBoundBlocks)); }
+
+// Suffix sums of the query-envelope LB_Keogh terms of one lane's candidate, block b of G columns:
+// sfx[256 b] = the sum of the terms of columns b G .. m-1, for b < ceil(m / G).  sfx points at the
+// lane's own entry of a [kBoundBlocks][256] LDS array, so only this lane touches it.  Un, Ln: the
+// query envelope in natural order (the same FP32 values the DTW cells use); the candidate value is
+// the one the DTW computes, fma(t - mu, s, o).  Each term is the single non-zero one of
+// max(c - U, 0) and max(L - c, 0), squared.
+__device__ __forceinline__ void bound_suffix(const float *Tp, float mu, float s, float o, const float *Un,
+                                             const float *Ln, int m, int G, float *sfx) {
+    const int nb = (m + G - 1) / G;
+    float acc = 0.0f;
+    for (int b = nb - 1; b >= 0; --b) {
+        const int j0 = b * G, j1 = j0 + G < m ? j0 + G : m;
+        float part = 0.0f;
+#pragma unroll 16
+        for (int j = j0; j < j1; ++j) {
+            const float c = fmaf(Tp[j] - mu, s, o);
+            const float e = fmaxf(c - Un[j], 0.0f) + fmaxf(Ln[j] - c, 0.0f);
+            part = fmaf(e, e, part);
+        }
+        acc += part;
+        sfx[256 * b] = acc;
+    }
+}
+
 // Banded DTW of one candidate per lane (register kernel; see dtw.hip).  qpad: the query's sentinel-padded
 // normalised values; key: best-so-far key read for abandoning (null: use thr0 only).  Returns the
 // distance in D and whether the lane stayed within the threshold; jdead is the number of columns
-// completed before abandoning and jrun the number of columns the wave executed.
+// completed before abandoning and jrun the number of columns the wave executed.  sfx (or null):
+// the lane's suffix bounds from bound_suffix with blocks of G columns, added to the band minimum in
+// the abandoning test.
 template <int NC>
 __device__ __forceinline__ void dtw_lanes(const float *T, int64_t start, float mu, float s, float o,
                                           const float *qpad, int m, int r, bool live, const uint64_t *key,
-                                          float thr0, bool &alive, float &D, int &jdead, int &jrun) {
+                                          float thr0, bool &alive, float &D, int &jdead, int &jrun,
+                                          const float *sfx = nullptr, int G = 16) {
     constexpr int W = 16 * NC;
     constexpr int R = 8 * NC - 1;
     const int ql = threadIdx.x & 15;
@@ -626,6 +666,11 @@ __device__ __forceinline__ void dtw_lanes(const float *T, int64_t start, float m
             if (key) {
                 thr = fminf(thr0, threshold_of(__uint_as_float(kpend)));
                 kpend = load_key_dist_bits(key);
+            }
+            if (sfx) {
+                // plus the bound of the columns after j from the first whole block after them
+                const int b = (j + G) / G;
+                if (b * G < m) mn += sfx[256 * b];
             }
             if (alive && mn > thr) {
                 alive = false;

@@ -303,6 +303,7 @@ __global__ __launch_bounds__(128) void k_dtw_diag(BatchArgs a) {
         atomicAdd(&a.counters[5], n_aband);
         atomicAdd(&a.counters[6], n_cells);
         atomicAdd(&a.counters[8], n_lane_cells);
+        atomicAdd(&a.counters[10], n_cells);
     }
 }
 
@@ -469,6 +470,7 @@ __global__ __launch_bounds__(128) void k_dtw_diag_list(DtwArgs a) {
         atomicAdd(&a.counters[5], n_aband);
         atomicAdd(&a.counters[6], n_cells);
         atomicAdd(&a.counters[8], n_lane_cells);
+        atomicAdd(&a.counters[10], n_cells);
     }
 }
 

@@ -24,12 +24,10 @@
 
 namespace dtws {
 
-
-
-
 template <int NC, bool SEARCH>
 __global__ __launch_bounds__(256) void k_dtw(DtwArgs a) {
     constexpr int W = 16 * NC;
+    extern __shared__ float bound_lds[];   // [kBoundBlocks][256] when the suffix bound is on
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -60,11 +58,20 @@ __global__ __launch_bounds__(256) void k_dtw(DtwArgs a) {
         } else {
             lane_stats(a.T + start, m, mu, s, o);
         }
+        const float *sfx = nullptr;
+        int G = 16;
+        if constexpr (NC >= kBoundMinNC) {
+            if (a.Un) {
+                G = bound_block(m);
+                bound_suffix(a.T + start, mu, s, o, a.Un, a.Ln, m, G, bound_lds + threadIdx.x);
+                sfx = bound_lds + threadIdx.x;
+            }
+        }
         bool alive;
         float D;
         int jdead, jrun;
         dtw_lanes<NC>(a.T, start, mu, s, o, a.qpad, m, r, valid && !bad, SEARCH ? a.key : nullptr,
-                      SEARCH ? INFINITY : a.abandon_at, alive, D, jdead, jrun);
+                      SEARCH ? INFINITY : a.abandon_at, alive, D, jdead, jrun, sfx, G);
         n_lane_cells += (unsigned long long)jrun * W;
         if (SEARCH) {
             if (valid && !bad) {
@@ -471,7 +478,7 @@ static hipError_t launch_dtw_t(const DtwArgs &a, int64_t max_count, int num_cu, 
     const dim3 g((unsigned)blocks), b(256);
     switch (nc) {
 #define DTWS_CASE(N) \
-    case N: hipLaunchKernelGGL((k_dtw<N, SEARCH>), g, b, 0, s, a); break;
+    case N: hipLaunchKernelGGL((k_dtw<N, SEARCH>), g, b, N >= kBoundMinNC && a.Un ? kBoundLdsBytes : 0, s, a); break;
         DTWS_CASE(1) DTWS_CASE(2) DTWS_CASE(3) DTWS_CASE(4) DTWS_CASE(5) DTWS_CASE(6) DTWS_CASE(7)
         DTWS_CASE(8) DTWS_CASE(9) DTWS_CASE(10) DTWS_CASE(11) DTWS_CASE(12) DTWS_CASE(13) DTWS_CASE(14)
 #undef DTWS_CASE

@@ -40,6 +40,8 @@ struct QueryBufs {
     float *qsorted;   // [m] normalised query in the LB visiting order
     float *Usorted;   // [m] query envelope (upper) in the LB visiting order
     float *Lsorted;   // [m] query envelope (lower) in the LB visiting order
+    float *Unat;      // [m] query envelope (upper) in natural order
+    float *Lnat;      // [m] query envelope (lower) in natural order
     int32_t *order;   // [m] LB visiting order: positions by decreasing |qhat|
 };
 
@@ -120,6 +122,7 @@ struct DtwArgs {
     int64_t single;              // >= 0: evaluate only this start
     const float *mu, *s, *o;     // per-window normalisation, or null to compute per lane
     bool stats_by_k;             // mu/s/o are indexed by the list position k, not by the start
+    const float *Un, *Ln;        // natural-order query envelope for the suffix bound, or null (off)
     float abandon_at;            // threshold of the stage entry point
     uint32_t diag_max;           // search rounds of at most this many survivors: one wave per candidate
     uint32_t nb_cap;             // capacity of the near-best list (entries beyond it are dropped and
@@ -161,6 +164,7 @@ struct BatchArgs {
     const double *qhat64;      // per query, stride max_m
     const int32_t *order;      // per query, stride mstride (16-padded visiting order)
     const float *Us, *Ls, *qs;
+    const float *Un, *Ln;      // per query, stride mstride: envelope in natural order
     int64_t mstride;
     uint64_t *keys;            // best-so-far per query
     // window statistics: per-window arrays (all queries share m) or the blocked prefix
@@ -323,6 +327,7 @@ struct dtws_ctx {
     float *qpad = nullptr;
     double *qhat64 = nullptr;
     float *qsorted = nullptr, *Usorted = nullptr, *Lsorted = nullptr;
+    float *Unat = nullptr, *Lnat = nullptr;   // query envelope in natural order, stride mstride
     int32_t *order = nullptr;
     uint64_t *keys = nullptr;             // best-so-far key per query
     // series-sized scratch
@@ -379,6 +384,7 @@ struct dtws_ctx {
     int rounds = 4;         // batched: rounds over the work queue (4, 2 or 1)
     int list_cap = 0;       // capacity of the near-best and batched survivor lists (0 = full size)
     int lb_tile = 1;        // batched: tiled multi-query cascade for rounds over the same candidates
+    int dtw_bound = 1;      // search DTW on one lane per candidate: suffix bound in the abandoning test
     uint64_t *lbs_keys = nullptr;   // LB-sorted order: 2 x max_n keys and the sort's temporary storage,
     void *lbs_temp = nullptr;       // allocated on first use
     size_t lbs_temp_bytes = 0;

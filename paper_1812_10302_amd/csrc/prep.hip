@@ -76,6 +76,8 @@ __device__ void query_prep_body(const float *__restrict__ Q, int m, int r, const
         }
         U[j] = u;
         L[j] = l;
+        b.Unat[j] = u;
+        b.Lnat[j] = l;
     }
     // bitonic sort of positions by decreasing |qhat| (padding keys sort last)
     int P = 1;
@@ -141,6 +143,8 @@ __global__ __launch_bounds__(1024) void k_query_prep_batch(const float *__restri
     b.qsorted = base.qsorted + k * mstride;
     b.Usorted = base.Usorted + k * mstride;
     b.Lsorted = base.Lsorted + k * mstride;
+    b.Unat = base.Unat + k * mstride;
+    b.Lnat = base.Lnat + k * mstride;
     b.order = base.order + k * mstride;
     query_prep_body(Qp + q.qoff, q.m, q.r, b);
 }
