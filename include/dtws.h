@@ -211,6 +211,22 @@ DTWS_API int dtws_dtw_band(dtws_ctx *ctx, const float *T_dev, int64_t n, const f
                            int32_t r, const int64_t *starts_dev, int64_t count, float abandon_at,
                            float *dist_dev, void *stream);
 
+/* dtws_dtw_band for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): no context, no
+ * allocation.  The prepared query (about 105 KB) lives in a static device array of
+ * this library, one per GPU, looked up on the first call on that GPU and held until
+ * the process ends.  Runs on the current HIP device; arguments and results as
+ * dtws_dtw_band.  Schedule: one wave per candidate when count <= 16384 or
+ * 2r+1 > 224, else one lane per candidate normalising its window in the lane.
+ * The query preparation rewrites all of the array that the DTW reads, so no
+ * state carries over between calls.  Limits: m <= 2048 and
+ * r <= 1023 after clamping r to m-1 (DTWS_EINVAL beyond them).  Every call on a GPU
+ * shares that GPU's array: calls on one stream are ordered, calls that overlap on
+ * one GPU (several streams or host threads) race. */
+DTWS_API int dtws_dtw_band_noalloc(const float *T_dev, int64_t n, const float *Q_dev, int32_t m, int32_t r,
+                                   const int64_t *starts_dev, int64_t count, float abandon_at, float *dist_dev,
+                                   void *stream);
+
 /* Best-so-far update (eq. (bsf)): for each k, atomically lowers keys_dev[0]
  * to min(keys_dev[0], (bits(d_dev[k]) << 32) | idx_dev[k]).  Keys order by
  * distance, then by index, so the minimum is the lowest-index best.

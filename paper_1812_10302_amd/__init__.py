@@ -103,6 +103,7 @@ def _load():
         "dtws_znorm_stats": ([P, P, I64, I32, P, P, P], ctypes.c_int),
         "dtws_lb_cascade": ([P, P, I64, P, I32, I32, F32, P, P, P, P, ctypes.POINTER(I64), P], ctypes.c_int),
         "dtws_dtw_band": ([P, P, I64, P, I32, I32, P, I64, F32, P, P], ctypes.c_int),
+        "dtws_dtw_band_noalloc": ([P, I64, P, I32, I32, P, I64, F32, P, P], ctypes.c_int),
         "dtws_bsf_update": ([P, P, P, P, I64, P], ctypes.c_int),
         "dtws_model_init": ([P, U64], ctypes.c_int),
         "dtws_model_get": ([P, P, I64], ctypes.c_int),
@@ -142,6 +143,26 @@ def _strerror(code: int) -> str:
 
 def device_count() -> int:
     return int(_load().dtws_device_count())
+
+
+def dtw_band_noalloc(T, Q, r: int, starts, out, abandon_at: float = math.inf):
+    """dtws_dtw_band_noalloc: FP32 banded DTW of the normalised query against the candidates at
+    `starts` (int64 CUDA tensor) into `out` (float32 CUDA tensor, caller-allocated), on T's device,
+    without a context and without device allocation."""
+    torch = _torch()
+    _dev_f32(T, "T")
+    _dev_f32(Q, "Q")
+    _dev_f32(out, "out")
+    if starts.dtype != torch.int64 or not starts.is_cuda or not starts.is_contiguous():
+        raise TypeError("starts must be a contiguous int64 CUDA tensor")
+    if out.numel() < starts.numel():
+        raise ValueError("out holds fewer values than starts")
+    with torch.cuda.device(T.device):
+        rc = _load().dtws_dtw_band_noalloc(T.data_ptr(), T.numel(), Q.data_ptr(), Q.numel(), int(r), starts.data_ptr(),
+                                           starts.numel(), float(abandon_at), out.data_ptr(), _stream(T))
+    if rc != OK:
+        raise DtwsError(rc, "dtws_dtw_band_noalloc")
+    return out
 
 
 def band(m: int, frac: float) -> int:
