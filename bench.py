@@ -84,7 +84,8 @@ def workload(name: str):
     elif name == "mix1e8_64q":
         T = W.sinusoid_mix(100_000_000, 7)
         wl = W.mixed_queries(T, 64, 256, seed=9000)
-        train = (lambda: W.sinusoid_mix(10_000_000, 8), [(256, 12)], 96, 12, 16384)
+        # about 1e6 (candidate, DTW) pairs from a separate n = 1e7 series
+        train = (lambda: W.sinusoid_mix(10_000_000, 8), [(256, 12)], 384, 12, 16384)
     elif name == "rw262144_1q":
         wl = W.single_query_small()
         train = None

@@ -275,6 +275,12 @@ typedef struct {
                                   terms of the columns still to come (query envelope, computed
                                   per candidate before its DTW; default), 0 = the band minimum
                                   alone */
+    int32_t dtw_rows;          /* batched search DTW on one lane per candidate, bands of 49 cells
+                                  and more: 1 = each wave works through a chunk of survivors as
+                                  four rows of 16 lanes, a row taking the next 16 candidates as
+                                  soon as all of its own have ended (default); 0 = a wave takes
+                                  64 candidates and runs until the last of them ends */
+    int32_t reserved;          /* 0 */
 } dtws_schedule;
 
 DTWS_API int dtws_get_schedule(dtws_ctx *ctx, dtws_schedule *out_host);
@@ -284,7 +290,7 @@ DTWS_API int dtws_set_schedule(dtws_ctx *ctx, const dtws_schedule *s_host);
 /* Autotuner: runs dtws_search_batch on the given batch (arguments as there;
  * DTWS_PROFILE is ignored) under candidate schedules, by coordinate descent over
  * diag_max, block, lb_blocks_per_cu, dtw_blocks_per_cu, stats_prefix,
- * data_envelope, rounds, lb_tile and dtw_bound starting from the current schedule; each candidate is called once untimed (graph capture) and then `reps`
+ * data_envelope, rounds, lb_tile, dtw_bound and dtw_rows starting from the current schedule; each candidate is called once untimed (graph capture) and then `reps`
  * times (1..100) timed on the host clock.  All candidates must return identical
  * matches (DTWS_EHIP otherwise, schedule unchanged).  Installs the fastest, writes
  * it to *best_host and its mean time per call (ms) to *best_ms_host.  Blocking. */

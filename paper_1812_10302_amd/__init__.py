@@ -50,10 +50,11 @@ class Schedule(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int64), ("lb_blocks_per_cu", ctypes.c_int32),
                 ("dtw_blocks_per_cu", ctypes.c_int32), ("diag_max", ctypes.c_int32), ("band_lanes", ctypes.c_int32),
                 ("stats_prefix", ctypes.c_int32), ("data_envelope", ctypes.c_int32), ("rounds", ctypes.c_int32),
-                ("list_cap", ctypes.c_int32), ("lb_tile", ctypes.c_int32), ("dtw_bound", ctypes.c_int32)]
+                ("list_cap", ctypes.c_int32), ("lb_tile", ctypes.c_int32), ("dtw_bound", ctypes.c_int32),
+                ("dtw_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
 
 
 class TrainCfg(ctypes.Structure):

@@ -509,6 +509,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     a.Us = c->Usorted;
     a.Ls = c->Lsorted;
     a.Un = c->dtw_bound ? c->Unat : nullptr;
+    a.rows = c->dtw_rows;
     a.Ln = c->dtw_bound ? c->Lnat : nullptr;
     a.qs = c->qsorted;
     a.mstride = c->mstride;
@@ -528,6 +529,8 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     a.heads = c->heads;
     a.surv_q = c->surv_q;
     a.surv_i = c->surv_i;
+    a.surv_lb = c->surv_lb;
+    a.sorted_lb = c->sorted_lb;
     a.surv_count = c->surv_count;
     a.qcnt = c->qcnt;
     a.overflow = c->overflow;
@@ -732,7 +735,7 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
         std::vector<int64_t> sig = {(int64_t)(uintptr_t)T, n, (int64_t)(uintptr_t)Qp, nq, (int64_t)flags,
                                     (int64_t)seed, p.block, c->lb_blocks_per_cu, c->dtw_blocks_per_cu, c->diag_max,
                                     c->stats_prefix, c->data_envelope, c->rounds, c->lb_tile, c->list_cap,
-                                    c->dtw_bound};
+                                    c->dtw_bound, c->dtw_rows};
         for (int k = 0; k < nq; ++k) {
             sig.push_back(qoff[k]);
             sig.push_back(mh[k]);
@@ -898,7 +901,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
     void *dev[] = {c->qpad, c->qhat64, c->qsorted, c->Usorted, c->Lsorted, c->Unat, c->Lnat, c->order, c->keys, c->st_mu,
                    c->st_s, c->st_o, c->envU, c->envL, c->surv, c->surv_count, c->nb_d, c->nb_idx,
                    c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_block, c->gen_rows, c->bq, c->PP, c->PPd, c->anc, c->tot,
-                   c->perm, c->heads, c->surv_q, c->surv_i, c->sorted, c->qcnt, c->fill, c->overflow,
+                   c->perm, c->heads, c->surv_q, c->surv_i, c->surv_lb, c->sorted, c->sorted_lb, c->qcnt, c->fill, c->overflow,
                    c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q,
                    c->mlp.theta, c->mlp.grad, c->mlp.adam_m, c->mlp.adam_v, c->mlp.W1T, c->mlp.W2T, c->mlp.W2b,
                    c->mlp.Xb, c->mlp.XbT, c->mlp.H1b, c->mlp.H1T, c->mlp.dA2b, c->mlp.dA2T, c->mlp.dA1T,
@@ -984,7 +987,7 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
     }
     if (ok) {
         c->maxblocks = (max_n + kMinBlock - 1) / kMinBlock + 1;
-        // batched survivor list: up to 2^28 entries (12 B each with the sorted copy)
+        // batched survivor list: up to 2^28 entries (20 B each with the sorted copy and the bounds)
         int64_t cap = Q * max_n < (int64_t(1) << 28) ? Q * max_n : (int64_t(1) << 28);
         if (cap < Q * kSeedCands) cap = Q * kSeedCands;   // round -1 of the learned order
         c->bsurv_cap = cap;
@@ -995,6 +998,7 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&c->tot, nblk) == hipSuccess && dalloc(&c->perm, Q * c->maxblocks) == hipSuccess &&
              dalloc(&c->heads, 8) == hipSuccess && dalloc(&c->surv_q, cap) == hipSuccess &&
              dalloc(&c->surv_i, cap) == hipSuccess && dalloc(&c->sorted, cap + 64 * Q) == hipSuccess &&
+             dalloc(&c->surv_lb, cap) == hipSuccess && dalloc(&c->sorted_lb, cap + 64 * Q) == hipSuccess &&
              dalloc(&c->qcnt, Q) == hipSuccess && dalloc(&c->fill, Q) == hipSuccess &&
              dalloc(&c->overflow, 1) == hipSuccess && dalloc(&c->qorder, Q + 1) == hipSuccess &&
              dalloc(&c->wstart, Q + 1) == hipSuccess && dalloc(&c->bucket_w, 2 * (kMaxChunks + 2)) == hipSuccess &&

@@ -175,6 +175,7 @@ __global__ void k_seed_random(BatchArgs a, uint64_t seed) {
         const int64_t N = a.bq[q].N;
         a.surv_q[q] = q;
         a.surv_i[q] = (int32_t)(splitmix64_d(seed + (uint64_t)q) % (uint64_t)N);
+        a.surv_lb[q] = 0.0f;
         a.qcnt[q] = 1;
     }
     if (threadIdx.x == 0) *a.surv_count = (uint32_t)a.nq;
@@ -300,15 +301,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                           a.qs + q * a.mstride, bq.m, (bq.m + 15) & ~15};
             const float *qh = a.qpad + q * a.qstride + kQPad;
             const float thr = threshold_of(load_bsf(a.keys + q));
-            const EmitBatch emit{a.surv_q, a.surv_i, a.surv_count, a.qcnt, a.overflow, a.surv_cap, q};
+            const EmitBatch emit{a.surv_q, a.surv_i, a.surv_lb, a.surv_count, a.qcnt, a.overflow, a.surv_cap, q};
             const float *eU = a.envU ? a.envU + bq.env_slot * a.slot_stride : nullptr;
             const float *eL = a.envU ? a.envL + bq.env_slot * a.slot_stride : nullptr;
             if (PREFIX) {
-                cascade<ENV>(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, q1s[wid], q2s[wid],
+                cascade<ENV>(v, a.T, eU, eL, thr, qh, src, q1s[wid], q2s[wid],
                         StatsPrefix{a.T, a.pre, bq.m, 1.0 / bq.m}, emit, cnt);
             } else {
                 const int64_t so = bq.stat_slot * a.slot_stride;
-                cascade<ENV>(v, a.T, eU, eL, thr, qh[0], qh[bq.m - 1], src, q1s[wid], q2s[wid],
+                cascade<ENV>(v, a.T, eU, eL, thr, qh, src, q1s[wid], q2s[wid],
                         StatsArr{a.mu + so, a.s + so, a.o + so}, emit, cnt);
             }
         }
@@ -378,7 +379,10 @@ __global__ void k_seg_scatter(BatchArgs a) {
             if (valid && q == q0) pos = b0 + (uint32_t)__popcll(peers & lanemask_lt());
             pending &= ~peers;
         }
-        if (valid) a.sorted[a.seg_off[q] + pos] = a.surv_i[e];
+        if (valid) {
+            a.sorted[a.seg_off[q] + pos] = a.surv_i[e];
+            a.sorted_lb[a.seg_off[q] + pos] = a.surv_lb[e];
+        }
     }
 }
 
@@ -453,6 +457,187 @@ __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
             atomicAdd(&a.counters[5], n_aband);
             atomicAdd(&a.counters[6], n_cells);
             atomicAdd(&a.counters[8], n_lane_cells);
+        }
+    }
+}
+
+// The same DTW with refilling rows.  A wave's lanes abandon their candidates at different columns,
+// and a wave that holds 64 candidates runs until the last of them ends.  Here a wave owns a chunk
+// of up to kRowChunk consecutive waves' worth of survivors and works on it as four independent rows
+// of 16 lanes (the query broadcast never leaves a 16-lane row, so the rows need not share the
+// column or even the query): whenever every lane of a row has ended its candidate, the row takes
+// the chunk's next 16 survivors and starts them at column 0.  All rows start at column 0 and end
+// candidates only at the test every 16 columns, so the tests stay aligned across the wave.  A
+// candidate that completes its last column (m - 1) between two tests keeps its distance from that
+// column; its row runs on (on clamped inputs) until the test.
+// The test also adds the query-envelope LB_Keogh terms of the columns still to come: the cascade's
+// full sum for the candidate (sorted_lb) minus the terms of the columns done, which the lane adds up
+// as it goes (one term per column, on the value the column uses).  The two sums round differently
+// by far less than the threshold's slack.  Without the suffix bound (a.Un null) the total is 0 and
+// the terms run on the query itself, so the bound adds max(0 - terms, 0) = 0 (no branch in the
+// column loop, which would cost registers).
+constexpr int kRowChunk = 8;
+
+template <int NC, bool PREFIX>
+__global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
+    constexpr int W = 16 * NC;
+    constexpr int R = 8 * NC - 1;
+    if (*a.overflow || *a.surv_count <= a.diag_max) return;
+    const int lane = threadIdx.x & 63, row = lane >> 4, ql = lane & 15;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t wlo = a.bucket_w[2 * NC], whi = a.bucket_w[2 * NC + 1];
+    // chunks of up to kRowChunk waves, fewer when the bucket would not give every wave one
+    int64_t cw = (whi - wlo) / nwaves;
+    cw = cw < 1 ? 1 : (cw > kRowChunk ? kRowChunk : cw);
+    const int64_t nchunks = (whi - wlo + cw - 1) / cw;
+    unsigned long long n_started = 0, n_aband = 0, n_cells = 0, n_steps = 0;
+    const bool bound = a.Un != nullptr;
+    const float *Ubase = bound ? a.Un : a.qpad + kQPad, *Lbase = bound ? a.Ln : a.qpad + kQPad;
+    const int64_t ustride = bound ? a.mstride : a.qstride;
+    for (int64_t ch = wave; ch < nchunks; ch += nwaves) {
+        const int64_t w0 = wlo + ch * cw;
+        const int64_t w1 = w0 + cw < whi ? w0 + cw : whi;
+        const int nslots = (int)(w1 - w0) * 4;   // rows of 16 survivors in the chunk
+        // per-lane state of the lane's current candidate
+        int q = 0, m = 2, r = 0, jl = 0, jdead = 0;
+        bool valid = false, alive = false, live = false;
+        float mu = 0.0f, s = 0.0f, o = 0.0f, thr = INFINITY, D = INFINITY, tcur = 0.0f;
+        float lbt = 0.0f, kpre = 0.0f, ucur = 0.0f, lcur = 0.0f;   // suffix bound: total, terms done
+        const float *Tp = a.T, *qp = a.qpad, *Unp = Ubase, *Lnp = Lbase;
+        const uint64_t *key = a.keys;
+        uint32_t kpend = ~0u;
+        int qoff[NC];
+        float arr[W + 1], qcur[NC];
+#pragma unroll
+        for (int x = 0; x <= W; ++x) arr[x] = INFINITY;
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            qoff[cc] = 0;
+            qcur[cc] = 0.0f;
+        }
+        // this lane's row takes row slot `slot` of the chunk
+        auto take = [&](int slot) {
+            const int64_t wv = w0 + slot / 4;
+            int32_t wq0;
+            q = wave_query(a, NC, wv, wq0);
+            const BatchQ bq = a.bq[q];
+            m = bq.m;
+            r = bq.r;
+            const int64_t off = (int64_t)(slot & 3) * 16 + ql;
+            valid = (wv - wq0) * 64 + off < (int64_t)a.qcnt[q];
+            const int64_t start = valid ? (int64_t)a.sorted[wv * 64 + off] : 0;
+            if (PREFIX) {
+                StatsPrefix{a.T, a.pre, m, 1.0 / m}(start, mu, s, o);
+            } else {
+                const int64_t so = bq.stat_slot * a.slot_stride;
+                StatsArr{a.mu + so, a.s + so, a.o + so}(start, mu, s, o);
+            }
+            qp = a.qpad + q * a.qstride;
+            key = a.keys + q;
+            lbt = bound && valid ? a.sorted_lb[wv * 64 + off] : 0.0f;
+            kpre = 0.0f;
+            Unp = Ubase + q * ustride;
+            Lnp = Lbase + q * ustride;
+            ucur = Unp[0];
+            lcur = Lnp[0];
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) {
+                const int kpos = 16 * cc + ql;
+                qoff[cc] = (kpos >= R - r && kpos <= R + r) ? kQPad - R + kpos : 0;
+                qcur[cc] = qp[qoff[cc]];
+            }
+#pragma unroll
+            for (int x = 0; x <= W; ++x) arr[x] = INFINITY;
+            arr[R] = 0.0f;
+            Tp = a.T + start;
+            tcur = Tp[0];
+            thr = threshold_of(load_bsf(key));
+            kpend = load_key_dist_bits(key);
+            jl = 0;
+            jdead = m;
+            D = INFINITY;
+            alive = valid;
+            live = valid;
+        };
+        if (row < nslots) take(row);
+        int next = nslots < 4 ? nslots : 4;
+        for (;;) {
+            // 16 columns; each lane's column jl (the same across its row)
+#pragma unroll 1
+            for (int u = 0; u < 16; ++u) {
+                const int jn = jl + 1 < m ? jl + 1 : m - 1;
+                const float tnext = Tp[jn];
+                float qnext[NC];
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) qnext[cc] = qp[qoff[cc] + jn];
+                const float c = fmaf(tcur - mu, s, o);
+                column<NC>(arr, qcur, c);
+                {
+                    const float unext = Unp[jn], lnext = Lnp[jn];
+                    const float e = fmaxf(c - ucur, 0.0f) + fmaxf(lcur - c, 0.0f);
+                    kpre = fmaf(e, e, kpre);
+                    ucur = unext;
+                    lcur = lnext;
+                }
+                if (jl == m - 1) D = arr[R];
+                tcur = tnext;
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) qcur[cc] = qnext[cc];
+                ++jl;
+            }
+            ++n_steps;
+            // the test: every path crosses column jl - 1, so its minimum bounds the distance
+            float mn = arr[0];
+#pragma unroll
+            for (int x = 1; x < W; ++x) mn = fminf(mn, arr[x]);
+            mn += fmaxf(lbt - kpre, 0.0f);
+            thr = fminf(thr, threshold_of(__uint_as_float(kpend)));
+            kpend = load_key_dist_bits(key);
+            if (alive && jl < m && mn > thr) {
+                alive = false;
+                jdead = jl;
+            }
+            if (live && (!alive || jl >= m)) {
+                // the candidate ended: abandoned, or complete with distance D
+                live = false;
+                ++n_started;
+                if (jdead < m) ++n_aband;
+                n_cells += band_cells(m, r, jdead);
+                if (alive && D <= thr) {
+                    const uint32_t start = (uint32_t)(Tp - a.T);
+                    atomicMin((unsigned long long *)key, (unsigned long long)pack_key(D, start));
+                    const uint32_t pos = atomicAdd(a.nb_count, 1u);
+                    if (pos < a.nb_cap) {
+                        a.nb_d[pos] = D;
+                        a.nb_idx[pos] = start;
+                        a.nb_q[pos] = q;
+                    }
+                }
+            }
+            // rows with no live lane take the chunk's next row slots, in row order
+            const uint64_t lm = __ballot(live);
+            uint32_t done = 0;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+                if (((lm >> (16 * rr)) & 0xFFFFull) == 0) done |= 1u << rr;
+            if (done && next < nslots) {
+                const int slot = next + __popc(done & ((1u << row) - 1u));
+                if (((done >> row) & 1u) && slot < nslots) take(slot);
+                next += __popc(done);
+            }
+            if (__ballot(live) == 0) break;
+        }
+    }
+    if (a.counters) {
+        n_started = wave_add(n_started);
+        n_aband = wave_add(n_aband);
+        n_cells = wave_add(n_cells);
+        if (lane == 0) {
+            atomicAdd(&a.counters[4], n_started);
+            atomicAdd(&a.counters[5], n_aband);
+            atomicAdd(&a.counters[6], n_cells);
+            atomicAdd(&a.counters[8], n_steps * 16ull * W * 64ull);
         }
     }
 }
@@ -724,7 +909,12 @@ static hipError_t launch_dtw_bucket_t(const BatchArgs &a, int nc, int blocks, hi
     const dim3 g(blocks), b(256);
     switch (nc) {
 #define DTWS_BCASE(N) \
-    case N: hipLaunchKernelGGL((k_dtw_batch<N, PREFIX>), g, b, N >= kBoundMinNC && a.Un ? kBoundLdsBytes : 0, s, a); break;
+    case N:                                                                                                    \
+        if (N >= 4 && a.rows)                                                                                  \
+            hipLaunchKernelGGL((k_dtw_batch_rows<(N >= 4 ? N : 4), PREFIX>), g, b, 0, s, a);                   \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_dtw_batch<N, PREFIX>), g, b, N >= kBoundMinNC && a.Un ? kBoundLdsBytes : 0, s, a); \
+        break;
         DTWS_BCASE(1) DTWS_BCASE(2) DTWS_BCASE(3) DTWS_BCASE(4) DTWS_BCASE(5) DTWS_BCASE(6) DTWS_BCASE(7)
         DTWS_BCASE(8) DTWS_BCASE(9) DTWS_BCASE(10) DTWS_BCASE(11) DTWS_BCASE(12) DTWS_BCASE(13) DTWS_BCASE(14)
 #undef DTWS_BCASE

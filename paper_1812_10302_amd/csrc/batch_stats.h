@@ -99,10 +99,12 @@ struct StatsArr {
 // an append past the capacity raises the overflow flag instead (the batch then falls back).
 struct EmitBatch {
     int32_t *surv_q, *surv_i;
+    float *surv_lb;
     uint32_t *count, *qcnt, *overflow;
     int64_t cap;
     int q;
-    __device__ void operator()(bool alive, int64_t i) const {
+    // lb: the survivor's query-envelope LB_Keogh sum, kept for the DTW's abandoning test
+    __device__ void operator()(bool alive, int64_t i, float lb) const {
         const uint64_t mask = __ballot(alive);
         if (!mask) return;
         const int lane = threadIdx.x & 63;
@@ -119,6 +121,7 @@ struct EmitBatch {
         if (alive && (int64_t)base + pc <= cap) {
             surv_q[pos] = q;
             surv_i[pos] = (int32_t)i;
+            surv_lb[pos] = lb;
         }
     }
 };

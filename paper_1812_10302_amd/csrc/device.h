@@ -59,7 +59,7 @@ __device__ inline uint32_t load_key_dist_bits(const uint64_t *key) {
 }
 
 // ---------------------------------------------------------------- bound terms
-// Query side of the bounds: positions in visiting order (decreasing |qhat|), padded with neutral
+// Query side of the bounds: positions in visiting order (decreasing expected term), padded with neutral
 // terms to a multiple of 16.
 struct QView {
     const int32_t *order;
@@ -184,7 +184,7 @@ struct CascadeCounts {
 // survivors go to
 // q2, whose full batches run the remaining terms with
 // early abandoning and then the data-envelope bound (level 2, if envU is set).  Candidates that
-// pass everything go to emit(alive, i).  A scheduler that is uniform across the wave serves a
+// pass everything go to emit(alive, i, kq), kq the candidate's full query-envelope sum.  A scheduler that is uniform across the wave serves a
 // full q2 batch first, then a full q1 batch, then new groups: q2 holds fewer than 64 entries when
 // level 1 pushes up to 64 into it, and q1 fewer than 64 when level 0 pushes up to two groups (128)
 // into it, which kQCap accommodates; at the end both queues are drained.
@@ -192,10 +192,11 @@ struct CascadeCounts {
 //   data-envelope bound out (fewer registers when the caller never passes an envelope).
 template <bool ENV = true, class Stats, class Emit, class Source>
 __device__ __forceinline__ void cascade(const QView &v, const float *T, const float *envU, const float *envL,
-                                        float thr, float q0, float ql, Source &src, WaveQueue &q1, WaveQueue2 &q2,
+                                        float thr, const float *qh, Source &src, WaveQueue &q1, WaveQueue2 &q2,
                                         const Stats &stats, const Emit &emit, CascadeCounts &cnt) {
     const int lane = threadIdx.x & 63;
     const int m = v.m, mpad = v.mpad;
+    const float q0 = ldc(qh), ql = ldc(qh + m - 1);
     const int K1 = mpad < kK1 ? mpad : kK1;
     uint32_t h1 = 0, t1 = 0, h2 = 0, t2 = 0;
     bool done = false;
@@ -235,7 +236,7 @@ __device__ __forceinline__ void cascade(const QView &v, const float *T, const fl
                     ++cnt.kd;
                 }
             }
-            emit(alive, i);
+            emit(alive, i, kq);
             continue;
         }
         if (t1 - h1 >= 64u || (done && t1 != h1)) {

@@ -42,7 +42,7 @@ struct QueryBufs {
     float *Lsorted;   // [m] query envelope (lower) in the LB visiting order
     float *Unat;      // [m] query envelope (upper) in natural order
     float *Lnat;      // [m] query envelope (lower) in natural order
-    int32_t *order;   // [m] LB visiting order: positions by decreasing |qhat|
+    int32_t *order;   // [m] LB visiting order: positions by decreasing expected LB_Keogh term
 };
 
 
@@ -166,6 +166,7 @@ struct BatchArgs {
     const float *Us, *Ls, *qs;
     const float *Un, *Ln;      // per query, stride mstride: envelope in natural order
     int64_t mstride;
+    int rows;                  // lane DTW of 4+ chunks: refilling rows (k_dtw_batch_rows)
     uint64_t *keys;            // best-so-far per query
     // window statistics: per-window arrays (all queries share m) or the blocked prefix
     const float *mu, *s, *o;
@@ -178,9 +179,11 @@ struct BatchArgs {
     uint32_t *heads;           // per round
     // survivors of the bound cascade, then sorted into per-query wave segments
     int32_t *surv_q, *surv_i;
+    float *surv_lb;            // each survivor's query-envelope LB_Keogh sum (0 where none was taken)
     uint32_t *surv_count, *qcnt, *overflow;
     int64_t surv_cap;
     int32_t *sorted;
+    float *sorted_lb;          // surv_lb in the order of `sorted`
     int32_t *qorder, *wstart;
     int64_t *seg_off;
     uint32_t *fill;
@@ -363,6 +366,7 @@ struct dtws_ctx {
     int64_t maxblocks = 0;
     uint32_t *heads = nullptr;
     int32_t *surv_q = nullptr, *surv_i = nullptr, *sorted = nullptr;
+    float *surv_lb = nullptr, *sorted_lb = nullptr;
     int64_t bsurv_cap = 0;
     uint32_t *qcnt = nullptr, *fill = nullptr, *overflow = nullptr;
     int32_t *qorder = nullptr, *wstart = nullptr, *bucket_w = nullptr, *bucket_j = nullptr;
@@ -385,6 +389,7 @@ struct dtws_ctx {
     int list_cap = 0;       // capacity of the near-best and batched survivor lists (0 = full size)
     int lb_tile = 1;        // batched: tiled multi-query cascade for rounds over the same candidates
     int dtw_bound = 1;      // search DTW on one lane per candidate: suffix bound in the abandoning test
+    int dtw_rows = 1;       // batched lane DTW (bands of 4+ chunks): rows of 16 lanes refill from a chunk
     uint64_t *lbs_keys = nullptr;   // LB-sorted order: 2 x max_n keys and the sort's temporary storage,
     void *lbs_temp = nullptr;       // allocated on first use
     size_t lbs_temp_bytes = 0;

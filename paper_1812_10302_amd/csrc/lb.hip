@@ -3,7 +3,7 @@
 // data envelope (the paper's "EQ", eq. (LBKeoghEQ)).  A later bound runs only on candidates
 // that survived the earlier ones (the cascade principle) and each sum stops as soon as it
 // exceeds the threshold (early abandoning).  The query positions are visited in order of
-// decreasing |qhat| so that the sums grow fastest first.
+// decreasing expected term (see the query preparation) so that the sums grow fastest first.
 //
 // Layout: one lane per candidate start, consecutive lanes on consecutive starts, so that for a
 // fixed query position j the 64 lanes of a wave read 64 consecutive series points (one
@@ -34,7 +34,7 @@ struct StatsArrays {
 struct EmitList {
     int32_t *surv;
     uint32_t *count;
-    __device__ void operator()(bool alive, int64_t i) const {
+    __device__ void operator()(bool alive, int64_t i, float) const {
         const uint64_t mask = __ballot(alive);
         if (mask) {
             const int lane = threadIdx.x & 63;
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_lb_prune(LbArgs a, QView v) {
     const float thr = a.key ? threshold_of(load_bsf(a.key)) : a.fixed_thr;
     CascadeCounts cnt;
     StrideSource src{a.first + wave * 64, nwaves * 64, a.last};
-    cascade(v, a.T, a.envU, a.envL, thr, a.qh[0], a.qh[a.m - 1], src, q1s[wid], q2s[wid],
+    cascade(v, a.T, a.envU, a.envL, thr, a.qh, src, q1s[wid], q2s[wid],
             StatsArrays{a.mu, a.s, a.o}, EmitList{a.surv, a.surv_count}, cnt);
     if (a.counters) {
         const unsigned long long c_kim = cnt.wave_kim(), c_kq = wave_add_u64(cnt.kq),

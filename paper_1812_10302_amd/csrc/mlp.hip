@@ -757,6 +757,7 @@ __global__ void k_seed_learned(BatchArgs a, const int32_t *bstart, const int64_t
     st = st < 0 ? 0 : (st > bq.N - 1 ? bq.N - 1 : st);
     a.surv_q[e] = q;
     a.surv_i[e] = (int32_t)st;
+    a.surv_lb[e] = 0.0f;
     if (k == 0) a.qcnt[q] = kSeedCands;
     if (e == 0) *a.surv_count = (uint32_t)(a.nq * kSeedCands);
 }

@@ -32,9 +32,22 @@ __device__ double block_sum(double v, double *red) {
     return s;
 }
 
-// Ordering used to sort query positions: larger |qhat| first, lower position on ties.
+// Ordering used to sort query positions: larger key first, lower position on ties.
 __device__ inline bool before(float ka, int ia, float kb, int ib) {
     return ka > kb || (ka == kb && ia < ib);
+}
+
+// Sort key of query position j: the expected query-envelope LB_Keogh term (eq. (LBKeoghEC)) of a
+// candidate value c ~ N(0, 1), which is what the points of a z-normalised window look like one at a
+// time: E[(c - U)+^2] + E[(L - c)+^2] = (1 + U^2) Q(U) - U phi(U) + (1 + L^2) Q(-L) + L phi(L), with
+// Q the standard normal upper tail and phi its density.  Visiting the positions in decreasing
+// expected term lets a sum pass the threshold after fewer terms than visiting them by |qhat|
+// alone, because a narrow envelope far from zero outweighs a large |qhat| inside a wide one.
+__device__ inline float expected_term(float u, float l) {
+    const float kInvSqrt2 = 0.70710678f, kInvSqrt2Pi = 0.39894228f;
+    const float tu = 0.5f * erfcf(u * kInvSqrt2), tl = 0.5f * erfcf(-l * kInvSqrt2);
+    const float pu = kInvSqrt2Pi * expf(-0.5f * u * u), pl = kInvSqrt2Pi * expf(-0.5f * l * l);
+    return fmaxf(fmaf(1.0f + u * u, tu, -u * pu), 0.0f) + fmaxf(fmaf(1.0f + l * l, tl, l * pl), 0.0f);
 }
 
 }  // namespace
@@ -79,11 +92,12 @@ __device__ void query_prep_body(const float *__restrict__ Q, int m, int r, const
         b.Unat[j] = u;
         b.Lnat[j] = l;
     }
-    // bitonic sort of positions by decreasing |qhat| (padding keys sort last)
+    __syncthreads();
+    // bitonic sort of positions by decreasing expected term (padding keys sort last)
     int P = 1;
     while (P < m) P <<= 1;
     for (int j = tid; j < P; j += nt) {
-        skey[j] = j < m ? fabsf(qh[j]) : -1.0f;
+        skey[j] = j < m ? expected_term(U[j], L[j]) : -1.0f;
         sidx[j] = j;
     }
     __syncthreads();

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_lb_tile(BatchArgs a, TileArgs t) {
             const QView v{a.order + q * a.mstride, a.Us + q * a.mstride, a.Ls + q * a.mstride, a.qs + q * a.mstride, m,
                           (m + 15) & ~15};
             const int K1 = v.mpad < kK1 ? v.mpad : kK1;
-            const EmitBatch emit{a.surv_q, a.surv_i, a.surv_count, a.qcnt, a.overflow, a.surv_cap, q};
+            const EmitBatch emit{a.surv_q, a.surv_i, a.surv_lb, a.surv_count, a.qcnt, a.overflow, a.surv_cap, q};
             const int eslot = ENV ? a.bq[q].env_slot : 0;
             const float *eU = ENV && a.envU ? a.envU + eslot * a.slot_stride : nullptr;
             const float *eL = ENV && a.envU ? a.envL + eslot * a.slot_stride : nullptr;
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void k_lb_tile(BatchArgs a, TileArgs t) {
                         ++cnt.kd;
                     }
                 }
-                emit(alive, t0 + local);
+                emit(alive, t0 + local, kq);
                 wave_sync();
             };
             for (uint32_t b = 0; b < n1; b += 64) {

@@ -417,16 +417,18 @@ def test_schedules_give_identical_results(ctx, casc):
         ctx.set_schedule(**default)
 
 
-def test_dtw_suffix_bound_same_matches(ctx, casc):
-    """The lane DTW with and without the suffix bound of the columns still to come: the oracle's
-    matches either way, for the plain and the batched search on the lane schedule, with bands of 7 to
-    14 chunks (m = 2048 takes blocks of 32 columns) and lengths that are not multiples of 16; the
-    bound can only abandon earlier, so it computes fewer DTW cells (up to the timing of best-so-far
-    updates)."""
+def test_dtw_suffix_bound_and_refilling_rows_same_matches(ctx, casc):
+    """The lane DTW with and without the suffix bound of the columns still to come, and the batched
+    lane DTW with whole waves and with refilling 16-lane rows: the oracle's matches every way, for the
+    plain and the batched search on the lane schedule, with bands of 4 to 14 chunks (m = 2048 takes
+    bound blocks of 32 columns), lengths that are not multiples of 16 and queries of several lengths
+    in one bucket; the bound can only abandon earlier, so it computes fewer DTW cells (up to the
+    timing of best-so-far updates)."""
     T = W.random_walk(400_009, 44)
-    specs = [(512, 51), (300, 60), (1024, 102), (2048, 111), (1000, 99), (777, 70)]
-    qs = [W.noisy_cut(T, 9_000 + 61_000 * k, m, 0.2, 1100 + k) if k % 2 == 0 else W.random_walk(m, 1110 + k)
-          for k, (m, _) in enumerate(specs)]
+    specs = [(512, 51), (300, 60), (1024, 102), (2048, 111), (1000, 99), (777, 70), (200, 30), (130, 31),
+             (1001, 50)]
+    qs = [W.noisy_cut(T, (9_000 + 61_000 * k) % (T.size - m), m, 0.2, 1100 + k) if k % 2 == 0
+          else W.random_walk(m, 1110 + k) for k, (m, _) in enumerate(specs)]
     rs = [r for _, r in specs]
     ref = _cascade_refs(casc, T, qs, rs)
     Td = dev(T)
@@ -434,16 +436,20 @@ def test_dtw_suffix_bound_same_matches(ctx, casc):
     default = ctx.get_schedule()
     cells = {}
     try:
-        for bound in (0, 1):
-            ctx.set_schedule(diag_max=0, dtw_bound=bound)
-            print("suffix bound", bound, flush=True)
-            _check_batch(ctx.search_batch(Td, Qd, rs, seed=5), ref)
-            cells[bound] = ctx.counters()["dtw_cells"]
-            _check_batch([ctx.search(Td, q, r, seed=5) for q, r in zip(Qd, rs)], ref)
+        for rows in (0, 1):
+            for bound in (0, 1):
+                ctx.set_schedule(diag_max=0, dtw_bound=bound, dtw_rows=rows)
+                print("suffix bound", bound, "refilling rows", rows, flush=True)
+                _check_batch(ctx.search_batch(Td, Qd, rs, seed=5), ref)
+                cells[rows, bound] = ctx.counters()["dtw_cells"]
+                _check_batch([ctx.search(Td, q, r, seed=5) for q, r in zip(Qd, rs)], ref)
+            for order in (dtws.ORDER_RANDOM, dtws.ORDER_NATURAL):
+                ctx.set_schedule(diag_max=0, rounds=1, block=2048, dtw_rows=rows)
+                _check_batch(ctx.search_batch(Td, Qd, rs, flags=order, seed=6), ref)
     finally:
         ctx.set_schedule(**default)
-    print(f"DTW cells, batched: without the bound {cells[0]}, with it {cells[1]}")
-    assert cells[1] <= 1.1 * cells[0]
+    print(f"DTW cells, batched (rows, bound): {cells}")
+    assert cells[0, 1] <= 1.1 * cells[0, 0]
 
 
 def test_tiled_cascade_equals_per_query_items(ctx, casc):
@@ -512,7 +518,7 @@ def test_set_schedule_rejects_bad_fields(ctx):
     default = ctx.get_schedule()
     for bad in ({"block": 3000}, {"diag_max": -2}, {"band_lanes": 2}, {"lb_blocks_per_cu": 65},
                 {"stats_prefix": 2}, {"data_envelope": -1}, {"rounds": 3}, {"list_cap": 63}, {"lb_tile": 2},
-                {"dtw_bound": 2}):
+                {"dtw_bound": 2}, {"dtw_rows": -1}):
         with pytest.raises(dtws.DtwsError):
             ctx.set_schedule(**bad)
         assert ctx.get_schedule() == default
