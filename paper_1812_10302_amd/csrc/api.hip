@@ -525,6 +525,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     a.envL = c->data_envelope ? c->envL : nullptr;
     a.slot_stride = c->max_n;
     a.perm = c->perm;
+    a.rank = c->rank;
     a.maxblocks = c->maxblocks;
     a.heads = c->heads;
     a.surv_q = c->surv_q;
@@ -625,6 +626,11 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         HIPCHK(c, launch_make_perm(a, (flags & DTWS_ORDER_MASK) == DTWS_ORDER_RANDOM ? 1 : 0, seed ^ 0xA5A5ull,
                                    max_nb, s));
     }
+    if ((flags & DTWS_ORDER_MASK) != DTWS_ORDER_NATURAL && c->rounds > 1) {
+        // the last round visits the rest of every query's blocks in series order (see below)
+        PROF(DTWS_K_OTHER);
+        HIPCHK(c, launch_perm_rank(a, max_nb, s));
+    }
     const int dtw_blocks = c->num_cu * (c->dtw_blocks_per_cu > 0 ? c->dtw_blocks_per_cu : 4);
     const int lb_blocks = c->num_cu * (c->lb_blocks_per_cu > 0 ? c->lb_blocks_per_cu : 8);
     // known_count: the round's survivor count when the host knows it (-1 otherwise); a count the
@@ -676,21 +682,29 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
             int parts = size <= k64 ? 16 : (size <= 2 * k1m ? 4 : 1);
             while (parts > 1 && B / parts < 256) parts /= 2;
             // series order, block-major, whenever the round's blocks are the same for every query:
-            // a round that holds them all, or any round of the series order
-            const bool natural = (rank_lo == 0 && rank_hi >= max_nb) ||
-                                 (flags & DTWS_ORDER_MASK) == DTWS_ORDER_NATURAL;
+            // a round that holds them all, or any round of the series order.  The last round of
+            // another order goes the same way over every block, each query skipping the blocks it
+            // visited in the earlier rounds (ranks below rank_lo).
+            const bool series = (flags & DTWS_ORDER_MASK) == DTWS_ORDER_NATURAL;
+            const bool rest = !series && rank_lo > 0 && rank_hi >= max_nb;
+            const bool natural = (rank_lo == 0 && rank_hi >= max_nb) || series || rest;
+            const int skip_below = rest ? (int)rank_lo : 0;
+            const int64_t item_lo = rest ? 0 : rank_lo;
             if (natural && c->lb_tile) {
                 // every query visits the same candidates: series tiles shared by all queries
                 TileArgs t{};
                 t.gfirst = c->tile_q;
                 t.qlist = c->tile_q + c->max_q + 1;
                 t.ngroups = p.ngroups;
-                t.c_lo = rank_lo * B;
+                t.c_lo = item_lo * B;
                 t.c_hi = rank_hi * B;
                 t.halo = max_m - 1;
+                t.skip_below = skip_below;
+                t.block = B;
                 HIPCHK(c, launch_lb_tile(a, t, !same_m, p.max_N, s));
             } else {
-                HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)rank_lo, (int)rank_hi, parts, natural, lb_blocks, s));
+                HIPCHK(c, launch_lb_batch(a, !same_m, round, (int)item_lo, (int)rank_hi, parts, natural, skip_below,
+                                          lb_blocks, s));
             }
         }
         rc = dtw_round(-1);
@@ -901,7 +915,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
     void *dev[] = {c->qpad, c->qhat64, c->qsorted, c->Usorted, c->Lsorted, c->Unat, c->Lnat, c->order, c->keys, c->st_mu,
                    c->st_s, c->st_o, c->envU, c->envL, c->surv, c->surv_count, c->nb_d, c->nb_idx,
                    c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_block, c->gen_rows, c->bq, c->PP, c->PPd, c->anc, c->tot,
-                   c->perm, c->heads, c->surv_q, c->surv_i, c->surv_lb, c->sorted, c->sorted_lb, c->qcnt, c->fill, c->overflow,
+                   c->perm, c->rank, c->heads, c->surv_q, c->surv_i, c->surv_lb, c->sorted, c->sorted_lb, c->qcnt, c->fill, c->overflow,
                    c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q,
                    c->mlp.theta, c->mlp.grad, c->mlp.adam_m, c->mlp.adam_v, c->mlp.W1T, c->mlp.W2T, c->mlp.W2b,
                    c->mlp.Xb, c->mlp.XbT, c->mlp.H1b, c->mlp.H1T, c->mlp.dA2b, c->mlp.dA2T, c->mlp.dA1T,
@@ -996,6 +1010,7 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&c->PP, max_n + 1) == hipSuccess && dalloc(&c->PPd, dec_total(max_n)) == hipSuccess &&
              dalloc(&c->anc, nblk) == hipSuccess &&
              dalloc(&c->tot, nblk) == hipSuccess && dalloc(&c->perm, Q * c->maxblocks) == hipSuccess &&
+             dalloc(&c->rank, Q * c->maxblocks) == hipSuccess &&
              dalloc(&c->heads, 8) == hipSuccess && dalloc(&c->surv_q, cap) == hipSuccess &&
              dalloc(&c->surv_i, cap) == hipSuccess && dalloc(&c->sorted, cap + 64 * Q) == hipSuccess &&
              dalloc(&c->surv_lb, cap) == hipSuccess && dalloc(&c->sorted_lb, cap + 64 * Q) == hipSuccess &&

@@ -169,6 +169,14 @@ __global__ void k_make_perm(BatchArgs a, int mode, uint64_t seed) {
     }
 }
 
+// The inverse of every query's block order: rank[q][perm[q][k]] = k.
+__global__ void k_perm_rank(BatchArgs a) {
+    const int q = blockIdx.y;
+    const int64_t nb = a.bq[q].nblocks;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += (int64_t)gridDim.x * blockDim.x)
+        a.rank[(int64_t)q * a.maxblocks + a.perm[(int64_t)q * a.maxblocks + k]] = (int32_t)k;
+}
+
 // Round -1: the best-so-far of every query starts from one seeded random candidate (Algorithm 1).
 __global__ void k_seed_random(BatchArgs a, uint64_t seed) {
     for (int q = threadIdx.x; q < a.nq; q += blockDim.x) {
@@ -188,7 +196,10 @@ __global__ void k_seed_random(BatchArgs a, uint64_t seed) {
 // (query, rank k, part); part selects one of `parts` equal pieces of the k-th block of the
 // query's visiting order.  They go out query-major, or block-major in series order when the
 // round's blocks are the same for every query (then the waves on the queries of one block run at
-// about the same time and share its data through the caches).
+// about the same time and share its data through the caches).  The last round of another order
+// also goes block-major in series order over every block, each query skipping the blocks it ranked
+// below skip_below (those it visited in the earlier rounds): the rest of every query's blocks, in
+// an order the queries share.
 struct ItemSource {
     const BatchArgs *a;
     int round, rank_lo, parts;
@@ -199,6 +210,7 @@ struct ItemSource {
     int pq = -1;
     int64_t pfirst = 0, plast = 0;
     bool natural = false;       // the round holds every block: series order, block-major
+    int skip_below = 0;         // natural: skip a query's blocks of rank below this
 
     // pops items until one that exists; false when the round is exhausted
     __device__ bool pop(int &qq, int64_t &first, int64_t &last) {
@@ -224,6 +236,7 @@ struct ItemSource {
             const BatchQ bq = a->bq[qq];
             if (k >= bq.nblocks) continue;
             const int64_t blk = natural ? k : a->perm[(int64_t)qq * a->maxblocks + k];
+            if (skip_below > 0 && a->rank[(int64_t)qq * a->maxblocks + blk] < skip_below) continue;
             const int64_t piece = a->block / parts;
             first = blk * a->block + part * piece;
             if (first >= bq.N) continue;
@@ -279,13 +292,14 @@ struct ItemSource {
 template <bool PREFIX, bool ENV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_lb_batch(BatchArgs a, int round,
                                                                                      int rank_lo, int rank_hi, int parts,
-                                                                                     int natural) {
+                                                                                     int natural, int skip_below) {
     __shared__ WaveQueue q1s[4];
     __shared__ WaveQueue2 q2s[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     ItemSource src{&a, round, rank_lo, parts, (uint32_t)(rank_hi - rank_lo) * (uint32_t)parts, 0u, -1};
     src.total = src.per_q * (uint32_t)a.nq;
     src.natural = natural != 0;
+    src.skip_below = skip_below;
     CascadeCounts cnt;
     int q;
     int64_t f, l;
@@ -875,26 +889,33 @@ hipError_t launch_make_perm(const BatchArgs &a, int mode, uint64_t seed, int64_t
     return hipGetLastError();
 }
 
+hipError_t launch_perm_rank(const BatchArgs &a, int64_t max_nblocks, hipStream_t s) {
+    int64_t bx = (max_nblocks + 255) / 256;
+    if (bx > 1024) bx = 1024;
+    hipLaunchKernelGGL(k_perm_rank, dim3((unsigned)bx, (unsigned)a.nq), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s) {
     hipLaunchKernelGGL(k_seed_random, dim3(1), dim3(256), 0, s, a, seed);
     return hipGetLastError();
 }
 
 hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
-                           bool natural, int blocks, hipStream_t s) {
+                           bool natural, int skip_below, int blocks, hipStream_t s) {
     const bool env = a.envU != nullptr;
     if (prefix && env)
         hipLaunchKernelGGL((k_lb_batch<true, true>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
-                           (int)natural);
+                           (int)natural, skip_below);
     else if (prefix)
         hipLaunchKernelGGL((k_lb_batch<true, false>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
-                           (int)natural);
+                           (int)natural, skip_below);
     else if (env)
         hipLaunchKernelGGL((k_lb_batch<false, true>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
-                           (int)natural);
+                           (int)natural, skip_below);
     else
         hipLaunchKernelGGL((k_lb_batch<false, false>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
-                           (int)natural);
+                           (int)natural, skip_below);
     return hipGetLastError();
 }
 

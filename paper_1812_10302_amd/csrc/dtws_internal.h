@@ -175,6 +175,7 @@ struct BatchArgs {
     int64_t slot_stride;       // elements per statistics / envelope slot
     // work queue
     int32_t *perm;             // per query: block visiting order, stride maxblocks
+    int32_t *rank;             // its inverse: rank of each block in the query's order
     int64_t maxblocks;
     uint32_t *heads;           // per round
     // survivors of the bound cascade, then sorted into per-query wave segments
@@ -215,6 +216,8 @@ struct TileArgs {
     int ngroups;
     int64_t c_lo, c_hi;      // candidate starts of the round, the same for every query
     int halo;                // largest query length of the batch - 1
+    int skip_below;          // > 0: a query skips the tiles of blocks it ranked below this (visited)
+    int64_t block;           // candidates per block (for skip_below)
 };
 
 // ---------------------------------------------------------------- ordering network
@@ -273,9 +276,10 @@ hipError_t launch_certify(const CertArgs &c, hipStream_t s);
 hipError_t launch_prefix(const float *T, int64_t n, double2 *PP, double *anc, double2 *tot, hipStream_t s,
                          const Decimated *dec = nullptr, uint32_t levels = 0);
 hipError_t launch_make_perm(const BatchArgs &a, int mode, uint64_t seed, int64_t max_nblocks, hipStream_t s);
+hipError_t launch_perm_rank(const BatchArgs &a, int64_t max_nblocks, hipStream_t s);
 hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s);
 hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
-                           bool natural, int blocks, hipStream_t s);
+                           bool natural, int skip_below, int blocks, hipStream_t s);
 hipError_t launch_segments(const BatchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_lb_tile(const BatchArgs &a, const TileArgs &t, bool prefix, int64_t max_N, hipStream_t s);
 size_t tile_lds_bytes(int max_m);
@@ -362,7 +366,7 @@ struct dtws_ctx {
     dtws::Decimated dec{};
     double *anc = nullptr;
     double2 *tot = nullptr;
-    int32_t *perm = nullptr;
+    int32_t *perm = nullptr, *rank = nullptr;
     int64_t maxblocks = 0;
     uint32_t *heads = nullptr;
     int32_t *surv_q = nullptr, *surv_i = nullptr, *sorted = nullptr;

@@ -116,6 +116,8 @@ __global__ __launch_bounds__(256) void k_lb_tile(BatchArgs a, TileArgs t) {
         }
         for (int qi = qbeg; qi < qend; ++qi) {
             const int q = __builtin_amdgcn_readfirstlane(ldc(t.qlist + qi));
+            // a block this query visited in an earlier round (the tile lies inside one block)
+            if (t.skip_below > 0 && ldc(a.rank + (int64_t)q * a.maxblocks + t0 / t.block) < t.skip_below) continue;
             const float *qh = a.qpad + (int64_t)q * a.qstride + kQPad;
             const float q0 = ldc(qh), ql = ldc(qh + m - 1);
             const float thr = threshold_of(load_bsf(a.keys + q));
