@@ -205,6 +205,29 @@ def measure(wl, train, steps: int, warmup: int, plain_queries: int, profile: boo
 ORACLE_SUBSET = {"rw262144_1q": [0], "rw1e8_3q": [0, 1, 2], "mix1e8_64q": [0, 40], "rw1e8_256q": [7, 25, 198]}
 
 
+def traffic_of(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from its committed counter summary
+    (profiles/traffic_<kernel>_<workload>.txt: FETCH_SIZE and WRITE_SIZE per dispatch from two
+    rocprofv3 --pmc passes, each scaled by what the counter reads for a device copy of known size),
+    or None when there is none or the kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for src in kv.get("sources", "").split():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != kv.get("sources_sha256"):
+        return None
+    return float(kv["bytes_per_launch"])
+
+
 def roofline_of(meas):
     """Roofline object for the dominant kernel class of the profiled pass."""
     prof, cnt = meas["kernel_ms"], meas["counters"]
@@ -230,14 +253,39 @@ def roofline_of(meas):
         # algorithmic unit: one band cell of the DTW recurrence (3 VALU lane-operations)
         c = cnt["dtw_cells"] - cnt["dtw_wave_cells"] if dominant == "dtw" else cnt["dtw_wave_cells"]
         g = c / (t_ms * 1e-3) / 1e9
-        name = ("k_dtw_batch (one lane per candidate)" if dominant == "dtw"
+        rows = sched.get("dtw_rows", 1)
+        name = (("k_dtw_batch_rows" if rows else "k_dtw_batch") + " (one lane per candidate)" if dominant == "dtw"
                 else "k_dtw_diag (one wave per candidate)")
+        traffic = (traffic_of("k_dtw_batch_rows", meas["workload_key"])
+                   if dominant == "dtw" and rows else None)
         return {"bound": "alu", "kernel": name, "achieved": round(g, 1), "peak": round(DTW_PEAK_GCUPS, 1),
-                "unit": "GCUPS", "frac": round(g / DTW_PEAK_GCUPS, 4), "traffic": None,
+                "unit": "GCUPS", "frac": round(g / DTW_PEAK_GCUPS, 4), "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "algorithmic_cells_per_launch": int(c / max(nl, 1)),
                 "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
     return {"bound": "latency", "kernel": f"class {dominant}", "achieved": None, "peak": None, "unit": None,
             "frac": None, "traffic": None, "avg_launch_ms": round(t_ms / max(nl, 1), 4), "launches": nl}
+
+
+RATE_SHAPES = [(128, 6), (128, 12), (256, 12), (512, 25), (1024, 51), (1024, 102), (2048, 102)]
+
+
+def dtw_rates_main():
+    """--dtw-rates: exact banded DTW (no abandoning) of random candidates of a 5e7-point random walk
+    through dtws_dtw_band on the one-lane-per-candidate schedule, for the shapes of the workloads.
+    Prints one JSON line; under rocprofv3 the kernel durations (k_dtw<NC, false>) give the DTW
+    kernel's own rate without the window-statistics pass that dtws_dtw_band runs first."""
+    import torch
+    import paper_1812_10302_amd as dtws
+    from paper_1812_10302_amd import workloads as W
+    n = 50_000_000
+    T = torch.from_numpy(W.random_walk(n, 5)).to("cuda:0")
+    ctx = dtws.Context(0, max_n=n, max_m=2048)
+    ctx.set_schedule(band_lanes=1)
+    shapes = [(torch.from_numpy(W.random_walk(m, 7 + m)).to("cuda:0"), m, r) for m, r in RATE_SHAPES]
+    out = dtw_rates(ctx, T, shapes, n)
+    ctx.close()
+    print(json.dumps({"dtw_rates": out, "peak_gcups": round(DTW_PEAK_GCUPS, 1)}), flush=True)
 
 
 def dtw_rates(ctx, T, shapes, n):
@@ -247,7 +295,7 @@ def dtw_rates(ctx, T, shapes, n):
     rng = np.random.default_rng(11)
     out = []
     for q, m, r in shapes:
-        count = (1 << 20) if m <= 256 else ((1 << 18) if r <= 111 else (1 << 16))
+        count = (1 << 21) if m <= 256 else ((1 << 19) if m <= 1024 and r <= 51 else ((1 << 18) if r <= 111 else (1 << 16)))
         st = torch.from_numpy(rng.integers(0, n - m + 1, count)).to(T.device)
         ctx.dtw_band(T, q, r, st)
         torch.cuda.synchronize()
@@ -275,6 +323,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=250_000_000, help="series points of the CPU baseline")
     ap.add_argument("--no-ablations", action="store_true", help="skip the natural / PAA order ablations")
+    ap.add_argument("--dtw-rates", action="store_true", help="only the exact DTW rates of the workloads' shapes")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="end with a device copy of this many MiB (the reference for HBM counters)")
     ap.add_argument("--schedule", default=None,
                     help="JSON object of schedule fields for the main workload instead of the autotuner")
     args = ap.parse_args()
@@ -285,6 +336,9 @@ def main():
 
     import torch
 
+    if args.dtw_rates:
+        dtw_rates_main()
+        return
     t0 = time.time()
     wl, train = workload(args.workload)
     log(f"workload {wl.name}: generated in {time.time() - t0:.1f}s")
@@ -297,6 +351,7 @@ def main():
 
     roofline, dtw_rate = None, []
     if not args.no_profile:
+        meas["workload_key"] = args.workload
         roofline = roofline_of(meas)
         shapes = []
         seen = set()
@@ -388,6 +443,13 @@ def main():
         "results": meas["results"][:8],
     }
     print(json.dumps(out), flush=True)
+    if args.copy_calibration_mib > 0:
+        # a plain device copy of known size, for scaling the HBM counters of a profiled run
+        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calibration_mib} MiB")
 
 
 if __name__ == "__main__":

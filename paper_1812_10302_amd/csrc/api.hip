@@ -578,7 +578,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     HIPCHK(c, hipMemcpyAsync(c->tile_q, c->h_tile_q, sizeof(int32_t) * (c->max_q + 1 + nq), hipMemcpyHostToDevice, s));
     {
         PROF(DTWS_K_OTHER);
-        HIPCHK(c, launch_reset_batch(c->keys, nq, c->counters, kNumCounters, c->heads, 8, c->nb_count, c->cert_count,
+        HIPCHK(c, launch_reset_batch(c->keys, nq, c->counters, kNumCounters, c->heads, 64, c->nb_count, c->cert_count,
                                      c->overflow, s));
     }
     {
@@ -1011,7 +1011,7 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&c->anc, nblk) == hipSuccess &&
              dalloc(&c->tot, nblk) == hipSuccess && dalloc(&c->perm, Q * c->maxblocks) == hipSuccess &&
              dalloc(&c->rank, Q * c->maxblocks) == hipSuccess &&
-             dalloc(&c->heads, 8) == hipSuccess && dalloc(&c->surv_q, cap) == hipSuccess &&
+             dalloc(&c->heads, 64) == hipSuccess && dalloc(&c->surv_q, cap) == hipSuccess &&
              dalloc(&c->surv_i, cap) == hipSuccess && dalloc(&c->sorted, cap + 64 * Q) == hipSuccess &&
              dalloc(&c->surv_lb, cap) == hipSuccess && dalloc(&c->sorted_lb, cap + 64 * Q) == hipSuccess &&
              dalloc(&c->qcnt, Q) == hipSuccess && dalloc(&c->fill, Q) == hipSuccess &&

@@ -211,28 +211,48 @@ struct ItemSource {
     int64_t pfirst = 0, plast = 0;
     bool natural = false;       // the round holds every block: series order, block-major
     int skip_below = 0;         // natural: skip a query's blocks of rank below this
+    uint32_t sub_done = 0;      // natural: sub-queues found empty
 
     // pops items until one that exists; false when the round is exhausted
     __device__ bool pop(int &qq, int64_t &first, int64_t &last) {
         const int lane = threadIdx.x & 63;
         for (;;) {
-            uint32_t idx = 0;
-            if (lane == 0) idx = atomicAdd(&a->heads[round], 1u);
-            idx = __builtin_amdgcn_readfirstlane(idx);   // wave-uniform: item state stays in SGPRs
-            if (idx >= total) return false;
-            // a round that holds every block visits them in series order, the queries of one
-            // block one after another (their windows share the prefix and series data, which the
-            // caches then serve to all of them); otherwise query by query in visiting order
-            uint32_t rest;
+            int k = 0, part = 0;
             if (natural) {
-                qq = (int)(idx % (uint32_t)a->nq);
-                rest = idx / (uint32_t)a->nq;
+                // series order in eight sub-queues: block b goes to the workgroups with
+                // blockIdx.x = b (mod 8), which the hardware places on one XCD, so the queries of a
+                // block share that XCD's L2; an empty sub-queue sends the wave to the others
+                const uint32_t nranks = (uint32_t)(per_q / (uint32_t)parts);
+                const int home = (int)(blockIdx.x & 7u);
+                bool got = false;
+                for (int j = 0; j < 8 && !got; ++j) {
+                    const int x = (home + j) & 7;
+                    if (sub_done & (1u << x)) continue;
+                    uint32_t c = 0;
+                    if (lane == 0) c = atomicAdd(&a->heads[round * 8 + x], 1u);
+                    c = __builtin_amdgcn_readfirstlane(c);
+                    const uint32_t nbx = nranks > (uint32_t)x ? (nranks - (uint32_t)x + 7u) / 8u : 0u;
+                    if (c >= nbx * (uint32_t)parts * (uint32_t)a->nq) {
+                        sub_done |= 1u << x;
+                        continue;
+                    }
+                    qq = (int)(c % (uint32_t)a->nq);
+                    const uint32_t rest = c / (uint32_t)a->nq;
+                    k = rank_lo + (int)(rest / (uint32_t)parts) * 8 + x;
+                    part = (int)(rest % (uint32_t)parts);
+                    got = true;
+                }
+                if (!got) return false;
             } else {
+                uint32_t idx = 0;
+                if (lane == 0) idx = atomicAdd(&a->heads[round * 8], 1u);
+                idx = __builtin_amdgcn_readfirstlane(idx);   // wave-uniform: item state stays in SGPRs
+                if (idx >= total) return false;
                 qq = (int)(idx / per_q);
-                rest = idx % per_q;
+                const uint32_t rest = idx % per_q;
+                k = rank_lo + (int)(rest / (uint32_t)parts);
+                part = (int)(rest % (uint32_t)parts);
             }
-            const int k = rank_lo + (int)(rest / (uint32_t)parts);
-            const int part = (int)(rest % (uint32_t)parts);
             const BatchQ bq = a->bq[qq];
             if (k >= bq.nblocks) continue;
             const int64_t blk = natural ? k : a->perm[(int64_t)qq * a->maxblocks + k];
@@ -490,7 +510,7 @@ __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
 // by far less than the threshold's slack.  Without the suffix bound (a.Un null) the total is 0 and
 // the terms run on the query itself, so the bound adds max(0 - terms, 0) = 0 (no branch in the
 // column loop, which would cost registers).
-constexpr int kRowChunk = 8;
+constexpr int kRowChunk = 32;
 
 template <int NC, bool PREFIX>
 __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
