@@ -290,8 +290,10 @@ DTWS_API int dtws_set_schedule(dtws_ctx *ctx, const dtws_schedule *s_host);
 /* Autotuner: runs dtws_search_batch on the given batch (arguments as there;
  * DTWS_PROFILE is ignored) under candidate schedules, by coordinate descent over
  * diag_max, block, lb_blocks_per_cu, dtw_blocks_per_cu, stats_prefix,
- * data_envelope, rounds, lb_tile, dtw_bound and dtw_rows starting from the current schedule; each candidate is called once untimed (graph capture) and then `reps`
- * times (1..100) timed on the host clock.  All candidates must return identical
+ * data_envelope, rounds, lb_tile, dtw_bound and dtw_rows starting from the
+ * current schedule, then once more over data_envelope, rounds and lb_tile; each
+ * candidate is called once untimed (graph capture) and then `reps` times
+ * (1..100) timed on the host clock.  All candidates must return identical
  * matches (DTWS_EHIP otherwise, schedule unchanged).  Installs the fastest, writes
  * it to *best_host and its mean time per call (ms) to *best_ms_host.  Blocking. */
 DTWS_API int dtws_autotune_batch(dtws_ctx *ctx, const float *T_dev, int64_t n, const float *Q_packed_dev,

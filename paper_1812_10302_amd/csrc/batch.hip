@@ -210,6 +210,7 @@ struct ItemSource {
     int pq = -1;
     int64_t pfirst = 0, plast = 0;
     bool natural = false;       // the round holds every block: series order, block-major
+    bool subq = false;          // natural: in eight sub-queues, one per XCD
     int skip_below = 0;         // natural: skip a query's blocks of rank below this
     uint32_t sub_done = 0;      // natural: sub-queues found empty
 
@@ -218,7 +219,7 @@ struct ItemSource {
         const int lane = threadIdx.x & 63;
         for (;;) {
             int k = 0, part = 0;
-            if (natural) {
+            if (subq) {
                 // series order in eight sub-queues: block b goes to the workgroups with
                 // blockIdx.x = b (mod 8), which the hardware places on one XCD, so the queries of a
                 // block share that XCD's L2; an empty sub-queue sends the wave to the others
@@ -248,8 +249,16 @@ struct ItemSource {
                 if (lane == 0) idx = atomicAdd(&a->heads[round * 8], 1u);
                 idx = __builtin_amdgcn_readfirstlane(idx);   // wave-uniform: item state stays in SGPRs
                 if (idx >= total) return false;
-                qq = (int)(idx / per_q);
-                const uint32_t rest = idx % per_q;
+                // series order, block-major (the queries of one block one after another), or query
+                // by query in visiting order
+                uint32_t rest;
+                if (natural) {
+                    qq = (int)(idx % (uint32_t)a->nq);
+                    rest = idx / (uint32_t)a->nq;
+                } else {
+                    qq = (int)(idx / per_q);
+                    rest = idx % per_q;
+                }
                 k = rank_lo + (int)(rest / (uint32_t)parts);
                 part = (int)(rest % (uint32_t)parts);
             }
@@ -318,7 +327,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     ItemSource src{&a, round, rank_lo, parts, (uint32_t)(rank_hi - rank_lo) * (uint32_t)parts, 0u, -1};
     src.total = src.per_q * (uint32_t)a.nq;
-    src.natural = natural != 0;
+    src.natural = (natural & 1) != 0;
+    src.subq = (natural & 2) != 0;
     src.skip_below = skip_below;
     CascadeCounts cnt;
     int q;
@@ -924,18 +934,21 @@ hipError_t launch_seed_random(const BatchArgs &a, uint64_t seed, hipStream_t s) 
 hipError_t launch_lb_batch(const BatchArgs &a, bool prefix, int round, int rank_lo, int rank_hi, int parts,
                            bool natural, int skip_below, int blocks, hipStream_t s) {
     const bool env = a.envU != nullptr;
+    // the XCD sub-queues pay when every wave gets many items (their ends cost a few failed pops)
+    const int64_t items = (int64_t)a.nq * (rank_hi - rank_lo) * parts;
+    const int mode = natural ? (items >= 64 * 4 * (int64_t)blocks ? 3 : 1) : 0;
     if (prefix && env)
         hipLaunchKernelGGL((k_lb_batch<true, true>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
-                           (int)natural, skip_below);
+                           mode, skip_below);
     else if (prefix)
         hipLaunchKernelGGL((k_lb_batch<true, false>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
-                           (int)natural, skip_below);
+                           mode, skip_below);
     else if (env)
         hipLaunchKernelGGL((k_lb_batch<false, true>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
-                           (int)natural, skip_below);
+                           mode, skip_below);
     else
         hipLaunchKernelGGL((k_lb_batch<false, false>), dim3(blocks), dim3(256), 0, s, a, round, rank_lo, rank_hi, parts,
-                           (int)natural, skip_below);
+                           mode, skip_below);
     return hipGetLastError();
 }
 

@@ -110,8 +110,10 @@ DTWS_API int dtws_autotune_batch(dtws_ctx *c, const float *T, int64_t n, const f
     dtws_schedule best = start;
     double best_ms = 0.0;
     int rc = run(best, ref, best_ms);
-    // coordinate descent: each knob in turn over its candidate values, keeping the fastest
-    for (int knob = 0; knob < kKnobs && rc == DTWS_OK; ++knob) {
+    // coordinate descent: each knob in turn over its candidate values, keeping the fastest; then a
+    // second pass over the knobs that interact most (the data envelope, the rounds and the tiled
+    // cascade: with one of them changed, the best value of another often changes)
+    auto sweep = [&](int knob) {
         const dtws_schedule base = best;
         for (int v = 0; v < kKnobValues[knob] && rc == DTWS_OK; ++v) {
             dtws_schedule t;
@@ -144,7 +146,10 @@ DTWS_API int dtws_autotune_batch(dtws_ctx *c, const float *T, int64_t n, const f
                 best = t;
             }
         }
-    }
+    };
+    for (int knob = 0; knob < kKnobs && rc == DTWS_OK; ++knob) sweep(knob);
+    for (int knob : {5, 6, 7})
+        if (rc == DTWS_OK) sweep(knob);
     if (rc != DTWS_OK) {
         dtws_set_schedule(c, &start);
         return rc;

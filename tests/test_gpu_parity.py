@@ -452,6 +452,36 @@ def test_dtw_suffix_bound_and_refilling_rows_same_matches(ctx, casc):
     assert cells[0, 1] <= 1.1 * cells[0, 0]
 
 
+def test_series_order_xcd_sub_queues(casc):
+    """A series-order round large enough for the eight XCD sub-queues (at least 64 work items per
+    wave: 128 queries x 977 blocks of 2048 candidates for 1024 waves), in series order and as the
+    last round of the random and PAA orders (with its skip of the blocks visited before): the
+    oracle's matches, and every (query, candidate) pair visited exactly once."""
+    n, m = 2_000_000, 64
+    T = W.random_walk(n, 46)
+    qs = [W.noisy_cut(T, (7_919 * (k + 1) * 13) % (n - m), m, 0.2, 1200 + k) if k % 2 == 0
+          else W.random_walk(m, 1300 + k) for k in range(128)]
+    rs = [3 + (k % 4) for k in range(128)]
+    ref, _ = casc.search_many(T, qs, rs)
+    c = dtws.Context(0, max_n=n, max_m=m, max_queries=128)
+    try:
+        Td = dev(T)
+        pq = dtws.PackedQueries([dev(q) for q in qs])
+        for sched, order in (({"rounds": 1}, dtws.ORDER_NATURAL), ({"rounds": 4}, dtws.ORDER_NATURAL),
+                             ({"rounds": 2}, dtws.ORDER_RANDOM), ({"rounds": 2}, dtws.ORDER_PAA)):
+            c.set_schedule(block=2048, lb_blocks_per_cu=1, lb_tile=0, **sched)
+            print("sub-queues", sched, order, flush=True)
+            _check_batch(c.search_batch(Td, pq, rs, flags=order, seed=4), ref)
+            cn = c.counters()
+            # every pair ends in one bound or in a DTW; the seeding adds its own DTWs (one random
+            # candidate per query, or 256 around the best proposals)
+            visited = cn["pruned_kim"] + cn["pruned_keogh_q"] + cn["pruned_keogh_d"] + cn["dtw_started"]
+            assert cn["fallbacks"] == 0
+            assert visited - 128 * (n - m + 1) in (128, 128 * 256), (visited, cn)
+    finally:
+        c.close()
+
+
 def test_tiled_cascade_equals_per_query_items(ctx, casc):
     """The tiled cascade (one LDS-staged series tile shared by every query of a length) against the
     per-query work items and the oracle: seven queries in four length groups (the longest, m = 2048,
