@@ -126,7 +126,9 @@ typedef struct {
 /* Create a context on HIP device `device` able to search series of up to
  * max_n points (max_n < 2^31) with queries of up to max_m points (2 <= max_m
  * <= 2048) and batches of up to max_queries queries.  Allocates all device
- * scratch (roughly 24 bytes per series point plus small per-query buffers).
+ * scratch: roughly 24 bytes per series point, small per-query buffers, and the
+ * batched survivor list of 20 bytes per entry for min(max_queries * max_n, L)
+ * entries, L = 2^30 on a device of at least 128 GiB, else 2^28.
  * Returns DTWS_ENODEV when no HIP device is present. */
 DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_queries, dtws_ctx **out);
 

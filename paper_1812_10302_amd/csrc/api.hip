@@ -1001,8 +1001,13 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
     }
     if (ok) {
         c->maxblocks = (max_n + kMinBlock - 1) / kMinBlock + 1;
-        // batched survivor list: up to 2^28 entries (20 B each with the sorted copy and the bounds)
-        int64_t cap = Q * max_n < (int64_t(1) << 28) ? Q * max_n : (int64_t(1) << 28);
+        // batched survivor list (20 B per entry with the sorted copy and the bounds): up to 2^30
+        // entries (21.5 GB) on a device of at least 128 GiB, else 2^28; a round that overflows it
+        // is redone by the plain search, so this only decides how often that happens
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) total_b = 0;
+        const int64_t lim = total_b >= (size_t(128) << 30) ? (int64_t(1) << 30) : (int64_t(1) << 28);
+        int64_t cap = Q * max_n < lim ? Q * max_n : lim;
         if (cap < Q * kSeedCands) cap = Q * kSeedCands;   // round -1 of the learned order
         c->bsurv_cap = cap;
         const int64_t nblk = max_n / 4096 + 2;
