@@ -673,7 +673,7 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
         {
             PROF(DTWS_K_OTHER);
             HIPCHK(c, launch_fill_u32(c->surv_count, 0, 1, s));
-            HIPCHK(c, launch_fill_u32(c->qcnt, 0, nq, s));
+            HIPCHK(c, launch_fill_u32(c->qcnt, 0, (int64_t)nq * kCntStride, s));
         }
         {
             PROF(DTWS_K_LB);
@@ -1019,7 +1019,7 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&c->heads, 64) == hipSuccess && dalloc(&c->surv_q, cap) == hipSuccess &&
              dalloc(&c->surv_i, cap) == hipSuccess && dalloc(&c->sorted, cap + 64 * Q) == hipSuccess &&
              dalloc(&c->surv_lb, cap) == hipSuccess && dalloc(&c->sorted_lb, cap + 64 * Q) == hipSuccess &&
-             dalloc(&c->qcnt, Q) == hipSuccess && dalloc(&c->fill, Q) == hipSuccess &&
+             dalloc(&c->qcnt, Q * kCntStride) == hipSuccess && dalloc(&c->fill, Q * kCntStride) == hipSuccess &&
              dalloc(&c->overflow, 1) == hipSuccess && dalloc(&c->qorder, Q + 1) == hipSuccess &&
              dalloc(&c->wstart, Q + 1) == hipSuccess && dalloc(&c->bucket_w, 2 * (kMaxChunks + 2)) == hipSuccess &&
              dalloc(&c->bucket_j, 2 * (kMaxChunks + 2)) == hipSuccess && dalloc(&c->seg_off, Q) == hipSuccess &&

@@ -184,7 +184,7 @@ __global__ void k_seed_random(BatchArgs a, uint64_t seed) {
         a.surv_q[q] = q;
         a.surv_i[q] = (int32_t)(splitmix64_d(seed + (uint64_t)q) % (uint64_t)N);
         a.surv_lb[q] = 0.0f;
-        a.qcnt[q] = 1;
+        a.qcnt[q * kCntStride] = 1;
     }
     if (threadIdx.x == 0) *a.surv_count = (uint32_t)a.nq;
 }
@@ -390,8 +390,8 @@ __global__ void k_seg_plan(BatchArgs a) {
             a.qorder[j] = q;
             a.wstart[j] = off;
             a.seg_off[q] = (int64_t)off * 64;
-            a.fill[q] = 0;
-            off += (int32_t)((a.qcnt[q] + 63u) / 64u);
+            a.fill[q * kCntStride] = 0;
+            off += (int32_t)((a.qcnt[q * kCntStride] + 63u) / 64u);
             ++j;
         }
         a.bucket_w[2 * c + 1] = off;
@@ -418,7 +418,7 @@ __global__ void k_seg_scatter(BatchArgs a) {
             const int q0 = __shfl(q, leader, 64);
             const uint64_t peers = __ballot(valid && q == q0);
             uint32_t b0 = 0;
-            if (lane == leader) b0 = atomicAdd(&a.fill[q0], (uint32_t)__popcll(peers));
+            if (lane == leader) b0 = atomicAdd(&a.fill[q0 * kCntStride], (uint32_t)__popcll(peers));
             b0 = __shfl(b0, leader, 64);
             if (valid && q == q0) pos = b0 + (uint32_t)__popcll(peers & lanemask_lt());
             pending &= ~peers;
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
         const int q = wave_query(a, NC, w, wq0);
         const BatchQ bq = a.bq[q];
         const int64_t local = (w - wq0) * 64 + lane;
-        const bool valid = local < (int64_t)a.qcnt[q];
+        const bool valid = local < (int64_t)a.qcnt[q * kCntStride];
         const int64_t start = valid ? (int64_t)a.sorted[w * 64 + lane] : 0;
         float mu, s, o;
         if (PREFIX) {
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
             m = bq.m;
             r = bq.r;
             const int64_t off = (int64_t)(slot & 3) * 16 + ql;
-            valid = (wv - wq0) * 64 + off < (int64_t)a.qcnt[q];
+            valid = (wv - wq0) * 64 + off < (int64_t)a.qcnt[q * kCntStride];
             const int64_t start = valid ? (int64_t)a.sorted[wv * 64 + off] : 0;
             if (PREFIX) {
                 StatsPrefix{a.T, a.pre, m, 1.0 / m}(start, mu, s, o);
@@ -702,7 +702,7 @@ __global__ __launch_bounds__(64) void k_dtw_batch_wide(BatchArgs a) {
         const BatchQ bq = a.bq[q];
         const int m = bq.m, r = bq.r;
         const int64_t local = (w - wq0) * 64 + lane;
-        if (local >= (int64_t)a.qcnt[q]) continue;
+        if (local >= (int64_t)a.qcnt[q * kCntStride]) continue;
         const int64_t start = a.sorted[w * 64 + lane];
         float mu, s, o;
         if (PREFIX) {

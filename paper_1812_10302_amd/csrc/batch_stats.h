@@ -114,7 +114,7 @@ struct EmitBatch {
         if (lane == leader) {
             base = atomicAdd(count, pc);
             if ((int64_t)base + pc > cap) atomicOr(overflow, 1u);
-            else atomicAdd(&qcnt[q], pc);
+            else atomicAdd(&qcnt[q * kCntStride], pc);
         }
         base = __shfl(base, leader, 64);
         const int64_t pos = (int64_t)base + __popcll(mask & lanemask_lt());

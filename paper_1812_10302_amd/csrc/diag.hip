@@ -259,7 +259,7 @@ __global__ __launch_bounds__(128) void k_dtw_diag(BatchArgs a) {
         } else {
             int32_t wq0;
             q = __builtin_amdgcn_readfirstlane(wave_query(a, cw, g >> 6, wq0));
-            if (((g >> 6) - wq0) * 64 + (g & 63) >= (int64_t)a.qcnt[q]) continue;
+            if (((g >> 6) - wq0) * 64 + (g & 63) >= (int64_t)a.qcnt[q * kCntStride]) continue;
             start = __builtin_amdgcn_readfirstlane(a.sorted[g]);
         }
         const BatchQ bq = a.bq[q];

@@ -152,6 +152,10 @@ struct CertArgs {
     unsigned long long *counters;
 };
 
+// Per-query counters updated by atomics from every wave (survivors per query, segment fill) sit one
+// 128-byte cache line apart, so that the atomics of different queries do not serialise on a line.
+constexpr int kCntStride = 32;
+
 struct BatchArgs {
     const float *T;
     int64_t n;
@@ -181,7 +185,7 @@ struct BatchArgs {
     // survivors of the bound cascade, then sorted into per-query wave segments
     int32_t *surv_q, *surv_i;
     float *surv_lb;            // each survivor's query-envelope LB_Keogh sum (0 where none was taken)
-    uint32_t *surv_count, *qcnt, *overflow;
+    uint32_t *surv_count, *qcnt, *overflow;   // qcnt and fill: one 128-byte line per query (kCntStride)
     int64_t surv_cap;
     int32_t *sorted;
     float *sorted_lb;          // surv_lb in the order of `sorted`

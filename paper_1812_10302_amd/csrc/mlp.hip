@@ -758,7 +758,7 @@ __global__ void k_seed_learned(BatchArgs a, const int32_t *bstart, const int64_t
     a.surv_q[e] = q;
     a.surv_i[e] = (int32_t)st;
     a.surv_lb[e] = 0.0f;
-    if (k == 0) a.qcnt[q] = kSeedCands;
+    if (k == 0) a.qcnt[q * kCntStride] = kSeedCands;
     if (e == 0) *a.surv_count = (uint32_t)(a.nq * kSeedCands);
 }
 
