@@ -119,6 +119,9 @@ typedef struct {
                                   list overflowed (their work is not in the counters)   */
     int64_t dtw_wave_cells;    /* the part of dtw_cells evaluated by the one-wave-per-
                                   candidate DTW kernels                                 */
+    int64_t dtw_evicted;       /* candidates moved out of a DTW row to resume in another
+                                  (schedule field dtw_evict; one candidate may move up
+                                  to twice)                                             */
 } dtws_counters;
 
 /* ---------------------------------------------------------------- context */
@@ -128,7 +131,10 @@ typedef struct {
  * <= 2048) and batches of up to max_queries queries.  Allocates all device
  * scratch: roughly 24 bytes per series point, small per-query buffers, and the
  * batched survivor list of 20 bytes per entry for min(max_queries * max_n, L)
- * entries, L = 2^30 on a device of at least 128 GiB, else 2^28.
+ * entries, L = 2^30 on a device of at least 128 GiB, else 2^28, and two
+ * buffers of 928 bytes per entry for the DTW rows' moved candidates (schedule
+ * field dtw_evict), each of min(that list, E) entries (at least 4096), E = 2^25
+ * on a device of at least 128 GiB (62 GB in all), else 2^20.
  * Returns DTWS_ENODEV when no HIP device is present. */
 DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_queries, dtws_ctx **out);
 
@@ -282,7 +288,12 @@ typedef struct {
                                   four rows of 16 lanes, a row taking the next 16 candidates as
                                   soon as all of its own have ended (default); 0 = a wave takes
                                   64 candidates and runs until the last of them ends */
-    int32_t reserved;          /* 0 */
+    int32_t dtw_evict;         /* with dtw_rows = 1, bands of 49 to 223 cells: 1..15 = at a test, a
+                                  row with at most this many live candidates (and two tests or
+                                  more to go) moves them out, band column and all, and takes new
+                                  ones; moved candidates resume later in full rows of 16 that
+                                  share query and column, up to three times (default 4); 0 = off.
+                                  The matches do not depend on it */
 } dtws_schedule;
 
 DTWS_API int dtws_get_schedule(dtws_ctx *ctx, dtws_schedule *out_host);
@@ -292,7 +303,7 @@ DTWS_API int dtws_set_schedule(dtws_ctx *ctx, const dtws_schedule *s_host);
 /* Autotuner: runs dtws_search_batch on the given batch (arguments as there;
  * DTWS_PROFILE is ignored) under candidate schedules, by coordinate descent over
  * diag_max, block, lb_blocks_per_cu, dtw_blocks_per_cu, stats_prefix,
- * data_envelope, rounds, lb_tile, dtw_bound and dtw_rows starting from the
+ * data_envelope, rounds, lb_tile, dtw_bound, dtw_rows and dtw_evict starting from the
  * current schedule, then once more over data_envelope, rounds and lb_tile; each
  * candidate is called once untimed (graph capture) and then `reps` times
  * (1..100) timed on the host clock.  All candidates must return identical

@@ -34,7 +34,7 @@ MAX_M = 2048
 
 COUNTER_FIELDS = ("candidates", "pruned_kim", "pruned_keogh_q", "pruned_keogh_d", "dtw_started",
                   "dtw_abandoned", "dtw_cells", "certified", "dtw_lane_cells", "lb_terms", "fallbacks",
-                  "dtw_wave_cells")
+                  "dtw_wave_cells", "dtw_evicted")
 
 
 class Match(ctypes.Structure):
@@ -51,10 +51,10 @@ class Schedule(ctypes.Structure):
                 ("dtw_blocks_per_cu", ctypes.c_int32), ("diag_max", ctypes.c_int32), ("band_lanes", ctypes.c_int32),
                 ("stats_prefix", ctypes.c_int32), ("data_envelope", ctypes.c_int32), ("rounds", ctypes.c_int32),
                 ("list_cap", ctypes.c_int32), ("lb_tile", ctypes.c_int32), ("dtw_bound", ctypes.c_int32),
-                ("dtw_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("dtw_rows", ctypes.c_int32), ("dtw_evict", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class TrainCfg(ctypes.Structure):

@@ -378,6 +378,7 @@ void parse_counters(dtws_ctx *c, int64_t candidates) {
     c->last.dtw_lane_cells = (int64_t)h[8];
     c->last.lb_terms = (int64_t)h[9];
     c->last.dtw_wave_cells = (int64_t)h[10];
+    c->last.dtw_evicted = (int64_t)h[11];
     c->last.fallbacks = 0;
 }
 
@@ -558,6 +559,20 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
     a.counters = c->counters;
     a.wide_rows = c->gen_rows;
     a.wide_lanes = c->gen_lanes;
+    a.ev_live = c->dtw_rows ? c->dtw_evict : 0;
+    a.ev_out = c->ev_buf[0];
+    a.ev_out_key = c->ev_keybuf[0];
+    a.ev_in_key = nullptr;
+    a.ev_out_count = c->ev_count;
+    a.ev_in = nullptr;
+    a.ev_in_count = nullptr;
+    a.ev_cap = c->ev_cap;
+    a.ev_order = c->ev_order;
+    a.ev_rows = c->ev_count + 16 * kCntStride;
+    a.ev_levels = c->ev_levels;
+    a.ev_kcnt = c->ev_keys;
+    a.ev_koff = c->ev_keys + (int64_t)c->max_q * c->ev_levels;
+    a.ev_kfill = c->ev_keys + 2 * (int64_t)c->max_q * c->ev_levels;
     a.diag_max = p.max_r <= kDiagMaxBand ? (uint32_t)diag_max_of(c) : 0u;
     a.diag_wide = p.max_r <= kDiagMaxBand;
 
@@ -642,7 +657,22 @@ int enqueue_batch(dtws_ctx *c, const BatchPlan &p, const float *T, int64_t n, co
             for (int nc = 1; nc <= kMaxChunks + 1; ++nc) {
                 if (!p.bucket_used[nc]) continue;
                 PROF(DTWS_K_DTW);
+                const bool evict = a.ev_live > 0 && nc >= 4 && nc <= kMaxChunks;
+                if (evict) HIPCHK(c, launch_fill_u32(c->ev_count, 0, 8 * kCntStride, s));
                 HIPCHK(c, launch_dtw_bucket(a, !same_m, nc, dtw_blocks, s));
+                // evicted candidates resume in full rows; each resume launch but the last may evict
+                // again, into the other buffer
+                for (int d = 1; evict && d <= kEvDepth; ++d) {
+                    BatchArgs ar = a;
+                    ar.ev_in = c->ev_buf[(d - 1) & 1];
+                    ar.ev_in_key = c->ev_keybuf[(d - 1) & 1];
+                    ar.ev_out_key = c->ev_keybuf[d & 1];
+                    ar.ev_in_count = c->ev_count + ((d - 1) & 1) * 8 * kCntStride;
+                    ar.ev_out = c->ev_buf[d & 1];
+                    ar.ev_out_count = c->ev_count + (d & 1) * 8 * kCntStride;
+                    ar.ev_live = d < kEvDepth ? a.ev_live : 0;
+                    HIPCHK(c, launch_dtw_resume(ar, !same_m, nc, dtw_blocks, c->num_cu, s));
+                }
             }
         }
         if (a.diag_max > 0 || a.diag_wide) {
@@ -749,7 +779,7 @@ int run_batch(dtws_ctx *c, const float *T, int64_t n, const float *Qp, const int
         std::vector<int64_t> sig = {(int64_t)(uintptr_t)T, n, (int64_t)(uintptr_t)Qp, nq, (int64_t)flags,
                                     (int64_t)seed, p.block, c->lb_blocks_per_cu, c->dtw_blocks_per_cu, c->diag_max,
                                     c->stats_prefix, c->data_envelope, c->rounds, c->lb_tile, c->list_cap,
-                                    c->dtw_bound, c->dtw_rows};
+                                    c->dtw_bound, c->dtw_rows, c->dtw_evict};
         for (int k = 0; k < nq; ++k) {
             sig.push_back(qoff[k]);
             sig.push_back(mh[k]);
@@ -916,6 +946,7 @@ DTWS_API void dtws_destroy(dtws_ctx *c) {
                    c->st_s, c->st_o, c->envU, c->envL, c->surv, c->surv_count, c->nb_d, c->nb_idx,
                    c->nb_count, c->cert_rows, c->cert_idx, c->cert_count, c->cert_d, c->res_block, c->gen_rows, c->bq, c->PP, c->PPd, c->anc, c->tot,
                    c->perm, c->rank, c->heads, c->surv_q, c->surv_i, c->surv_lb, c->sorted, c->sorted_lb, c->qcnt, c->fill, c->overflow,
+                   c->ev_buf[0], c->ev_buf[1], c->ev_keybuf[0], c->ev_keybuf[1], c->ev_count, c->ev_order, c->ev_keys,
                    c->qorder, c->wstart, c->bucket_w, c->bucket_j, c->seg_off, c->nb_q, c->cert_q,
                    c->mlp.theta, c->mlp.grad, c->mlp.adam_m, c->mlp.adam_v, c->mlp.W1T, c->mlp.W2T, c->mlp.W2b,
                    c->mlp.Xb, c->mlp.XbT, c->mlp.H1b, c->mlp.H1T, c->mlp.dA2b, c->mlp.dA2T, c->mlp.dA1T,
@@ -1026,6 +1057,18 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&c->nb_q, kNearBestCap) == hipSuccess && dalloc(&c->cert_q, kNearBestCap) == hipSuccess &&
              dalloc(&c->tile_q, 2 * Q + 2) == hipSuccess &&
              hipHostMalloc((void **)&c->h_tile_q, sizeof(int32_t) * (2 * Q + 2), 0) == hipSuccess;
+        // eviction entries of the rows DTW kernel (928 B each, two buffers, each in eight parts, one
+        // per XCD): 2^25 on a device of at least 128 GiB (62 GB in all), else 2^20; a lane finding
+        // its part full keeps its candidate
+        c->ev_cap = total_b >= (size_t(128) << 30) ? (int64_t(1) << 25) : (int64_t(1) << 20);
+        if (c->ev_cap > cap) c->ev_cap = cap < 4096 ? 4096 : cap;
+        c->ev_cap &= ~int64_t(7);
+        c->ev_levels = (int)(max_m / 16 + 1);
+        const int64_t nkeys = Q * c->ev_levels;
+        ok = ok && dalloc(&c->ev_buf[0], c->ev_cap * kEvStride) == hipSuccess &&
+             dalloc(&c->ev_buf[1], c->ev_cap * kEvStride) == hipSuccess && dalloc(&c->ev_count, 16 * kCntStride + 1) == hipSuccess &&
+             dalloc(&c->ev_keybuf[0], c->ev_cap) == hipSuccess && dalloc(&c->ev_keybuf[1], c->ev_cap) == hipSuccess &&
+             dalloc(&c->ev_order, c->ev_cap + 16 * nkeys) == hipSuccess && dalloc(&c->ev_keys, 3 * nkeys) == hipSuccess;
         if (ok) {
             int64_t off = 0;
             for (int L = kDecFirst; L < kDecLevels; ++L) {

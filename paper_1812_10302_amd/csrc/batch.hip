@@ -520,31 +520,47 @@ __global__ __launch_bounds__(256) void k_dtw_batch(BatchArgs a) {
 // by far less than the threshold's slack.  Without the suffix bound (a.Un null) the total is 0 and
 // the terms run on the query itself, so the bound adds max(0 - terms, 0) = 0 (no branch in the
 // column loop, which would cost registers).
+//
+// Eviction (a.ev_live > 0).  Neighbouring starts abandon at nearly the same column, but a row still
+// runs until its last candidate ends, so most of its idle lanes sit in rows where one to a few
+// candidates run on.  At a test, a row with 1..ev_live live candidates and at least two tests to go
+// moves them out: band column, running suffix terms and position into entries of a.ev_out, and
+// takes the next 16 candidates.  The moved candidates are bucketed by (query, column) and resumed
+// by the RESUME instance of this kernel in full rows of 16 that share query and column, so the
+// query broadcast still holds.  A candidate's arithmetic does not change when it moves: the same
+// values continue from the same column.  When ev_out is full a row keeps its candidates.
 constexpr int kRowChunk = 32;
 
-template <int NC, bool PREFIX>
+template <int NC, bool PREFIX, bool RESUME>
 __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
     constexpr int W = 16 * NC;
     constexpr int R = 8 * NC - 1;
+    static_assert(W + 1 <= kEvKpre, "eviction entry layout");
     if (*a.overflow || *a.surv_count <= a.diag_max) return;
     const int lane = threadIdx.x & 63, row = lane >> 4, ql = lane & 15;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t wlo = a.bucket_w[2 * NC], whi = a.bucket_w[2 * NC + 1];
+    // work: waves of 64 survivors (4 rows each) of this bucket, or resume rows of 16 entries
+    const int64_t wlo = RESUME ? 0 : a.bucket_w[2 * NC];
+    const int64_t whi = RESUME ? ((int64_t)*a.ev_rows + 3) / 4 : a.bucket_w[2 * NC + 1];
+    const int64_t nrows_total = RESUME ? (int64_t)*a.ev_rows : 4 * (whi - wlo);
     // chunks of up to kRowChunk waves, fewer when the bucket would not give every wave one
     int64_t cw = (whi - wlo) / nwaves;
     cw = cw < 1 ? 1 : (cw > kRowChunk ? kRowChunk : cw);
     const int64_t nchunks = (whi - wlo + cw - 1) / cw;
-    unsigned long long n_started = 0, n_aband = 0, n_cells = 0, n_steps = 0;
+    unsigned long long n_started = 0, n_aband = 0, n_cells = 0, n_steps = 0, n_evicted = 0;
     const bool bound = a.Un != nullptr;
     const float *Ubase = bound ? a.Un : a.qpad + kQPad, *Lbase = bound ? a.Ln : a.qpad + kQPad;
     const int64_t ustride = bound ? a.mstride : a.qstride;
     for (int64_t ch = wave; ch < nchunks; ch += nwaves) {
         const int64_t w0 = wlo + ch * cw;
         const int64_t w1 = w0 + cw < whi ? w0 + cw : whi;
-        const int nslots = (int)(w1 - w0) * 4;   // rows of 16 survivors in the chunk
+        // rows of 16 in the chunk (a resume chunk's last wave may hold fewer than 4)
+        int64_t nsl = (w1 - w0) * 4;
+        if (RESUME && (w0 - wlo) * 4 + nsl > nrows_total) nsl = nrows_total - (w0 - wlo) * 4;
+        const int nslots = (int)nsl;
         // per-lane state of the lane's current candidate
-        int q = 0, m = 2, r = 0, jl = 0, jdead = 0;
+        int q = 0, m = 2, r = 0, jl = 0, j0 = 0, jdead = 0;
         bool valid = false, alive = false, live = false;
         float mu = 0.0f, s = 0.0f, o = 0.0f, thr = INFINITY, D = INFINITY, tcur = 0.0f;
         float lbt = 0.0f, kpre = 0.0f, ucur = 0.0f, lcur = 0.0f;   // suffix bound: total, terms done
@@ -562,15 +578,31 @@ __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
         }
         // this lane's row takes row slot `slot` of the chunk
         auto take = [&](int slot) {
-            const int64_t wv = w0 + slot / 4;
-            int32_t wq0;
-            q = wave_query(a, NC, wv, wq0);
+            int64_t start = 0;
+            const float *ent = nullptr;
+            if (RESUME) {
+                const uint32_t e = a.ev_order[((w0 - wlo) * 4 + slot) * 16 + ql];
+                valid = e != ~0u;
+                // an empty lane copies the row's first entry (rows never start empty) and stays idle
+                const uint32_t e0 = a.ev_order[((w0 - wlo) * 4 + slot) * 16];
+                ent = a.ev_in + (int64_t)(valid ? e : e0) * kEvStride;
+                q = __float_as_int(ent[kEvQ]);
+                start = (int64_t)(uint32_t)__float_as_int(ent[kEvStart]);
+                j0 = __float_as_int(ent[kEvCol]);
+            } else {
+                const int64_t wv = w0 + slot / 4;
+                int32_t wq0;
+                q = wave_query(a, NC, wv, wq0);
+                const int64_t off = (int64_t)(slot & 3) * 16 + ql;
+                valid = (wv - wq0) * 64 + off < (int64_t)a.qcnt[q * kCntStride];
+                start = valid ? (int64_t)a.sorted[wv * 64 + off] : 0;
+                j0 = 0;
+                lbt = bound && valid ? a.sorted_lb[wv * 64 + off] : 0.0f;
+                kpre = 0.0f;
+            }
             const BatchQ bq = a.bq[q];
             m = bq.m;
             r = bq.r;
-            const int64_t off = (int64_t)(slot & 3) * 16 + ql;
-            valid = (wv - wq0) * 64 + off < (int64_t)a.qcnt[q * kCntStride];
-            const int64_t start = valid ? (int64_t)a.sorted[wv * 64 + off] : 0;
             if (PREFIX) {
                 StatsPrefix{a.T, a.pre, m, 1.0 / m}(start, mu, s, o);
             } else {
@@ -579,26 +611,39 @@ __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
             }
             qp = a.qpad + q * a.qstride;
             key = a.keys + q;
-            lbt = bound && valid ? a.sorted_lb[wv * 64 + off] : 0.0f;
-            kpre = 0.0f;
             Unp = Ubase + q * ustride;
             Lnp = Lbase + q * ustride;
-            ucur = Unp[0];
-            lcur = Lnp[0];
+            ucur = Unp[j0];
+            lcur = Lnp[j0];
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc) {
                 const int kpos = 16 * cc + ql;
                 qoff[cc] = (kpos >= R - r && kpos <= R + r) ? kQPad - R + kpos : 0;
-                qcur[cc] = qp[qoff[cc]];
+                qcur[cc] = qp[qoff[cc] + j0];
             }
+            if (RESUME) {
+                lbt = ent[kEvLbt];
+                kpre = ent[kEvKpre];
+                const float4 *e4 = (const float4 *)ent;
 #pragma unroll
-            for (int x = 0; x <= W; ++x) arr[x] = INFINITY;
-            arr[R] = 0.0f;
+                for (int x = 0; x < W / 4; ++x) {
+                    const float4 v = e4[x];
+                    arr[4 * x] = v.x;
+                    arr[4 * x + 1] = v.y;
+                    arr[4 * x + 2] = v.z;
+                    arr[4 * x + 3] = v.w;
+                }
+                arr[W] = ent[W];
+            } else {
+#pragma unroll
+                for (int x = 0; x <= W; ++x) arr[x] = INFINITY;
+                arr[R] = 0.0f;
+            }
             Tp = a.T + start;
-            tcur = Tp[0];
+            tcur = Tp[j0];
             thr = threshold_of(load_bsf(key));
             kpend = load_key_dist_bits(key);
-            jl = 0;
+            jl = j0;
             jdead = m;
             D = INFINITY;
             alive = valid;
@@ -647,7 +692,7 @@ __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
                 live = false;
                 ++n_started;
                 if (jdead < m) ++n_aband;
-                n_cells += band_cells(m, r, jdead);
+                n_cells += band_cells(m, r, jdead) - band_cells(m, r, j0);
                 if (alive && D <= thr) {
                     const uint32_t start = (uint32_t)(Tp - a.T);
                     atomicMin((unsigned long long *)key, (unsigned long long)pack_key(D, start));
@@ -656,6 +701,40 @@ __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
                         a.nb_d[pos] = D;
                         a.nb_idx[pos] = start;
                         a.nb_q[pos] = q;
+                    }
+                }
+            }
+            if (a.ev_live > 0) {
+                // a row with 1..ev_live live candidates and two tests or more to go moves them out;
+                // one atomic per wave reserves the entries in this XCD's part of the buffer, and
+                // lanes whose entry would fall beyond it keep their candidate
+                const uint32_t rl = (uint32_t)((__ballot(live) >> (16 * row)) & 0xFFFFull);
+                const int nl = __popc(rl);
+                const bool want = live && nl <= a.ev_live && jl + 32 <= m;
+                const uint64_t evl = __ballot(want);
+                if (evl) {
+                    const int x = (int)(blockIdx.x & 7u);
+                    const int64_t part = a.ev_cap / 8;
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(a.ev_out_count + x * kCntStride, (uint32_t)__popcll(evl));
+                    base = __shfl(base, 0, 64);
+                    const uint32_t idx = base + (uint32_t)__popcll(evl & lanemask_lt());
+                    if (want && (int64_t)idx < part) {
+                        float *ent = a.ev_out + ((int64_t)x * part + idx) * kEvStride;
+                        float4 *e4 = (float4 *)ent;
+#pragma unroll
+                        for (int y = 0; y < W / 4; ++y)
+                            e4[y] = make_float4(arr[4 * y], arr[4 * y + 1], arr[4 * y + 2], arr[4 * y + 3]);
+                        ent[W] = arr[W];
+                        ent[kEvKpre] = kpre;
+                        ent[kEvLbt] = lbt;
+                        ent[kEvStart] = __int_as_float((int32_t)(uint32_t)(Tp - a.T));
+                        ent[kEvQ] = __int_as_float(q);
+                        ent[kEvCol] = __int_as_float(jl);
+                        a.ev_out_key[(int64_t)x * part + idx] = (uint32_t)(q * a.ev_levels + jl / 16);
+                        n_cells += band_cells(m, r, jl) - band_cells(m, r, j0);
+                        ++n_evicted;
+                        live = false;
                     }
                 }
             }
@@ -677,13 +756,76 @@ __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
         n_started = wave_add(n_started);
         n_aband = wave_add(n_aband);
         n_cells = wave_add(n_cells);
+        n_evicted = wave_add(n_evicted);
         if (lane == 0) {
             atomicAdd(&a.counters[4], n_started);
             atomicAdd(&a.counters[5], n_aband);
             atomicAdd(&a.counters[6], n_cells);
             atomicAdd(&a.counters[8], n_steps * 16ull * W * 64ull);
+            if (n_evicted) atomicAdd(&a.counters[11], n_evicted);
         }
     }
+}
+
+// Bucketing of the evicted entries by (query, column level): counts, then a plan that gives every
+// key a run of whole rows (padding lanes ~0u), then the scatter of entry indices into the runs.
+
+template <bool SCATTER>
+__global__ void k_ev_bucket(BatchArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const int64_t part = a.ev_cap / 8;
+    for (int x = 0; x < 8; ++x) {
+        uint32_t cnt = a.ev_in_count[x * kCntStride];
+        if ((int64_t)cnt > part) cnt = (uint32_t)part;
+        for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < cnt; base += stride) {
+            const uint32_t e = (uint32_t)(x * part) + base + lane;
+            const bool valid = base + lane < cnt;
+            const int k = valid ? (int)a.ev_in_key[e] : -1;
+            // one atomic per distinct key among the wave's 64 entries
+            uint64_t pending = __ballot(valid);
+            uint32_t pos = 0;
+            while (pending) {
+                const int leader = __ffsll((unsigned long long)pending) - 1;
+                const int k0 = __shfl(k, leader, 64);
+                const uint64_t peers = __ballot(valid && k == k0);
+                uint32_t b0 = 0;
+                if (lane == leader) b0 = atomicAdd(SCATTER ? &a.ev_kfill[k0] : &a.ev_kcnt[k0], (uint32_t)__popcll(peers));
+                b0 = __shfl(b0, leader, 64);
+                if (valid && k == k0) pos = b0 + (uint32_t)__popcll(peers & lanemask_lt());
+                pending &= ~peers;
+            }
+            if (SCATTER && valid) a.ev_order[a.ev_koff[k] + pos] = e;
+        }
+    }
+}
+
+// One workgroup of 1024: exclusive scan of the keys' counts rounded up to 16.
+__global__ __launch_bounds__(1024) void k_ev_plan(BatchArgs a) {
+    __shared__ uint32_t part[1024];
+    const int nkeys = a.nq * a.ev_levels;
+    const int t = threadIdx.x;
+    const int per = (nkeys + 1023) / 1024;
+    const int k0 = t * per, k1 = k0 + per < nkeys ? k0 + per : nkeys;
+    uint32_t sum = 0;
+    for (int k = k0; k < k1; ++k) sum += (a.ev_kcnt[k] + 15u) & ~15u;
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t v = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t off = part[t] - sum;
+    for (int k = k0; k < k1; ++k) {
+        const uint32_t c = a.ev_kcnt[k], c16 = (c + 15u) & ~15u;
+        a.ev_koff[k] = off;
+        a.ev_kfill[k] = 0;
+        for (uint32_t x = c; x < c16; ++x) a.ev_order[off + x] = ~0u;
+        off += c16;
+    }
+    if (t == 1023) *a.ev_rows = part[1023] / 16u;
 }
 
 // Wide bands (r > 8 * kMaxChunks - 1): one lane per candidate, DP rows in global scratch.
@@ -965,7 +1107,7 @@ static hipError_t launch_dtw_bucket_t(const BatchArgs &a, int nc, int blocks, hi
 #define DTWS_BCASE(N) \
     case N:                                                                                                    \
         if (N >= 4 && a.rows)                                                                                  \
-            hipLaunchKernelGGL((k_dtw_batch_rows<(N >= 4 ? N : 4), PREFIX>), g, b, 0, s, a);                   \
+            hipLaunchKernelGGL((k_dtw_batch_rows<(N >= 4 ? N : 4), PREFIX, false>), g, b, 0, s, a);            \
         else                                                                                                   \
             hipLaunchKernelGGL((k_dtw_batch<N, PREFIX>), g, b, N >= kBoundMinNC && a.Un ? kBoundLdsBytes : 0, s, a); \
         break;
@@ -985,6 +1127,38 @@ static hipError_t launch_dtw_bucket_t(const BatchArgs &a, int nc, int blocks, hi
 
 hipError_t launch_dtw_bucket(const BatchArgs &a, bool prefix, int nc, int blocks, hipStream_t s) {
     return prefix ? launch_dtw_bucket_t<true>(a, nc, blocks, s) : launch_dtw_bucket_t<false>(a, nc, blocks, s);
+}
+
+template <bool PREFIX>
+static void launch_resume_t(const BatchArgs &a, int nc, int blocks, hipStream_t s) {
+    const dim3 g(blocks), b(256);
+    switch (nc) {
+#define DTWS_RCASE(N) \
+    case N: hipLaunchKernelGGL((k_dtw_batch_rows<N, PREFIX, true>), g, b, 0, s, a); break;
+        DTWS_RCASE(4) DTWS_RCASE(5) DTWS_RCASE(6) DTWS_RCASE(7) DTWS_RCASE(8) DTWS_RCASE(9) DTWS_RCASE(10)
+        DTWS_RCASE(11) DTWS_RCASE(12) DTWS_RCASE(13) DTWS_RCASE(14)
+#undef DTWS_RCASE
+        default: break;
+    }
+}
+
+// Resumes the entries of a.ev_in (written by the previous launch for this bucket): buckets them by
+// (query, column level) into rows, then runs the rows kernel on them, evicting into a.ev_out when
+// a.ev_live > 0.
+hipError_t launch_dtw_resume(const BatchArgs &a, bool prefix, int nc, int blocks, int num_cu, hipStream_t s) {
+    if (nc < 4 || nc > kMaxChunks) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_u32(a.ev_kcnt, 0, (int64_t)a.nq * a.ev_levels, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ev_bucket<false>, dim3(num_cu * 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ev_plan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_ev_bucket<true>, dim3(num_cu * 4), dim3(256), 0, s, a);
+    if (a.ev_live > 0) {
+        e = launch_fill_u32(a.ev_out_count, 0, 8 * kCntStride, s);
+        if (e != hipSuccess) return e;
+    }
+    if (prefix) launch_resume_t<true>(a, nc, blocks, s);
+    else launch_resume_t<false>(a, nc, blocks, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_cert_batch(const BatchArgs &a, int max_m, int max_r, hipStream_t s) {

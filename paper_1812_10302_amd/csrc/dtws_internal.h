@@ -156,6 +156,14 @@ struct CertArgs {
 // 128-byte cache line apart, so that the atomics of different queries do not serialise on a line.
 constexpr int kCntStride = 32;
 
+// Eviction from the refilling-rows DTW kernel: a row whose live candidates have dropped to a few
+// moves them, band column and all, into an entry of kEvStride floats (the column, then the meta
+// words below), and takes new candidates; the moved ones are bucketed by (query, column) and
+// resumed in full rows.  kEvLevels bounds the column levels (columns / 16) of a query.
+constexpr int kEvStride = 232;                 // 16 * kMaxChunks + 1 column values, padded, + 5 meta
+constexpr int kEvKpre = 227, kEvLbt = 228, kEvStart = 229, kEvQ = 230, kEvCol = 231;
+constexpr int kEvDepth = 3;                    // resume launches per bucket (the last one evicts nothing)
+
 struct BatchArgs {
     const float *T;
     int64_t n;
@@ -211,6 +219,19 @@ struct BatchArgs {
     uint32_t diag_max;         // rounds with at most this many survivors use one wave per candidate
     uint32_t nb_cap;           // capacity of the near-best and certification lists
     bool diag_wide;            // bands 112..255 always use one wave per candidate
+    // eviction (k_dtw_batch_rows): rows with 1..ev_live live candidates move them to ev_out
+    int ev_live;               // 0: off
+    float *ev_out;             // entries of kEvStride floats, in 8 parts of ev_cap / 8 (one per XCD)
+    uint32_t *ev_out_count;    // the parts' counts, kCntStride apart
+    uint32_t *ev_out_key;      // each entry's bucket key: query * ev_levels + column / 16
+    const float *ev_in;        // entries being resumed (resume launches)
+    const uint32_t *ev_in_key;
+    const uint32_t *ev_in_count;
+    int64_t ev_cap;            // entries per buffer
+    uint32_t *ev_order;        // resume rows: 16 entry indices per row, ~0u = empty lane
+    uint32_t *ev_rows;         // number of resume rows
+    uint32_t *ev_kcnt, *ev_koff, *ev_kfill;   // per (query, column level): count, offset, fill
+    int ev_levels;             // column levels per query (max_m / 16 + 1)
 };
 
 // Tiled bound cascade (tile.hip): the queries of a batch grouped by length.
@@ -288,6 +309,7 @@ hipError_t launch_segments(const BatchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_lb_tile(const BatchArgs &a, const TileArgs &t, bool prefix, int64_t max_N, hipStream_t s);
 size_t tile_lds_bytes(int max_m);
 hipError_t launch_dtw_bucket(const BatchArgs &a, bool prefix, int nc, int blocks, hipStream_t s);
+hipError_t launch_dtw_resume(const BatchArgs &a, bool prefix, int nc, int blocks, int num_cu, hipStream_t s);
 hipError_t launch_cert_batch(const BatchArgs &a, int max_m, int max_r, hipStream_t s);
 hipError_t mlp_init(const MlpBufs &b, uint64_t seed, hipStream_t s);
 hipError_t mlp_refresh(const MlpBufs &b, hipStream_t s);
@@ -398,6 +420,14 @@ struct dtws_ctx {
     int lb_tile = 1;        // batched: tiled multi-query cascade for rounds over the same candidates
     int dtw_bound = 1;      // search DTW on one lane per candidate: suffix bound in the abandoning test
     int dtw_rows = 1;       // batched lane DTW (bands of 4+ chunks): rows of 16 lanes refill from a chunk
+    int dtw_evict = 4;      // rows kernel: move a row's live candidates out when at most this many remain
+    float *ev_buf[2] = {nullptr, nullptr};   // eviction entries, ev_cap each
+    uint32_t *ev_keybuf[2] = {nullptr, nullptr};   // their bucket keys
+    uint32_t *ev_count = nullptr;            // per buffer 8 part counts (kCntStride apart), then resume rows
+    int64_t ev_cap = 0;
+    uint32_t *ev_order = nullptr;            // ev_cap + 16 per key
+    uint32_t *ev_keys = nullptr;             // 3 x max_q x ev_levels: count, offset, fill
+    int ev_levels = 0;
     uint64_t *lbs_keys = nullptr;   // LB-sorted order: 2 x max_n keys and the sort's temporary storage,
     void *lbs_temp = nullptr;       // allocated on first use
     size_t lbs_temp_bytes = 0;

@@ -17,8 +17,9 @@ constexpr int32_t kDiagMaxes[] = {0, 2048, 16384, 65536};
 constexpr int32_t kLbWidths[] = {4, 8, 16, 32};
 constexpr int32_t kDtwWidths[] = {2, 4, 8};
 constexpr int32_t kRounds[] = {4, 2, 1};
-constexpr int kKnobs = 10;
-constexpr int kKnobValues[kKnobs] = {4, 4, 4, 3, 2, 2, 3, 2, 2, 2};
+constexpr int32_t kEvicts[] = {4, 0, 2, 6};
+constexpr int kKnobs = 11;
+constexpr int kKnobValues[kKnobs] = {4, 4, 4, 3, 2, 2, 3, 2, 2, 2, 4};
 
 bool valid_block(int64_t b) {
     if (b == 0) return true;
@@ -51,7 +52,7 @@ DTWS_API int dtws_get_schedule(dtws_ctx *c, dtws_schedule *out) {
     out->lb_tile = c->lb_tile;
     out->dtw_bound = c->dtw_bound;
     out->dtw_rows = c->dtw_rows;
-    out->reserved = 0;
+    out->dtw_evict = c->dtw_evict;
     return DTWS_OK;
 }
 
@@ -62,7 +63,8 @@ DTWS_API int dtws_set_schedule(dtws_ctx *c, const dtws_schedule *s) {
         (s->band_lanes != 0 && s->band_lanes != 1 && s->band_lanes != 64) || (s->stats_prefix != 0 && s->stats_prefix != 1) ||
         (s->data_envelope != 0 && s->data_envelope != 1) || (s->rounds != 1 && s->rounds != 2 && s->rounds != 4) ||
         (s->list_cap != 0 && (s->list_cap < 64 || s->list_cap > (1 << 20))) || (s->lb_tile != 0 && s->lb_tile != 1) ||
-        (s->dtw_bound != 0 && s->dtw_bound != 1) || (s->dtw_rows != 0 && s->dtw_rows != 1))
+        (s->dtw_bound != 0 && s->dtw_bound != 1) || (s->dtw_rows != 0 && s->dtw_rows != 1) ||
+        s->dtw_evict < 0 || s->dtw_evict > 15)
         return DTWS_EINVAL;
     c->block = s->block;
     c->lb_blocks_per_cu = s->lb_blocks_per_cu;
@@ -81,6 +83,7 @@ DTWS_API int dtws_set_schedule(dtws_ctx *c, const dtws_schedule *s) {
     c->lb_tile = s->lb_tile;
     c->dtw_bound = s->dtw_bound;
     c->dtw_rows = s->dtw_rows;
+    c->dtw_evict = s->dtw_evict;
     return DTWS_OK;
 }
 
@@ -128,7 +131,8 @@ DTWS_API int dtws_autotune_batch(dtws_ctx *c, const float *T, int64_t n, const f
             case 6: t.rounds = kRounds[v]; break;
             case 7: t.lb_tile = 1 - v; break;
             case 8: t.dtw_bound = 1 - v; break;
-            default: t.dtw_rows = 1 - v; break;
+            case 9: t.dtw_rows = 1 - v; break;
+            default: t.dtw_evict = kEvicts[v]; break;
             }
             if (memcmp(&t, &base, sizeof(t)) == 0) continue;
             // the learned order keeps the block its model was trained with

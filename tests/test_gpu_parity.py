@@ -452,6 +452,36 @@ def test_dtw_suffix_bound_and_refilling_rows_same_matches(ctx, casc):
     assert cells[0, 1] <= 1.1 * cells[0, 0]
 
 
+def test_dtw_eviction_same_matches(ctx, casc):
+    """Rows of the batched lane DTW that move their last few live candidates out and resume them in
+    full rows (dtw_evict): the oracle's matches for thresholds 0 (off), 1, 6 and 15, with bands of 4
+    to 14 chunks, several lengths per bucket, and in the random, natural and PAA orders; rows did
+    move candidates (counter dtw_evicted) whenever the threshold is on."""
+    T = W.random_walk(400_009, 45)
+    specs = [(512, 51), (300, 60), (1024, 102), (2048, 111), (1000, 99), (777, 70), (200, 30), (130, 31),
+             (1001, 50), (1024, 100)]
+    qs = [W.noisy_cut(T, (7_000 + 53_000 * k) % (T.size - m), m, 0.3, 1200 + k) if k % 2 == 0
+          else W.random_walk(m, 1210 + k) for k, (m, _) in enumerate(specs)]
+    rs = [r for _, r in specs]
+    ref = _cascade_refs(casc, T, qs, rs)
+    Td = dev(T)
+    Qd = [dev(q) for q in qs]
+    default = ctx.get_schedule()
+    moved = {}
+    try:
+        for ev in (0, 1, 6, 15):
+            for order in (dtws.ORDER_RANDOM, dtws.ORDER_NATURAL, dtws.ORDER_PAA):
+                ctx.set_schedule(diag_max=0, dtw_rows=1, dtw_bound=1, dtw_evict=ev, rounds=4, block=4096)
+                print("dtw_evict", ev, "order", order, flush=True)
+                _check_batch(ctx.search_batch(Td, Qd, rs, flags=order, seed=8), ref)
+                moved[ev, order] = ctx.counters()["dtw_evicted"]
+    finally:
+        ctx.set_schedule(**default)
+    print(f"candidates moved: {moved}")
+    assert all(v == 0 for (ev, _), v in moved.items() if ev == 0)
+    assert all(v > 0 for (ev, _), v in moved.items() if ev > 0)
+
+
 def test_series_order_xcd_sub_queues(casc):
     """A series-order round large enough for the eight XCD sub-queues (at least 64 work items per
     wave: 128 queries x 977 blocks of 2048 candidates for 1024 waves), in series order and as the
@@ -548,7 +578,7 @@ def test_set_schedule_rejects_bad_fields(ctx):
     default = ctx.get_schedule()
     for bad in ({"block": 3000}, {"diag_max": -2}, {"band_lanes": 2}, {"lb_blocks_per_cu": 65},
                 {"stats_prefix": 2}, {"data_envelope": -1}, {"rounds": 3}, {"list_cap": 63}, {"lb_tile": 2},
-                {"dtw_bound": 2}, {"dtw_rows": -1}):
+                {"dtw_bound": 2}, {"dtw_rows": -1}, {"dtw_evict": -1}, {"dtw_evict": 16}):
         with pytest.raises(dtws.DtwsError):
             ctx.set_schedule(**bad)
         assert ctx.get_schedule() == default
