@@ -567,15 +567,16 @@ __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
         const float *Tp = a.T, *qp = a.qpad, *Unp = Ubase, *Lnp = Lbase;
         const uint64_t *key = a.keys;
         uint32_t kpend = ~0u;
-        int qoff[NC];
+        // the query value of band slot 16 cc + ql at column j is qb[j + 16 cc]; the slots outside
+        // the band (only in the first and the last chunk, since 8 NC - 8 <= r <= 8 NC - 1) take the
+        // sentinel instead, so that their cells cost infinity
+        const float *qb = a.qpad;
+        bool inlo = false, inhi = false;
         float arr[W + 1], qcur[NC];
 #pragma unroll
         for (int x = 0; x <= W; ++x) arr[x] = INFINITY;
 #pragma unroll
-        for (int cc = 0; cc < NC; ++cc) {
-            qoff[cc] = 0;
-            qcur[cc] = 0.0f;
-        }
+        for (int cc = 0; cc < NC; ++cc) qcur[cc] = 0.0f;
         // this lane's row takes row slot `slot` of the chunk
         auto take = [&](int slot) {
             int64_t start = 0;
@@ -615,12 +616,13 @@ __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
             Lnp = Lbase + q * ustride;
             ucur = Unp[j0];
             lcur = Lnp[j0];
+            qb = qp + (kQPad - R + ql);
+            inlo = ql >= R - r;
+            inhi = 16 * (NC - 1) + ql <= R + r;
 #pragma unroll
-            for (int cc = 0; cc < NC; ++cc) {
-                const int kpos = 16 * cc + ql;
-                qoff[cc] = (kpos >= R - r && kpos <= R + r) ? kQPad - R + kpos : 0;
-                qcur[cc] = qp[qoff[cc] + j0];
-            }
+            for (int cc = 0; cc < NC; ++cc) qcur[cc] = qb[j0 + 16 * cc];
+            qcur[0] = inlo ? qcur[0] : kSentinel;
+            qcur[NC - 1] = inhi ? qcur[NC - 1] : kSentinel;
             if (RESUME) {
                 lbt = ent[kEvLbt];
                 kpre = ent[kEvKpre];
@@ -658,8 +660,11 @@ __global__ __launch_bounds__(256) void k_dtw_batch_rows(BatchArgs a) {
                 const int jn = jl + 1 < m ? jl + 1 : m - 1;
                 const float tnext = Tp[jn];
                 float qnext[NC];
+                const float *qj = qb + jn;
 #pragma unroll
-                for (int cc = 0; cc < NC; ++cc) qnext[cc] = qp[qoff[cc] + jn];
+                for (int cc = 0; cc < NC; ++cc) qnext[cc] = qj[16 * cc];
+                qnext[0] = inlo ? qnext[0] : kSentinel;
+                qnext[NC - 1] = inhi ? qnext[NC - 1] : kSentinel;
                 const float c = fmaf(tcur - mu, s, o);
                 column<NC>(arr, qcur, c);
                 {

@@ -573,14 +573,23 @@ __device__ __forceinline__ void dtw_lanes(const float *T, int64_t start, float m
     constexpr int W = 16 * NC;
     constexpr int R = 8 * NC - 1;
     const int ql = threadIdx.x & 15;
-    // per-chunk offset into the padded query: in-band cells read q_{j-R+k}, the others read the
-    // sentinel at the start of the padding (offset + j stays below kQPad for every column)
-    int qoff[NC];
+    // the query value of band slot k = 16 cc + ql at column j is q_{j-R+k} = qb[j + 16 cc]: one base
+    // pointer and immediate offsets.  NC is the smallest with 8 NC - 1 >= r, so the slots outside the
+    // band lie in the first chunk (k < R - r <= 7) and the last (k > R + r >= 16 NC - 9); they take the
+    // sentinel, so that their cells cost infinity
+    const float *qb = qpad + (kQPad - R + ql);
+    const bool inlo = ql >= R - r, inhi = 16 * (NC - 1) + ql <= R + r;
+    auto qload = [&](float (&q)[NC], int jj) {
+        const float *qj = qb + jj;
 #pragma unroll
-    for (int cc = 0; cc < NC; ++cc) {
-        const int kpos = 16 * cc + ql;
-        qoff[cc] = (kpos >= R - r && kpos <= R + r) ? kQPad - R + kpos : 0;
-    }
+        for (int cc = 0; cc < NC; ++cc) q[cc] = qj[16 * cc];
+        if (NC == 1) {
+            q[0] = inlo && inhi ? q[0] : kSentinel;
+        } else {
+            q[0] = inlo ? q[0] : kSentinel;
+            q[NC - 1] = inhi ? q[NC - 1] : kSentinel;
+        }
+    };
     float arr[W + 1];
 #pragma unroll
     for (int x = 0; x <= W; ++x) arr[x] = INFINITY;
@@ -592,8 +601,7 @@ __device__ __forceinline__ void dtw_lanes(const float *T, int64_t start, float m
     jdead = m;
     const float *Tp = T + start;
     float qcur[NC];
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc) qcur[cc] = qpad[qoff[cc]];
+    qload(qcur, 0);
     if constexpr (NC <= 3) {
         // narrow bands: a column is little work (16 NC cells), so one column of work cannot cover
         // the latency of the next column's series load; the series comes in blocks of 16 columns,
@@ -614,8 +622,7 @@ __device__ __forceinline__ void dtw_lanes(const float *T, int64_t start, float m
                 if (jc < m) {
                     const int jn = jc + 1 < m ? jc + 1 : jc;
                     float qnext[NC];
-#pragma unroll
-                    for (int cc = 0; cc < NC; ++cc) qnext[cc] = qpad[qoff[cc] + jn];
+                    qload(qnext, jn);
                     column<NC>(arr, qcur, fmaf(tb[u] - mu, s, o));
 #pragma unroll
                     for (int cc = 0; cc < NC; ++cc) qcur[cc] = qnext[cc];
@@ -653,8 +660,7 @@ __device__ __forceinline__ void dtw_lanes(const float *T, int64_t start, float m
         const int jn = j + 1 < m ? j + 1 : j;
         const float tnext = Tp[jn];
         float qnext[NC];
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) qnext[cc] = qpad[qoff[cc] + jn];
+        qload(qnext, jn);
         const float c = fmaf(tcur - mu, s, o);
         column<NC>(arr, qcur, c);
         tcur = tnext;
