@@ -134,7 +134,7 @@ typedef struct {
  * entries, L = 2^30 on a device of at least 128 GiB, else 2^28, and two
  * buffers of 928 bytes per entry for the DTW rows' moved candidates (schedule
  * field dtw_evict), each of min(that list, E) entries (at least 4096), E = 2^25
- * on a device of at least 128 GiB (62 GB in all), else 2^20.
+ * on a device of at least 256 GiB (62 GB in all), 2^24 from 128 GiB, else 2^20.
  * Returns DTWS_ENODEV when no HIP device is present. */
 DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_queries, dtws_ctx **out);
 

@@ -1058,9 +1058,11 @@ DTWS_API int dtws_create(int device, int64_t max_n, int32_t max_m, int32_t max_q
              dalloc(&c->tile_q, 2 * Q + 2) == hipSuccess &&
              hipHostMalloc((void **)&c->h_tile_q, sizeof(int32_t) * (2 * Q + 2), 0) == hipSuccess;
         // eviction entries of the rows DTW kernel (928 B each, two buffers, each in eight parts, one
-        // per XCD): 2^25 on a device of at least 128 GiB (62 GB in all), else 2^20; a lane finding
-        // its part full keeps its candidate
-        c->ev_cap = total_b >= (size_t(128) << 30) ? (int64_t(1) << 25) : (int64_t(1) << 20);
+        // per XCD): 2^25 on a device of at least 256 GiB (62 GB in all), 2^24 from 128 GiB, else 2^20;
+        // a lane finding its part full keeps its candidate
+        c->ev_cap = total_b >= (size_t(256) << 30)   ? (int64_t(1) << 25)
+                    : total_b >= (size_t(128) << 30) ? (int64_t(1) << 24)
+                                                     : (int64_t(1) << 20);
         if (c->ev_cap > cap) c->ev_cap = cap < 4096 ? 4096 : cap;
         c->ev_cap &= ~int64_t(7);
         c->ev_levels = (int)(max_m / 16 + 1);
