@@ -473,7 +473,8 @@ static hipError_t launch_dtw_t(const DtwArgs &a, int64_t max_count, int num_cu, 
         return hipGetLastError();
     }
     int64_t blocks = (max_count + 255) / 256;
-    const int64_t cap = (int64_t)num_cu * 4;
+    // narrow bands (a few registers per lane) run more waves per SIMD to cover their loads' latency
+    const int64_t cap = (int64_t)num_cu * (nc <= 3 ? 16 : 4);
     if (blocks > cap) blocks = cap;
     const dim3 g((unsigned)blocks), b(256);
     switch (nc) {
